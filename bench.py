@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark: time to a true residual of 1e-12 and Wilson-operator HBM GB/s.
+
+Workload (one GPU): 32^3 x 64 lattice, synthetic SU(3) links
+U = exp(i eps sum_a c_a lambda_a) with eps = 0.3 (re-unitarised), kappa =
+0.124, periodic boundaries, one Gaussian complex source.  A step is one
+full solve D x = b from x = 0 with the FP64 iterative refinement around the
+rescaled FP16-storage BiCGStab (s = 128, sigma = 64), with all inputs
+resident in device memory.  The FP64 BiCGStab and the FP32-inner refinement
+are timed beside it, the Wilson operator is timed on its own with HIP events
+for the roofline, and the CPU oracle is timed on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-12 residual + Dslash HBM GB/s at 32^3x64, FP16-inner vs FP64 BiCGStab"
+PEAK_HBM_GBS = 8000.0
+DSLASH_BYTES = {0: 960, 1: 480, 2: 240}    # algorithmic bytes per site: links + input + output
+DSLASH_FLOP_PER_SITE = 1368                 # 8 hops x 168 - 24 + 48 for 1 - kappa H
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--dims", type=str, default="32,32,32,64")
+    ap.add_argument("--kappa", type=float, default=0.124)
+    ap.add_argument("--eps", type=float, default=0.3)
+    ap.add_argument("--dslash-reps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    return ap.parse_args()
+
+
+def time_dslash(q, torch, g, prec, reps, V):
+    """Average duration of the native-layout Wilson operator, HIP events on
+    the launch stream; three buffer pairs rotate so repeats are not served
+    from the last-level cache."""
+    bufs = []
+    src = torch.randn(V * 12 * 2, dtype=torch.float64, device="cuda").view(torch.complex128)
+    for _ in range(3):
+        a, b = g.native_spinor(prec), g.native_spinor(prec)
+        q.convert(g, prec, a, src, want_norm=False)
+        bufs.append((a, b))
+    stream = torch.cuda.current_stream()
+    for i in range(5):
+        a, b = bufs[i % 3]
+        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(reps):
+        a, b = bufs[i % 3]
+        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return ms
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2602_14450_amd as q
+    import qcd_inputs as qi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dims = tuple(int(v) for v in args.dims.split(","))
+    V = int(np.prod(dims))
+    k = args.kappa
+    t0 = time.time()
+    U = qi.gauge_field(dims, args.eps, 201)
+    b = qi.gaussian_source(dims, 202)
+    gen_s = time.time() - t0
+    g = q.gauge_upload(torch.from_numpy(U).cuda(), dims)
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bd)
+    max_iter = 20000
+    ws = torch.empty(g.workspace_bytes(0, q.FP16, max_iter), dtype=torch.uint8, device="cuda")
+    ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
+    ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
+
+    def solve_fp16():
+        return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,
+                                inner_max_iter=max_iter, workspace=ws)
+
+    def solve_fp32():
+        return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP32, s=1.0, recalc_shat=False, sigma=0.0, tol=1e-12,
+                                inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws32)
+
+    def solve_fp64():
+        return q.bicgstab(g, k, x, bd, prec=q.FP64, tol=1e-12, max_iter=max_iter, workspace=ws64, history=False)
+
+    for _ in range(args.warmup):
+        solve_fp16()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        infos.append(solve_fp16())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    s_per_solve = elapsed / args.steps
+    i16 = infos[-1]
+    print(f"[bench] fp16-inner: {s_per_solve*1e3:.2f} ms/solve outer={i16.outer_iters} inner={i16.inner_iters} "
+          f"res={i16.true_rel_residual:.2e}", file=sys.stderr, flush=True)
+
+    # comparison solvers (one warm run, then one timed)
+    others = {}
+    for name, fn in (("fp64_bicgstab", solve_fp64), ("fp32_inner_ir", solve_fp32)):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        inf = fn()
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        others[name] = dict(seconds=te, outer=inf.outer_iters, iters=inf.inner_iters, matvec_low=inf.matvec_low,
+                            matvec_fp64=inf.matvec_fp64, true_rel_residual=inf.true_rel_residual)
+        print(f"[bench] {name}: {te*1e3:.2f} ms, iters={inf.inner_iters}", file=sys.stderr, flush=True)
+    others["fp16_inner_ir"] = dict(seconds=s_per_solve, outer=i16.outer_iters, iters=i16.inner_iters,
+                                   matvec_low=i16.matvec_low, matvec_fp64=i16.matvec_fp64,
+                                   true_rel_residual=i16.true_rel_residual)
+
+    # Wilson operator roofline (dominant kernel of the inner solve)
+    dsl = {}
+    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+        ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
+        gbs = DSLASH_BYTES[prec] * V / (ms * 1e-3) / 1e9
+        dsl[name] = dict(us=ms * 1e3, GBps=gbs, frac=gbs / PEAK_HBM_GBS,
+                         GFLOPs=DSLASH_FLOP_PER_SITE * V / (ms * 1e-3) / 1e9)
+        print(f"[bench] dslash {name}: {ms*1e3:.1f} us {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    roof = dict(bound="hbm", achieved=dsl["fp16"]["GBps"], peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=dsl["fp16"]["frac"], traffic=None, kernel="k_dslash<__half2, D>",
+                bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import solvers as S
+        n_it = args.cpu_sample_iters
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        A = lambda v: oracle.dslash(U, v, k, dims)
+        ts = time.perf_counter()
+        S.bicgstab(A, b, S.FP64, tol2=0.0, maxiter=n_it)
+        per_it = (time.perf_counter() - ts) / n_it
+        it64 = others["fp64_bicgstab"]["iters"]
+        cpu = dict(value=per_it * it64, unit="s", cores=threads, kind="oracle",
+                   sample=f"{n_it} iterations of the oracle's FP64 BiCGStab at {dims}, "
+                          f"scaled to the {it64} iterations the FP64 solve needs")
+        print(f"[bench] cpu oracle: {per_it:.2f} s/iteration", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC, "value": s_per_solve, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": s_per_solve * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp16-storage/fp32-arith, fp64 refinement", "data": "synthetic",
+        "config": {"workload": f"Wilson D x = b, {'x'.join(map(str, dims))} lattice, eps={args.eps} SU(3) links, "
+                               f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64), tol 1e-12",
+                   "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12},
+        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl,
+        "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
+        "input_generation_s": gen_s,
+    }
+    print(json.dumps(out), flush=True)
+    g.close()
+
+
+if __name__ == "__main__":
+    main()

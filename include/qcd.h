@@ -1,0 +1,173 @@
+/*
+ * libqcd: Wilson-Dirac solver with FP16/FP32 inner BiCGStab and FP64
+ * iterative refinement, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kanamori et al., "Mixed precision solvers with half-precision
+ * floating point numbers for Lattice QCD on A64FX processor" (SCA/HPCAsia
+ * 2026 Workshops).  The operator is the Wilson matrix of eq. (1), the inner
+ * solver the rescaled BiCGStab of Alg. 4 / Alg. 5, the outer solver the
+ * rescaled iterative refinement of Alg. 3 (Alg. 2 as a special case).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: extents dims[4] = {Lx, Ly, Lz, Lt}, each even and >= 2; periodic
+ *   boundaries in all four directions.  Site index s = x + Lx*(y + Ly*(z + Lz*t)).
+ * Canonical layouts (device memory, complex128 = two doubles re, im):
+ *   gauge field U[s][mu][a][b], mu = 0..3 for x, y, z, t; U_mu(x) is the link
+ *   from x to x + mu (Sec. 2, first paragraph);
+ *   spinor field psi[s][spin][colour] (12 complex per site).
+ * Native layout: the library's own device layout (checkerboarded, blocks of
+ *   64 sites, component-major within a block) in a chosen precision; sizes
+ *   from qcd_spinor_bytes().  Only pass native buffers produced by this
+ *   library for the same gauge handle.
+ * Gamma matrices: the Dirac basis whose gamma_1 is the one printed in Sec. 2
+ *   (gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = diag(1,1,-1,-1)).
+ * Pointers named *_dev are device pointers; the caller owns all device
+ *   memory passed in.  `stream` is a hipStream_t (NULL = default stream).
+ *   Entry points that return solver results synchronise with `stream`.
+ * Errors: a negative status; qcd_last_error() gives a message (per thread).
+ *   No C++ exception crosses this interface.
+ */
+#ifndef QCD_H
+#define QCD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QCD_OK = 0,
+  QCD_NOT_CONVERGED = 1,   /* warning: outputs valid, tolerance not reached in max iterations */
+  QCD_ERR_ARG = -1,        /* invalid argument (null pointer, odd extent, kappa <= 0, ...) */
+  QCD_ERR_HIP = -2,        /* a HIP runtime call failed */
+  QCD_ERR_NONFINITE = -3,  /* a solver scalar became Inf/NaN (e.g. FP16 overflow) */
+  QCD_ERR_WORKSPACE = -4,  /* caller workspace smaller than qcd_workspace_bytes() */
+  QCD_ERR_UNSUPPORTED = -5,
+  QCD_ERR_BREAKDOWN = -6   /* BiCGStab breakdown: rho = (r*, r) = 0 or (r*, A p) = 0 */
+} qcd_status;
+
+typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2 } qcd_prec;
+typedef enum { QCD_LAYOUT_CANONICAL = 0, QCD_LAYOUT_NATIVE = 1 } qcd_layout;
+/* D = 1 - kappa H (eq. (1)); H is the hopping sum; D^dag = gamma_5 D gamma_5. */
+typedef enum { QCD_OP_D = 0, QCD_OP_H = 1, QCD_OP_DDAG = 2, QCD_OP_HDAG = 3 } qcd_op;
+
+typedef struct qcd_gauge qcd_gauge; /* opaque handle */
+
+/* Parameters of the rescaled BiCGStab (Alg. 4; Alg. 5 when sigma_lambda > 0). */
+typedef struct {
+  double tol;          /* stop when |r| / gamma' <= tol * |b| (relative, unscaled residual) */
+  int max_iter;        /* iteration cap (> 0) */
+  double sigma;        /* rescale the residual to norm sigma after each iteration; 0 = off (gamma = 1) */
+  double sigma_lambda; /* rescale the solution to norm sigma_lambda (Alg. 5); 0 = off */
+  int recalc_gamma;    /* 1: gamma is the measured ratio |r stored| / |r before rescaling| */
+  double omega0;       /* omega prescription threshold; the paper uses 0.7; 0 disables */
+  int ftz;             /* 1: a binary16 store below 2^-14 in magnitude is flushed to zero */
+  int check_every;     /* host polls the convergence flag every this many iterations (0: 4) */
+} qcd_bicgstab_params;
+
+/* Parameters of the rescaled iterative refinement (Alg. 3; Alg. 2 is s = 1, recalc_shat = 0). */
+typedef struct {
+  double tol;               /* stop when |b - D x|_2 / |b|_2 <= tol, checked in FP64 */
+  int max_outer;            /* outer iteration cap (> 0) */
+  qcd_prec inner_prec;      /* storage precision of the inner solve (FP16, FP32 or FP64) */
+  double s;                 /* the residual is rescaled to norm s before conversion */
+  int recalc_shat;          /* 1: correct with s^ = |single(y~)| (Alg. 3); 0: with s */
+  qcd_bicgstab_params inner;/* inner.tol is eps_tol (the paper's eps_tol^2 = 1e-4 is tol = 1e-2) */
+} qcd_ir_params;
+
+typedef struct {
+  int outer_iters;          /* refinement steps (0 for qcd_bicgstab) */
+  int inner_iters;          /* BiCGStab iterations in total */
+  int matvec_low;           /* applications of D in the inner precision */
+  int matvec_fp64;          /* FP64 applications of D (outer residuals, final check) */
+  double true_rel_residual; /* |b - D x| / |b| in FP64 at return */
+  double seconds;           /* wall-clock time inside the call */
+  int inner_status;         /* last inner-solver stop reason: 1 converged, 2 max_iter, 3 non-finite, 4 breakdown */
+  double first_shat_over_s; /* s^/s of the first refinement step (rounding of the FP16 conversion) */
+  double* history;          /* optional caller-owned host array: (|r|/gamma')^2/|b|^2 per inner iteration,
+                               concatenated over refinement steps */
+  int history_cap;          /* capacity of history */
+  int history_len;          /* entries written */
+  double* outer_history;    /* optional caller-owned host array: |r|/|b| after each refinement step */
+  int outer_history_cap;
+  double* zeros;            /* optional: zero reals in y~ per refinement step (Fig. 9 diagnostic) */
+} qcd_solve_info;
+
+/* Message for the last error on this thread ("" if none). */
+const char* qcd_last_error(void);
+
+/* Gauge upload.  Converts the canonical FP64 field U_dev (complex128
+ * [V][4][3][3], device) to native copies in the precisions selected by
+ * prec_mask (bit (1 << QCD_FP64) etc.; 0 selects all three; the FP64 copy
+ * is always built because the outer refinement needs it).  The handle owns
+ * those copies and a reusable workspace; free it with qcd_gauge_free.
+ * FP64 -> FP32/FP16 rounding is one round-to-nearest-even step.
+ * Implements the low-precision matrix A~ of Alg. 3 (links stored in the
+ * inner precision).  Synchronises with stream.  Errors: QCD_ERR_ARG for a
+ * null pointer or an odd / < 2 extent, QCD_ERR_HIP on allocation failure. */
+qcd_status qcd_gauge_upload(qcd_gauge** g, const int dims[4], const void* U_dev, int prec_mask, void* stream);
+qcd_status qcd_gauge_free(qcd_gauge* g);
+
+/* Bytes of one native spinor field in precision prec. */
+size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
+
+/* Workspace bytes that qcd_solve_mixed_ir (what = 0), qcd_bicgstab (what = 1)
+ * or qcd_dslash with canonical layout (what = 2) need for inner precision
+ * prec and max_iter history entries.  Passing ws = NULL to those calls makes
+ * the handle's own cached workspace be used (allocated on first use). */
+size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter);
+
+/* Precision conversion with rescaling (Alg. 3, the steps y = alpha r and
+ * y~ = low_prec(y)): native_dev = round_prec(scale * canonical_dev) with
+ * one round-to-nearest-even conversion from FP64, optional flush to
+ * zero of binary16 subnormals; if norm2 is not NULL it receives
+ * sum |stored|^2 computed per site in the arithmetic precision and in FP64
+ * across sites (the s^ of Alg. 3 is its square root).  Synchronises when
+ * norm2 is requested. */
+qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, void* native_dev, const void* canonical_dev, double scale,
+                       int ftz, double* norm2, void* stream);
+
+/* Inverse conversion: canonical_dev (complex128) = scale * double(native_dev). */
+qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, void* canonical_dev, const void* native_dev, double scale,
+                         void* stream);
+
+/* Wilson operator (eq. (1), Alg. 1 with the projection of Sec. 2):
+ * out = op(in) with op one of D, H, D^dag, H^dag.  prec selects the link
+ * copy, the storage of in/out (native layout) and the arithmetic (FP64 for
+ * FP64, FP32 otherwise).  With QCD_LAYOUT_CANONICAL, in and out are
+ * complex128 canonical fields, converted to/from prec around the
+ * application.  out must not alias in.  Asynchronous on stream. */
+qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, void* out_dev,
+                      const void* in_dev, void* stream);
+
+/* FP64 true residual of Alg. 3: r = b - D x (canonical complex128), and if
+ * norm2 is not NULL, |r|^2.  Synchronises when norm2 is requested. */
+qcd_status qcd_residual(const qcd_gauge* g, double kappa, void* r_dev, const void* x_dev, const void* b_dev,
+                        double* norm2, void* stream);
+
+/* Rescaled BiCGStab (Alg. 4 / Alg. 5) solving D x = b in precision prec,
+ * x0 = 0, r* = b.  b_dev and x_dev are canonical complex128; b is rounded to
+ * prec, the solution is returned in FP64 as x = lambda-unscaled inner x.
+ * info (may be NULL) receives counts and the FP64 true residual.
+ * Returns QCD_OK, QCD_NOT_CONVERGED, QCD_ERR_NONFINITE or QCD_ERR_BREAKDOWN
+ * (x holds the last iterate in the last three cases).  Synchronises. */
+qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, void* x_dev, const void* b_dev,
+                        const qcd_bicgstab_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+/* FP64 iterative refinement around the rescaled low-precision BiCGStab
+ * (Alg. 3 with Alg. 4 / Alg. 5; Alg. 2 when s = 1 and recalc_shat = 0):
+ *   x = 0, r = b; while |r|/|b| > tol: y~ = low(r s/|r|), s^ = |single(y~)|,
+ *   solve A~ t = y~, x += (|r|/s^) double(t), r = b - D x (FP64).
+ * b_dev, x_dev canonical complex128.  Returns QCD_OK when the FP64 true
+ * residual reaches tol, QCD_NOT_CONVERGED after max_outer steps (x valid),
+ * QCD_ERR_NONFINITE / QCD_ERR_BREAKDOWN if an inner solve failed before any
+ * progress.  Synchronises. */
+qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, void* x_dev, const void* b_dev, const qcd_ir_params* p,
+                              qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QCD_H */

@@ -23,7 +23,8 @@ reason in the design notes):
 * Inner stopping test: (|r| / gamma')^2 <= eps_tol^2 * |b|^2, relative to the
   inner right-hand side.
 * Alg. 5 returns the solution divided by the accumulated factor lambda'.
-* FP64 -> FP16 conversion rounds to nearest-even through FP32.
+* FP64 -> FP16 conversion is one round-to-nearest-even step (IEEE 754
+  format conversion), not two roundings through FP32.
 """
 from __future__ import annotations
 
@@ -51,8 +52,8 @@ def lowp(v: np.ndarray, prec: str, ftz: bool = False) -> np.ndarray:
     if prec == FP32:
         return v.astype(np.complex64).astype(np.complex128)
     if prec == FP16:
-        re = v.real.astype(np.float32).astype(np.float16)
-        im = v.imag.astype(np.float32).astype(np.float16)
+        re = v.real.astype(np.float16)
+        im = v.imag.astype(np.float16)
         if ftz:
             re = np.where(np.abs(re) < FP16_MIN_NORMAL, np.float16(0) * re, re)
             im = np.where(np.abs(im) < FP16_MIN_NORMAL, np.float16(0) * im, im)

@@ -1,0 +1,241 @@
+"""Python binding of libqcd (Wilson-Dirac mixed-precision solver for MI355X).
+
+Argument marshalling only: every step runs in the HIP kernels of libqcd.so,
+reached through its C ABI (``include/qcd.h``).  PyTorch supplies device
+memory and the current stream.  There is no fallback: importing this module
+without the built library raises.
+
+Functions keep the C names without the ``qcd_`` prefix: :func:`gauge_upload`,
+:func:`dslash`, :func:`bicgstab`, :func:`solve_mixed_ir`, :func:`convert`,
+:func:`unconvert`, :func:`residual`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqcd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_2602_14450_amd/build.py (or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FP64, FP32, FP16 = 0, 1, 2
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
+CANONICAL, NATIVE = 0, 1
+OP_D, OP_H, OP_DDAG, OP_HDAG = 0, 1, 2, 3
+STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_hip", -3: "err_nonfinite", -4: "err_workspace",
+          -5: "err_unsupported", -6: "err_breakdown"}
+
+
+class BicgstabParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("sigma", ctypes.c_double),
+                ("sigma_lambda", ctypes.c_double), ("recalc_gamma", ctypes.c_int), ("omega0", ctypes.c_double),
+                ("ftz", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class IRParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("inner_prec", ctypes.c_int),
+                ("s", ctypes.c_double), ("recalc_shat", ctypes.c_int), ("inner", BicgstabParams)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("inner_iters", ctypes.c_int), ("matvec_low", ctypes.c_int),
+                ("matvec_fp64", ctypes.c_int), ("true_rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("inner_status", ctypes.c_int), ("first_shat_over_s", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("history_len", ctypes.c_int), ("outer_history", ctypes.POINTER(ctypes.c_double)),
+                ("outer_history_cap", ctypes.c_int), ("zeros", ctypes.POINTER(ctypes.c_double))]
+
+
+_vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_lib.qcd_last_error.restype = ctypes.c_char_p
+_lib.qcd_gauge_upload.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_i), _vp, _i, _vp]
+_lib.qcd_gauge_free.argtypes = [_vp]
+_lib.qcd_spinor_bytes.argtypes = [_vp, _i]
+_lib.qcd_spinor_bytes.restype = _sz
+_lib.qcd_workspace_bytes.argtypes = [_vp, _i, _i, _i]
+_lib.qcd_workspace_bytes.restype = _sz
+_lib.qcd_convert.argtypes = [_vp, _i, _vp, _vp, _d, _i, ctypes.POINTER(_d), _vp]
+_lib.qcd_unconvert.argtypes = [_vp, _i, _vp, _vp, _d, _vp]
+_lib.qcd_dslash.argtypes = [_vp, _d, _i, _i, _i, _vp, _vp, _vp]
+_lib.qcd_residual.argtypes = [_vp, _d, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]
+_lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(BicgstabParams), ctypes.POINTER(SolveInfo),
+                              _vp, _sz, _vp]
+_lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
+                                    _sz, _vp]
+for _f in ("qcd_gauge_upload", "qcd_gauge_free", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual",
+           "qcd_bicgstab", "qcd_solve_mixed_ir"):
+    getattr(_lib, _f).restype = _i
+
+EXPORTED = ["qcd_last_error", "qcd_gauge_upload", "qcd_gauge_free", "qcd_spinor_bytes", "qcd_workspace_bytes",
+            "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"]
+
+
+class QcdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code, allow=(0,)):
+    if code not in allow:
+        raise QcdError(code, _lib.qcd_last_error().decode())
+    return code
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _as_c128(t: torch.Tensor) -> torch.Tensor:
+    assert t.dtype == torch.complex128, "canonical fields are complex128"
+    return t.contiguous()
+
+
+class Gauge:
+    """A gauge field uploaded to the device in the native layout (FP64 plus
+    the selected low-precision copies)."""
+
+    def __init__(self, U: torch.Tensor, dims, precs=(FP64, FP32, FP16)):
+        U = _as_c128(U)
+        self.dims = tuple(int(d) for d in dims)
+        mask = 0
+        for p in precs:
+            mask |= 1 << PREC[p]
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int * 4)(*self.dims)
+        _check(_lib.qcd_gauge_upload(ctypes.byref(h), d, _ptr(U), mask, _stream()))
+        self.handle = h
+        self.volume = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+
+    def close(self):
+        if self.handle:
+            _lib.qcd_gauge_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spinor_bytes(self, prec) -> int:
+        return int(_lib.qcd_spinor_bytes(self.handle, PREC[prec]))
+
+    def workspace_bytes(self, what, prec, max_iter) -> int:
+        return int(_lib.qcd_workspace_bytes(self.handle, int(what), PREC[prec], int(max_iter)))
+
+    def native_spinor(self, prec) -> torch.Tensor:
+        """An uninitialised device buffer for one native spinor field."""
+        return torch.empty(self.spinor_bytes(prec), dtype=torch.uint8, device="cuda")
+
+
+def gauge_upload(U, dims, precs=(FP64, FP32, FP16)) -> Gauge:
+    return Gauge(U, dims, precs)
+
+
+def convert(g: Gauge, prec, native: torch.Tensor, canonical: torch.Tensor, scale=1.0, ftz=False, want_norm=True):
+    n2 = ctypes.c_double(0.0)
+    _check(_lib.qcd_convert(g.handle, PREC[prec], _ptr(native), _ptr(_as_c128(canonical)), float(scale), int(ftz),
+                            ctypes.byref(n2) if want_norm else None, _stream()))
+    return n2.value if want_norm else None
+
+
+def unconvert(g: Gauge, prec, canonical: torch.Tensor, native: torch.Tensor, scale=1.0):
+    _check(_lib.qcd_unconvert(g.handle, PREC[prec], _ptr(canonical), _ptr(native), float(scale), _stream()))
+
+
+def dslash(g: Gauge, kappa, out: torch.Tensor, inp: torch.Tensor, op=OP_D, prec=FP64, layout=CANONICAL):
+    _check(_lib.qcd_dslash(g.handle, float(kappa), int(op), PREC[prec], int(layout), _ptr(out), _ptr(inp), _stream()))
+    return out
+
+
+def residual(g: Gauge, kappa, r: torch.Tensor, x: torch.Tensor, b: torch.Tensor) -> float:
+    n2 = ctypes.c_double(0.0)
+    _check(_lib.qcd_residual(g.handle, float(kappa), _ptr(r), _ptr(_as_c128(x)), _ptr(_as_c128(b)),
+                             ctypes.byref(n2), _stream()))
+    return n2.value
+
+
+@dataclass
+class Info:
+    status: str
+    outer_iters: int
+    inner_iters: int
+    matvec_low: int
+    matvec_fp64: int
+    true_rel_residual: float
+    seconds: float
+    inner_status: int
+    first_shat_over_s: float
+    history: list = field(default_factory=list)
+    outer_history: list = field(default_factory=list)
+    zeros: list = field(default_factory=list)
+
+
+def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every):
+    return BicgstabParams(float(tol), int(max_iter), float(sigma or 0.0), float(sigma_lambda or 0.0),
+                          int(bool(recalc_gamma)), float(omega0), int(bool(ftz)), int(check_every))
+
+
+def _make_info(hist_cap, outer_cap):
+    info = SolveInfo()
+    hist = (ctypes.c_double * max(hist_cap, 1))()
+    outer = (ctypes.c_double * max(outer_cap, 1))()
+    zeros = (ctypes.c_double * max(outer_cap, 1))()
+    info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    info.history_cap = hist_cap
+    info.outer_history = ctypes.cast(outer, ctypes.POINTER(ctypes.c_double))
+    info.outer_history_cap = outer_cap
+    info.zeros = ctypes.cast(zeros, ctypes.POINTER(ctypes.c_double))
+    return info, hist, outer, zeros
+
+
+def _info_out(code, info, hist, outer, zeros):
+    n_out = min(info.outer_iters, info.outer_history_cap)
+    return Info(STATUS.get(code, str(code)), info.outer_iters, info.inner_iters, info.matvec_low, info.matvec_fp64,
+                info.true_rel_residual, info.seconds, info.inner_status, info.first_shat_over_s,
+                list(hist[:info.history_len]), list(outer[:n_out]), list(zeros[:n_out]))
+
+
+def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1e-12, max_iter=10000, sigma=0.0,
+             sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=4, workspace=None,
+             history=True, raise_on_error=True) -> Info:
+    """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors."""
+    p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
+    info, hist, outer, zeros = _make_info(max_iter if history else 0, 1)
+    ws = _ptr(workspace) if workspace is not None else None
+    wsb = workspace.numel() if workspace is not None else 0
+    code = _lib.qcd_bicgstab(g.handle, float(kappa), PREC[prec], _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
+                             ctypes.byref(info), ws, wsb, _stream())
+    if raise_on_error:
+        _check(code, allow=(0, 1))
+    return _info_out(code, info, hist, outer, zeros)
+
+
+def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
+                   s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
+                   recalc_gamma=True, omega0=0.7, ftz=False, check_every=4, workspace=None, history=False,
+                   raise_on_error=True) -> Info:
+    """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab."""
+    inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
+    p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner)
+    info, hist, outer, zeros = _make_info(inner_max_iter * 4 if history else 0, max_outer)
+    ws = _ptr(workspace) if workspace is not None else None
+    wsb = workspace.numel() if workspace is not None else 0
+    code = _lib.qcd_solve_mixed_ir(g.handle, float(kappa), _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
+                                   ctypes.byref(info), ws, wsb, _stream())
+    if raise_on_error:
+        _check(code, allow=(0, 1))
+    return _info_out(code, info, hist, outer, zeros)

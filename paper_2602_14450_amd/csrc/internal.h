@@ -1,0 +1,84 @@
+// Declarations shared by the library's translation units (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace qcd {
+
+enum { kFP64 = 0, kFP32 = 1, kFP16 = 2 };
+enum { kOpD = 0, kOpH = 1, kOpDdag = 2, kOpHdag = 3 };
+enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3 };
+
+// Inner-solver status codes kept on the device.
+enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4 };
+
+inline size_t prec_complex_bytes(int prec) { return prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4); }
+
+// Scalars of the rescaled BiCGStab (Alg. 4 / Alg. 5) and of the outer
+// refinement (Alg. 2 / Alg. 3), all FP64, resident in device memory.
+// Complex values are (re, im) pairs.
+struct Scalars {
+  // parameters
+  double sigma;          // residual norm after rescaling (0: gamma = 1)
+  double sigma_lambda;   // solution norm after rescaling (0: lambda = 1)
+  double omega0;         // omega prescription threshold
+  double tol2;           // inner stop: (|r|/gamma')^2 <= tol2 * |b|^2
+  int recalc_gamma;
+  int max_iter;
+  // BiCGStab recurrences
+  double bnorm2;
+  double rho[2], rho_prev[2];    // rho = (r*, r), rho' (rescaled)
+  double alpha[2], alpha_prev[2];
+  double omega[2], omega_prev[2];
+  double beta[2];
+  double pcoef[2];               // beta * gamma: folds the p, v rescaling into the next p update
+  double xcoef;                  // lambda' / gamma' for the x update
+  double xscale;                 // pending lambda, applied to x at the next x update
+  double gamma_pred;             // factor applied to the new residual when stored
+  double gamma, gamma_cum, lambda_cum;
+  double rnorm2;                 // |r_stored|^2
+  int iter;
+  int first;                     // first iteration: p = r, x = 0
+  int active;                    // 0 once the solver stopped
+  int status;
+  // outer refinement
+  double out_rnorm;              // |r| of the FP64 residual
+  double out_scale;              // s / |r|
+  double shat;                   // |single(y~)|
+  double zeros;                  // zero reals in y~
+  double pad[4];
+};
+
+// launchers (dslash.hip)
+void launch_dslash(int prec, const Geom& g, int op, int epi, void* out, const void* in, const void* U, double kappa,
+                   const void* aux, double* partials, int par0, int npar, const int* active, int ftz,
+                   hipStream_t st);
+int dslash_partial_rows(const Geom& g, int npar);
+
+// launchers (blas.hip)
+int site_grid(const Geom& g);  // blocks of the per-site streaming kernels (both parities)
+void launch_pack_links(const Geom& g, int prec, void* dst, const double* Ucanon, hipStream_t st);
+void launch_pack_spinor(const Geom& g, int prec, void* dst, const double* canon, double scale, int ftz,
+                        double* partials, hipStream_t st);
+void launch_unpack_spinor(const Geom& g, int prec, double* canon, const void* src, double scale, hipStream_t st);
+void launch_zero(const Geom& g, int prec, void* dst, hipStream_t st);
+
+void launch_bicg_init(Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_p_update(const Geom& g, int prec, Scalars* sc, void* p, const void* v, const void* r, int ftz,
+                     hipStream_t st);
+void launch_alpha(Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_s_update(const Geom& g, int prec, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st);
+void launch_omega(Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_xr_update(const Geom& g, int prec, Scalars* sc, void* x, void* r, const void* t, const void* p,
+                      const void* rstar, double* partials, int ftz, hipStream_t st);
+void launch_iter_end(Scalars* sc, const double* partials, int nrows, double* history, hipStream_t st);
+
+void launch_outer_residual_norm(Scalars* sc, const double* partials, int nrows, double s_target, hipStream_t st);
+void launch_convert(const Geom& g, int prec, Scalars* sc, const double* r64, void* y, void* rstar, void* x,
+                    double* partials, int ftz, hipStream_t st);
+void launch_convert_finish(Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
+                           hipStream_t st);
+void launch_correct(const Geom& g, int prec, Scalars* sc, double* x64, const void* xlo, hipStream_t st);
+void launch_finish_sum(const double* partials, int nrows, int nv, double* out, hipStream_t st);
+
+}  // namespace qcd

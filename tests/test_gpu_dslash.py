@@ -1,0 +1,129 @@
+"""Parity of the HIP Wilson operator and conversions with the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import qcd_inputs as qi  # noqa: E402
+from oracle import solvers as S  # noqa: E402
+from gpu_common import TOL, compare, fields, to_dev, to_host  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+SHAPES = [(2, 2, 2, 2), (2, 4, 6, 8), (4, 6, 8, 10), (2, 4, 6, 10), (8, 8, 8, 8), (6, 4, 2, 12)]
+OPS = [0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_dslash_all_ops(q, dims, prec):
+    U, psi = fields(dims, gseed=11 + sum(dims), sseed=12)
+    g = q.gauge_upload(to_dev(U), dims)
+    k = 0.124
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    for op in OPS:
+        q.dslash(g, k, out, x, op=op, prec=prec, layout=q.CANONICAL)
+        torch.cuda.synchronize()
+        want = oracle.dslash(U, psi, k, dims, op)
+        compare(to_host(out), want, TOL[prec], f"dims={dims} prec={prec} op={op}")
+    g.close()
+
+
+def test_dslash_native_layout_and_bitwise_rerun(q):
+    dims = (4, 6, 8, 10)
+    U, psi = fields(dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    for prec in (0, 1, 2):
+        a = g.native_spinor(prec)
+        b1 = g.native_spinor(prec)
+        b2 = g.native_spinor(prec)
+        q.convert(g, prec, a, to_dev(psi))
+        q.dslash(g, 0.13, b1, a, prec=prec, layout=q.NATIVE)
+        q.dslash(g, 0.13, b2, a, prec=prec, layout=q.NATIVE)
+        torch.cuda.synchronize()
+        assert torch.equal(b1, b2)
+        out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+        q.unconvert(g, prec, out, b1)
+        compare(to_host(out), oracle.dslash(U, psi, 0.13, dims), TOL[prec], f"native prec={prec}")
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_convert_is_bit_exact(q, prec):
+    dims = (2, 4, 6, 10)
+    U, psi = fields(dims)
+    psi = psi * np.geomspace(1e-9, 50.0, psi.size).reshape(psi.shape)   # FP16 subnormals up to ~3e4 after scaling
+    g = q.gauge_upload(to_dev(U), dims)
+    for scale, ftz in [(1.0, False), (128.0, False), (3.7e-3, True), (40.0, True)]:
+        nat = g.native_spinor(prec)
+        n2 = q.convert(g, prec, nat, to_dev(psi), scale=scale, ftz=ftz)
+        back = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+        q.unconvert(g, prec, back, nat)
+        torch.cuda.synchronize()
+        want = S.lowp(scale * psi, S.FP32 if prec == 1 else S.FP16, ftz=ftz)
+        got = to_host(back)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), f"scale={scale} ftz={ftz}"
+        assert abs(n2 - S.norm2(want)) <= 1e-6 * S.norm2(want)
+    g.close()
+
+
+def test_residual_fp64(q):
+    dims = (4, 4, 6, 8)
+    U, b = fields(dims)
+    x = qi.gaussian_source(dims, 77)
+    g = q.gauge_upload(to_dev(U), dims)
+    r = torch.empty_like(to_dev(b))
+    n2 = q.residual(g, 0.12, r, to_dev(x), to_dev(b))
+    want = b - oracle.dslash(U, x, 0.12, dims)
+    compare(to_host(r), want, 1e-14, "residual")
+    assert abs(n2 - S.norm2(want)) < 1e-12 * S.norm2(want)
+    g.close()
+
+
+def test_invalid_arguments(q):
+    dims = (3, 4, 4, 4)
+    U = to_dev(qi.unit_gauge(dims))
+    with pytest.raises(q.QcdError):
+        q.gauge_upload(U, dims)
+    dims = (4, 4, 4, 4)
+    g = q.gauge_upload(to_dev(qi.unit_gauge(dims)), dims)
+    x = to_dev(qi.gaussian_source(dims, 1))
+    with pytest.raises(q.QcdError):
+        q.dslash(g, 0.1, x, x)          # aliasing
+    with pytest.raises(q.QcdError):
+        q.dslash(g, -0.1, torch.empty_like(x), x)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_dslash_full_size_sampled(q, prec):
+    # The benchmark lattice 32^3 x 64 in the launch configuration the
+    # benchmark times (native layout); outputs compared at sampled sites.
+    dims = (32, 32, 32, 64)
+    U, psi = fields(dims, gseed=201, sseed=202)
+    g = q.gauge_upload(to_dev(U), dims, precs=(0, prec))
+    a = g.native_spinor(prec)
+    b = g.native_spinor(prec)
+    q.convert(g, prec, a, to_dev(psi), want_norm=False)
+    q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE)
+    out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    q.unconvert(g, prec, out, b)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    V = int(np.prod(dims))
+    sites = np.concatenate([[0, 1, 31, 32, V - 1, V - 32 * 32 * 32], rng.choice(V, 4000, replace=False)])
+    got = to_host(out)[sites]
+    want = oracle.dslash_sites(U, psi, 0.124, dims, sites)
+    compare(got, want, TOL[prec], f"32^3x64 prec={prec}")
+    g.close()

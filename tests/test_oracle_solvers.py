@@ -53,6 +53,10 @@ def test_binary16_rounding_matches_table1():
     # flush to zero removes subnormals only
     z = S.lowp(np.array([2.0 ** -15, 2.0 ** -14], complex), S.FP16, ftz=True).real
     assert z[0] == 0.0 and z[1] == 2.0 ** -14
+    # one rounding from FP64: 1 + 2^-11 + 2^-40 is just above the tie and
+    # rounds up; two roundings through FP32 would land on the tie and give 1
+    d = S.lowp(np.array([1 + 2.0 ** -11 + 2.0 ** -40], complex), S.FP16).real
+    assert d[0] == 1 + 2.0 ** -10
     e32 = S.lowp(np.array([1 + 2.0 ** -24, 1 + 3 * 2.0 ** -24], complex), S.FP32).real
     assert e32[0] == 1.0 and e32[1] == 1 + 2.0 ** -22
 
