@@ -110,6 +110,17 @@ const char* qcd_last_error(void);
 qcd_status qcd_gauge_upload(qcd_gauge** g, const int dims[4], const void* U_dev, int prec_mask, void* stream);
 qcd_status qcd_gauge_free(qcd_gauge* g);
 
+/* Launch shape of the Wilson operator for precision prec (picked by a tuner):
+ * sched 0 orders thread blocks by half-lattice index; sched 1 gives each of
+ * the GPU's eight XCDs its own slab of z, swept in t order (applies when
+ * (Lx/2)*Ly is a multiple of 128 and Lz of 8, else falls back to 0);
+ * variant 0..5 selects how many hops' loads are prefetched while one hop is
+ * computed and the minimum waves per SIMD the kernel is compiled for:
+ * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4).
+ * Results do not depend on these choices. */
+qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant);
+qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant);
+
 /* Bytes of one native spinor field in precision prec. */
 size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 

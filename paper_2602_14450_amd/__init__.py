@@ -69,12 +69,14 @@ _lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(BicgstabPara
                               _vp, _sz, _vp]
 _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
                                     _sz, _vp]
-for _f in ("qcd_gauge_upload", "qcd_gauge_free", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual",
-           "qcd_bicgstab", "qcd_solve_mixed_ir"):
+_lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i]
+_lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
+for _f in ("qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
+           "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
 
-EXPORTED = ["qcd_last_error", "qcd_gauge_upload", "qcd_gauge_free", "qcd_spinor_bytes", "qcd_workspace_bytes",
-            "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"]
+EXPORTED = ["qcd_last_error", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
+            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"]
 
 
 class QcdError(RuntimeError):
@@ -129,6 +131,14 @@ class Gauge:
             self.close()
         except Exception:
             pass
+
+    def set_tuning(self, prec, sched: int, occupancy: int):
+        _check(_lib.qcd_set_dslash_tuning(self.handle, PREC[prec], int(sched), int(occupancy)))
+
+    def get_tuning(self, prec):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.qcd_get_dslash_tuning(self.handle, PREC[prec], ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def spinor_bytes(self, prec) -> int:
         return int(_lib.qcd_spinor_bytes(self.handle, PREC[prec]))

@@ -2,7 +2,9 @@
 // FP64 iterative refinement driver.  The host only sequences kernels and
 // polls a small status record; every vector operation runs in the kernels of
 // dslash.hip and blas.hip.
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -20,6 +22,7 @@ struct qcd_gauge {
   void* ws;          // cached workspace used when the caller passes none
   size_t ws_bytes;
   Scalars* host_sc;  // pinned mirror of the device scalars
+  DslashTune tune[3];
 };
 
 namespace {
@@ -53,7 +56,12 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t spinor_bytes(const Geom& g, int prec) { return spinor_elems(g) * prec_complex_bytes(prec); }
-size_t partial_bytes(const Geom& g) { return (size_t)site_grid(g) * 8 * sizeof(double); }
+size_t partial_bytes(const Geom& g) {
+  int rows = site_grid(g);
+  for (int p = 0; p < 3; p++) rows = std::max(rows, flat_rows(g, p));
+  rows = std::max(rows, dslash_partial_rows(g));
+  return (size_t)rows * 8 * sizeof(double);
+}
 
 // Workspace carve-up.
 struct Carve {
@@ -175,16 +183,23 @@ qcd_status check_bicg_params(const qcd_bicgstab_params* p) {
 // One BiCGStab iteration of Alg. 4 / Alg. 5, entirely on the device.
 void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, int ftz, hipStream_t st) {
   const Geom& G = g->g;
-  const int rows = site_grid(G);
+  const int drows = dslash_partial_rows(G), frows = flat_rows(G, prec);
   const void* U = g->U[prec];
+  const DslashTune& tu = g->tune[prec];
   launch_p_update(G, prec, w.sc, w.p, w.v, w.r, ftz, st);
-  launch_dslash(prec, G, kOpD, kEpiDotAux, w.v, w.p, U, kappa, w.rstar, w.partials, 0, 2, &w.sc->active, ftz, st);
-  launch_alpha(w.sc, w.partials, rows, st);
+  launch_dslash(prec, G, tu, kOpD, kEpiDotAux, w.v, w.p, U, kappa, w.rstar, w.partials, &w.sc->active, ftz, st);
+  launch_alpha(w.sc, w.partials, drows, st);
   launch_s_update(G, prec, w.sc, w.r, w.v, ftz, st);
-  launch_dslash(prec, G, kOpD, kEpiTS, w.t, w.r, U, kappa, nullptr, w.partials, 0, 2, &w.sc->active, ftz, st);
-  launch_omega(w.sc, w.partials, rows, st);
+  launch_dslash(prec, G, tu, kOpD, kEpiTS, w.t, w.r, U, kappa, nullptr, w.partials, &w.sc->active, ftz, st);
+  launch_omega(w.sc, w.partials, drows, st);
   launch_xr_update(G, prec, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
-  launch_iter_end(w.sc, w.partials, rows, w.history, st);
+  launch_iter_end(w.sc, w.partials, frows, w.history, st);
+}
+
+// FP64 residual r = b - D x with |r|^2 partials (one row per Wilson-operator block).
+void residual64(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
+  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.r64, w.x64, g->U[kFP64], kappa, w.b64, w.partials,
+                nullptr, 0, st);
 }
 
 // Run the inner loop from initialised scalars until the device reports a
@@ -238,6 +253,10 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   qcd_gauge* g = new qcd_gauge();
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
+  // defaults measured on MI355X at 32^3 x 64 (the tuner may override them)
+  g->tune[kFP64] = DslashTune{1, 0};
+  g->tune[kFP32] = DslashTune{1, 1};
+  g->tune[kFP16] = DslashTune{1, 1};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
@@ -272,6 +291,21 @@ qcd_status qcd_gauge_free(qcd_gauge* g) {
   if (g->ws) (void)hipFree(g->ws);
   if (g->host_sc) (void)hipHostFree(g->host_sc);
   delete g;
+  return QCD_OK;
+}
+
+qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant) {
+  if (!g || !valid_prec(prec)) return fail(QCD_ERR_ARG, "invalid handle or precision");
+  if (sched < 0 || sched > 1 || variant < 0 || variant >= kDslashVariants)
+    return fail(QCD_ERR_ARG, "sched must be 0 or 1 and variant 0..%d", kDslashVariants - 1);
+  g->tune[prec] = DslashTune{sched, variant};
+  return QCD_OK;
+}
+
+qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant) {
+  if (!g || !valid_prec(prec) || !sched || !variant) return fail(QCD_ERR_ARG, "invalid argument");
+  *sched = g->tune[prec].sched;
+  *variant = g->tune[prec].variant;
   return QCD_OK;
 }
 
@@ -322,7 +356,8 @@ qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   hipStream_t st = S(stream);
   if (layout == QCD_LAYOUT_NATIVE) {
-    launch_dslash(prec, g->g, op, kEpiNone, out_dev, in_dev, g->U[prec], kappa, nullptr, nullptr, 0, 2, nullptr, 0, st);
+    launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, out_dev, in_dev, g->U[prec], kappa, nullptr, nullptr,
+                  nullptr, 0, st);
     HIP_LAUNCHED();
     return QCD_OK;
   }
@@ -331,7 +366,8 @@ qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec
   rc = get_work(g, 2, prec, 0, nullptr, 0, &w);
   if (rc) return rc;
   launch_pack_spinor(g->g, prec, w.x, (const double*)in_dev, 1.0, 0, nullptr, st);
-  launch_dslash(prec, g->g, op, kEpiNone, w.r, w.x, g->U[prec], kappa, nullptr, nullptr, 0, 2, nullptr, 0, st);
+  launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, w.r, w.x, g->U[prec], kappa, nullptr, nullptr, nullptr, 0,
+                st);
   launch_unpack_spinor(g->g, prec, (double*)out_dev, w.r, 1.0, st);
   HIP_LAUNCHED();
   return QCD_OK;
@@ -348,10 +384,10 @@ qcd_status qcd_residual(const qcd_gauge* g, double kappa, void* r_dev, const voi
   if (rc) return rc;
   launch_pack_spinor(g->g, kFP64, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
   launch_pack_spinor(g->g, kFP64, w.b64, (const double*)b_dev, 1.0, 0, nullptr, st);
-  launch_dslash(kFP64, g->g, kOpD, kEpiResid, w.r64, w.x64, g->U[kFP64], kappa, w.b64, w.partials, 0, 2, nullptr, 0, st);
+  residual64(g, kappa, w, st);
   launch_unpack_spinor(g->g, kFP64, (double*)r_dev, w.r64, 1.0, st);
   HIP_LAUNCHED();
-  if (norm2) return read_sum(w, site_grid(g->g), 1, norm2, st);
+  if (norm2) return read_sum(w, dslash_partial_rows(g->g), 1, norm2, st);
   return QCD_OK;
 }
 
@@ -390,8 +426,8 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, void* x
   launch_pack_spinor(G, kFP64, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
   if ((rc = read_sum(w, rows, 1, &b2, st))) return rc;
   launch_pack_spinor(G, kFP64, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
-  launch_dslash(kFP64, G, kOpD, kEpiResid, w.r64, w.x64, g->U[kFP64], kappa, w.b64, w.partials, 0, 2, nullptr, 0, st);
-  if ((rc = read_sum(w, rows, 1, &r2, st))) return rc;
+  residual64(g, kappa, w, st);
+  if ((rc = read_sum(w, dslash_partial_rows(G), 1, &r2, st))) return rc;
   if (info) {
     info->outer_iters = 0;
     info->inner_iters = iters;
@@ -475,9 +511,8 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, void* x_dev, con
       }
       // x += (|r| / s^) double(t~); r = b - D x in FP64
       launch_correct(G, prec, w.sc, (double*)w.x64, w.x, st);
-      launch_dslash(kFP64, G, kOpD, kEpiResid, w.r64, w.x64, g->U[kFP64], kappa, w.b64, w.partials, 0, 2, nullptr, 0,
-                    st);
-      launch_outer_residual_norm(w.sc, w.partials, rows, p->s, st);
+      residual64(g, kappa, w, st);
+      launch_outer_residual_norm(w.sc, w.partials, dslash_partial_rows(G), p->s, st);
       HIP_LAUNCHED();
       mv64++;
       outer++;

@@ -10,16 +10,28 @@
 
 namespace qcd {
 
-static inline int nbp_of(const Geom& g) { return (g.Vh + 255) / 256; }
-int site_grid(const Geom& g) { return 2 * nbp_of(g); }
+// Site-ordered kernels (layout / precision conversions) use one thread per
+// site; the BLAS-1 kernels walk the native vectors as flat arrays of 16-byte
+// granules with a fixed grid, so their partial-sum rows number at most
+// kFlatBlocks.
+constexpr int kFlatBlocks = 2048;
+int site_grid(const Geom& g) { return (2 * g.Vh + 255) / 256; }
+template <typename S> static int flat_grid(const Geom& g) {
+  const size_t n = spinor_granules<S>(g);
+  const size_t b = (n + 255) / 256;
+  return (int)(b < (size_t)kFlatBlocks ? b : (size_t)kFlatBlocks);
+}
+int flat_rows(const Geom& g, int prec) {
+  return prec == kFP64 ? flat_grid<double2>(g) : (prec == kFP32 ? flat_grid<float2>(g) : flat_grid<__half2>(g));
+}
 
 struct SiteId { int par, h; bool valid; };
 __device__ __forceinline__ SiteId site_id(const Geom& g) {
-  const int nbp = (g.Vh + 255) / 256;
+  const int i = blockIdx.x * 256 + threadIdx.x;
   SiteId s;
-  s.par = blockIdx.x / nbp;
-  s.h = (blockIdx.x % nbp) * 256 + threadIdx.x;
-  s.valid = s.h < g.Vh;
+  s.par = i >= g.Vh;
+  s.h = i - s.par * g.Vh;
+  s.valid = i < 2 * g.Vh;
   return s;
 }
 __device__ __forceinline__ int64_t lex_site(const Geom& g, int par, int h) {
@@ -35,11 +47,14 @@ __global__ __launch_bounds__(256) void k_pack_links(Geom g, S* __restrict__ dst,
   SiteId id = site_id(g);
   if (!id.valid) return;
   const int64_t s = lex_site(g, id.par, id.h);
-  for (int mu = 0; mu < 4; mu++)
+  const int lane = id.h & 63;
+  for (int mu = 0; mu < 4; mu++) {
+    S* b = dst + lk_block(g, mu, id.par, id.h);
     for (int k = 0; k < 9; k++) {
       const double* src = Uc + ((s * 4 + mu) * 9 + k) * 2;
-      dst[lk_index(g, mu, id.par, id.h, k)] = pack_from_double<S>(src[0], src[1], 0);
+      b[lk_off<S>(k, lane)] = pack_from_double<S>(src[0], src[1], 0);
     }
+  }
 }
 
 // dst = round(scale * canon); partial |dst|^2 per block (from stored values).
@@ -51,10 +66,12 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst
   double red[1] = {0.0};
   if (id.valid) {
     const int64_t s = lex_site(g, id.par, id.h);
+    const int lane = id.h & 63;
+    S* b = dst + sp_block(g, id.par, id.h);
     T acc = 0;
     for (int k = 0; k < 12; k++) {
       const S v = pack_from_double<S>(scale * src[(s * 12 + k) * 2], scale * src[(s * 12 + k) * 2 + 1], ftz);
-      dst[sp_index(g, id.par, id.h, k)] = v;
+      b[sp_off<S>(k, lane)] = v;
       acc += norm2(Traits<S>::load(&v));
     }
     red[0] = acc;
@@ -68,24 +85,33 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(Geom g, double* __restric
   SiteId id = site_id(g);
   if (!id.valid) return;
   const int64_t s = lex_site(g, id.par, id.h);
+  cx<typename Traits<S>::T> f[12];
+  load_site(src, g, id.par, id.h, f);
   for (int k = 0; k < 12; k++) {
-    const auto v = Traits<S>::load(src + sp_index(g, id.par, id.h, k));
-    dst[(s * 12 + k) * 2] = scale * (double)v.re;
-    dst[(s * 12 + k) * 2 + 1] = scale * (double)v.im;
+    dst[(s * 12 + k) * 2] = scale * (double)f[k].re;
+    dst[(s * 12 + k) * 2 + 1] = scale * (double)f[k].im;
   }
 }
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_zero(Geom g, S* __restrict__ dst) {
-  SiteId id = site_id(g);
-  if (!id.valid) return;
-  using T = typename Traits<S>::T;
-  for (int k = 0; k < 12; k++) dst[sp_index(g, id.par, id.h, k)] = Traits<S>::pack(cx<T>(0, 0), 0);
+  using Gr = typename Lay<S>::Gran;
+  const size_t n = spinor_granules<S>(g);
+  Gr z;
+  for (int c = 0; c < Lay<S>::C; c++) z.s[c] = Traits<S>::pack(cx<typename Traits<S>::T>(0, 0), 0);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+    reinterpret_cast<Gr*>(dst)[e] = z;
 }
 
 // ---------------------------------------------------------------------------
 // BiCGStab body (Alg. 4 / Alg. 5).  Vectors: x, r (holds s between the two
-// matrix applications), r*, p, v, t.
+// matrix applications), r*, p, v, t.  All are walked granule by granule.
+
+#define QCD_FLAT_LOOP(S) \
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x, n_ = spinor_granules<S>(g); e < n_; \
+       e += (size_t)gridDim.x * 256)
+
+template <typename S> using GrOf = typename Lay<S>::Gran;
 
 // p := beta (p - omega' v) + r, with the previous iteration's rescaling of
 // p and v by gamma folded into the coefficient (pcoef = beta * gamma).  In
@@ -94,18 +120,27 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_p_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ p,
                                                   const S* __restrict__ v, const S* __restrict__ r, int ftz) {
   using T = typename Traits<S>::T;
+  using Gr = GrOf<S>;
   if (!sc->active) return;
-  SiteId id = site_id(g);
-  if (!id.valid) return;
   const int first = sc->first;
   const cx<T> c((T)sc->pcoef[0], (T)sc->pcoef[1]);
   const cx<T> w((T)sc->omega_prev[0], (T)sc->omega_prev[1]);
-  for (int k = 0; k < 12; k++) {
-    const size_t i = sp_index(g, id.par, id.h, k);
-    cx<T> rv = Traits<S>::load(r + i);
-    cx<T> o = rv;
-    if (!first) o = c * (Traits<S>::load(p + i) - w * Traits<S>::load(v + i)) + rv;
-    p[i] = Traits<S>::pack(o, ftz);
+  QCD_FLAT_LOOP(S) {
+    if (!gran_valid<S>(g, e)) continue;
+    const Gr rg = reinterpret_cast<const Gr*>(r)[e];
+    Gr out;
+    if (first) {
+      out = rg;
+    } else {
+      const Gr pg = reinterpret_cast<const Gr*>(p)[e];
+      const Gr vg = reinterpret_cast<const Gr*>(v)[e];
+#pragma unroll
+      for (int i = 0; i < Lay<S>::C; i++) {
+        const cx<T> o = c * (Traits<S>::load(&pg.s[i]) - w * Traits<S>::load(&vg.s[i])) + Traits<S>::load(&rg.s[i]);
+        out.s[i] = Traits<S>::pack(o, ftz);
+      }
+    }
+    reinterpret_cast<Gr*>(p)[e] = out;
   }
 }
 
@@ -114,56 +149,67 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_s_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ r,
                                                   const S* __restrict__ v, int ftz) {
   using T = typename Traits<S>::T;
+  using Gr = GrOf<S>;
   if (!sc->active) return;
-  SiteId id = site_id(g);
-  if (!id.valid) return;
   const cx<T> a((T)sc->alpha[0], (T)sc->alpha[1]);
-  for (int k = 0; k < 12; k++) {
-    const size_t i = sp_index(g, id.par, id.h, k);
-    r[i] = Traits<S>::pack(Traits<S>::load(r + i) - a * Traits<S>::load(v + i), ftz);
+  QCD_FLAT_LOOP(S) {
+    if (!gran_valid<S>(g, e)) continue;
+    Gr rg = reinterpret_cast<const Gr*>(r)[e];
+    const Gr vg = reinterpret_cast<const Gr*>(v)[e];
+#pragma unroll
+    for (int i = 0; i < Lay<S>::C; i++)
+      rg.s[i] = Traits<S>::pack(Traits<S>::load(&rg.s[i]) - a * Traits<S>::load(&vg.s[i]), ftz);
+    reinterpret_cast<Gr*>(r)[e] = rg;
   }
 }
 
 // x := xscale x + (lambda'/gamma') (omega s + alpha p);
 // r := gamma_pred (s - omega t), stored in the buffer that held s.
-// Partials (from the values as stored): |s - omega t|^2 before the rescaling
-// (FP32/FP64 arithmetic, unrounded), |r|^2, (r*, r) and |x|^2.
+// Partials: |s - omega t|^2 before the rescaling (unrounded), and from the
+// stored values |r|^2, (r*, r) and |x|^2.  Each thread accumulates in the
+// arithmetic precision, the block and the finish kernel in FP64.
 template <typename S>
 __global__ __launch_bounds__(256) void k_xr_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ x,
                                                    S* __restrict__ r, const S* __restrict__ t,
                                                    const S* __restrict__ p, const S* __restrict__ rstar,
                                                    double* __restrict__ partials, int ftz) {
   using T = typename Traits<S>::T;
+  using Gr = GrOf<S>;
   if (!sc->active) return;
-  SiteId id = site_id(g);
-  double red[5] = {0, 0, 0, 0, 0};
-  if (id.valid) {
-    const int first = sc->first;
-    const T xs = (T)sc->xscale, xc = (T)sc->xcoef, gp = (T)sc->gamma_pred;
-    const cx<T> om((T)sc->omega[0], (T)sc->omega[1]);
-    const cx<T> al((T)sc->alpha[0], (T)sc->alpha[1]);
-    T ww = 0, rr = 0, rsr_re = 0, rsr_im = 0, xx = 0;
-    for (int k = 0; k < 12; k++) {
-      const size_t i = sp_index(g, id.par, id.h, k);
-      const cx<T> s = Traits<S>::load(r + i);
-      const cx<T> pk = Traits<S>::load(p + i);
-      cx<T> xn = xc * (om * s + al * pk);
-      if (!first) xn = xs * Traits<S>::load(x + i) + xn;
-      const S xst = Traits<S>::pack(xn, ftz);
-      x[i] = xst;
-      const cx<T> w = s - om * Traits<S>::load(t + i);
-      const S rst = Traits<S>::pack(gp * w, ftz);
-      r[i] = rst;
-      const cx<T> rs = Traits<S>::load(&rst), xsv = Traits<S>::load(&xst);
-      const cx<T> q = Traits<S>::load(rstar + i);
+  const int first = sc->first;
+  const T xs = (T)sc->xscale, xc = (T)sc->xcoef, gp = (T)sc->gamma_pred;
+  const cx<T> om((T)sc->omega[0], (T)sc->omega[1]);
+  const cx<T> al((T)sc->alpha[0], (T)sc->alpha[1]);
+  T ww = 0, rr = 0, rsr_re = 0, rsr_im = 0, xx = 0;
+  QCD_FLAT_LOOP(S) {
+    if (!gran_valid<S>(g, e)) continue;
+    const Gr sg = reinterpret_cast<const Gr*>(r)[e];
+    const Gr pg = reinterpret_cast<const Gr*>(p)[e];
+    const Gr tg = reinterpret_cast<const Gr*>(t)[e];
+    const Gr qg = reinterpret_cast<const Gr*>(rstar)[e];
+    Gr xg;
+    if (!first) xg = reinterpret_cast<const Gr*>(x)[e];
+    Gr xo, ro;
+#pragma unroll
+    for (int i = 0; i < Lay<S>::C; i++) {
+      const cx<T> s = Traits<S>::load(&sg.s[i]);
+      cx<T> xn = xc * (om * s + al * Traits<S>::load(&pg.s[i]));
+      if (!first) xn = xs * Traits<S>::load(&xg.s[i]) + xn;
+      xo.s[i] = Traits<S>::pack(xn, ftz);
+      const cx<T> w = s - om * Traits<S>::load(&tg.s[i]);
+      ro.s[i] = Traits<S>::pack(gp * w, ftz);
+      const cx<T> rs = Traits<S>::load(&ro.s[i]), xsv = Traits<S>::load(&xo.s[i]);
+      const cx<T> q = Traits<S>::load(&qg.s[i]);
       ww += norm2(w);
       rr += norm2(rs);
       rsr_re += q.re * rs.re + q.im * rs.im;
       rsr_im += q.re * rs.im - q.im * rs.re;
       xx += norm2(xsv);
     }
-    red[0] = ww; red[1] = rr; red[2] = rsr_re; red[3] = rsr_im; red[4] = xx;
+    reinterpret_cast<Gr*>(x)[e] = xo;
+    reinterpret_cast<Gr*>(r)[e] = ro;
   }
+  double red[5] = {(double)ww, (double)rr, (double)rsr_re, (double)rsr_im, (double)xx};
   block_reduce_store<5>(red, partials, blockIdx.x);
 }
 
@@ -177,21 +223,31 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const Scalars* __restri
                                                  S* __restrict__ y, S* __restrict__ rstar,
                                                  double* __restrict__ partials, int ftz) {
   using T = typename Traits<S>::T;
+  using Gr = GrOf<S>;
+  constexpr int C = Lay<S>::C;
   SiteId id = site_id(g);
   double red[2] = {0, 0};
   if (id.valid) {
     const double sc_ = sc->out_scale;
+    cx<double> f[12];
+    load_site(r64, g, id.par, id.h, f);
+    S* yb = y + sp_block(g, id.par, id.h) + (id.h & 63) * C;
+    S* qb = rstar + sp_block(g, id.par, id.h) + (id.h & 63) * C;
     T acc = 0;
     int zeros = 0;
-    for (int k = 0; k < 12; k++) {
-      const size_t i = sp_index(g, id.par, id.h, k);
-      const double2 v = r64[i];
-      const S st = pack_from_double<S>(sc_ * v.x, sc_ * v.y, ftz);
-      y[i] = st;
-      rstar[i] = st;
-      const cx<T> f = Traits<S>::load(&st);
-      acc += norm2(f);
-      zeros += (f.re == (T)0) + (f.im == (T)0);
+#pragma unroll
+    for (int j = 0; j < Lay<S>::G; j++) {
+      Gr v;
+#pragma unroll
+      for (int c = 0; c < C; c++) {
+        const int k = j * C + c;
+        v.s[c] = pack_from_double<S>(sc_ * f[k].re, sc_ * f[k].im, ftz);
+        const cx<T> q = Traits<S>::load(&v.s[c]);
+        acc += norm2(q);
+        zeros += (q.re == (T)0) + (q.im == (T)0);
+      }
+      *reinterpret_cast<Gr*>(yb + j * 64 * C) = v;
+      *reinterpret_cast<Gr*>(qb + j * 64 * C) = v;
     }
     red[0] = acc;
     red[1] = zeros;
@@ -206,14 +262,15 @@ __global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restri
   SiteId id = site_id(g);
   if (!id.valid) return;
   const double c = sc->out_rnorm / sc->shat * sc->xscale / sc->lambda_cum;
+  cx<typename Traits<S>::T> f[12];
+  cx<double> xo[12];
+  load_site(xlo, g, id.par, id.h, f);
+  load_site(x64, g, id.par, id.h, xo);
   for (int k = 0; k < 12; k++) {
-    const size_t i = sp_index(g, id.par, id.h, k);
-    const auto v = Traits<S>::load(xlo + i);
-    double2 o = x64[i];
-    o.x += c * (double)v.re;
-    o.y += c * (double)v.im;
-    x64[i] = o;
+    xo[k].re += c * (double)f[k].re;
+    xo[k].im += c * (double)f[k].im;
   }
+  store_site(x64, g, id.par, id.h, xo, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +494,7 @@ void launch_unpack_spinor(const Geom& g, int prec, double* canon, const void* sr
 }
 
 template <typename S> static void zero_t(const Geom& g, void* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero<S>, dim3(site_grid(g)), dim3(256), 0, st, g, (S*)dst);
+  hipLaunchKernelGGL(k_zero<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, (S*)dst);
 }
 void launch_zero(const Geom& g, int prec, void* dst, hipStream_t st) { QCD_DISPATCH(prec, zero_t, g, dst, st); }
 
@@ -447,8 +504,8 @@ void launch_bicg_init(Scalars* sc, const double* partials, int nrows, hipStream_
 
 template <typename S>
 static void p_update_t(const Geom& g, Scalars* sc, void* p, const void* v, const void* r, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_p_update<S>, dim3(site_grid(g)), dim3(256), 0, st, g, sc, (S*)p, (const S*)v, (const S*)r,
-                     ftz);
+  hipLaunchKernelGGL(k_p_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)p, (const S*)v,
+                     (const S*)r, ftz);
 }
 void launch_p_update(const Geom& g, int prec, Scalars* sc, void* p, const void* v, const void* r, int ftz,
                      hipStream_t st) {
@@ -461,7 +518,7 @@ void launch_alpha(Scalars* sc, const double* partials, int nrows, hipStream_t st
 
 template <typename S>
 static void s_update_t(const Geom& g, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_s_update<S>, dim3(site_grid(g)), dim3(256), 0, st, g, sc, (S*)r, (const S*)v, ftz);
+  hipLaunchKernelGGL(k_s_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)r, (const S*)v, ftz);
 }
 void launch_s_update(const Geom& g, int prec, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
   QCD_DISPATCH(prec, s_update_t, g, sc, r, v, ftz, st);
@@ -474,7 +531,7 @@ void launch_omega(Scalars* sc, const double* partials, int nrows, hipStream_t st
 template <typename S>
 static void xr_update_t(const Geom& g, Scalars* sc, void* x, void* r, const void* t, const void* p, const void* rs,
                         double* partials, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_xr_update<S>, dim3(site_grid(g)), dim3(256), 0, st, g, sc, (S*)x, (S*)r, (const S*)t,
+  hipLaunchKernelGGL(k_xr_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)x, (S*)r, (const S*)t,
                      (const S*)p, (const S*)rs, partials, ftz);
 }
 void launch_xr_update(const Geom& g, int prec, Scalars* sc, void* x, void* r, const void* t, const void* p,

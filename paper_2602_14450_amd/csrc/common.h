@@ -106,19 +106,23 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return (__umul
 //
 // Sites are split by parity p = (x+y+z+t) & 1.  Within a parity, site
 // (x,y,z,t) has half index h = (x>>1) + Lx/2*(y + Ly*(z + Lz*t)).  Half
-// indices are grouped in blocks of 64 (one wavefront).  A spinor stores, for
-// each block, its 12 complex components (spin-major, colour fastest) as 12
-// runs of 64 consecutive elements, so that lane i of a wave reading
-// component k of block b touches element ((p*nb + b)*12 + k)*64 + i:
-// every wave-wide access is one contiguous segment.  Links are stored the
-// same way per direction: element (((mu*2 + p)*nb + b)*9 + 3a + c)*64 + i.
+// indices are grouped in blocks of 64 (one wavefront).  Each block stores its
+// complex components in 16-byte granules: with C = 16 / sizeof(stored
+// complex) components per granule (4 for FP16, 2 for FP32, 1 for FP64),
+// granule row j holds components [jC, jC+C) of the 64 sites, lane-major, so
+// that lane i of a wave reading row j issues one 16-byte load at
+// (block*12*64 + j*64*C + i*C) and the wave reads one contiguous 1 KB
+// segment.  A spinor block holds 12 components (spin-major, colour fastest);
+// a link block (per direction and parity) holds the 9 entries U[a][b]
+// (row-major), the first F = (9/C)*C in full granule rows and the rest in
+// rows of one component per lane.
 struct Geom {
   int L[4];
   int Lxh;         // Lx / 2
   int Vh;          // sites per parity
   int nb;          // 64-site blocks per parity
   int sy, sz, st;  // half-index strides of y, z, t
-  FastDiv dx, dy, dz;
+  FastDiv dx, dy, dz, dnb;
 };
 
 inline Geom make_geom(const int dims[4]) {
@@ -133,18 +137,35 @@ inline Geom make_geom(const int dims[4]) {
   g.dx = make_fastdiv(g.Lxh);
   g.dy = make_fastdiv(dims[1]);
   g.dz = make_fastdiv(dims[2]);
+  g.dnb = make_fastdiv(g.nb);
   return g;
 }
 
-// Elements of one full native spinor (both parities, padding included).
-inline size_t spinor_elems(const Geom& g) { return (size_t)2 * g.nb * 12 * 64; }
-inline size_t link_elems(const Geom& g) { return (size_t)4 * 2 * g.nb * 9 * 64; }
+// Elements (stored complex numbers) of one full native spinor / link field.
+__host__ __device__ inline size_t spinor_elems(const Geom& g) { return (size_t)2 * g.nb * 12 * 64; }
+__host__ __device__ inline size_t link_elems(const Geom& g) { return (size_t)4 * 2 * g.nb * 9 * 64; }
 
-__device__ __forceinline__ size_t sp_index(const Geom& g, int par, int h, int k) {
-  return ((size_t)(par * g.nb + (h >> 6)) * 12 + k) * 64 + (h & 63);
+template <typename S> struct Lay {
+  static constexpr int C = 16 / (int)sizeof(S);  // components per granule
+  static constexpr int G = 12 / C;               // granule rows of a spinor block
+  static constexpr int F = (9 / C) * C;          // link entries in full granule rows
+  struct alignas(16) Gran { S s[C]; };
+};
+
+__device__ __forceinline__ size_t sp_block(const Geom& g, int par, int h) {
+  return (size_t)(par * g.nb + (h >> 6)) * (12 * 64);
 }
-__device__ __forceinline__ size_t lk_index(const Geom& g, int mu, int par, int h, int k) {
-  return ((size_t)((mu * 2 + par) * g.nb + (h >> 6)) * 9 + k) * 64 + (h & 63);
+__device__ __forceinline__ size_t lk_block(const Geom& g, int mu, int par, int h) {
+  return (size_t)((mu * 2 + par) * g.nb + (h >> 6)) * (9 * 64);
+}
+// element offset of spinor component k of lane `lane` within its block
+template <typename S> __device__ __forceinline__ int sp_off(int k, int lane) {
+  constexpr int C = Lay<S>::C;
+  return (k / C) * 64 * C + lane * C + (k % C);
+}
+template <typename S> __device__ __forceinline__ int lk_off(int k, int lane) {
+  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  return k < F ? (k / C) * 64 * C + lane * C + (k % C) : F * 64 + (k - F) * 64 + lane;
 }
 
 struct Coord { int x, y, z, t; };
@@ -159,6 +180,49 @@ __device__ __forceinline__ Coord decode(const Geom& g, int par, int h) {
   int x = 2 * xh + ((par + y + z + t) & 1);
   return {x, y, z, t};
 }
+
+// Site-level access to a native spinor (used by the site-ordered kernels).
+template <typename S>
+__device__ __forceinline__ void load_site(const S* __restrict__ base, const Geom& g, int par, int h,
+                                          cx<typename Traits<S>::T> (&f)[12]) {
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C;
+  const S* b = base + sp_block(g, par, h);
+  const int lane = h & 63;
+#pragma unroll
+  for (int j = 0; j < Lay<S>::G; j++) {
+    const Gr v = *reinterpret_cast<const Gr*>(b + j * 64 * C + lane * C);
+#pragma unroll
+    for (int c = 0; c < C; c++) f[j * C + c] = Traits<S>::load(&v.s[c]);
+  }
+}
+template <typename S>
+__device__ __forceinline__ void store_site(S* __restrict__ base, const Geom& g, int par, int h,
+                                           const cx<typename Traits<S>::T> (&f)[12], int ftz) {
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C;
+  S* b = base + sp_block(g, par, h);
+  const int lane = h & 63;
+#pragma unroll
+  for (int j = 0; j < Lay<S>::G; j++) {
+    Gr v;
+#pragma unroll
+    for (int c = 0; c < C; c++) v.s[c] = Traits<S>::pack(f[j * C + c], ftz);
+    *reinterpret_cast<Gr*>(b + j * 64 * C + lane * C) = v;
+  }
+}
+
+// Flat granule view of a native spinor: granule e lies in 64-site block
+// e / (768/C), lane (e % (768/C)) % 64.  Padding sites of the last block of
+// each parity are skipped.
+template <typename S> __device__ __forceinline__ bool gran_valid(const Geom& g, size_t e) {
+  constexpr int PER = 768 / Lay<S>::C;
+  const uint32_t blk = (uint32_t)(e / PER);
+  const int lane = (int)(e % PER) & 63;
+  const uint32_t b = blk - fdiv(blk, g.dnb) * (uint32_t)g.nb;
+  return b != (uint32_t)(g.nb - 1) || lane < g.Vh - (g.nb - 1) * 64;
+}
+template <typename S> __host__ __device__ inline size_t spinor_granules(const Geom& g) { return spinor_elems(g) / Lay<S>::C; }
 
 // ---------------------------------------------------------------------------
 // Deterministic reductions.  Each thread holds NV FP64 values; the block

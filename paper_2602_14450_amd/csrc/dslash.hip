@@ -73,17 +73,26 @@ __device__ __forceinline__ void accumulate(cx<T> (&a)[4][3], const cx<T> (&u1)[3
   }
 }
 
-// Load the spin components a hop in direction MU needs (all four, or two
-// for the t direction where the projector keeps only one spin pair).
+// Load the spinor granules a hop in direction MU needs: all of them, or for
+// the t direction only those holding the spin pair its projector keeps.
 template <int MU, bool MINUS, typename S, typename T>
 __device__ __forceinline__ void load_spinor(const Geom& g, const S* __restrict__ in, int par, int h,
                                             cx<T> (&f)[4][3]) {
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C;
+  const S* b = in + sp_block(g, par, h) + (h & 63) * C;
 #pragma unroll
-  for (int s = 0; s < 4; s++) {
-    const bool need = (MU != 3) || (MINUS ? s >= 2 : s < 2);
+  for (int j = 0; j < Lay<S>::G; j++) {
+    // components [jC, jC + C) hold spins (jC)/3 .. (jC + C - 1)/3
+    const int s_lo = (j * C) / 3, s_hi = (j * C + C - 1) / 3;
+    const bool need = (MU != 3) || (MINUS ? s_hi >= 2 : s_lo < 2);
     if (need) {
+      const Gr v = *reinterpret_cast<const Gr*>(b + j * 64 * C);
 #pragma unroll
-      for (int c = 0; c < 3; c++) f[s][c] = Traits<S>::load(in + sp_index(g, par, h, 3 * s + c));
+      for (int c = 0; c < C; c++) {
+        const int k = j * C + c;
+        f[k / 3][k % 3] = Traits<S>::load(&v.s[c]);
+      }
     }
   }
 }
@@ -91,70 +100,198 @@ __device__ __forceinline__ void load_spinor(const Geom& g, const S* __restrict__
 template <typename S, typename T>
 __device__ __forceinline__ void load_link(const Geom& g, const S* __restrict__ U, int mu, int par, int h,
                                           cx<T> (&u)[9]) {
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  const int lane = h & 63;
+  const S* b = U + lk_block(g, mu, par, h);
 #pragma unroll
-  for (int k = 0; k < 9; k++) u[k] = Traits<S>::load(U + lk_index(g, mu, par, h, k));
+  for (int j = 0; j < F / C; j++) {
+    const Gr v = *reinterpret_cast<const Gr*>(b + j * 64 * C + lane * C);
+#pragma unroll
+    for (int c = 0; c < C; c++) u[j * C + c] = Traits<S>::load(&v.s[c]);
+  }
+#pragma unroll
+  for (int k = F; k < 9; k++) u[k] = Traits<S>::load(b + F * 64 + (k - F) * 64 + lane);
 }
 
-// One forward and one backward hop in direction MU.
-template <int MU, bool DAG, typename S, typename T>
-__device__ __forceinline__ void hop_dir(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
-                                        int h, const Coord& c, cx<T> (&a)[4][3]) {
-  constexpr bool FWD_MINUS = !DAG;  // forward hop uses (1 - gamma) for D
-  const int npar = par ^ 1;
-  int hf, hb;
+// Raw (still packed) data of one hop: the neighbour's spinor granules and
+// the link granules.  Hops are numbered HOP = 2*mu + (0 forward, 1 backward).
+template <typename S> struct HopRaw {
+  typename Lay<S>::Gran sp[Lay<S>::G];
+  typename Lay<S>::Gran lk[Lay<S>::F / Lay<S>::C];
+  S tail[9 - Lay<S>::F > 0 ? 9 - Lay<S>::F : 1];
+};
+
+// Spin pair a hop needs: the t-direction projectors keep spins (2,3) for
+// (1 - g4) and (0,1) for (1 + g4); the others need all four.
+template <int MU, bool MINUS, typename S> __device__ __forceinline__ constexpr bool gran_needed(int j) {
+  constexpr int C = Lay<S>::C;
+  return (MU != 3) || (MINUS ? (j * C + C - 1) / 3 >= 2 : (j * C) / 3 < 2);
+}
+
+template <int HOP, bool DAG, typename S>
+__device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
+                                         int h, const Coord& c, HopRaw<S>& d, int dep = 0) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr bool MINUS = BWD ? DAG : !DAG;  // forward hop of D uses (1 - gamma)
+  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  using Gr = typename Lay<S>::Gran;
+  int hn;
   if constexpr (MU == 0) {
     const int base = h - (c.x >> 1);
-    const int xf = (c.x + 1 == g.L[0]) ? 0 : c.x + 1;
-    const int xb = (c.x == 0) ? g.L[0] - 1 : c.x - 1;
-    hf = base + (xf >> 1);
-    hb = base + (xb >> 1);
+    const int xn = BWD ? ((c.x == 0) ? g.L[0] - 1 : c.x - 1) : ((c.x + 1 == g.L[0]) ? 0 : c.x + 1);
+    hn = base + (xn >> 1);
   } else if constexpr (MU == 1) {
-    hf = (c.y + 1 == g.L[1]) ? h - (g.L[1] - 1) * g.sy : h + g.sy;
-    hb = (c.y == 0) ? h + (g.L[1] - 1) * g.sy : h - g.sy;
+    hn = BWD ? ((c.y == 0) ? h + (g.L[1] - 1) * g.sy : h - g.sy) : ((c.y + 1 == g.L[1]) ? h - (g.L[1] - 1) * g.sy : h + g.sy);
   } else if constexpr (MU == 2) {
-    hf = (c.z + 1 == g.L[2]) ? h - (g.L[2] - 1) * g.sz : h + g.sz;
-    hb = (c.z == 0) ? h + (g.L[2] - 1) * g.sz : h - g.sz;
+    hn = BWD ? ((c.z == 0) ? h + (g.L[2] - 1) * g.sz : h - g.sz) : ((c.z + 1 == g.L[2]) ? h - (g.L[2] - 1) * g.sz : h + g.sz);
   } else {
-    hf = (c.t + 1 == g.L[3]) ? h - (g.L[3] - 1) * g.st : h + g.st;
-    hb = (c.t == 0) ? h + (g.L[3] - 1) * g.st : h - g.st;
+    hn = BWD ? ((c.t == 0) ? h + (g.L[3] - 1) * g.st : h - g.st) : ((c.t + 1 == g.L[3]) ? h - (g.L[3] - 1) * g.st : h + g.st);
   }
-  {  // forward: (1 -/+ gamma) U_mu(x) phi(x + mu)
-    cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
-    load_spinor<MU, FWD_MINUS>(g, in, npar, hf, f);
-    project<MU, FWD_MINUS>(f, h1, h2);
-    load_link(g, U, MU, par, h, u);
+  hn += dep;  // dep is an opaque zero that orders these loads after an earlier hop
+  const int npar = par ^ 1;
+  const S* sb = in + sp_block(g, npar, hn) + (hn & 63) * C;
+#pragma unroll
+  for (int j = 0; j < Lay<S>::G; j++)
+    if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = *reinterpret_cast<const Gr*>(sb + j * 64 * C);
+  // forward: U_mu(x) stored at x; backward: U_mu(x - mu) stored at the neighbour
+  const int lp = BWD ? npar : par, lh = BWD ? hn : h + dep;
+  const S* lb = U + lk_block(g, MU, lp, lh);
+  const int lane = lh & 63;
+#pragma unroll
+  for (int j = 0; j < F / C; j++) d.lk[j] = *reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C);
+#pragma unroll
+  for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
+}
+
+template <int HOP, bool DAG, typename S, typename T>
+__device__ __forceinline__ T hop_compute(const HopRaw<S>& d, cx<T> (&a)[4][3]) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr bool MINUS = BWD ? DAG : !DAG;
+  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
+#pragma unroll
+  for (int j = 0; j < Lay<S>::G; j++)
+    if (gran_needed<MU, MINUS, S>(j)) {
+#pragma unroll
+      for (int cc = 0; cc < C; cc++) {
+        const int k = j * C + cc;
+        f[k / 3][k % 3] = Traits<S>::load(&d.sp[j].s[cc]);
+      }
+    }
+#pragma unroll
+  for (int j = 0; j < F / C; j++)
+#pragma unroll
+    for (int cc = 0; cc < C; cc++) u[j * C + cc] = Traits<S>::load(&d.lk[j].s[cc]);
+#pragma unroll
+  for (int k = F; k < 9; k++) u[k] = Traits<S>::load(&d.tail[k - F]);
+  project<MU, MINUS>(f, h1, h2);
+  if constexpr (!BWD) {  // U_mu(x) h
 #pragma unroll
     for (int r = 0; r < 3; r++) {
       w1[r] = u[3 * r] * h1[0] + u[3 * r + 1] * h1[1] + u[3 * r + 2] * h1[2];
       w2[r] = u[3 * r] * h2[0] + u[3 * r + 1] * h2[1] + u[3 * r + 2] * h2[2];
     }
-    accumulate<MU, FWD_MINUS>(a, w1, w2);
-  }
-  {  // backward: (1 +/- gamma) U_mu(x - mu)^dag phi(x - mu)
-    cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
-    load_spinor<MU, !FWD_MINUS>(g, in, npar, hb, f);
-    project<MU, !FWD_MINUS>(f, h1, h2);
-    load_link(g, U, MU, npar, hb, u);
+  } else {  // U_mu(x - mu)^dagger h
 #pragma unroll
     for (int r = 0; r < 3; r++) {
       w1[r] = cmulc(u[r], h1[0]) + cmulc(u[3 + r], h1[1]) + cmulc(u[6 + r], h1[2]);
       w2[r] = cmulc(u[r], h2[0]) + cmulc(u[3 + r], h2[1]) + cmulc(u[6 + r], h2[2]);
     }
-    accumulate<MU, !FWD_MINUS>(a, w1, w2);
+  }
+  accumulate<MU, MINUS>(a, w1, w2);
+  return w1[0].re + w2[2].im;  // a value that exists only once this hop is done
+}
+
+#define QCD_FENCE() __builtin_amdgcn_sched_barrier(0)
+
+// Register barrier: the accumulators pass through empty asm statements as
+// in/out operands, so every instruction producing them must be complete
+// here and none of the hop's arithmetic can be sunk to the epilogue.
+template <typename T> __device__ __forceinline__ void reg_barrier(cx<T> (&a)[4][3]) {
+#pragma unroll
+  for (int s = 0; s < 4; s++)
+    asm volatile("" : "+v"(a[s][0].re), "+v"(a[s][0].im), "+v"(a[s][1].re), "+v"(a[s][1].im), "+v"(a[s][2].re),
+                 "+v"(a[s][2].im));
+}
+
+// The eight hops as a software pipeline: before hop i is computed, the loads
+// of hops i .. i+DEPTH are in flight.  The loads of hop i+DEPTH+1 are issued
+// only after hop i is computed: their base pointers pass through an empty
+// asm statement that takes hop i's product as an input, which the compiler
+// must treat as a dependency.  This bounds the registers held by loaded data
+// (otherwise all eight hops' loads are hoisted to the top and spilled).
+struct PipeArgs {
+  int par, h;
+  Coord c;
+};
+
+template <int I, int DEPTH, bool DAG, typename S, typename T>
+__device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
+                                         const PipeArgs& pa, HopRaw<S> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
+  if constexpr (I < 8) {
+    hop_compute<I, DAG>(buf[I % (DEPTH + 1)], a);
+    reg_barrier(a);
+    if constexpr (I + DEPTH + 1 < 8) {
+      int dep = 0;
+      asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
+      hop_load<I + DEPTH + 1, DAG>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
+    }
+    QCD_FENCE();
+    hop_pipe<I + 1, DEPTH, DAG>(g, in, U, pa, buf, a);
   }
 }
 
-// out = D in, H in, D^dag in, or b - D in, over the sites of parities
-// [par0, par0 + npar), with optional reduction epilogues.
-template <typename S, int OP, int EPI>
-__global__ __launch_bounds__(256) void k_dslash(Geom g, S* __restrict__ out, const S* __restrict__ in,
-                                                const S* __restrict__ U, double kappa, const S* __restrict__ aux,
-                                                double* __restrict__ partials, int par0, int nbp,
-                                                const int* __restrict__ active, int ftz) {
+template <int I, int DEPTH, bool DAG, typename S>
+__device__ __forceinline__ void hop_prologue(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
+                                             const PipeArgs& pa, HopRaw<S> (&buf)[DEPTH + 1]) {
+  if constexpr (I <= DEPTH) {
+    hop_load<I, DAG>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
+    hop_prologue<I + 1, DEPTH, DAG>(g, in, U, pa, buf);
+  }
+}
+
+template <int DEPTH, bool DAG, typename S, typename T>
+__device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
+                                        int h, const Coord& c, cx<T> (&a)[4][3]) {
+  HopRaw<S> buf[DEPTH + 1];
+  const PipeArgs pa{par, h, c};
+  hop_prologue<0, DEPTH, DAG>(g, in, U, pa, buf);
+  hop_pipe<0, DEPTH, DAG>(g, in, U, pa, buf, a);
+}
+
+// Thread -> site.  A block of 256 threads covers 128 consecutive half
+// indices in both parities (waves 0,1: first 64 of parity 0,1; waves 2,3:
+// next 64), so a link read as the forward link of one site is read as the
+// backward link of its neighbour by the same block.  With sched.mode 1 the
+// blocks are ordered so that the eight XCDs (which receive consecutive
+// workgroups in turn) each sweep their own slab of z in t-major order, which
+// keeps the t-neighbours of a slab inside that XCD's L2.
+__device__ __forceinline__ int block_h0(const DslashSched& sc) {
+  const int b = blockIdx.x;
+  if (sc.mode == 1) {
+    const int xcd = b & 7, j = b >> 3;
+    const int per_t = sc.zc * sc.bp;
+    const int t = j / per_t, rem = j - t * per_t;
+    const int zl = rem / sc.bp, yb = rem - zl * sc.bp;
+    return ((t * sc.Lz + xcd * sc.zc + zl) * sc.bp + yb) * 128;
+  }
+  return b * 128;
+}
+
+// out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues.
+template <typename S, int OP, int EPI, int DEPTH, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, S* __restrict__ out,
+                                                     const S* __restrict__ in, const S* __restrict__ U, double kappa,
+                                                     const S* __restrict__ aux, double* __restrict__ partials,
+                                                     const int* __restrict__ active, int ftz) {
   using T = typename Traits<S>::T;
   if (active && *active == 0) return;
-  const int par = par0 + blockIdx.x / nbp;
-  const int h = (blockIdx.x % nbp) * 256 + threadIdx.x;
+  const int tid = threadIdx.x;
+  const int par = (tid >> 6) & 1;
+  const int h = block_h0(sched) + ((tid >> 7) << 6) + (tid & 63);
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (EPI == kEpiTS ? 4 : 1));
   double red[NV];
@@ -167,45 +304,49 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, S* __restrict__ out, con
     for (int s = 0; s < 4; s++)
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T>(0, 0);
-    hop_dir<0, DAG>(g, in, U, par, h, c, a);
-    hop_dir<1, DAG>(g, in, U, par, h, c, a);
-    hop_dir<2, DAG>(g, in, U, par, h, c, a);
-    hop_dir<3, DAG>(g, in, U, par, h, c, a);
+    hop_all<DEPTH, DAG>(g, in, U, par, h, c, a);
     const T k = (T)kappa;
+    cx<T> o[12], ctr[12], ax[12];
+    if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(in, g, par, h, ctr);
+    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux) load_site(aux, g, par, h, ax);
+#pragma unroll
+    for (int i = 0; i < 12; i++) {
+      if constexpr (OP == kOpH || OP == kOpHdag) {
+        o[i] = a[i / 3][i % 3];
+      } else {
+        o[i] = ctr[i] - k * a[i / 3][i % 3];
+        if constexpr (EPI == kEpiResid) o[i] = ax[i] - o[i];
+      }
+    }
+    // round to storage; the reductions see the stored values
+    using Gr = typename Lay<S>::Gran;
+    constexpr int C = Lay<S>::C;
+    S* ob = out + sp_block(g, par, h) + (h & 63) * C;
     T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
 #pragma unroll
-    for (int s = 0; s < 4; s++)
+    for (int j = 0; j < Lay<S>::G; j++) {
+      Gr v;
 #pragma unroll
-      for (int cc = 0; cc < 3; cc++) {
-        const int comp = 3 * s + cc;
-        const size_t idx = sp_index(g, par, h, comp);
-        cx<T> o, ctr;
-        if constexpr (OP == kOpH || OP == kOpHdag) {
-          o = a[s][cc];
-        } else {
-          ctr = Traits<S>::load(in + idx);
-          o = ctr - k * a[s][cc];
-          if constexpr (EPI == kEpiResid) o = Traits<S>::load(aux + idx) - o;
-        }
-        const S st = Traits<S>::pack(o, ftz);
-        out[idx] = st;
+      for (int cc = 0; cc < C; cc++) {
+        const int i = j * C + cc;
+        v.s[cc] = Traits<S>::pack(o[i], ftz);
         if constexpr (EPI != kEpiNone) {
-          // reductions see the stored value
-          const cx<T> os = Traits<S>::load(&st);
+          const cx<T> os = Traits<S>::load(&v.s[cc]);
           if constexpr (EPI == kEpiDotAux) {  // (aux, out) = sum conj(aux) out
-            const cx<T> r = Traits<S>::load(aux + idx);
-            acc0 += r.re * os.re + r.im * os.im;
-            acc1 += r.re * os.im - r.im * os.re;
+            acc0 += ax[i].re * os.re + ax[i].im * os.im;
+            acc1 += ax[i].re * os.im - ax[i].im * os.re;
           } else if constexpr (EPI == kEpiTS) {  // (t, s) with t = out, s = in; |t|^2, |s|^2
-            acc0 += os.re * ctr.re + os.im * ctr.im;
-            acc1 += os.re * ctr.im - os.im * ctr.re;
+            acc0 += os.re * ctr[i].re + os.im * ctr[i].im;
+            acc1 += os.re * ctr[i].im - os.im * ctr[i].re;
             acc2 += norm2(os);
-            acc3 += norm2(ctr);
+            acc3 += norm2(ctr[i]);
           } else {
             acc0 += norm2(os);
           }
         }
       }
+      *reinterpret_cast<Gr*>(ob + j * 64 * C) = v;
+    }
     if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
     if constexpr (EPI == kEpiTS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
     if constexpr (EPI == kEpiResid) { red[0] = acc0; }
@@ -213,18 +354,33 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, S* __restrict__ out, con
   if constexpr (EPI != kEpiNone) block_reduce_store<NV>(red, partials, blockIdx.x);
 }
 
-template <typename S>
-static void launch_dslash_t(const Geom& g, int op, int epi, void* out, const void* in, const void* U, double kappa,
-                            const void* aux, double* partials, int par0, int npar, const int* active, int ftz,
-                            hipStream_t st) {
-  const int nbp = (g.Vh + 255) / 256;
-  dim3 grid(nbp * npar), block(256);
+DslashSched make_sched(const Geom& g, int mode) {
+  DslashSched s;
+  s.nblocks = (g.Vh + 127) / 128;
+  s.mode = 0;
+  s.Lz = g.L[2];
+  s.bp = 1;
+  s.zc = 1;
+  const int plane = g.Lxh * g.L[1];
+  if (mode == 1 && plane % 128 == 0 && g.L[2] % 8 == 0) {
+    s.mode = 1;
+    s.bp = plane / 128;
+    s.zc = g.L[2] / 8;
+  }
+  return s;
+}
+
+template <typename S, int DEPTH, int OCC>
+static void launch_dslash_occ(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
+                              const void* U, double kappa, const void* aux, double* partials, const int* active,
+                              int ftz, hipStream_t st) {
+  dim3 grid(sc.nblocks), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
   const S* u = (const S*)U;
   const S* x = (const S*)aux;
 #define QCD_LAUNCH(OPV, EPIV) \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV>), grid, block, 0, st, g, o, i, u, kappa, x, partials, par0, nbp, active, ftz)
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, active, ftz)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -242,17 +398,32 @@ static void launch_dslash_t(const Geom& g, int op, int epi, void* out, const voi
 #undef QCD_LAUNCH
 }
 
-void launch_dslash(int prec, const Geom& g, int op, int epi, void* out, const void* in, const void* U, double kappa,
-                   const void* aux, double* partials, int par0, int npar, const int* active, int ftz,
-                   hipStream_t st) {
-  if (prec == kFP64)
-    launch_dslash_t<double2>(g, op, epi, out, in, U, kappa, aux, partials, par0, npar, active, ftz, st);
-  else if (prec == kFP32)
-    launch_dslash_t<float2>(g, op, epi, out, in, U, kappa, aux, partials, par0, npar, active, ftz, st);
-  else
-    launch_dslash_t<__half2>(g, op, epi, out, in, U, kappa, aux, partials, par0, npar, active, ftz, st);
+template <typename S>
+static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const int* active,
+                            int ftz, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched);
+  switch (tune.variant) {
+    case 1: launch_dslash_occ<S, 2, 2>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    case 2: launch_dslash_occ<S, 0, 3>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    case 3: launch_dslash_occ<S, 1, 3>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    case 4: launch_dslash_occ<S, 0, 4>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    case 5: launch_dslash_occ<S, 1, 4>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    default: launch_dslash_occ<S, 1, 2>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+  }
 }
 
-int dslash_partial_rows(const Geom& g, int npar) { return ((g.Vh + 255) / 256) * npar; }
+void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
+                   const void* U, double kappa, const void* aux, double* partials, const int* active, int ftz,
+                   hipStream_t st) {
+  if (prec == kFP64)
+    launch_dslash_t<double2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
+  else if (prec == kFP32)
+    launch_dslash_t<float2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
+  else
+    launch_dslash_t<__half2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
+}
+
+int dslash_partial_rows(const Geom& g) { return (g.Vh + 127) / 128; }
 
 }  // namespace qcd

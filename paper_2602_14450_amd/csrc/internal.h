@@ -49,14 +49,26 @@ struct Scalars {
   double pad[4];
 };
 
+// Launch choices of the Wilson operator (picked by the tuner).
+struct DslashTune {
+  int sched;    // 0: blocks in half-index order; 1: XCD-slab order when the lattice allows it
+  int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
+};
+constexpr int kDslashVariants = 6;
+struct DslashSched {
+  int mode, nblocks, Lz, bp, zc;
+};
+DslashSched make_sched(const Geom& g, int mode);
+
 // launchers (dslash.hip)
-void launch_dslash(int prec, const Geom& g, int op, int epi, void* out, const void* in, const void* U, double kappa,
-                   const void* aux, double* partials, int par0, int npar, const int* active, int ftz,
+void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
+                   const void* U, double kappa, const void* aux, double* partials, const int* active, int ftz,
                    hipStream_t st);
-int dslash_partial_rows(const Geom& g, int npar);
+int dslash_partial_rows(const Geom& g);
 
 // launchers (blas.hip)
-int site_grid(const Geom& g);  // blocks of the per-site streaming kernels (both parities)
+int site_grid(const Geom& g);              // blocks (and partial rows) of the site-ordered kernels
+int flat_rows(const Geom& g, int prec);    // blocks (and partial rows) of the BLAS-1 kernels
 void launch_pack_links(const Geom& g, int prec, void* dst, const double* Ucanon, hipStream_t st);
 void launch_pack_spinor(const Geom& g, int prec, void* dst, const double* canon, double scale, int ftz,
                         double* partials, hipStream_t st);
