@@ -40,7 +40,19 @@ def parse():
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--only-dslash", action="store_true",
+                    help="time only the Wilson operator and the calibration copy (for counter runs)")
     return ap.parse_args()
+
+
+def calibration_copy(torch, nbytes=1 << 30):
+    """A plain device copy of known size (nbytes read + nbytes written),
+    used to scale the L2-to-memory byte counters."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return nbytes
 
 
 def time_dslash(q, torch, g, prec, reps, V):
@@ -97,6 +109,15 @@ def main():
     ws = torch.empty(g.workspace_bytes(0, q.FP16, max_iter), dtype=torch.uint8, device="cuda")
     ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
     ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
+
+    calib_bytes = calibration_copy(torch)
+    if args.only_dslash:
+        for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+            ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
+            print(f"[bench] dslash {name}: {ms*1e3:.1f} us {DSLASH_BYTES[prec] * V / ms / 1e6:.0f} GB/s", flush=True)
+        print(f"[bench] calibration copy: {calib_bytes} bytes read and written", flush=True)
+        g.close()
+        return
 
     def solve_fp16():
         return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,

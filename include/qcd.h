@@ -64,7 +64,8 @@ typedef struct {
   int recalc_gamma;    /* 1: gamma is the measured ratio |r stored| / |r before rescaling| */
   double omega0;       /* omega prescription threshold; the paper uses 0.7; 0 disables */
   int ftz;             /* 1: a binary16 store below 2^-14 in magnitude is flushed to zero */
-  int check_every;     /* host polls the convergence flag every this many iterations (0: 4) */
+  int check_every;     /* > 0: host polls the convergence flag every this many iterations; 0: adaptive
+                          (first poll after 4, then after the number the convergence rate predicts) */
 } qcd_bicgstab_params;
 
 /* Parameters of the rescaled iterative refinement (Alg. 3; Alg. 2 is s = 1, recalc_shat = 0). */

@@ -220,7 +220,7 @@ def _info_out(code, info, hist, outer, zeros):
 
 
 def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1e-12, max_iter=10000, sigma=0.0,
-             sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=4, workspace=None,
+             sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None,
              history=True, raise_on_error=True) -> Info:
     """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors."""
     p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
@@ -236,7 +236,7 @@ def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1
 
 def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
                    s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
-                   recalc_gamma=True, omega0=0.7, ftz=False, check_every=4, workspace=None, history=False,
+                   recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None, history=False,
                    raise_on_error=True) -> Info:
     """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab."""
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)

@@ -203,19 +203,38 @@ void residual64(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st)
 }
 
 // Run the inner loop from initialised scalars until the device reports a
-// stop; fills the host mirror.
+// stop; fills the host mirror.  Iterations are queued in chunks without host
+// synchronisation (kernels of a stopped solve return at once).  After the
+// first chunk, the chunk length is the number of iterations the observed
+// convergence rate predicts are still needed, plus one.
 qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, const qcd_bicgstab_params& p,
                      hipStream_t st) {
-  const int K = p.check_every > 0 ? p.check_every : 4;
+  const int K0 = p.check_every > 0 ? p.check_every : 4;
   qcd_status s = read_scalars(g, w, st);
   if (s) return s;
-  int launched = 0;
-  while (g->host_sc->active && launched <= p.max_iter + K) {
-    for (int j = 0; j < K; j++) bicg_iteration(g, prec, kappa, w, p.ftz, st);
+  int launched = 0, chunk = K0;
+  double prev_res2 = g->host_sc->bnorm2;
+  int prev_iter = 0;
+  while (g->host_sc->active && launched <= p.max_iter + K0) {
+    for (int j = 0; j < chunk; j++) bicg_iteration(g, prec, kappa, w, p.ftz, st);
     HIP_LAUNCHED();
-    launched += K;
+    launched += chunk;
     s = read_scalars(g, w, st);
     if (s) return s;
+    const Scalars& h = *g->host_sc;
+    if (!h.active) break;
+    chunk = K0;
+    if (p.check_every <= 0 && h.iter > prev_iter) {
+      const double res2 = h.rnorm2 / (h.gamma_cum * h.gamma_cum);
+      const double target = h.tol2 * h.bnorm2;
+      const double rate = std::pow(res2 / prev_res2, 1.0 / (h.iter - prev_iter));  // per iteration
+      if (rate > 0.0 && rate < 0.999 && res2 > target) {
+        const double need = std::log(target / res2) / std::log(rate);
+        chunk = (int)std::min(64.0, std::max(1.0, std::ceil(need) + 1.0));
+      }
+      prev_res2 = res2;
+      prev_iter = h.iter;
+    }
   }
   return QCD_OK;
 }
