@@ -24,6 +24,10 @@
  *   (gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = diag(1,1,-1,-1)).
  * Pointers named *_dev are device pointers; the caller owns all device
  *   memory passed in.  `stream` is a hipStream_t (NULL = default stream).
+ * Several right-hand sides: calls taking nrhs (1..64) expect nrhs fields
+ *   back to back (canonical: [rhs][site][spin][colour]; native: nrhs native
+ *   fields of qcd_spinor_bytes() each); per-right-hand-side outputs (norms,
+ *   info) are arrays of nrhs entries.
  *   Entry points that return solver results synchronise with `stream`.
  * Errors: a negative status; qcd_last_error() gives a message (per thread).
  *   No C++ exception crosses this interface.
@@ -93,7 +97,8 @@ typedef struct {
   int history_len;          /* entries written */
   double* outer_history;    /* optional caller-owned host array: |r|/|b| after each refinement step */
   int outer_history_cap;
-  double* zeros;            /* optional: zero reals in y~ per refinement step (Fig. 9 diagnostic) */
+  double* zeros;            /* optional: zero reals in y~ per refinement step (Fig. 9 diagnostic),
+                               capacity outer_history_cap */
 } qcd_solve_info;
 
 /* Message for the last error on this thread ("" if none). */
@@ -118,18 +123,21 @@ qcd_status qcd_gauge_free(qcd_gauge* g);
  * variant 0..5 selects how many hops' loads are prefetched while one hop is
  * computed and the minimum waves per SIMD the kernel is compiled for:
  * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4).
- * Results do not depend on these choices. */
-qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant);
-qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant);
+ * rhs_tile (0 = automatic, 1, 2, 4) is the number of right-hand sides whose
+ * lanes share one wave's link loads in a multi-RHS application (it must divide
+ * nrhs, else 1 is used).  Results do not depend on these choices. */
+qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile);
+qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile);
 
 /* Bytes of one native spinor field in precision prec. */
 size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 
 /* Workspace bytes that qcd_solve_mixed_ir (what = 0), qcd_bicgstab (what = 1)
  * or qcd_dslash with canonical layout (what = 2) need for inner precision
- * prec and max_iter history entries.  Passing ws = NULL to those calls makes
- * the handle's own cached workspace be used (allocated on first use). */
-size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter);
+ * prec, max_iter history entries and nrhs right-hand sides.  Passing ws =
+ * NULL to those calls makes the handle's own cached workspace be used
+ * (allocated on first use; a handle is not safe for concurrent calls). */
+size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs);
 
 /* Precision conversion with rescaling (Alg. 3, the steps y = alpha r and
  * y~ = low_prec(y)): native_dev = round_prec(scale * canonical_dev) with
@@ -138,25 +146,27 @@ size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_
  * sum |stored|^2 computed per site in the arithmetic precision and in FP64
  * across sites (the s^ of Alg. 3 is its square root).  Synchronises when
  * norm2 is requested. */
-qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, void* native_dev, const void* canonical_dev, double scale,
-                       int ftz, double* norm2, void* stream);
+qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* native_dev, const void* canonical_dev,
+                       double scale, int ftz, double* norm2, void* stream);
 
 /* Inverse conversion: canonical_dev (complex128) = scale * double(native_dev). */
-qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, void* canonical_dev, const void* native_dev, double scale,
-                         void* stream);
+qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* canonical_dev, const void* native_dev,
+                         double scale, void* stream);
 
 /* Wilson operator (eq. (1), Alg. 1 with the projection of Sec. 2):
  * out = op(in) with op one of D, H, D^dag, H^dag.  prec selects the link
  * copy, the storage of in/out (native layout) and the arithmetic (FP64 for
  * FP64, FP32 otherwise).  With QCD_LAYOUT_CANONICAL, in and out are
  * complex128 canonical fields, converted to/from prec around the
- * application.  out must not alias in.  Asynchronous on stream. */
-qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, void* out_dev,
-                      const void* in_dev, void* stream);
+ * application.  With nrhs > 1 the links are read once per site for all
+ * right-hand sides (a wave's lanes interleave sites and right-hand sides).
+ * out must not alias in.  Asynchronous on stream. */
+qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, int nrhs,
+                      void* out_dev, const void* in_dev, void* stream);
 
 /* FP64 true residual of Alg. 3: r = b - D x (canonical complex128), and if
  * norm2 is not NULL, |r|^2.  Synchronises when norm2 is requested. */
-qcd_status qcd_residual(const qcd_gauge* g, double kappa, void* r_dev, const void* x_dev, const void* b_dev,
+qcd_status qcd_residual(const qcd_gauge* g, double kappa, int nrhs, void* r_dev, const void* x_dev, const void* b_dev,
                         double* norm2, void* stream);
 
 /* Rescaled BiCGStab (Alg. 4 / Alg. 5) solving D x = b in precision prec,
@@ -165,19 +175,22 @@ qcd_status qcd_residual(const qcd_gauge* g, double kappa, void* r_dev, const voi
  * info (may be NULL) receives counts and the FP64 true residual.
  * Returns QCD_OK, QCD_NOT_CONVERGED, QCD_ERR_NONFINITE or QCD_ERR_BREAKDOWN
  * (x holds the last iterate in the last three cases).  Synchronises. */
-qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, void* x_dev, const void* b_dev,
+qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrhs, void* x_dev, const void* b_dev,
                         const qcd_bicgstab_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
 /* FP64 iterative refinement around the rescaled low-precision BiCGStab
  * (Alg. 3 with Alg. 4 / Alg. 5; Alg. 2 when s = 1 and recalc_shat = 0):
  *   x = 0, r = b; while |r|/|b| > tol: y~ = low(r s/|r|), s^ = |single(y~)|,
  *   solve A~ t = y~, x += (|r|/s^) double(t), r = b - D x (FP64).
- * b_dev, x_dev canonical complex128.  Returns QCD_OK when the FP64 true
- * residual reaches tol, QCD_NOT_CONVERGED after max_outer steps (x valid),
- * QCD_ERR_NONFINITE / QCD_ERR_BREAKDOWN if an inner solve failed before any
- * progress.  Synchronises. */
-qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, void* x_dev, const void* b_dev, const qcd_ir_params* p,
-                              qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
+ * b_dev, x_dev canonical complex128.  nrhs right-hand sides are solved
+ * together: every kernel handles all of them, each with its own scalars,
+ * and a right-hand side that has met the tolerance is skipped by the kernels
+ * (per-right-hand-side masks).  Returns (the worst over right-hand sides)
+ * QCD_OK when the FP64 true residual reaches tol, QCD_NOT_CONVERGED after
+ * max_outer steps (x valid), QCD_ERR_NONFINITE / QCD_ERR_BREAKDOWN if an
+ * inner solve failed before any progress.  Synchronises. */
+qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
+                              const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -59,18 +59,18 @@ _lib.qcd_gauge_upload.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_i), _vp, 
 _lib.qcd_gauge_free.argtypes = [_vp]
 _lib.qcd_spinor_bytes.argtypes = [_vp, _i]
 _lib.qcd_spinor_bytes.restype = _sz
-_lib.qcd_workspace_bytes.argtypes = [_vp, _i, _i, _i]
+_lib.qcd_workspace_bytes.argtypes = [_vp, _i, _i, _i, _i]
 _lib.qcd_workspace_bytes.restype = _sz
-_lib.qcd_convert.argtypes = [_vp, _i, _vp, _vp, _d, _i, ctypes.POINTER(_d), _vp]
-_lib.qcd_unconvert.argtypes = [_vp, _i, _vp, _vp, _d, _vp]
-_lib.qcd_dslash.argtypes = [_vp, _d, _i, _i, _i, _vp, _vp, _vp]
-_lib.qcd_residual.argtypes = [_vp, _d, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]
-_lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(BicgstabParams), ctypes.POINTER(SolveInfo),
+_lib.qcd_convert.argtypes = [_vp, _i, _i, _vp, _vp, _d, _i, ctypes.POINTER(_d), _vp]
+_lib.qcd_unconvert.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp]
+_lib.qcd_dslash.argtypes = [_vp, _d, _i, _i, _i, _i, _vp, _vp, _vp]
+_lib.qcd_residual.argtypes = [_vp, _d, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]
+_lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _i, _vp, _vp, ctypes.POINTER(BicgstabParams), ctypes.POINTER(SolveInfo),
                               _vp, _sz, _vp]
-_lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
+_lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
                                     _sz, _vp]
-_lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i]
-_lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]
+_lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
+_lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
 for _f in ("qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
@@ -132,50 +132,69 @@ class Gauge:
         except Exception:
             pass
 
-    def set_tuning(self, prec, sched: int, occupancy: int):
-        _check(_lib.qcd_set_dslash_tuning(self.handle, PREC[prec], int(sched), int(occupancy)))
+    def set_tuning(self, prec, sched: int, variant: int, rhs_tile: int = 0):
+        _check(_lib.qcd_set_dslash_tuning(self.handle, PREC[prec], int(sched), int(variant), int(rhs_tile)))
 
     def get_tuning(self, prec):
-        a, b = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.qcd_get_dslash_tuning(self.handle, PREC[prec], ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.qcd_get_dslash_tuning(self.handle, PREC[prec], ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def nrhs_of(self, t: torch.Tensor) -> int:
+        """Number of canonical spinor fields a complex128 tensor holds."""
+        per = self.volume * 12
+        assert t.numel() % per == 0, "tensor is not a whole number of spinor fields"
+        return t.numel() // per
 
     def spinor_bytes(self, prec) -> int:
         return int(_lib.qcd_spinor_bytes(self.handle, PREC[prec]))
 
-    def workspace_bytes(self, what, prec, max_iter) -> int:
-        return int(_lib.qcd_workspace_bytes(self.handle, int(what), PREC[prec], int(max_iter)))
+    def workspace_bytes(self, what, prec, max_iter, nrhs=1) -> int:
+        return int(_lib.qcd_workspace_bytes(self.handle, int(what), PREC[prec], int(max_iter), int(nrhs)))
 
-    def native_spinor(self, prec) -> torch.Tensor:
-        """An uninitialised device buffer for one native spinor field."""
-        return torch.empty(self.spinor_bytes(prec), dtype=torch.uint8, device="cuda")
+    def native_spinor(self, prec, nrhs=1) -> torch.Tensor:
+        """An uninitialised device buffer for nrhs native spinor fields."""
+        return torch.empty(self.spinor_bytes(prec) * nrhs, dtype=torch.uint8, device="cuda")
 
 
 def gauge_upload(U, dims, precs=(FP64, FP32, FP16)) -> Gauge:
     return Gauge(U, dims, precs)
 
 
+def _one_or_list(vals, n):
+    return vals[0] if n == 1 else list(vals)
+
+
 def convert(g: Gauge, prec, native: torch.Tensor, canonical: torch.Tensor, scale=1.0, ftz=False, want_norm=True):
-    n2 = ctypes.c_double(0.0)
-    _check(_lib.qcd_convert(g.handle, PREC[prec], _ptr(native), _ptr(_as_c128(canonical)), float(scale), int(ftz),
-                            ctypes.byref(n2) if want_norm else None, _stream()))
-    return n2.value if want_norm else None
+    """native = round_prec(scale * canonical); returns |native|^2 per right-hand side."""
+    n = g.nrhs_of(canonical)
+    n2 = (ctypes.c_double * n)()
+    _check(_lib.qcd_convert(g.handle, PREC[prec], n, _ptr(native), _ptr(_as_c128(canonical)), float(scale), int(ftz),
+                            n2 if want_norm else None, _stream()))
+    return _one_or_list(n2, n) if want_norm else None
 
 
 def unconvert(g: Gauge, prec, canonical: torch.Tensor, native: torch.Tensor, scale=1.0):
-    _check(_lib.qcd_unconvert(g.handle, PREC[prec], _ptr(canonical), _ptr(native), float(scale), _stream()))
+    n = g.nrhs_of(canonical)
+    _check(_lib.qcd_unconvert(g.handle, PREC[prec], n, _ptr(canonical), _ptr(native), float(scale), _stream()))
 
 
-def dslash(g: Gauge, kappa, out: torch.Tensor, inp: torch.Tensor, op=OP_D, prec=FP64, layout=CANONICAL):
-    _check(_lib.qcd_dslash(g.handle, float(kappa), int(op), PREC[prec], int(layout), _ptr(out), _ptr(inp), _stream()))
+def dslash(g: Gauge, kappa, out: torch.Tensor, inp: torch.Tensor, op=OP_D, prec=FP64, layout=CANONICAL, nrhs=None):
+    """out = op(inp); nrhs defaults to the number of canonical fields in inp (native layout: 1)."""
+    if nrhs is None:
+        nrhs = g.nrhs_of(inp) if layout == CANONICAL else 1
+    _check(_lib.qcd_dslash(g.handle, float(kappa), int(op), PREC[prec], int(layout), int(nrhs), _ptr(out), _ptr(inp),
+                           _stream()))
     return out
 
 
-def residual(g: Gauge, kappa, r: torch.Tensor, x: torch.Tensor, b: torch.Tensor) -> float:
-    n2 = ctypes.c_double(0.0)
-    _check(_lib.qcd_residual(g.handle, float(kappa), _ptr(r), _ptr(_as_c128(x)), _ptr(_as_c128(b)),
-                             ctypes.byref(n2), _stream()))
-    return n2.value
+def residual(g: Gauge, kappa, r: torch.Tensor, x: torch.Tensor, b: torch.Tensor):
+    n = g.nrhs_of(b)
+    n2 = (ctypes.c_double * n)()
+    _check(_lib.qcd_residual(g.handle, float(kappa), n, _ptr(r), _ptr(_as_c128(x)), _ptr(_as_c128(b)), n2,
+                             _stream()))
+    return _one_or_list(n2, n)
 
 
 @dataclass
@@ -199,53 +218,64 @@ def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, 
                           int(bool(recalc_gamma)), float(omega0), int(bool(ftz)), int(check_every))
 
 
-def _make_info(hist_cap, outer_cap):
-    info = SolveInfo()
-    hist = (ctypes.c_double * max(hist_cap, 1))()
-    outer = (ctypes.c_double * max(outer_cap, 1))()
-    zeros = (ctypes.c_double * max(outer_cap, 1))()
-    info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
-    info.history_cap = hist_cap
-    info.outer_history = ctypes.cast(outer, ctypes.POINTER(ctypes.c_double))
-    info.outer_history_cap = outer_cap
-    info.zeros = ctypes.cast(zeros, ctypes.POINTER(ctypes.c_double))
-    return info, hist, outer, zeros
+def _make_infos(n, hist_cap, outer_cap):
+    infos = (SolveInfo * n)()
+    keep = []
+    for i in range(n):
+        hist = (ctypes.c_double * max(hist_cap, 1))()
+        outer = (ctypes.c_double * max(outer_cap, 1))()
+        zeros = (ctypes.c_double * max(outer_cap, 1))()
+        infos[i].history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        infos[i].history_cap = hist_cap
+        infos[i].outer_history = ctypes.cast(outer, ctypes.POINTER(ctypes.c_double))
+        infos[i].outer_history_cap = outer_cap
+        infos[i].zeros = ctypes.cast(zeros, ctypes.POINTER(ctypes.c_double))
+        keep.append((hist, outer, zeros))
+    return infos, keep
 
 
-def _info_out(code, info, hist, outer, zeros):
-    n_out = min(info.outer_iters, info.outer_history_cap)
-    return Info(STATUS.get(code, str(code)), info.outer_iters, info.inner_iters, info.matvec_low, info.matvec_fp64,
-                info.true_rel_residual, info.seconds, info.inner_status, info.first_shat_over_s,
-                list(hist[:info.history_len]), list(outer[:n_out]), list(zeros[:n_out]))
+def _infos_out(code, infos, keep):
+    out = []
+    for info, (hist, outer, zeros) in zip(infos, keep):
+        n_out = min(info.outer_iters, info.outer_history_cap)
+        out.append(Info(STATUS.get(code, str(code)), info.outer_iters, info.inner_iters, info.matvec_low,
+                        info.matvec_fp64, info.true_rel_residual, info.seconds, info.inner_status,
+                        info.first_shat_over_s, list(hist[:info.history_len]), list(outer[:n_out]),
+                        list(zeros[:n_out])))
+    return out[0] if len(out) == 1 else out
 
 
 def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1e-12, max_iter=10000, sigma=0.0,
              sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None,
-             history=True, raise_on_error=True) -> Info:
-    """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors."""
+             history=True, raise_on_error=True):
+    """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors
+    (one or several right-hand sides); returns an Info or a list of them."""
+    n = g.nrhs_of(b)
     p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
-    info, hist, outer, zeros = _make_info(max_iter if history else 0, 1)
+    infos, keep = _make_infos(n, max_iter if history else 0, 1)
     ws = _ptr(workspace) if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
-    code = _lib.qcd_bicgstab(g.handle, float(kappa), PREC[prec], _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
-                             ctypes.byref(info), ws, wsb, _stream())
+    code = _lib.qcd_bicgstab(g.handle, float(kappa), PREC[prec], n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
+                             infos, ws, wsb, _stream())
     if raise_on_error:
         _check(code, allow=(0, 1))
-    return _info_out(code, info, hist, outer, zeros)
+    return _infos_out(code, infos, keep)
 
 
 def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
                    s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                    recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None, history=False,
-                   raise_on_error=True) -> Info:
-    """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab."""
+                   raise_on_error=True):
+    """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab,
+    for one or several right-hand sides; returns an Info or a list of them."""
+    n = g.nrhs_of(b)
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
     p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner)
-    info, hist, outer, zeros = _make_info(inner_max_iter * 4 if history else 0, max_outer)
+    infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
     ws = _ptr(workspace) if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
-    code = _lib.qcd_solve_mixed_ir(g.handle, float(kappa), _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
-                                   ctypes.byref(info), ws, wsb, _stream())
+    code = _lib.qcd_solve_mixed_ir(g.handle, float(kappa), n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p), infos,
+                                   ws, wsb, _stream())
     if raise_on_error:
         _check(code, allow=(0, 1))
-    return _info_out(code, info, hist, outer, zeros)
+    return _infos_out(code, infos, keep)

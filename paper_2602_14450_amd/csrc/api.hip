@@ -21,7 +21,7 @@ struct qcd_gauge {
   void* U[3];
   void* ws;          // cached workspace used when the caller passes none
   size_t ws_bytes;
-  Scalars* host_sc;  // pinned mirror of the device scalars
+  Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
   DslashTune tune[3];
 };
 
@@ -56,11 +56,12 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t spinor_bytes(const Geom& g, int prec) { return spinor_elems(g) * prec_complex_bytes(prec); }
-size_t partial_bytes(const Geom& g) {
+size_t canon_bytes(const Geom& g) { return (size_t)2 * g.Vh * 12 * 16; }
+int max_rows(const Geom& g, const DslashTune* tune, int n) {
   int rows = site_grid(g);
   for (int p = 0; p < 3; p++) rows = std::max(rows, flat_rows(g, p));
-  rows = std::max(rows, dslash_partial_rows(g));
-  return (size_t)rows * 8 * sizeof(double);
+  for (int p = 0; p < 3; p++) rows = std::max(rows, dslash_partial_rows(g, tune[p], n));
+  return rows;
 }
 
 // Workspace carve-up.
@@ -75,6 +76,7 @@ struct Carve {
 };
 
 struct Work {
+  int n = 1;
   double2* x64 = nullptr;
   double2* b64 = nullptr;
   double2* r64 = nullptr;
@@ -87,39 +89,46 @@ struct Work {
   double* partials = nullptr;
   Scalars* sc = nullptr;
   double* history = nullptr;
+  int hist_stride = 1;
   double* sums = nullptr;
+  double* scale = nullptr;
   size_t bytes = 0;
 };
 
 // what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout
-Work carve(const Geom& g, int what, int prec, int max_iter, char* base) {
+Work carve(const qcd_gauge* G, int what, int prec, int max_iter, int n, char* base) {
+  const Geom& g = G->g;
   Carve c{base};
   Work w;
+  w.n = n;
   if (what == 0 || what == 1) {
-    w.x64 = (double2*)c.take(spinor_bytes(g, kFP64));
-    w.b64 = (double2*)c.take(spinor_bytes(g, kFP64));
-    w.r64 = (double2*)c.take(spinor_bytes(g, kFP64));
-    w.x = c.take(spinor_bytes(g, prec));
-    w.r = c.take(spinor_bytes(g, prec));
-    w.rstar = c.take(spinor_bytes(g, prec));
-    w.p = c.take(spinor_bytes(g, prec));
-    w.v = c.take(spinor_bytes(g, prec));
-    w.t = c.take(spinor_bytes(g, prec));
-    w.history = (double*)c.take(sizeof(double) * (size_t)(max_iter > 0 ? max_iter : 1));
+    w.x64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.r64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.x = c.take(n * spinor_bytes(g, prec));
+    w.r = c.take(n * spinor_bytes(g, prec));
+    w.rstar = c.take(n * spinor_bytes(g, prec));
+    w.p = c.take(n * spinor_bytes(g, prec));
+    w.v = c.take(n * spinor_bytes(g, prec));
+    w.t = c.take(n * spinor_bytes(g, prec));
+    w.hist_stride = max_iter > 0 ? max_iter : 1;
+    w.history = (double*)c.take(sizeof(double) * (size_t)w.hist_stride * n);
   } else {
-    w.x = c.take(spinor_bytes(g, prec));
-    w.r = c.take(spinor_bytes(g, prec));
+    w.x = c.take(n * spinor_bytes(g, prec));
+    w.r = c.take(n * spinor_bytes(g, prec));
   }
-  w.partials = (double*)c.take(partial_bytes(g));
-  w.sc = (Scalars*)c.take(sizeof(Scalars));
-  w.sums = (double*)c.take(8 * sizeof(double));
+  w.partials = (double*)c.take((size_t)max_rows(g, G->tune, n) * 8 * sizeof(double) * n);
+  w.sc = (Scalars*)c.take(sizeof(Scalars) * n);
+  w.sums = (double*)c.take(8 * sizeof(double) * n);
+  w.scale = (double*)c.take(sizeof(double) * n);
   w.bytes = c.off;
   return w;
 }
 
-qcd_status get_work(const qcd_gauge* gc, int what, int prec, int max_iter, void* ws, size_t ws_bytes, Work* out) {
+qcd_status get_work(const qcd_gauge* gc, int what, int prec, int max_iter, int n, void* ws, size_t ws_bytes,
+                    Work* out) {
   qcd_gauge* g = const_cast<qcd_gauge*>(gc);
-  Work need = carve(g->g, what, prec, max_iter, nullptr);
+  Work need = carve(g, what, prec, max_iter, n, nullptr);
   char* base;
   if (ws) {
     if (ws_bytes < need.bytes)
@@ -135,7 +144,7 @@ qcd_status get_work(const qcd_gauge* gc, int what, int prec, int max_iter, void*
     }
     base = (char*)g->ws;
   }
-  *out = carve(g->g, what, prec, max_iter, base);
+  *out = carve(g, what, prec, max_iter, n, base);
   return QCD_OK;
 }
 
@@ -148,16 +157,21 @@ qcd_status check_gauge(const qcd_gauge* g, int prec) {
   return QCD_OK;
 }
 
+qcd_status check_nrhs(int n) {
+  if (n < 1 || n > kMaxRhs) return fail(QCD_ERR_ARG, "nrhs must be in 1..%d", kMaxRhs);
+  return QCD_OK;
+}
+
 qcd_status read_scalars(const qcd_gauge* g, const Work& w, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(g->host_sc, w.sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(g->host_sc, w.sc, sizeof(Scalars) * w.n, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return QCD_OK;
 }
 
 qcd_status read_sum(const Work& w, int nrows, int nv, double* out, hipStream_t st) {
-  launch_finish_sum(w.partials, nrows, nv, w.sums, st);
+  launch_finish_sum(w.n, w.partials, nrows, nv, w.sums, st);
   HIP_LAUNCHED();
-  HIP_TRY(hipMemcpyAsync(out, w.sums, nv * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(out, w.sums, w.n * nv * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return QCD_OK;
 }
@@ -170,6 +184,8 @@ void init_params(Scalars* h, const qcd_bicgstab_params& p) {
   h->tol2 = p.tol * p.tol;
   h->recalc_gamma = p.recalc_gamma;
   h->max_iter = p.max_iter;
+  h->outer_active = 1;
+  h->out_bnorm = -1.0;
 }
 
 qcd_status check_bicg_params(const qcd_bicgstab_params* p) {
@@ -180,71 +196,88 @@ qcd_status check_bicg_params(const qcd_bicgstab_params* p) {
   return QCD_OK;
 }
 
-// One BiCGStab iteration of Alg. 4 / Alg. 5, entirely on the device.
+// One BiCGStab iteration of Alg. 4 / Alg. 5 for all right-hand sides, entirely on the device.
 void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, int ftz, hipStream_t st) {
   const Geom& G = g->g;
-  const int drows = dslash_partial_rows(G), frows = flat_rows(G, prec);
-  const void* U = g->U[prec];
+  const int n = w.n;
   const DslashTune& tu = g->tune[prec];
-  launch_p_update(G, prec, w.sc, w.p, w.v, w.r, ftz, st);
-  launch_dslash(prec, G, tu, kOpD, kEpiDotAux, w.v, w.p, U, kappa, w.rstar, w.partials, &w.sc->active, ftz, st);
-  launch_alpha(w.sc, w.partials, drows, st);
-  launch_s_update(G, prec, w.sc, w.r, w.v, ftz, st);
-  launch_dslash(prec, G, tu, kOpD, kEpiTS, w.t, w.r, U, kappa, nullptr, w.partials, &w.sc->active, ftz, st);
-  launch_omega(w.sc, w.partials, drows, st);
-  launch_xr_update(G, prec, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
-  launch_iter_end(w.sc, w.partials, frows, w.history, st);
+  const int drows = dslash_partial_rows(G, tu, n), frows = flat_rows(G, prec);
+  const void* U = g->U[prec];
+  launch_p_update(G, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
+  launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.p, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
+  launch_alpha(n, w.sc, w.partials, drows, st);
+  launch_s_update(G, prec, n, w.sc, w.r, w.v, ftz, st);
+  launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.r, U, kappa, nullptr, w.partials, w.sc, ftz, st);
+  launch_omega(n, w.sc, w.partials, drows, st);
+  launch_xr_update(G, prec, n, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
+  launch_iter_end(n, w.sc, w.partials, frows, w.history, w.hist_stride, st);
 }
 
-// FP64 residual r = b - D x with |r|^2 partials (one row per Wilson-operator block).
-void residual64(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
-  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.r64, w.x64, g->U[kFP64], kappa, w.b64, w.partials,
-                nullptr, 0, st);
+// FP64 residual r = b - D x with |r|^2 partials for all right-hand sides
+// (only those still refining are computed).
+void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* outer_mask, hipStream_t st) {
+  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.r64, w.x64, g->U[kFP64], kappa, w.b64,
+                w.partials, outer_mask, 0, st);
+}
+
+bool any_active(const qcd_gauge* g, int n) {
+  for (int i = 0; i < n; i++)
+    if (g->host_sc[i].active) return true;
+  return false;
 }
 
 // Run the inner loop from initialised scalars until the device reports a
-// stop; fills the host mirror.  Iterations are queued in chunks without host
-// synchronisation (kernels of a stopped solve return at once).  After the
-// first chunk, the chunk length is the number of iterations the observed
-// convergence rate predicts are still needed, plus one.
+// stop for every right-hand side; fills the host mirror.  Iterations are
+// queued in chunks without host synchronisation (kernels of a stopped solve
+// return at once).  After the first chunk, the chunk length is the number of
+// iterations the observed convergence rate predicts the slowest right-hand
+// side still needs, plus one.
 qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, const qcd_bicgstab_params& p,
                      hipStream_t st) {
   const int K0 = p.check_every > 0 ? p.check_every : 4;
+  const int n = w.n;
   qcd_status s = read_scalars(g, w, st);
   if (s) return s;
   int launched = 0, chunk = K0;
-  double prev_res2 = g->host_sc->bnorm2;
-  int prev_iter = 0;
-  while (g->host_sc->active && launched <= p.max_iter + K0) {
+  double prev_res2[kMaxRhs];
+  int prev_iter[kMaxRhs];
+  for (int i = 0; i < n; i++) {
+    prev_res2[i] = g->host_sc[i].bnorm2;
+    prev_iter[i] = 0;
+  }
+  while (any_active(g, n) && launched <= p.max_iter + K0) {
     for (int j = 0; j < chunk; j++) bicg_iteration(g, prec, kappa, w, p.ftz, st);
     HIP_LAUNCHED();
     launched += chunk;
     s = read_scalars(g, w, st);
     if (s) return s;
-    const Scalars& h = *g->host_sc;
-    if (!h.active) break;
     chunk = K0;
-    if (p.check_every <= 0 && h.iter > prev_iter) {
+    if (p.check_every > 0) continue;
+    int need_max = 0;
+    for (int i = 0; i < n; i++) {
+      const Scalars& h = g->host_sc[i];
+      if (!h.active || h.iter <= prev_iter[i]) continue;
       const double res2 = h.rnorm2 / (h.gamma_cum * h.gamma_cum);
       const double target = h.tol2 * h.bnorm2;
-      const double rate = std::pow(res2 / prev_res2, 1.0 / (h.iter - prev_iter));  // per iteration
-      if (rate > 0.0 && rate < 0.999 && res2 > target) {
-        const double need = std::log(target / res2) / std::log(rate);
-        chunk = (int)std::min(64.0, std::max(1.0, std::ceil(need) + 1.0));
-      }
-      prev_res2 = res2;
-      prev_iter = h.iter;
+      const double rate = std::pow(res2 / prev_res2[i], 1.0 / (h.iter - prev_iter[i]));  // per iteration
+      int need = K0;
+      if (rate > 0.0 && rate < 0.999 && res2 > target)
+        need = (int)std::min(64.0, std::max(1.0, std::ceil(std::log(target / res2) / std::log(rate)) + 1.0));
+      need_max = std::max(need_max, need);
+      prev_res2[i] = res2;
+      prev_iter[i] = h.iter;
     }
+    if (need_max > 0) chunk = need_max;
   }
   return QCD_OK;
 }
 
-void copy_history(qcd_solve_info* info, const Work& w, int n, double bn2, hipStream_t st) {
-  if (!info || !info->history || info->history_cap <= info->history_len || n <= 0) return;
-  int m = n;
+void copy_history(qcd_solve_info* info, const Work& w, int rhs, int niter, double bn2, hipStream_t st) {
+  if (!info || !info->history || info->history_cap <= info->history_len || niter <= 0) return;
+  int m = niter;
   if (m > info->history_cap - info->history_len) m = info->history_cap - info->history_len;
-  if (hipMemcpyAsync(info->history + info->history_len, w.history, m * sizeof(double), hipMemcpyDeviceToHost, st) !=
-      hipSuccess)
+  if (hipMemcpyAsync(info->history + info->history_len, w.history + (size_t)rhs * w.hist_stride, m * sizeof(double),
+                     hipMemcpyDeviceToHost, st) != hipSuccess)
     return;
   if (hipStreamSynchronize(st) != hipSuccess) return;
   for (int i = 0; i < m; i++) info->history[info->history_len + i] /= bn2;
@@ -273,9 +306,9 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
   // defaults measured on MI355X at 32^3 x 64 (the tuner may override them)
-  g->tune[kFP64] = DslashTune{1, 0};
-  g->tune[kFP32] = DslashTune{1, 1};
-  g->tune[kFP16] = DslashTune{1, 1};
+  g->tune[kFP64] = DslashTune{1, 0, 0};
+  g->tune[kFP32] = DslashTune{1, 1, 0};
+  g->tune[kFP16] = DslashTune{1, 1, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
@@ -292,7 +325,7 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
     launch_pack_links(g->g, p, g->U[p], (const double*)U_dev, st);
     if (hipGetLastError() != hipSuccess) rc = fail(QCD_ERR_HIP, "link packing launch failed");
   }
-  if (rc == QCD_OK && hipHostMalloc((void**)&g->host_sc, sizeof(Scalars), 0) != hipSuccess)
+  if (rc == QCD_OK && hipHostMalloc((void**)&g->host_sc, sizeof(Scalars) * kMaxRhs, 0) != hipSuccess)
     rc = fail(QCD_ERR_HIP, "hipHostMalloc failed");
   if (rc == QCD_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QCD_ERR_HIP, "synchronise failed");
   if (rc != QCD_OK) {
@@ -313,18 +346,21 @@ qcd_status qcd_gauge_free(qcd_gauge* g) {
   return QCD_OK;
 }
 
-qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant) {
+qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile) {
   if (!g || !valid_prec(prec)) return fail(QCD_ERR_ARG, "invalid handle or precision");
   if (sched < 0 || sched > 1 || variant < 0 || variant >= kDslashVariants)
     return fail(QCD_ERR_ARG, "sched must be 0 or 1 and variant 0..%d", kDslashVariants - 1);
-  g->tune[prec] = DslashTune{sched, variant};
+  if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4)
+    return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2 or 4");
+  g->tune[prec] = DslashTune{sched, variant, rhs_tile};
   return QCD_OK;
 }
 
-qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant) {
-  if (!g || !valid_prec(prec) || !sched || !variant) return fail(QCD_ERR_ARG, "invalid argument");
+qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile) {
+  if (!g || !valid_prec(prec) || !sched || !variant || !rhs_tile) return fail(QCD_ERR_ARG, "invalid argument");
   *sched = g->tune[prec].sched;
   *variant = g->tune[prec].variant;
+  *rhs_tile = g->tune[prec].rhs_tile;
   return QCD_OK;
 }
 
@@ -333,227 +369,282 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec) {
   return spinor_bytes(g->g, prec);
 }
 
-size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter) {
-  if (!g || !valid_prec(prec) || what < 0 || what > 2) return 0;
-  return carve(g->g, what, prec, max_iter, nullptr).bytes;
+size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs) {
+  if (!g || !valid_prec(prec) || what < 0 || what > 2 || nrhs < 1 || nrhs > kMaxRhs) return 0;
+  return carve(g, what, prec, max_iter, nrhs, nullptr).bytes;
 }
 
-qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, void* native_dev, const void* canonical_dev, double scale,
-                       int ftz, double* norm2, void* stream) {
+qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* native_dev, const void* canonical_dev,
+                       double scale, int ftz, double* norm2, void* stream) {
   qcd_status rc = check_gauge(g, kFP64);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!valid_prec(prec) || !native_dev || !canonical_dev) return fail(QCD_ERR_ARG, "invalid argument");
   hipStream_t st = S(stream);
   Work w;
   if (norm2) {
-    rc = get_work(g, 2, prec, 0, nullptr, 0, &w);
+    rc = get_work(g, 2, prec, 0, nrhs, nullptr, 0, &w);
     if (rc) return rc;
   }
-  launch_pack_spinor(g->g, prec, native_dev, (const double*)canonical_dev, scale, ftz, norm2 ? w.partials : nullptr,
-                     st);
+  launch_pack_spinor(g->g, prec, nrhs, native_dev, (const double*)canonical_dev, scale, ftz,
+                     norm2 ? w.partials : nullptr, st);
   HIP_LAUNCHED();
   if (norm2) return read_sum(w, site_grid(g->g), 1, norm2, st);
   return QCD_OK;
 }
 
-qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, void* canonical_dev, const void* native_dev, double scale,
-                         void* stream) {
+qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* canonical_dev, const void* native_dev,
+                         double scale, void* stream) {
   qcd_status rc = check_gauge(g, kFP64);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!valid_prec(prec) || !native_dev || !canonical_dev) return fail(QCD_ERR_ARG, "invalid argument");
-  launch_unpack_spinor(g->g, prec, (double*)canonical_dev, native_dev, scale, S(stream));
+  launch_unpack_spinor(g->g, prec, nrhs, (double*)canonical_dev, native_dev, nullptr, scale, S(stream));
   HIP_LAUNCHED();
   return QCD_OK;
 }
 
-qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, void* out_dev,
-                      const void* in_dev, void* stream) {
+qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, int nrhs,
+                      void* out_dev, const void* in_dev, void* stream) {
   qcd_status rc = check_gauge(g, prec);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!out_dev || !in_dev || out_dev == in_dev) return fail(QCD_ERR_ARG, "out and in must be distinct non-null buffers");
   if (op < QCD_OP_D || op > QCD_OP_HDAG) return fail(QCD_ERR_ARG, "invalid op %d", (int)op);
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   hipStream_t st = S(stream);
   if (layout == QCD_LAYOUT_NATIVE) {
-    launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, out_dev, in_dev, g->U[prec], kappa, nullptr, nullptr,
+    launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, nrhs, out_dev, in_dev, g->U[prec], kappa, nullptr, nullptr,
                   nullptr, 0, st);
     HIP_LAUNCHED();
     return QCD_OK;
   }
   if (layout != QCD_LAYOUT_CANONICAL) return fail(QCD_ERR_ARG, "invalid layout");
   Work w;
-  rc = get_work(g, 2, prec, 0, nullptr, 0, &w);
+  rc = get_work(g, 2, prec, 0, nrhs, nullptr, 0, &w);
   if (rc) return rc;
-  launch_pack_spinor(g->g, prec, w.x, (const double*)in_dev, 1.0, 0, nullptr, st);
-  launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, w.r, w.x, g->U[prec], kappa, nullptr, nullptr, nullptr, 0,
-                st);
-  launch_unpack_spinor(g->g, prec, (double*)out_dev, w.r, 1.0, st);
+  launch_pack_spinor(g->g, prec, nrhs, w.x, (const double*)in_dev, 1.0, 0, nullptr, st);
+  launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, nrhs, w.r, w.x, g->U[prec], kappa, nullptr, nullptr, nullptr,
+                0, st);
+  launch_unpack_spinor(g->g, prec, nrhs, (double*)out_dev, w.r, nullptr, 1.0, st);
   HIP_LAUNCHED();
   return QCD_OK;
 }
 
-qcd_status qcd_residual(const qcd_gauge* g, double kappa, void* r_dev, const void* x_dev, const void* b_dev,
+qcd_status qcd_residual(const qcd_gauge* g, double kappa, int nrhs, void* r_dev, const void* x_dev, const void* b_dev,
                         double* norm2, void* stream) {
   qcd_status rc = check_gauge(g, kFP64);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!r_dev || !x_dev || !b_dev) return fail(QCD_ERR_ARG, "null argument");
   hipStream_t st = S(stream);
   Work w;
-  rc = get_work(g, 1, kFP64, 1, nullptr, 0, &w);
+  rc = get_work(g, 1, kFP64, 1, nrhs, nullptr, 0, &w);
   if (rc) return rc;
-  launch_pack_spinor(g->g, kFP64, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
-  launch_pack_spinor(g->g, kFP64, w.b64, (const double*)b_dev, 1.0, 0, nullptr, st);
-  residual64(g, kappa, w, st);
-  launch_unpack_spinor(g->g, kFP64, (double*)r_dev, w.r64, 1.0, st);
+  launch_pack_spinor(g->g, kFP64, nrhs, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
+  launch_pack_spinor(g->g, kFP64, nrhs, w.b64, (const double*)b_dev, 1.0, 0, nullptr, st);
+  residual64(g, kappa, w, nullptr, st);
+  launch_unpack_spinor(g->g, kFP64, nrhs, (double*)r_dev, w.r64, nullptr, 1.0, st);
   HIP_LAUNCHED();
-  if (norm2) return read_sum(w, dslash_partial_rows(g->g), 1, norm2, st);
+  if (norm2) return read_sum(w, dslash_partial_rows(g->g, g->tune[kFP64], nrhs), 1, norm2, st);
   return QCD_OK;
 }
 
-qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, void* x_dev, const void* b_dev,
+static qcd_status status_of(int s, int iters) {
+  switch (s) {
+    case kConverged: return QCD_OK;
+    case kMaxIter: return QCD_NOT_CONVERGED;
+    case kBreakdown: return fail(QCD_ERR_BREAKDOWN, "BiCGStab breakdown after %d iterations", iters);
+    case kNonFinite: return fail(QCD_ERR_NONFINITE, "non-finite solver scalar after %d iterations", iters);
+    default: return fail(QCD_ERR_HIP, "solver stopped in an unknown state %d", s);
+  }
+}
+
+// worst of two statuses: errors (negative) beat warnings beat QCD_OK
+static qcd_status worse(qcd_status a, qcd_status b) {
+  if (a < 0 || b < 0) return a < b ? a : b;
+  return a > b ? a : b;
+}
+
+qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrhs, void* x_dev, const void* b_dev,
                         const qcd_bicgstab_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   const double t0 = now_s();
   qcd_status rc = check_gauge(g, prec);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!x_dev || !b_dev) return fail(QCD_ERR_ARG, "null vector");
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   if ((rc = check_bicg_params(p))) return rc;
   hipStream_t st = S(stream);
   Work w;
-  if ((rc = get_work(g, 1, prec, p->max_iter, ws, ws_bytes, &w))) return rc;
+  if ((rc = get_work(g, 1, prec, p->max_iter, nrhs, ws, ws_bytes, &w))) return rc;
   const Geom& G = g->g;
+  const int n = nrhs;
   const int rows = site_grid(G);
-  Scalars hs;
-  init_params(&hs, *p);
-  HIP_TRY(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, st));
+  Scalars hs[kMaxRhs];
+  for (int i = 0; i < n; i++) init_params(&hs[i], *p);
+  HIP_TRY(hipMemcpyAsync(w.sc, hs, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
   // r = r* = low(b), x0 = 0
-  launch_pack_spinor(G, prec, w.r, (const double*)b_dev, 1.0, p->ftz, w.partials, st);
-  HIP_TRY(hipMemcpyAsync(w.rstar, w.r, spinor_bytes(G, prec), hipMemcpyDeviceToDevice, st));
-  launch_bicg_init(w.sc, w.partials, rows, st);
+  launch_pack_spinor(G, prec, n, w.r, (const double*)b_dev, 1.0, p->ftz, w.partials, st);
+  HIP_TRY(hipMemcpyAsync(w.rstar, w.r, n * spinor_bytes(G, prec), hipMemcpyDeviceToDevice, st));
+  launch_bicg_init(n, w.sc, w.partials, rows, st);
   HIP_LAUNCHED();
   if ((rc = bicg_loop(g, prec, kappa, w, *p, st))) return rc;
-  const Scalars sc = *g->host_sc;
-  const int iters = sc.iter;
-  if (iters > 0) {
-    launch_unpack_spinor(G, prec, (double*)x_dev, w.x, sc.xscale / sc.lambda_cum, st);
-  } else {
-    HIP_TRY(hipMemsetAsync(x_dev, 0, (size_t)G.Vh * 2 * 12 * 16, st));
+  Scalars sc[kMaxRhs];
+  memcpy(sc, g->host_sc, sizeof(Scalars) * n);
+  // x = xscale X / lambda' (zero for a right-hand side that made no step)
+  double scales[kMaxRhs];
+  for (int i = 0; i < n; i++) {
+    scales[i] = sc[i].iter > 0 ? sc[i].xscale / sc[i].lambda_cum : 0.0;
+    if (sc[i].iter == 0)  // x of a right-hand side without a step was never written
+      launch_zero(G, prec, 1, (char*)w.x + i * spinor_bytes(G, prec), st);
   }
+  HIP_TRY(hipMemcpyAsync(w.scale, scales, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  launch_unpack_spinor(G, prec, n, (double*)x_dev, w.x, w.scale, 1.0, st);
   HIP_LAUNCHED();
-  // FP64 true residual of the returned solution
-  double r2 = 0, b2 = 0;
-  launch_pack_spinor(G, kFP64, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
-  if ((rc = read_sum(w, rows, 1, &b2, st))) return rc;
-  launch_pack_spinor(G, kFP64, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
-  residual64(g, kappa, w, st);
-  if ((rc = read_sum(w, dslash_partial_rows(G), 1, &r2, st))) return rc;
-  if (info) {
-    info->outer_iters = 0;
-    info->inner_iters = iters;
-    info->matvec_low = 2 * iters;
-    info->matvec_fp64 = 1;
-    info->true_rel_residual = b2 > 0 ? sqrt(r2 / b2) : 0.0;
-    info->inner_status = sc.status;
-    info->first_shat_over_s = 1.0;
-    info->history_len = 0;
-    copy_history(info, w, iters, sc.bnorm2, st);
-    info->seconds = now_s() - t0;
+  // FP64 true residual of the returned solutions
+  double r2[kMaxRhs], b2[kMaxRhs];
+  launch_pack_spinor(G, kFP64, n, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
+  if ((rc = read_sum(w, rows, 1, b2, st))) return rc;
+  launch_pack_spinor(G, kFP64, n, w.x64, (const double*)x_dev, 1.0, 0, nullptr, st);
+  residual64(g, kappa, w, nullptr, st);
+  if ((rc = read_sum(w, dslash_partial_rows(G, g->tune[kFP64], n), 1, r2, st))) return rc;
+  qcd_status result = QCD_OK;
+  for (int i = 0; i < n; i++) {
+    if (info) {
+      qcd_solve_info* in = info + i;
+      in->outer_iters = 0;
+      in->inner_iters = sc[i].iter;
+      in->matvec_low = 2 * sc[i].iter;
+      in->matvec_fp64 = 1;
+      in->true_rel_residual = b2[i] > 0 ? sqrt(r2[i] / b2[i]) : 0.0;
+      in->inner_status = sc[i].status;
+      in->first_shat_over_s = 1.0;
+      in->history_len = 0;
+      copy_history(in, w, i, sc[i].iter, sc[i].bnorm2, st);
+      in->seconds = now_s() - t0;
+    }
+    result = worse(result, status_of(sc[i].status, sc[i].iter));
   }
-  switch (sc.status) {
-    case kConverged: return QCD_OK;
-    case kMaxIter: return QCD_NOT_CONVERGED;
-    case kBreakdown: return fail(QCD_ERR_BREAKDOWN, "BiCGStab breakdown after %d iterations", iters);
-    case kNonFinite: return fail(QCD_ERR_NONFINITE, "non-finite solver scalar after %d iterations", iters);
-    default: return fail(QCD_ERR_HIP, "solver stopped in an unknown state %d", sc.status);
-  }
+  return result;
 }
 
-qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, void* x_dev, const void* b_dev, const qcd_ir_params* p,
-                              qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
+                              const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   const double t0 = now_s();
   if (!p) return fail(QCD_ERR_ARG, "null parameters");
   qcd_status rc = check_gauge(g, p->inner_prec);
   if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
   if (!x_dev || !b_dev) return fail(QCD_ERR_ARG, "null vector");
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   if (!(p->tol > 0) || p->max_outer <= 0 || !(p->s > 0)) return fail(QCD_ERR_ARG, "tol > 0, max_outer > 0, s > 0 required");
   if ((rc = check_bicg_params(&p->inner))) return rc;
   const int prec = p->inner_prec;
+  const int n = nrhs;
   hipStream_t st = S(stream);
   Work w;
-  if ((rc = get_work(g, 0, prec, p->inner.max_iter, ws, ws_bytes, &w))) return rc;
+  if ((rc = get_work(g, 0, prec, p->inner.max_iter, n, ws, ws_bytes, &w))) return rc;
   const Geom& G = g->g;
   const int rows = site_grid(G);
-  Scalars hs;
-  init_params(&hs, p->inner);
-  HIP_TRY(hipMemcpyAsync(w.sc, &hs, sizeof(Scalars), hipMemcpyHostToDevice, st));
+  const int drows64 = dslash_partial_rows(G, g->tune[kFP64], n);
+  Scalars hs[kMaxRhs];
+  for (int i = 0; i < n; i++) {
+    init_params(&hs[i], p->inner);
+    hs[i].out_tol = p->tol;
+  }
+  HIP_TRY(hipMemcpyAsync(w.sc, hs, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
   // b in the native FP64 layout; r = b, x = 0
-  launch_pack_spinor(G, kFP64, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
-  launch_outer_residual_norm(w.sc, w.partials, rows, p->s, st);
-  HIP_TRY(hipMemcpyAsync(w.r64, w.b64, spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
-  launch_zero(G, kFP64, w.x64, st);
+  launch_pack_spinor(G, kFP64, n, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
+  launch_outer_residual_norm(n, w.sc, w.partials, rows, p->s, st);
+  HIP_TRY(hipMemcpyAsync(w.r64, w.b64, n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
+  launch_zero(G, kFP64, n, w.x64, st);
   HIP_LAUNCHED();
   if ((rc = read_scalars(g, w, st))) return rc;
-  const double bn = g->host_sc->out_rnorm;
-  if (info) {
-    info->history_len = 0;
-    info->inner_iters = info->matvec_low = info->matvec_fp64 = info->outer_iters = 0;
-    info->first_shat_over_s = 0;
-  }
-  int outer = 0, inner_total = 0, mv64 = 0, last_status = kConverged;
-  qcd_status result = QCD_OK;
-  double rn = bn;
-  if (bn == 0.0 || !std::isfinite(bn)) {
-    launch_zero(G, kFP64, w.x64, st);
-    if (!std::isfinite(bn)) result = fail(QCD_ERR_ARG, "non-finite right-hand side");
-    rn = bn;
-  } else {
-    while (true) {
-      if (rn / bn <= p->tol) break;
-      if (outer >= p->max_outer) { result = QCD_NOT_CONVERGED; break; }
-      // y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start
-      launch_convert(G, prec, w.sc, (const double*)w.r64, w.r, w.rstar, w.x, w.partials, p->inner.ftz, st);
-      launch_convert_finish(w.sc, w.partials, rows, p->recalc_shat, p->s, st);
-      HIP_LAUNCHED();
-      if ((rc = bicg_loop(g, prec, kappa, w, p->inner, st))) return rc;
-      const Scalars sc = *g->host_sc;
-      if (info && outer == 0) info->first_shat_over_s = sc.shat / p->s;
-      if (info && info->zeros && outer < info->outer_history_cap) info->zeros[outer] = sc.zeros;
-      copy_history(info, w, sc.iter, sc.bnorm2, st);
-      inner_total += sc.iter;
-      last_status = sc.status;
-      if (sc.status == kNonFinite || sc.iter == 0) {
-        // no usable correction from this step
-        result = fail(sc.status == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
-                      "inner solve failed (status %d) in refinement step %d", sc.status, outer);
-        break;
-      }
-      // x += (|r| / s^) double(t~); r = b - D x in FP64
-      launch_correct(G, prec, w.sc, (double*)w.x64, w.x, st);
-      residual64(g, kappa, w, st);
-      launch_outer_residual_norm(w.sc, w.partials, dslash_partial_rows(G), p->s, st);
-      HIP_LAUNCHED();
-      mv64++;
-      outer++;
-      if ((rc = read_scalars(g, w, st))) return rc;
-      rn = g->host_sc->out_rnorm;
-      if (info && info->outer_history && outer - 1 < info->outer_history_cap) info->outer_history[outer - 1] = rn / bn;
-      if (!std::isfinite(rn)) { result = fail(QCD_ERR_NONFINITE, "non-finite outer residual"); break; }
+  double bn[kMaxRhs], rn[kMaxRhs];
+  int outer[kMaxRhs], inner_total[kMaxRhs], last_status[kMaxRhs];
+  qcd_status result[kMaxRhs];
+  bool any = false;
+  for (int i = 0; i < n; i++) {
+    bn[i] = rn[i] = g->host_sc[i].out_rnorm;
+    outer[i] = inner_total[i] = 0;
+    last_status[i] = kConverged;
+    result[i] = QCD_OK;
+    if (!std::isfinite(bn[i])) result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
+    if (info) {
+      info[i].history_len = 0;
+      info[i].first_shat_over_s = 0;
     }
+    any |= g->host_sc[i].outer_active && std::isfinite(bn[i]);
   }
-  launch_unpack_spinor(G, kFP64, (double*)x_dev, w.x64, 1.0, st);
+  if (!std::isfinite(bn[0]) && n == 1) any = false;
+  int step = 0;
+  while (any) {
+    if (step >= p->max_outer) {
+      for (int i = 0; i < n; i++)
+        if (g->host_sc[i].outer_active) result[i] = worse(result[i], QCD_NOT_CONVERGED);
+      break;
+    }
+    // y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start (right-hand
+    // sides that met the tolerance are skipped by the kernels)
+    launch_convert(G, prec, n, w.sc, (const double*)w.r64, w.r, w.rstar, w.partials, p->inner.ftz, st);
+    launch_convert_finish(n, w.sc, w.partials, rows, p->recalc_shat, p->s, st);
+    HIP_LAUNCHED();
+    if ((rc = bicg_loop(g, prec, kappa, w, p->inner, st))) return rc;
+    Scalars sc[kMaxRhs];
+    memcpy(sc, g->host_sc, sizeof(Scalars) * n);
+    for (int i = 0; i < n; i++) {
+      if (!sc[i].outer_active) continue;
+      if (info && outer[i] == 0) info[i].first_shat_over_s = sc[i].shat / p->s;
+      if (info && info[i].zeros && outer[i] < info[i].outer_history_cap) info[i].zeros[outer[i]] = sc[i].zeros;
+      copy_history(info ? info + i : nullptr, w, i, sc[i].iter, sc[i].bnorm2, st);
+      inner_total[i] += sc[i].iter;
+      last_status[i] = sc[i].status;
+      if (sc[i].status == kNonFinite || sc[i].iter == 0)
+        result[i] = fail(sc[i].status == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
+                         "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
+                         sc[i].status, outer[i]);
+    }
+    // x += (|r| / s^) double(t~); r = b - D x in FP64 (skipped where not refining)
+    launch_correct(G, prec, n, w.sc, (double*)w.x64, w.x, st);
+    residual64(g, kappa, w, nullptr, st);
+    launch_outer_residual_norm(n, w.sc, w.partials, drows64, p->s, st);
+    HIP_LAUNCHED();
+    if ((rc = read_scalars(g, w, st))) return rc;
+    any = false;
+    for (int i = 0; i < n; i++) {
+      if (!sc[i].outer_active) continue;
+      outer[i]++;
+      rn[i] = g->host_sc[i].out_rnorm;
+      if (info && info[i].outer_history && outer[i] - 1 < info[i].outer_history_cap)
+        info[i].outer_history[outer[i] - 1] = rn[i] / bn[i];
+      if (!std::isfinite(rn[i])) result[i] = fail(QCD_ERR_NONFINITE, "non-finite outer residual");
+      if (result[i] < 0) {  // stop refining this right-hand side
+        g->host_sc[i].outer_active = 0;
+        HIP_TRY(hipMemcpyAsync(&w.sc[i].outer_active, &g->host_sc[i].outer_active, sizeof(int),
+                               hipMemcpyHostToDevice, st));
+      }
+      any |= g->host_sc[i].outer_active != 0;
+    }
+    step++;
+  }
+  launch_unpack_spinor(G, kFP64, n, (double*)x_dev, w.x64, nullptr, 1.0, st);
   HIP_LAUNCHED();
   HIP_TRY(hipStreamSynchronize(st));
-  if (info) {
-    info->outer_iters = outer;
-    info->inner_iters = inner_total;
-    info->matvec_low = 2 * inner_total;
-    info->matvec_fp64 = mv64;
-    info->true_rel_residual = bn > 0 ? rn / bn : 0.0;
-    info->inner_status = last_status;
-    info->seconds = now_s() - t0;
+  qcd_status res = QCD_OK;
+  for (int i = 0; i < n; i++) {
+    if (info) {
+      info[i].outer_iters = outer[i];
+      info[i].inner_iters = inner_total[i];
+      info[i].matvec_low = 2 * inner_total[i];
+      info[i].matvec_fp64 = outer[i];
+      info[i].true_rel_residual = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+      info[i].inner_status = last_status[i];
+      info[i].seconds = now_s() - t0;
+    }
+    res = worse(res, result[i]);
   }
-  return result;
+  return res;
 }
 
 }  // extern "C"

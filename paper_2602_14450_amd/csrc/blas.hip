@@ -1,20 +1,20 @@
 // Streaming vector kernels of the rescaled BiCGStab (Alg. 4 / Alg. 5) and
 // the rescaled iterative refinement (Alg. 2 / Alg. 3), plus layout and
-// precision conversions.  One thread handles the 12 complex components of
-// one site; every wave-wide access is a contiguous run of the native layout.
-// Reductions are formed from the stored values and written as per-block FP64
-// partials; the single-block finish kernels sum them in a fixed order and
-// advance the FP64 scalar recurrences held in device memory.
+// precision conversions, for n right-hand sides at once (grid.y indexes the
+// right-hand side; vectors are n native spinors back to back).  Reductions
+// are formed from the stored values and written as per-block FP64 partials;
+// the finish kernels (one block per right-hand side) sum them in a fixed
+// order and advance the FP64 scalar recurrences held in device memory.
 #include "common.h"
 #include "internal.h"
 
 namespace qcd {
 
 // Site-ordered kernels (layout / precision conversions) use one thread per
-// site; the BLAS-1 kernels walk the native vectors as flat arrays of 16-byte
-// granules with a fixed grid, so their partial-sum rows number at most
-// kFlatBlocks.
-constexpr int kFlatBlocks = 2048;
+// site; the BLAS-1 kernels walk each native vector as a flat array of
+// 16-byte granules with a fixed grid, so their partial-sum rows number at
+// most kFlatBlocks per right-hand side.
+constexpr int kFlatBlocks = 1024;
 int site_grid(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 template <typename S> static int flat_grid(const Geom& g) {
   const size_t n = spinor_granules<S>(g);
@@ -38,6 +38,7 @@ __device__ __forceinline__ int64_t lex_site(const Geom& g, int par, int h) {
   Coord c = decode(g, par, h);
   return c.x + (int64_t)g.L[0] * (c.y + (int64_t)g.L[1] * (c.z + (int64_t)g.L[2] * c.t));
 }
+__device__ __forceinline__ int64_t volume(const Geom& g) { return 2 * (int64_t)g.Vh; }
 
 // ---------------------------------------------------------------------------
 // Layout conversions
@@ -57,12 +58,16 @@ __global__ __launch_bounds__(256) void k_pack_links(Geom g, S* __restrict__ dst,
   }
 }
 
-// dst = round(scale * canon); partial |dst|^2 per block (from stored values).
+// dst = round(scale * canon) for right-hand side blockIdx.y; partial
+// |dst|^2 per block from the stored values.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst, const double* __restrict__ src,
                                                      double scale, int ftz, double* __restrict__ partials) {
   using T = typename Traits<S>::T;
   SiteId id = site_id(g);
+  const int rhs = blockIdx.y;
+  dst += (size_t)rhs * spinor_elems(g);
+  src += (size_t)rhs * volume(g) * 24;
   double red[1] = {0.0};
   if (id.valid) {
     const int64_t s = lex_site(g, id.par, id.h);
@@ -76,14 +81,19 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst
     }
     red[0] = acc;
   }
-  if (partials) block_reduce_store<1>(red, partials, blockIdx.x);
+  if (partials) block_reduce_store<1>(red, partials + (size_t)rhs * gridDim.x, blockIdx.x);
 }
 
+// canon = scale * double(src) with scale = scale_dev[rhs] (if given) or scale.
 template <typename S>
 __global__ __launch_bounds__(256) void k_unpack_spinor(Geom g, double* __restrict__ dst, const S* __restrict__ src,
-                                                       double scale) {
+                                                       const double* __restrict__ scale_dev, double scale) {
   SiteId id = site_id(g);
   if (!id.valid) return;
+  const int rhs = blockIdx.y;
+  src += (size_t)rhs * spinor_elems(g);
+  dst += (size_t)rhs * volume(g) * 24;
+  if (scale_dev) scale = scale_dev[rhs];
   const int64_t s = lex_site(g, id.par, id.h);
   cx<typename Traits<S>::T> f[12];
   load_site(src, g, id.par, id.h, f);
@@ -97,6 +107,7 @@ template <typename S>
 __global__ __launch_bounds__(256) void k_zero(Geom g, S* __restrict__ dst) {
   using Gr = typename Lay<S>::Gran;
   const size_t n = spinor_granules<S>(g);
+  dst += (size_t)blockIdx.y * spinor_elems(g);
   Gr z;
   for (int c = 0; c < Lay<S>::C; c++) z.s[c] = Traits<S>::pack(cx<typename Traits<S>::T>(0, 0), 0);
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
@@ -110,6 +121,7 @@ __global__ __launch_bounds__(256) void k_zero(Geom g, S* __restrict__ dst) {
 #define QCD_FLAT_LOOP(S) \
   for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x, n_ = spinor_granules<S>(g); e < n_; \
        e += (size_t)gridDim.x * 256)
+#define QCD_RHS_OFFSET(S, ptr) ptr += (size_t)blockIdx.y * spinor_elems(g)
 
 template <typename S> using GrOf = typename Lay<S>::Gran;
 
@@ -117,11 +129,13 @@ template <typename S> using GrOf = typename Lay<S>::Gran;
 // p and v by gamma folded into the coefficient (pcoef = beta * gamma).  In
 // the first iteration p = r (p = v = 0 initially).
 template <typename S>
-__global__ __launch_bounds__(256) void k_p_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ p,
+__global__ __launch_bounds__(256) void k_p_update(Geom g, const Scalars* __restrict__ scal, S* __restrict__ p,
                                                   const S* __restrict__ v, const S* __restrict__ r, int ftz) {
   using T = typename Traits<S>::T;
   using Gr = GrOf<S>;
+  const Scalars* sc = scal + blockIdx.y;
   if (!sc->active) return;
+  QCD_RHS_OFFSET(S, p); QCD_RHS_OFFSET(S, v); QCD_RHS_OFFSET(S, r);
   const int first = sc->first;
   const cx<T> c((T)sc->pcoef[0], (T)sc->pcoef[1]);
   const cx<T> w((T)sc->omega_prev[0], (T)sc->omega_prev[1]);
@@ -146,11 +160,13 @@ __global__ __launch_bounds__(256) void k_p_update(Geom g, const Scalars* __restr
 
 // r := r - alpha v   (the vector s of the standard formulation)
 template <typename S>
-__global__ __launch_bounds__(256) void k_s_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ r,
+__global__ __launch_bounds__(256) void k_s_update(Geom g, const Scalars* __restrict__ scal, S* __restrict__ r,
                                                   const S* __restrict__ v, int ftz) {
   using T = typename Traits<S>::T;
   using Gr = GrOf<S>;
+  const Scalars* sc = scal + blockIdx.y;
   if (!sc->active) return;
+  QCD_RHS_OFFSET(S, r); QCD_RHS_OFFSET(S, v);
   const cx<T> a((T)sc->alpha[0], (T)sc->alpha[1]);
   QCD_FLAT_LOOP(S) {
     if (!gran_valid<S>(g, e)) continue;
@@ -169,13 +185,15 @@ __global__ __launch_bounds__(256) void k_s_update(Geom g, const Scalars* __restr
 // stored values |r|^2, (r*, r) and |x|^2.  Each thread accumulates in the
 // arithmetic precision, the block and the finish kernel in FP64.
 template <typename S>
-__global__ __launch_bounds__(256) void k_xr_update(Geom g, const Scalars* __restrict__ sc, S* __restrict__ x,
+__global__ __launch_bounds__(256) void k_xr_update(Geom g, const Scalars* __restrict__ scal, S* __restrict__ x,
                                                    S* __restrict__ r, const S* __restrict__ t,
                                                    const S* __restrict__ p, const S* __restrict__ rstar,
                                                    double* __restrict__ partials, int ftz) {
   using T = typename Traits<S>::T;
   using Gr = GrOf<S>;
+  const Scalars* sc = scal + blockIdx.y;
   if (!sc->active) return;
+  QCD_RHS_OFFSET(S, x); QCD_RHS_OFFSET(S, r); QCD_RHS_OFFSET(S, t); QCD_RHS_OFFSET(S, p); QCD_RHS_OFFSET(S, rstar);
   const int first = sc->first;
   const T xs = (T)sc->xscale, xc = (T)sc->xcoef, gp = (T)sc->gamma_pred;
   const cx<T> om((T)sc->omega[0], (T)sc->omega[1]);
@@ -210,7 +228,7 @@ __global__ __launch_bounds__(256) void k_xr_update(Geom g, const Scalars* __rest
     reinterpret_cast<Gr*>(r)[e] = ro;
   }
   double red[5] = {(double)ww, (double)rr, (double)rsr_re, (double)rsr_im, (double)xx};
-  block_reduce_store<5>(red, partials, blockIdx.x);
+  block_reduce_store<5>(red, partials + (size_t)blockIdx.y * gridDim.x * 5, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,13 +237,17 @@ __global__ __launch_bounds__(256) void k_xr_update(Geom g, const Scalars* __rest
 // the arithmetic precision per site (FP64 across sites), and the number of
 // zero reals in y~ (the underflow diagnostic of Fig. 9).
 template <typename S>
-__global__ __launch_bounds__(256) void k_convert(Geom g, const Scalars* __restrict__ sc, const double2* __restrict__ r64,
-                                                 S* __restrict__ y, S* __restrict__ rstar,
-                                                 double* __restrict__ partials, int ftz) {
+__global__ __launch_bounds__(256) void k_convert(Geom g, const Scalars* __restrict__ scal,
+                                                 const double2* __restrict__ r64, S* __restrict__ y,
+                                                 S* __restrict__ rstar, double* __restrict__ partials, int ftz) {
   using T = typename Traits<S>::T;
   using Gr = GrOf<S>;
   constexpr int C = Lay<S>::C;
+  const Scalars* sc = scal + blockIdx.y;
+  if (!sc->outer_active) return;
   SiteId id = site_id(g);
+  r64 += (size_t)blockIdx.y * spinor_elems(g);
+  QCD_RHS_OFFSET(S, y); QCD_RHS_OFFSET(S, rstar);
   double red[2] = {0, 0};
   if (id.valid) {
     const double sc_ = sc->out_scale;
@@ -252,15 +274,20 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const Scalars* __restri
     red[0] = acc;
     red[1] = zeros;
   }
-  block_reduce_store<2>(red, partials, blockIdx.x);
+  block_reduce_store<2>(red, partials + (size_t)blockIdx.y * gridDim.x * 2, blockIdx.x);
 }
 
-// x64 := x64 + (|r| / s^) * double(x_inner), with x_inner = xscale * X / lambda'.
+// x64 := x64 + (|r| / s^) * double(x_inner), with x_inner = xscale * X / lambda'
+// (skipped for right-hand sides whose inner solve made no step).
 template <typename S>
-__global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restrict__ sc, double2* __restrict__ x64,
+__global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restrict__ scal, double2* __restrict__ x64,
                                                  const S* __restrict__ xlo) {
+  const Scalars* sc = scal + blockIdx.y;
+  if (!sc->outer_active || sc->iter == 0 || sc->status == kNonFinite) return;
   SiteId id = site_id(g);
   if (!id.valid) return;
+  x64 += (size_t)blockIdx.y * spinor_elems(g);
+  QCD_RHS_OFFSET(S, xlo);
   const double c = sc->out_rnorm / sc->shat * sc->xscale / sc->lambda_cum;
   cx<typename Traits<S>::T> f[12];
   cx<double> xo[12];
@@ -274,7 +301,8 @@ __global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Finish kernels: one block sums the partial rows, thread 0 updates scalars.
+// Finish kernels: block b sums the partial rows of right-hand side b, thread
+// 0 updates that right-hand side's scalars.
 
 __device__ __forceinline__ cx<double> cd(const double* a) { return cx<double>(a[0], a[1]); }
 __device__ __forceinline__ void setc(double* a, cx<double> v) { a[0] = v.re; a[1] = v.im; }
@@ -312,18 +340,21 @@ __device__ void bicg_init_dev(Scalars* sc, double bn2) {
   else if (bn2 <= sc->tol2 * bn2) stop(sc, kConverged);
 }
 
-__global__ void k_bicg_init(Scalars* sc, const double* partials, int nrows) {
-  double s[1];
-  finish_sum<1>(partials, nrows, s);
-  if (threadIdx.x == 0) bicg_init_dev(sc, s[0]);
+#define QCD_FINISH_BEGIN(NV)                                                  \
+  Scalars* sc = scal + blockIdx.x;                                            \
+  double s[NV];                                                               \
+  finish_sum<NV>(partials + (size_t)blockIdx.x * nrows * NV, nrows, s);       \
+  if (threadIdx.x != 0) return;
+
+__global__ void k_bicg_init(Scalars* scal, const double* partials, int nrows) {
+  QCD_FINISH_BEGIN(1)
+  bicg_init_dev(sc, s[0]);
 }
 
 // alpha = rho / (r*, v)
-__global__ void k_alpha(Scalars* sc, const double* partials, int nrows) {
-  if (!sc->active) return;
-  double s[2];
-  finish_sum<2>(partials, nrows, s);
-  if (threadIdx.x != 0) return;
+__global__ void k_alpha(Scalars* scal, const double* partials, int nrows) {
+  if (!scal[blockIdx.x].active) return;
+  QCD_FINISH_BEGIN(2)
   const cx<double> rv(s[0], s[1]);
   if (rv.re == 0.0 && rv.im == 0.0) { stop(sc, kBreakdown); return; }
   const cx<double> a = cdiv(cd(sc->rho), rv);
@@ -334,11 +365,9 @@ __global__ void k_alpha(Scalars* sc, const double* partials, int nrows) {
 // omega = (t,s)/(t,t) with the omega_0 prescription; the x-update factor
 // lambda'/gamma'; and the factor that rescales the new residual to norm
 // sigma, from |s - omega t|^2 = (s,s) - 2 Re(conj(omega)(t,s)) + |omega|^2 (t,t).
-__global__ void k_omega(Scalars* sc, const double* partials, int nrows) {
-  if (!sc->active) return;
-  double s[4];
-  finish_sum<4>(partials, nrows, s);
-  if (threadIdx.x != 0) return;
+__global__ void k_omega(Scalars* scal, const double* partials, int nrows) {
+  if (!scal[blockIdx.x].active) return;
+  QCD_FINISH_BEGIN(4)
   const cx<double> ts(s[0], s[1]);
   const double tt = s[2], ss = s[3];
   if (!(tt > 0.0)) {  // t = A s = 0 means s = 0: the previous step solved the system
@@ -369,11 +398,9 @@ __global__ void k_omega(Scalars* sc, const double* partials, int nrows) {
 
 // End of an iteration: gamma (applied or recalculated), rho' = gamma rho,
 // gamma' *= gamma, the next rho and beta, lambda for Alg. 5, the stopping test.
-__global__ void k_iter_end(Scalars* sc, const double* partials, int nrows, double* history) {
-  if (!sc->active) return;
-  double s[5];
-  finish_sum<5>(partials, nrows, s);
-  if (threadIdx.x != 0) return;
+__global__ void k_iter_end(Scalars* scal, const double* partials, int nrows, double* history, int hist_stride) {
+  if (!scal[blockIdx.x].active) return;
+  QCD_FINISH_BEGIN(5)
   const double ww = s[0], rr = s[1], xx = s[4];
   const cx<double> rsr(s[2], s[3]);
   double gamma = 1.0;
@@ -403,7 +430,7 @@ __global__ void k_iter_end(Scalars* sc, const double* partials, int nrows, doubl
   sc->rnorm2 = rr;
   sc->first = 0;
   const double res2 = rr / (sc->gamma_cum * sc->gamma_cum);
-  if (history && sc->iter < sc->max_iter) history[sc->iter] = res2;
+  if (history && sc->iter < sc->max_iter) history[(size_t)blockIdx.x * hist_stride + sc->iter] = res2;
   sc->iter += 1;
   if (!isfinite(res2) || !finite_c(beta) || !isfinite(sc->lambda_cum) || !isfinite(sc->gamma_cum)) {
     // an exact zero residual ends the run as converged
@@ -416,27 +443,33 @@ __global__ void k_iter_end(Scalars* sc, const double* partials, int nrows, doubl
   if (sc->iter >= sc->max_iter) stop(sc, kMaxIter);
 }
 
-// Outer step: |r| of the FP64 residual and the rescaling factor s / |r|.
-__global__ void k_outer_norm(Scalars* sc, const double* partials, int nrows, double s_target) {
-  double s[1];
-  finish_sum<1>(partials, nrows, s);
-  if (threadIdx.x != 0) return;
+// Outer step: |r| of the FP64 residual, the rescaling factor s / |r| and the
+// outer stopping test (|r| <= tol |b|); the first call (from the packing of
+// b) also records |b|.
+__global__ void k_outer_norm(Scalars* scal, const double* partials, int nrows, double s_target) {
+  if (!scal[blockIdx.x].outer_active) return;
+  QCD_FINISH_BEGIN(1)
   sc->out_rnorm = sqrt(s[0]);
+  if (sc->out_bnorm < 0.0) sc->out_bnorm = sc->out_rnorm;
   sc->out_scale = (s[0] > 0.0) ? s_target / sc->out_rnorm : 0.0;
+  if (!(sc->out_rnorm > sc->out_tol * sc->out_bnorm)) sc->outer_active = 0;
 }
 
 // After the conversion: s^ (Alg. 3) and the start of the inner BiCGStab.
-__global__ void k_convert_finish(Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target) {
-  double s[2];
-  finish_sum<2>(partials, nrows, s);
-  if (threadIdx.x != 0) return;
+__global__ void k_convert_finish(Scalars* scal, const double* partials, int nrows, int recalc_shat, double s_target) {
+  if (!scal[blockIdx.x].outer_active) {
+    if (threadIdx.x == 0) { scal[blockIdx.x].active = 0; scal[blockIdx.x].iter = 0; }
+    return;
+  }
+  QCD_FINISH_BEGIN(2)
   sc->shat = recalc_shat ? sqrt(s[0]) : s_target;
   sc->zeros = s[1];
   bicg_init_dev(sc, s[0]);
 }
 
 __global__ void k_finish_sum_any(const double* partials, int nrows, int nv, double* out) {
-  // generic: sums up to 8 columns (used for norms the host asks for)
+  // generic: sums up to 8 columns of right-hand side blockIdx.x
+  partials += (size_t)blockIdx.x * nrows * nv;
   double acc[8];
   for (int i = 0; i < 8; i++) acc[i] = 0;
   for (int r = threadIdx.x; r < nrows; r += blockDim.x)
@@ -453,7 +486,7 @@ __global__ void k_finish_sum_any(const double* partials, int nrows, int nv, doub
     for (int i = 0; i < nv; i++) {
       double s = 0;
       for (int w = 0; w < (int)(blockDim.x >> 6); w++) s += red[i][w];
-      out[i] = s;
+      out[(size_t)blockIdx.x * nv + i] = s;
     }
   }
 }
@@ -476,103 +509,110 @@ void launch_pack_links(const Geom& g, int prec, void* dst, const double* U, hipS
 }
 
 template <typename S>
-static void pack_spinor_t(const Geom& g, void* dst, const double* c, double scale, int ftz, double* partials,
+static void pack_spinor_t(const Geom& g, int n, void* dst, const double* c, double scale, int ftz, double* partials,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_spinor<S>, dim3(site_grid(g)), dim3(256), 0, st, g, (S*)dst, c, scale, ftz, partials);
+  hipLaunchKernelGGL(k_pack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, (S*)dst, c, scale, ftz, partials);
 }
-void launch_pack_spinor(const Geom& g, int prec, void* dst, const double* canon, double scale, int ftz,
+void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double* canon, double scale, int ftz,
                         double* partials, hipStream_t st) {
-  QCD_DISPATCH(prec, pack_spinor_t, g, dst, canon, scale, ftz, partials, st);
+  QCD_DISPATCH(prec, pack_spinor_t, g, n, dst, canon, scale, ftz, partials, st);
 }
 
 template <typename S>
-static void unpack_spinor_t(const Geom& g, double* c, const void* src, double scale, hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3(site_grid(g)), dim3(256), 0, st, g, c, (const S*)src, scale);
+static void unpack_spinor_t(const Geom& g, int n, double* c, const void* src, const double* sd, double scale,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, c, (const S*)src, sd, scale);
 }
-void launch_unpack_spinor(const Geom& g, int prec, double* canon, const void* src, double scale, hipStream_t st) {
-  QCD_DISPATCH(prec, unpack_spinor_t, g, canon, src, scale, st);
+void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
+                          double scale, hipStream_t st) {
+  QCD_DISPATCH(prec, unpack_spinor_t, g, n, canon, src, scale_dev, scale, st);
 }
 
-template <typename S> static void zero_t(const Geom& g, void* dst, hipStream_t st) {
-  hipLaunchKernelGGL(k_zero<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, (S*)dst);
+template <typename S> static void zero_t(const Geom& g, int n, void* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero<S>, dim3(flat_grid<S>(g), n), dim3(256), 0, st, g, (S*)dst);
 }
-void launch_zero(const Geom& g, int prec, void* dst, hipStream_t st) { QCD_DISPATCH(prec, zero_t, g, dst, st); }
+void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st) {
+  QCD_DISPATCH(prec, zero_t, g, n, dst, st);
+}
 
-void launch_bicg_init(Scalars* sc, const double* partials, int nrows, hipStream_t st) {
-  hipLaunchKernelGGL(k_bicg_init, dim3(1), dim3(1024), 0, st, sc, partials, nrows);
+void launch_bicg_init(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st) {
+  hipLaunchKernelGGL(k_bicg_init, dim3(n), dim3(1024), 0, st, sc, partials, nrows);
 }
 
 template <typename S>
-static void p_update_t(const Geom& g, Scalars* sc, void* p, const void* v, const void* r, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_p_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)p, (const S*)v,
+static void p_update_t(const Geom& g, int n, Scalars* sc, void* p, const void* v, const void* r, int ftz,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_p_update<S>, dim3(flat_grid<S>(g), n), dim3(256), 0, st, g, sc, (S*)p, (const S*)v,
                      (const S*)r, ftz);
 }
-void launch_p_update(const Geom& g, int prec, Scalars* sc, void* p, const void* v, const void* r, int ftz,
+void launch_p_update(const Geom& g, int prec, int n, Scalars* sc, void* p, const void* v, const void* r, int ftz,
                      hipStream_t st) {
-  QCD_DISPATCH(prec, p_update_t, g, sc, p, v, r, ftz, st);
+  QCD_DISPATCH(prec, p_update_t, g, n, sc, p, v, r, ftz, st);
 }
 
-void launch_alpha(Scalars* sc, const double* partials, int nrows, hipStream_t st) {
-  hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, st, sc, partials, nrows);
-}
-
-template <typename S>
-static void s_update_t(const Geom& g, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_s_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)r, (const S*)v, ftz);
-}
-void launch_s_update(const Geom& g, int prec, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
-  QCD_DISPATCH(prec, s_update_t, g, sc, r, v, ftz, st);
-}
-
-void launch_omega(Scalars* sc, const double* partials, int nrows, hipStream_t st) {
-  hipLaunchKernelGGL(k_omega, dim3(1), dim3(1024), 0, st, sc, partials, nrows);
+void launch_alpha(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st) {
+  hipLaunchKernelGGL(k_alpha, dim3(n), dim3(1024), 0, st, sc, partials, nrows);
 }
 
 template <typename S>
-static void xr_update_t(const Geom& g, Scalars* sc, void* x, void* r, const void* t, const void* p, const void* rs,
-                        double* partials, int ftz, hipStream_t st) {
-  hipLaunchKernelGGL(k_xr_update<S>, dim3(flat_grid<S>(g)), dim3(256), 0, st, g, sc, (S*)x, (S*)r, (const S*)t,
+static void s_update_t(const Geom& g, int n, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
+  hipLaunchKernelGGL(k_s_update<S>, dim3(flat_grid<S>(g), n), dim3(256), 0, st, g, sc, (S*)r, (const S*)v, ftz);
+}
+void launch_s_update(const Geom& g, int prec, int n, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st) {
+  QCD_DISPATCH(prec, s_update_t, g, n, sc, r, v, ftz, st);
+}
+
+void launch_omega(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st) {
+  hipLaunchKernelGGL(k_omega, dim3(n), dim3(1024), 0, st, sc, partials, nrows);
+}
+
+template <typename S>
+static void xr_update_t(const Geom& g, int n, Scalars* sc, void* x, void* r, const void* t, const void* p,
+                        const void* rs, double* partials, int ftz, hipStream_t st) {
+  hipLaunchKernelGGL(k_xr_update<S>, dim3(flat_grid<S>(g), n), dim3(256), 0, st, g, sc, (S*)x, (S*)r, (const S*)t,
                      (const S*)p, (const S*)rs, partials, ftz);
 }
-void launch_xr_update(const Geom& g, int prec, Scalars* sc, void* x, void* r, const void* t, const void* p,
+void launch_xr_update(const Geom& g, int prec, int n, Scalars* sc, void* x, void* r, const void* t, const void* p,
                       const void* rstar, double* partials, int ftz, hipStream_t st) {
-  QCD_DISPATCH(prec, xr_update_t, g, sc, x, r, t, p, rstar, partials, ftz, st);
+  QCD_DISPATCH(prec, xr_update_t, g, n, sc, x, r, t, p, rstar, partials, ftz, st);
 }
 
-void launch_iter_end(Scalars* sc, const double* partials, int nrows, double* history, hipStream_t st) {
-  hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1024), 0, st, sc, partials, nrows, history);
+void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, double* history, int hist_stride,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_iter_end, dim3(n), dim3(1024), 0, st, sc, partials, nrows, history, hist_stride);
 }
 
-void launch_outer_residual_norm(Scalars* sc, const double* partials, int nrows, double s_target, hipStream_t st) {
-  hipLaunchKernelGGL(k_outer_norm, dim3(1), dim3(1024), 0, st, sc, partials, nrows, s_target);
+void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_outer_norm, dim3(n), dim3(1024), 0, st, sc, partials, nrows, s_target);
 }
 
 template <typename S>
-static void convert_t(const Geom& g, Scalars* sc, const double* r64, void* y, void* rstar, double* partials, int ftz,
-                      hipStream_t st) {
-  hipLaunchKernelGGL(k_convert<S>, dim3(site_grid(g)), dim3(256), 0, st, g, sc, (const double2*)r64, (S*)y,
+static void convert_t(const Geom& g, int n, Scalars* sc, const double* r64, void* y, void* rstar, double* partials,
+                      int ftz, hipStream_t st) {
+  hipLaunchKernelGGL(k_convert<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, sc, (const double2*)r64, (S*)y,
                      (S*)rstar, partials, ftz);
 }
-void launch_convert(const Geom& g, int prec, Scalars* sc, const double* r64, void* y, void* rstar, void*,
+void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r64, void* y, void* rstar,
                     double* partials, int ftz, hipStream_t st) {
-  QCD_DISPATCH(prec, convert_t, g, sc, r64, y, rstar, partials, ftz, st);
+  QCD_DISPATCH(prec, convert_t, g, n, sc, r64, y, rstar, partials, ftz, st);
 }
 
-void launch_convert_finish(Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
+void launch_convert_finish(int n, Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_convert_finish, dim3(1), dim3(1024), 0, st, sc, partials, nrows, recalc_shat, s_target);
+  hipLaunchKernelGGL(k_convert_finish, dim3(n), dim3(1024), 0, st, sc, partials, nrows, recalc_shat, s_target);
 }
 
 template <typename S>
-static void correct_t(const Geom& g, Scalars* sc, double* x64, const void* xlo, hipStream_t st) {
-  hipLaunchKernelGGL(k_correct<S>, dim3(site_grid(g)), dim3(256), 0, st, g, sc, (double2*)x64, (const S*)xlo);
+static void correct_t(const Geom& g, int n, Scalars* sc, double* x64, const void* xlo, hipStream_t st) {
+  hipLaunchKernelGGL(k_correct<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, sc, (double2*)x64, (const S*)xlo);
 }
-void launch_correct(const Geom& g, int prec, Scalars* sc, double* x64, const void* xlo, hipStream_t st) {
-  QCD_DISPATCH(prec, correct_t, g, sc, x64, xlo, st);
+void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, const void* xlo, hipStream_t st) {
+  QCD_DISPATCH(prec, correct_t, g, n, sc, x64, xlo, st);
 }
 
-void launch_finish_sum(const double* partials, int nrows, int nv, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_sum_any, dim3(1), dim3(1024), 0, st, partials, nrows, nv, out);
+void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_sum_any, dim3(n), dim3(1024), 0, st, partials, nrows, nv, out);
 }
 
 }  // namespace qcd

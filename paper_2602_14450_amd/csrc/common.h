@@ -252,6 +252,32 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* part
   }
 }
 
+// Per-right-hand-side block reduction for blocks whose lanes interleave T
+// right-hand sides (lane = site * T + r): lane groups are reduced separately
+// and value i of right-hand side r goes to partials[(r0 + r) * rstride + row) * NV + i].
+template <int NV, int T>
+__device__ __forceinline__ void block_reduce_store_T(double (&v)[NV], double* partials, int r0, int rstride, int row) {
+  __shared__ double red[NV][T][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; i++) {
+    double a = v[i];
+#pragma unroll
+    for (int off = 32; off >= T; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (lane < T) red[i][lane][wid] = a;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < T) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      double s = 0;
+      for (int w = 0; w < nw; w++) s += red[i][threadIdx.x][w];
+      partials[((size_t)(r0 + threadIdx.x) * rstride + row) * NV + i] = s;
+    }
+  }
+}
+
 // Sum rows [0, nrows) of partials[nrows][NV] in one block, fixed order.
 // Result is valid in out[] on thread 0 after the call.
 template <int NV>

@@ -262,51 +262,78 @@ __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in,
   hop_pipe<0, DEPTH, DAG>(g, in, U, pa, buf, a);
 }
 
-// Thread -> site.  A block of 256 threads covers 128 consecutive half
-// indices in both parities (waves 0,1: first 64 of parity 0,1; waves 2,3:
-// next 64), so a link read as the forward link of one site is read as the
-// backward link of its neighbour by the same block.  With sched.mode 1 the
-// blocks are ordered so that the eight XCDs (which receive consecutive
-// workgroups in turn) each sweep their own slab of z in t-major order, which
-// keeps the t-neighbours of a slab inside that XCD's L2.
-__device__ __forceinline__ int block_h0(const DslashSched& sc) {
+// Thread -> (site, right-hand side).  A block of 256 threads is four waves:
+// waves 0 and 1 take parity 0 and 1 of the first H/2 half indices of the
+// block, waves 2 and 3 the next H/2, so the link a site reads as its forward
+// link is read as the backward link of its neighbour by the same block.
+// Within a wave, lane = s * T + r: 64/T sites times T right-hand sides, so
+// the T lanes of one site request the same link granule in one instruction.
+// With sched.mode 1 the blocks are ordered so that the eight XCDs (which
+// receive consecutive workgroups in turn) each sweep their own slab of z in t
+// order, all right-hand-side tiles of a site block back to back; this keeps
+// t-neighbours and links inside that XCD's L2.
+struct BlockPos { int h0, tile, sb; };
+__device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
   const int b = blockIdx.x;
+  BlockPos p;
   if (sc.mode == 1) {
     const int xcd = b & 7, j = b >> 3;
+    p.tile = j % sc.ntiles;
+    const int js = j / sc.ntiles;
     const int per_t = sc.zc * sc.bp;
-    const int t = j / per_t, rem = j - t * per_t;
+    const int t = js / per_t, rem = js - t * per_t;
     const int zl = rem / sc.bp, yb = rem - zl * sc.bp;
-    return ((t * sc.Lz + xcd * sc.zc + zl) * sc.bp + yb) * 128;
+    p.sb = (t * sc.Lz + xcd * sc.zc + zl) * sc.bp + yb;
+  } else {
+    p.tile = b % sc.ntiles;
+    p.sb = b / sc.ntiles;
   }
-  return b * 128;
+  p.h0 = p.sb * sc.H;
+  return p;
 }
 
-// out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues.
-template <typename S, int OP, int EPI, int DEPTH, int OCC>
+// out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues,
+// for T right-hand sides per wave (vectors of right-hand side r start at
+// r * vstride elements).
+template <typename S, int OP, int EPI, int DEPTH, int OCC, int T>
 __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, S* __restrict__ out,
                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                      const S* __restrict__ aux, double* __restrict__ partials,
-                                                     const int* __restrict__ active, int ftz) {
-  using T = typename Traits<S>::T;
-  if (active && *active == 0) return;
+                                                     const Scalars* __restrict__ scal, int ftz) {
+  using T_ = typename Traits<S>::T;
+  const BlockPos bp = block_pos(sched);
   const int tid = threadIdx.x;
-  const int par = (tid >> 6) & 1;
-  const int h = block_h0(sched) + ((tid >> 7) << 6) + (tid & 63);
+  const int lane = tid & 63, wid = tid >> 6;
+  const int r = lane % T;
+  const int rhs = bp.tile * T + r;
+  if (scal) {  // skip blocks whose right-hand sides have all stopped
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < T; i++) any |= scal[bp.tile * T + i].active != 0;
+    if (!any) return;
+  }
+  const bool live = !scal || scal[rhs].active != 0;
+  const int par = wid & 1;
+  const int h = bp.h0 + (wid >> 1) * (64 / T) + lane / T;
+  const size_t vo = (size_t)rhs * spinor_elems(g);
+  in += vo;
+  out += vo;
+  if (aux) aux += vo;
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (EPI == kEpiTS ? 4 : 1));
   double red[NV];
 #pragma unroll
   for (int i = 0; i < NV; i++) red[i] = 0.0;
-  if (h < g.Vh) {
+  if (h < g.Vh && live) {
     const Coord c = decode(g, par, h);
-    cx<T> a[4][3];
+    cx<T_> a[4][3];
 #pragma unroll
     for (int s = 0; s < 4; s++)
 #pragma unroll
-      for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T>(0, 0);
+      for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T_>(0, 0);
     hop_all<DEPTH, DAG>(g, in, U, par, h, c, a);
-    const T k = (T)kappa;
-    cx<T> o[12], ctr[12], ax[12];
+    const T_ k = (T_)kappa;
+    cx<T_> o[12], ctr[12], ax[12];
     if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(in, g, par, h, ctr);
     if constexpr (EPI == kEpiResid || EPI == kEpiDotAux) load_site(aux, g, par, h, ax);
 #pragma unroll
@@ -322,7 +349,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     using Gr = typename Lay<S>::Gran;
     constexpr int C = Lay<S>::C;
     S* ob = out + sp_block(g, par, h) + (h & 63) * C;
-    T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
 #pragma unroll
     for (int j = 0; j < Lay<S>::G; j++) {
       Gr v;
@@ -331,7 +358,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
         const int i = j * C + cc;
         v.s[cc] = Traits<S>::pack(o[i], ftz);
         if constexpr (EPI != kEpiNone) {
-          const cx<T> os = Traits<S>::load(&v.s[cc]);
+          const cx<T_> os = Traits<S>::load(&v.s[cc]);
           if constexpr (EPI == kEpiDotAux) {  // (aux, out) = sum conj(aux) out
             acc0 += ax[i].re * os.re + ax[i].im * os.im;
             acc1 += ax[i].re * os.im - ax[i].im * os.re;
@@ -351,36 +378,52 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     if constexpr (EPI == kEpiTS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
     if constexpr (EPI == kEpiResid) { red[0] = acc0; }
   }
-  if constexpr (EPI != kEpiNone) block_reduce_store<NV>(red, partials, blockIdx.x);
+  if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
 }
 
-DslashSched make_sched(const Geom& g, int mode) {
+int rhs_tile_for(const DslashTune& tune, int n) {
+  int T = tune.rhs_tile;
+  if (T <= 0) T = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
+  if (T != 1 && T != 2 && T != 4) T = 1;
+  if (n % T) T = 1;
+  return T;
+}
+
+DslashSched make_sched(const Geom& g, int mode, int T, int n) {
   DslashSched s;
-  s.nblocks = (g.Vh + 127) / 128;
+  s.H = 128 / T;
+  s.nsb = (g.Vh + s.H - 1) / s.H;
+  s.ntiles = n / T;
   s.mode = 0;
   s.Lz = g.L[2];
   s.bp = 1;
   s.zc = 1;
   const int plane = g.Lxh * g.L[1];
-  if (mode == 1 && plane % 128 == 0 && g.L[2] % 8 == 0) {
+  if (mode == 1 && plane % s.H == 0 && g.L[2] % 8 == 0) {
     s.mode = 1;
-    s.bp = plane / 128;
+    s.bp = plane / s.H;
     s.zc = g.L[2] / 8;
   }
   return s;
 }
 
-template <typename S, int DEPTH, int OCC>
-static void launch_dslash_occ(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
-                              const void* U, double kappa, const void* aux, double* partials, const int* active,
-                              int ftz, hipStream_t st) {
-  dim3 grid(sc.nblocks), block(256);
+int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n) {
+  const int T = rhs_tile_for(tune, n);
+  return (g.Vh + 128 / T - 1) / (128 / T);
+}
+
+template <typename S, int DEPTH, int OCC, int T>
+static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                            int ftz, hipStream_t st) {
+  dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
   const S* u = (const S*)U;
   const S* x = (const S*)aux;
-#define QCD_LAUNCH(OPV, EPIV) \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, active, ftz)
+#define QCD_LAUNCH(OPV, EPIV)                                                                                      \
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
+                     scal, ftz)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -398,32 +441,47 @@ static void launch_dslash_occ(const Geom& g, const DslashSched& sc, int op, int 
 #undef QCD_LAUNCH
 }
 
-template <typename S>
-static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
-                            const void* U, double kappa, const void* aux, double* partials, const int* active,
-                            int ftz, hipStream_t st) {
-  const DslashSched sc = make_sched(g, tune.sched);
+template <typename S, int T>
+static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
+                               const void* in, const void* U, double kappa, const void* aux, double* partials,
+                               const Scalars* scal, int ftz, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched, T, n);
+  if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
+    launch_dslash_v<S, 1, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st);
+    return;
+  }
   switch (tune.variant) {
-    case 1: launch_dslash_occ<S, 2, 2>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
-    case 2: launch_dslash_occ<S, 0, 3>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
-    case 3: launch_dslash_occ<S, 1, 3>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
-    case 4: launch_dslash_occ<S, 0, 4>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
-    case 5: launch_dslash_occ<S, 1, 4>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
-    default: launch_dslash_occ<S, 1, 2>(g, sc, op, epi, out, in, U, kappa, aux, partials, active, ftz, st); break;
+    case 1: launch_dslash_v<S, 2, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 2: launch_dslash_v<S, 0, 3, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 3: launch_dslash_v<S, 1, 3, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 4: launch_dslash_v<S, 0, 4, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 5: launch_dslash_v<S, 1, 4, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    default: launch_dslash_v<S, 1, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
   }
 }
 
-void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
-                   const void* U, double kappa, const void* aux, double* partials, const int* active, int ftz,
-                   hipStream_t st) {
-  if (prec == kFP64)
-    launch_dslash_t<double2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
-  else if (prec == kFP32)
-    launch_dslash_t<float2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
+template <typename S>
+static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                            int ftz, hipStream_t st) {
+  const int T = rhs_tile_for(tune, n);
+  if (T == 4)
+    launch_dslash_tile<S, 4>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else if (T == 2)
+    launch_dslash_tile<S, 2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
   else
-    launch_dslash_t<__half2>(g, tune, op, epi, out, in, U, kappa, aux, partials, active, ftz, st);
+    launch_dslash_tile<S, 1>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
 }
 
-int dslash_partial_rows(const Geom& g) { return (g.Vh + 127) / 128; }
+void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                   const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
+                   hipStream_t st) {
+  if (prec == kFP64)
+    launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else if (prec == kFP32)
+    launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else
+    launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
 
 }  // namespace qcd

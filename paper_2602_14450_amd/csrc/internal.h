@@ -12,6 +12,8 @@ enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3 };
 // Inner-solver status codes kept on the device.
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4 };
 
+constexpr int kMaxRhs = 64;  // right-hand sides per call
+
 inline size_t prec_complex_bytes(int prec) { return prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4); }
 
 // Scalars of the rescaled BiCGStab (Alg. 4 / Alg. 5) and of the outer
@@ -41,56 +43,68 @@ struct Scalars {
   int first;                     // first iteration: p = r, x = 0
   int active;                    // 0 once the solver stopped
   int status;
+  int outer_active;              // 0 once this right-hand side met the outer tolerance
   // outer refinement
   double out_rnorm;              // |r| of the FP64 residual
   double out_scale;              // s / |r|
   double shat;                   // |single(y~)|
   double zeros;                  // zero reals in y~
-  double pad[4];
+  double out_bnorm;              // |b|, for the outer stopping test
+  double out_tol;
+  double pad[2];
 };
 
 // Launch choices of the Wilson operator (picked by the tuner).
 struct DslashTune {
   int sched;    // 0: blocks in half-index order; 1: XCD-slab order when the lattice allows it
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
+  int rhs_tile; // right-hand sides sharing a wave's link loads: 0 = automatic, or 1, 2, 4
 };
 constexpr int kDslashVariants = 6;
 struct DslashSched {
-  int mode, nblocks, Lz, bp, zc;
+  int mode, nsb, ntiles, Lz, bp, zc, H;  // H: half-sites per parity per block
 };
-DslashSched make_sched(const Geom& g, int mode);
+DslashSched make_sched(const Geom& g, int mode, int T, int n);
+int rhs_tile_for(const DslashTune& tune, int n);
+
+// Every launcher takes n, the number of right-hand sides: vector arguments
+// hold n native spinors back to back (stride spinor_elems), sc points to
+// Scalars[n], and partial sums are laid out [rhs][row][value].
 
 // launchers (dslash.hip)
-void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, void* out, const void* in,
-                   const void* U, double kappa, const void* aux, double* partials, const int* active, int ftz,
+void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                   const void* U, double kappa, const void* aux, double* partials, const Scalars* sc, int ftz,
                    hipStream_t st);
-int dslash_partial_rows(const Geom& g);
+int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n);  // rows per right-hand side
 
 // launchers (blas.hip)
-int site_grid(const Geom& g);              // blocks (and partial rows) of the site-ordered kernels
-int flat_rows(const Geom& g, int prec);    // blocks (and partial rows) of the BLAS-1 kernels
+int site_grid(const Geom& g);              // blocks (and partial rows) per right-hand side, site-ordered kernels
+int flat_rows(const Geom& g, int prec);    // blocks (and partial rows) per right-hand side, BLAS-1 kernels
 void launch_pack_links(const Geom& g, int prec, void* dst, const double* Ucanon, hipStream_t st);
-void launch_pack_spinor(const Geom& g, int prec, void* dst, const double* canon, double scale, int ftz,
+void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double* canon, double scale, int ftz,
                         double* partials, hipStream_t st);
-void launch_unpack_spinor(const Geom& g, int prec, double* canon, const void* src, double scale, hipStream_t st);
-void launch_zero(const Geom& g, int prec, void* dst, hipStream_t st);
+void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
+                          double scale, hipStream_t st);
+void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st);
 
-void launch_bicg_init(Scalars* sc, const double* partials, int nrows, hipStream_t st);
-void launch_p_update(const Geom& g, int prec, Scalars* sc, void* p, const void* v, const void* r, int ftz,
+void launch_bicg_init(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_p_update(const Geom& g, int prec, int n, Scalars* sc, void* p, const void* v, const void* r, int ftz,
                      hipStream_t st);
-void launch_alpha(Scalars* sc, const double* partials, int nrows, hipStream_t st);
-void launch_s_update(const Geom& g, int prec, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st);
-void launch_omega(Scalars* sc, const double* partials, int nrows, hipStream_t st);
-void launch_xr_update(const Geom& g, int prec, Scalars* sc, void* x, void* r, const void* t, const void* p,
+void launch_alpha(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_s_update(const Geom& g, int prec, int n, Scalars* sc, void* r, const void* v, int ftz, hipStream_t st);
+void launch_omega(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st);
+void launch_xr_update(const Geom& g, int prec, int n, Scalars* sc, void* x, void* r, const void* t, const void* p,
                       const void* rstar, double* partials, int ftz, hipStream_t st);
-void launch_iter_end(Scalars* sc, const double* partials, int nrows, double* history, hipStream_t st);
+void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, double* history, int hist_stride,
+                     hipStream_t st);
 
-void launch_outer_residual_norm(Scalars* sc, const double* partials, int nrows, double s_target, hipStream_t st);
-void launch_convert(const Geom& g, int prec, Scalars* sc, const double* r64, void* y, void* rstar, void* x,
+void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
+                                hipStream_t st);
+void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r64, void* y, void* rstar,
                     double* partials, int ftz, hipStream_t st);
-void launch_convert_finish(Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
+void launch_convert_finish(int n, Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
                            hipStream_t st);
-void launch_correct(const Geom& g, int prec, Scalars* sc, double* x64, const void* xlo, hipStream_t st);
-void launch_finish_sum(const double* partials, int nrows, int nv, double* out, hipStream_t st);
+void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, const void* xlo, hipStream_t st);
+void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st);
 
 }  // namespace qcd
