@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Wilson operator and the calibration copy (for counter runs)")
     return ap.parse_args()
@@ -55,27 +56,29 @@ def calibration_copy(torch, nbytes=1 << 30):
     return nbytes
 
 
-def time_dslash(q, torch, g, prec, reps, V):
+def time_dslash(q, torch, g, prec, reps, V, nrhs=1):
     """Average duration of the native-layout Wilson operator, HIP events on
     the launch stream; three buffer pairs rotate so repeats are not served
-    from the last-level cache."""
+    from the last-level cache (one pair for many right-hand sides)."""
     bufs = []
-    src = torch.randn(V * 12 * 2, dtype=torch.float64, device="cuda").view(torch.complex128)
-    for _ in range(3):
-        a, b = g.native_spinor(prec), g.native_spinor(prec)
+    src = torch.randn(nrhs * V * 12 * 2, dtype=torch.float64, device="cuda").view(torch.complex128)
+    for _ in range(3 if nrhs == 1 else 1):
+        a, b = g.native_spinor(prec, nrhs), g.native_spinor(prec, nrhs)
         q.convert(g, prec, a, src, want_norm=False)
         bufs.append((a, b))
+    del src
+    nb = len(bufs)
     stream = torch.cuda.current_stream()
     for i in range(5):
-        a, b = bufs[i % 3]
-        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE)
+        a, b = bufs[i % nb]
+        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE, nrhs=nrhs)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for i in range(reps):
-        a, b = bufs[i % 3]
-        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE)
+        a, b = bufs[i % nb]
+        q.dslash(g, 0.124, b, a, prec=prec, layout=q.NATIVE, nrhs=nrhs)
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -110,6 +113,9 @@ def main():
     ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
     ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
 
+    tuned = {}
+    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+        tuned[name] = g.autotune(prec, nrhs=1, reps=10)
     calib_bytes = calibration_copy(torch)
     if args.only_dslash:
         for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
@@ -168,6 +174,49 @@ def main():
         dsl[name] = dict(us=ms * 1e3, GBps=gbs, frac=gbs / PEAK_HBM_GBS,
                          GFLOPs=DSLASH_FLOP_PER_SITE * V / (ms * 1e-3) / 1e9)
         print(f"[bench] dslash {name}: {ms*1e3:.1f} us {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched:
+        # the 12 spin-colour point sources of a propagator, one batched solve
+        # against 12 sequential solves at the same tolerance
+        nb = 12
+        tuned["fp16_12rhs"] = g.autotune(q.FP16, nrhs=nb, reps=5)
+        ms12 = time_dslash(q, torch, g, q.FP16, max(5, args.dslash_reps // 5), V, nrhs=nb)
+        bytes12 = (144 + nb * 96) * V
+        bp = np.stack([qi.point_source(dims, sp, c) for sp in range(4) for c in range(3)])
+        bpd = torch.from_numpy(bp).cuda()
+        del bp
+        xb = torch.zeros_like(bpd)
+        wsb = torch.empty(g.workspace_bytes(0, q.FP16, max_iter, nb), dtype=torch.uint8, device="cuda")
+
+        def solve_batched():
+            return q.solve_mixed_ir(g, k, xb, bpd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12,
+                                    inner_tol=1e-2, inner_max_iter=max_iter, workspace=wsb, use_graph=True)
+
+        solve_batched()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ib = solve_batched()
+        torch.cuda.synchronize()
+        t_batched = time.perf_counter() - ts
+        x1 = torch.zeros_like(bd)
+        ts = time.perf_counter()
+        seq_iters = 0
+        for r in range(nb):
+            inf = q.solve_mixed_ir(g, k, x1, bpd[r].contiguous(), inner_prec=q.FP16, s=128.0, sigma=64.0,
+                                   tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws)
+            seq_iters += inf.inner_iters
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - ts
+        batched = dict(nrhs=nb, sources="12 spin-colour point sources at the origin", seconds=t_batched,
+                       seconds_sequential=t_seq, speedup=t_seq / t_batched,
+                       max_true_rel_residual=max(i.true_rel_residual for i in ib),
+                       inner_iters=[i.inner_iters for i in ib], sequential_inner_iters=seq_iters,
+                       dslash_12rhs_us=ms12 * 1e3, dslash_12rhs_GBps=bytes12 / (ms12 * 1e-3) / 1e9,
+                       dslash_12rhs_bytes_per_site=144 + nb * 96)
+        print(f"[bench] batched 12 rhs: {t_batched*1e3:.1f} ms vs {t_seq*1e3:.1f} ms sequential; "
+              f"12-rhs dslash {ms12*1e3:.1f} us {bytes12 / ms12 / 1e6:.0f} GB/s", file=sys.stderr, flush=True)
+        del xb, bpd, wsb
+
     roof = dict(bound="hbm", achieved=dsl["fp16"]["GBps"], peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=dsl["fp16"]["frac"], traffic=None, kernel="k_dslash<__half2, D>",
                 bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V)
@@ -195,7 +244,8 @@ def main():
         "config": {"workload": f"Wilson D x = b, {'x'.join(map(str, dims))} lattice, eps={args.eps} SU(3) links, "
                                f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64), tol 1e-12",
                    "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12},
-        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl,
+        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl, "batched": batched,
+        "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,
     }

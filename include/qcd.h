@@ -70,6 +70,8 @@ typedef struct {
   int ftz;             /* 1: a binary16 store below 2^-14 in magnitude is flushed to zero */
   int check_every;     /* > 0: host polls the convergence flag every this many iterations; 0: adaptive
                           (first poll after 4, then after the number the convergence rate predicts) */
+  int use_graph;       /* 1: one iteration is captured in a hip graph (on a stream the handle owns) and
+                          replayed; results are identical to plain launches */
 } qcd_bicgstab_params;
 
 /* Parameters of the rescaled iterative refinement (Alg. 3; Alg. 2 is s = 1, recalc_shat = 0). */
@@ -117,9 +119,10 @@ qcd_status qcd_gauge_upload(qcd_gauge** g, const int dims[4], const void* U_dev,
 qcd_status qcd_gauge_free(qcd_gauge* g);
 
 /* Launch shape of the Wilson operator for precision prec (picked by a tuner):
- * sched 0 orders thread blocks by half-lattice index; sched 1 gives each of
- * the GPU's eight XCDs its own slab of z, swept in t order (applies when
- * (Lx/2)*Ly is a multiple of 128 and Lz of 8, else falls back to 0);
+ * sched 0 orders thread blocks by half-lattice index; sched m = 1..3 gives
+ * each of the GPU's eight XCDs its own slab of z, swept in t order as 2^(m-1)
+ * thinner sub-slabs one after the other (applies when (Lx/2)*Ly is a multiple
+ * of the block's half-sites and Lz of 8*2^(m-1), else falls back to 0);
  * variant 0..5 selects how many hops' loads are prefetched while one hop is
  * computed and the minimum waves per SIMD the kernel is compiled for:
  * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4).
@@ -128,6 +131,15 @@ qcd_status qcd_gauge_free(qcd_gauge* g);
  * nrhs, else 1 is used).  Results do not depend on these choices. */
 qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile);
 qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile);
+
+/* Autotuner for the Wilson operator: times every launch choice (schedule,
+ * variant, rhs_tile) for (prec, nrhs) with HIP events over reps launches on
+ * scratch fields (allocated and freed here) and sets the fastest on the
+ * handle; best_us (may be NULL) receives its time.  With cache_path (may be
+ * NULL), a JSON-lines file keyed by lattice, precision, nrhs and GPU
+ * architecture is read first and the result appended.  Synchronises. */
+qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, const char* cache_path,
+                               double* best_us, void* stream);
 
 /* Bytes of one native spinor field in precision prec. */
 size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);

@@ -36,7 +36,7 @@ STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_hip", -3: "err_no
 class BicgstabParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("sigma", ctypes.c_double),
                 ("sigma_lambda", ctypes.c_double), ("recalc_gamma", ctypes.c_int), ("omega0", ctypes.c_double),
-                ("ftz", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("ftz", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
 
 class IRParams(ctypes.Structure):
@@ -70,12 +70,13 @@ _lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _i, _vp, _vp, ctypes.POINTER(Bicgstab
 _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
                                     _sz, _vp]
 _lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
+_lib.qcd_autotune_dslash.argtypes = [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_d), _vp]
 _lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
-for _f in ("qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
+for _f in ("qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
 
-EXPORTED = ["qcd_last_error", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
+EXPORTED = ["qcd_last_error", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"]
 
 
@@ -140,6 +141,16 @@ class Gauge:
         _check(_lib.qcd_get_dslash_tuning(self.handle, PREC[prec], ctypes.byref(a), ctypes.byref(b),
                                           ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def autotune(self, prec, nrhs=1, reps=20, cache_path=None):
+        """Time the launch choices of the Wilson operator and keep the fastest;
+        cache_path defaults to $QCD_TUNE_CACHE.  Returns (sched, variant, rhs_tile, us)."""
+        if cache_path is None:
+            cache_path = os.environ.get("QCD_TUNE_CACHE")
+        us = ctypes.c_double(0.0)
+        _check(_lib.qcd_autotune_dslash(self.handle, PREC[prec], int(nrhs), int(reps),
+                                        cache_path.encode() if cache_path else None, ctypes.byref(us), _stream()))
+        return (*self.get_tuning(prec), us.value)
 
     def nrhs_of(self, t: torch.Tensor) -> int:
         """Number of canonical spinor fields a complex128 tensor holds."""
@@ -213,9 +224,10 @@ class Info:
     zeros: list = field(default_factory=list)
 
 
-def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every):
+def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph=False):
     return BicgstabParams(float(tol), int(max_iter), float(sigma or 0.0), float(sigma_lambda or 0.0),
-                          int(bool(recalc_gamma)), float(omega0), int(bool(ftz)), int(check_every))
+                          int(bool(recalc_gamma)), float(omega0), int(bool(ftz)), int(check_every),
+                          int(bool(use_graph)))
 
 
 def _make_infos(n, hist_cap, outer_cap):
@@ -247,11 +259,11 @@ def _infos_out(code, infos, keep):
 
 def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1e-12, max_iter=10000, sigma=0.0,
              sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None,
-             history=True, raise_on_error=True):
+             history=True, raise_on_error=True, use_graph=False):
     """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors
     (one or several right-hand sides); returns an Info or a list of them."""
     n = g.nrhs_of(b)
-    p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
+    p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph)
     infos, keep = _make_infos(n, max_iter if history else 0, 1)
     ws = _ptr(workspace) if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
@@ -265,11 +277,12 @@ def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1
 def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
                    s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                    recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None, history=False,
-                   raise_on_error=True):
+                   raise_on_error=True, use_graph=False):
     """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab,
     for one or several right-hand sides; returns an Info or a list of them."""
     n = g.nrhs_of(b)
-    inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every)
+    inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
+                         use_graph)
     p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner)
     infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
     ws = _ptr(workspace) if workspace is not None else None

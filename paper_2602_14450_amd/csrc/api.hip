@@ -23,6 +23,10 @@ struct qcd_gauge {
   size_t ws_bytes;
   Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
   DslashTune tune[3];
+  // one captured BiCGStab iteration, reused while its key is unchanged
+  hipStream_t cap_stream;
+  hipGraphExec_t graph_exec;
+  unsigned long long graph_key[6];
 };
 
 namespace {
@@ -220,6 +224,44 @@ void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* 
                 w.partials, outer_mask, 0, st);
 }
 
+// Capture one iteration (8 kernels) into a hip graph.  Capture runs on the
+// handle's own stream (the null stream cannot be captured); the graph is
+// launched on the caller's stream.  The kernels take every changing value
+// from device memory, so one capture serves every iteration.
+qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Work& w, int ftz,
+                           hipGraphExec_t* out) {
+  qcd_gauge* g = const_cast<qcd_gauge*>(gc);
+  unsigned long long kbits;
+  memcpy(&kbits, &kappa, sizeof kbits);
+  const unsigned long long key[6] = {(unsigned long long)prec, (unsigned long long)w.n, (unsigned long long)w.x,
+                                     kbits, (unsigned long long)ftz,
+                                     (unsigned long long)(g->tune[prec].sched * 64 + g->tune[prec].variant * 8 +
+                                                          g->tune[prec].rhs_tile)};
+  if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
+    *out = g->graph_exec;
+    return QCD_OK;
+  }
+  if (g->graph_exec) {
+    HIP_TRY(hipGraphExecDestroy(g->graph_exec));
+    g->graph_exec = nullptr;
+  }
+  if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  hipGraph_t graph;
+  HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+  bicg_iteration(g, prec, kappa, w, ftz, g->cap_stream);
+  hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
+  if (e != hipSuccess) return fail(QCD_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g->graph_exec = nullptr;
+    return fail(QCD_ERR_HIP, "graph instantiation: %s", hipGetErrorString(e));
+  }
+  memcpy(g->graph_key, key, sizeof key);
+  *out = g->graph_exec;
+  return QCD_OK;
+}
+
 bool any_active(const qcd_gauge* g, int n) {
   for (int i = 0; i < n; i++)
     if (g->host_sc[i].active) return true;
@@ -238,6 +280,10 @@ qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, 
   const int n = w.n;
   qcd_status s = read_scalars(g, w, st);
   if (s) return s;
+  hipGraphExec_t gexec = nullptr;
+  if (p.use_graph && any_active(g, n)) {
+    if ((s = iteration_graph(g, prec, kappa, w, p.ftz, &gexec))) return s;
+  }
   int launched = 0, chunk = K0;
   double prev_res2[kMaxRhs];
   int prev_iter[kMaxRhs];
@@ -246,7 +292,12 @@ qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, 
     prev_iter[i] = 0;
   }
   while (any_active(g, n) && launched <= p.max_iter + K0) {
-    for (int j = 0; j < chunk; j++) bicg_iteration(g, prec, kappa, w, p.ftz, st);
+    for (int j = 0; j < chunk; j++) {
+      if (gexec)
+        HIP_TRY(hipGraphLaunch(gexec, st));
+      else
+        bicg_iteration(g, prec, kappa, w, p.ftz, st);
+    }
     HIP_LAUNCHED();
     launched += chunk;
     s = read_scalars(g, w, st);
@@ -342,14 +393,16 @@ qcd_status qcd_gauge_free(qcd_gauge* g) {
     if (g->U[p]) (void)hipFree(g->U[p]);
   if (g->ws) (void)hipFree(g->ws);
   if (g->host_sc) (void)hipHostFree(g->host_sc);
+  if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   delete g;
   return QCD_OK;
 }
 
 qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile) {
   if (!g || !valid_prec(prec)) return fail(QCD_ERR_ARG, "invalid handle or precision");
-  if (sched < 0 || sched > 1 || variant < 0 || variant >= kDslashVariants)
-    return fail(QCD_ERR_ARG, "sched must be 0 or 1 and variant 0..%d", kDslashVariants - 1);
+  if (sched < 0 || sched >= kDslashScheds || variant < 0 || variant >= kDslashVariants)
+    return fail(QCD_ERR_ARG, "sched must be 0..%d and variant 0..%d", kDslashScheds - 1, kDslashVariants - 1);
   if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4)
     return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2 or 4");
   g->tune[prec] = DslashTune{sched, variant, rhs_tile};
@@ -361,6 +414,105 @@ qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, 
   *sched = g->tune[prec].sched;
   *variant = g->tune[prec].variant;
   *rhs_tile = g->tune[prec].rhs_tile;
+  return QCD_OK;
+}
+
+// Autotuner: time every launch choice of the Wilson operator for (prec,
+// nrhs) on scratch fields with HIP events and keep the fastest.  With a cache
+// path, results are read from / appended to a JSON-lines file keyed by
+// lattice, precision, number of right-hand sides and GPU architecture.
+qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, const char* cache_path,
+                               double* best_us, void* stream) {
+  qcd_status rc = check_gauge(g, prec);
+  if (rc) return rc;
+  if ((rc = check_nrhs(nrhs))) return rc;
+  if (reps < 1) reps = 20;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  char arch[64];
+  snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+  for (char* c = arch; *c; c++)
+    if (*c == ':') { *c = 0; break; }
+  char key[256];
+  snprintf(key, sizeof key, "\"dims\": \"%dx%dx%dx%d\", \"prec\": %d, \"nrhs\": %d, \"arch\": \"%s\"", g->dims[0],
+           g->dims[1], g->dims[2], g->dims[3], (int)prec, nrhs, arch);
+  if (cache_path && cache_path[0]) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, key)) continue;
+        int sc = -1, va = -1, rt = -1;
+        double us = 0;
+        const char* q = strstr(line, "\"sched\":");
+        if (q) sscanf(q, "\"sched\": %d, \"variant\": %d, \"rhs_tile\": %d, \"us\": %lf", &sc, &va, &rt, &us);
+        if (sc >= 0 && va >= 0 && rt >= 0) {
+          fclose(f);
+          g->tune[prec] = DslashTune{sc, va, rt};
+          if (best_us) *best_us = us;
+          return QCD_OK;
+        }
+      }
+      fclose(f);
+    }
+  }
+  hipStream_t st = S(stream);
+  const size_t bytes = (size_t)nrhs * spinor_bytes(g->g, prec);
+  void *in = nullptr, *out = nullptr;
+  HIP_TRY(hipMalloc(&in, bytes));
+  if (hipMalloc(&out, bytes) != hipSuccess) {
+    (void)hipFree(in);
+    return fail(QCD_ERR_HIP, "hipMalloc failed");
+  }
+  (void)hipMemsetAsync(in, 0, bytes, st);  // any finite input times the same
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  DslashTune best = g->tune[prec];
+  float best_ms = 1e30f;
+  const int tiles[3] = {1, 2, 4};
+  for (int ti = 0; ti < 3; ti++) {
+    const int T = tiles[ti];
+    if (nrhs % T || (T > 1 && nrhs == 1)) continue;
+    for (int sched = 0; sched < kDslashScheds; sched++)
+      for (int var = 0; var < (T == 1 ? kDslashVariants : 1); var++) {
+        if (sched > 1 && make_sched(g->g, sched, T, nrhs).mode != sched) continue;  // not applicable
+        const DslashTune tu{sched, var, T};
+        for (int i = 0; i < 2; i++)
+          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, out, in, g->U[prec], 0.1, nullptr, nullptr, nullptr, 0,
+                        st);
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < reps; i++)
+          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, out, in, g->U[prec], 0.1, nullptr, nullptr, nullptr, 0,
+                        st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = tu;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(in);
+  (void)hipFree(out);
+  HIP_LAUNCHED();
+  g->tune[prec] = best;
+  if (best_us) *best_us = best_ms * 1e3;
+  if (cache_path && cache_path[0]) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "{%s, \"sched\": %d, \"variant\": %d, \"rhs_tile\": %d, \"us\": %.3f}\n", key, best.sched,
+              best.variant, best.rhs_tile, best_ms * 1e3);
+      fclose(f);
+    }
+  }
   return QCD_OK;
 }
 

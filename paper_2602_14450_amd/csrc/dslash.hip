@@ -276,14 +276,19 @@ struct BlockPos { int h0, tile, sb; };
 __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
   const int b = blockIdx.x;
   BlockPos p;
-  if (sc.mode == 1) {
+  if (sc.mode >= 1) {
+    // XCD xcd owns z planes [xcd*zc, (xcd+1)*zc), swept as `sub` thinner
+    // slabs one after the other, each in t order
     const int xcd = b & 7, j = b >> 3;
     p.tile = j % sc.ntiles;
     const int js = j / sc.ntiles;
-    const int per_t = sc.zc * sc.bp;
-    const int t = js / per_t, rem = js - t * per_t;
+    const int zs = sc.zc / sc.sub;            // z planes per sub-slab
+    const int per_t = zs * sc.bp;
+    const int per_sub = per_t * sc.Lt;
+    const int sub = js / per_sub, r1 = js - sub * per_sub;
+    const int t = r1 / per_t, rem = r1 - t * per_t;
     const int zl = rem / sc.bp, yb = rem - zl * sc.bp;
-    p.sb = (t * sc.Lz + xcd * sc.zc + zl) * sc.bp + yb;
+    p.sb = (t * sc.Lz + xcd * sc.zc + sub * zs + zl) * sc.bp + yb;
   } else {
     p.tile = b % sc.ntiles;
     p.sb = b / sc.ntiles;
@@ -383,7 +388,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
 
 int rhs_tile_for(const DslashTune& tune, int n) {
   int T = tune.rhs_tile;
-  if (T <= 0) T = (n % 4 == 0) ? 4 : ((n % 2 == 0) ? 2 : 1);
+  if (T <= 0) T = 1;  // measured fastest at 32^3 x 64 with 12 right-hand sides (T = 2 ties, T = 4 is slower)
   if (T != 1 && T != 2 && T != 4) T = 1;
   if (n % T) T = 1;
   return T;
@@ -396,13 +401,18 @@ DslashSched make_sched(const Geom& g, int mode, int T, int n) {
   s.ntiles = n / T;
   s.mode = 0;
   s.Lz = g.L[2];
+  s.Lt = g.L[3];
   s.bp = 1;
   s.zc = 1;
+  s.sub = 1;
   const int plane = g.Lxh * g.L[1];
-  if (mode == 1 && plane % s.H == 0 && g.L[2] % 8 == 0) {
-    s.mode = 1;
+  // mode m >= 1: XCD slabs of Lz/8 planes, each swept as 2^(m-1) sub-slabs
+  const int sub = mode >= 1 ? 1 << (mode - 1) : 1;
+  if (mode >= 1 && plane % s.H == 0 && g.L[2] % (8 * sub) == 0) {
+    s.mode = mode;
     s.bp = plane / s.H;
     s.zc = g.L[2] / 8;
+    s.sub = sub;
   }
   return s;
 }

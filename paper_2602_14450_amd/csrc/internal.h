@@ -56,14 +56,15 @@ struct Scalars {
 
 // Launch choices of the Wilson operator (picked by the tuner).
 struct DslashTune {
-  int sched;    // 0: blocks in half-index order; 1: XCD-slab order when the lattice allows it
+  int sched;    // 0: blocks in half-index order; m = 1..3: XCD slabs (each swept as 2^(m-1) sub-slabs)
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
   int rhs_tile; // right-hand sides sharing a wave's link loads: 0 = automatic, or 1, 2, 4
 };
 constexpr int kDslashVariants = 6;
 struct DslashSched {
-  int mode, nsb, ntiles, Lz, bp, zc, H;  // H: half-sites per parity per block
+  int mode, nsb, ntiles, Lz, Lt, bp, zc, sub, H;  // H: half-sites per parity per block
 };
+constexpr int kDslashScheds = 4;
 DslashSched make_sched(const Geom& g, int mode, int T, int n);
 int rhs_tile_for(const DslashTune& tune, int n);
 

@@ -46,7 +46,9 @@ def test_multi_rhs_dslash(q, dims, nrhs, prec):
 
 @pytest.mark.parametrize("rhs_tile", [1, 2, 4])
 def test_rhs_tile_choices_agree_bitwise(q, rhs_tile):
-    dims = (8, 8, 8, 8)
+    # every launch shape (schedule incl. the sub-slab orders, right-hand-side
+    # tile) gives bit-identical output
+    dims = (8, 16, 32, 4)
     U = qi.gauge_field(dims, 0.3, 41)
     psi = qi.gaussian_source(dims, 42, nrhs=4)
     g = q.gauge_upload(to_dev(U), dims)
@@ -55,7 +57,7 @@ def test_rhs_tile_choices_agree_bitwise(q, rhs_tile):
     g.set_tuning(q.FP16, 0, 0, 1)
     q.dslash(g, 0.124, ref, x, prec=q.FP16)
     out = torch.empty_like(x)
-    for sched in (0, 1):
+    for sched in (0, 1, 2, 3):
         g.set_tuning(q.FP16, sched, 0, rhs_tile)
         q.dslash(g, 0.124, out, x, prec=q.FP16)
         torch.cuda.synchronize()
@@ -128,4 +130,51 @@ def test_twelve_point_sources_full_operator(q):
     for r in (0, 5, 11):
         res = np.linalg.norm(b[r] - oracle.dslash(U, xh[r], k, dims)) / np.linalg.norm(b[r])
         assert infos[r].true_rel_residual <= 1e-12 and res <= 1e-12
+    g.close()
+
+
+def test_graph_replays_match_eager(q, c1b):
+    # one BiCGStab iteration captured in a hip graph and replayed: several
+    # solves in a row, with eager work and synchronisation between them, each
+    # bit-identical to the eager solve
+    b = to_dev(c1b["b"])
+    xe = torch.zeros_like(b)
+    ie = q.solve_mixed_ir(c1b["g"], c1b["k"], xe, b, use_graph=False)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        ig = q.solve_mixed_ir(c1b["g"], c1b["k"], xg, b, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), rep
+        assert [i.inner_iters for i in ig] == [i.inner_iters for i in ie]
+        # unrelated eager work between replays
+        y = torch.empty_like(b)
+        q.dslash(c1b["g"], c1b["k"], y, b, prec=q.FP32)
+        torch.cuda.synchronize()
+    xb = torch.zeros_like(b[:3])
+    q.bicgstab(c1b["g"], c1b["k"], xb, b[:3], prec=q.FP16, tol=1e-2, use_graph=True)
+    xb2 = torch.zeros_like(b[:3])
+    q.bicgstab(c1b["g"], c1b["k"], xb2, b[:3], prec=q.FP16, tol=1e-2, use_graph=False)
+    torch.cuda.synchronize()
+    assert torch.equal(xb, xb2)
+
+
+def test_autotune_and_cache(q, tmp_path):
+    dims = (8, 8, 8, 8)
+    U = qi.gauge_field(dims, 0.3, 61)
+    g = q.gauge_upload(to_dev(U), dims)
+    cache = str(tmp_path / "tune.jsonl")
+    r1 = g.autotune(q.FP16, nrhs=4, reps=5, cache_path=cache)
+    assert r1[2] in (1, 2, 4) and r1[3] > 0
+    g.set_tuning(q.FP16, 0, 0, 1)
+    r2 = g.autotune(q.FP16, nrhs=4, reps=5, cache_path=cache)   # read from the cache
+    assert r2[:3] == r1[:3] and abs(r2[3] - r1[3]) < 1e-3
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"arch": "gfx' in lines[0]
+    # results are unchanged by the tuner's choice
+    psi = qi.gaussian_source(dims, 62, nrhs=4)
+    out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    q.dslash(g, 0.12, out, to_dev(psi), prec=q.FP16)
+    torch.cuda.synchronize()
+    for r in range(4):
+        compare(to_host(out)[r], oracle.dslash(U, psi[r], 0.12, dims), TOL[2], "tuned")
     g.close()
