@@ -204,6 +204,46 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
 qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
                               const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned preconditioner: a gauge-covariant parallel-transport network.
+ * A layer maps C_in spinor fields to C_out fields,
+ *   out_j(x) = sum_i sum_p W[p][j][i] (T_p psi_i)(x),
+ * over nine paths p = 0, +x, -x, +y, -y, +z, -z, +t, -t (in that order) with
+ *   (T_{+mu} psi)(x) = U_mu(x) psi(x + mu), (T_{-mu} psi)(x) = U_mu(x - mu)^dag psi(x - mu),
+ * and W[p][j][i] a complex 4x4 spin matrix [s'][s].  Layers compose linearly
+ * (a fixed linear, gauge-covariant operator M).  Channel mixing runs on BF16
+ * matrix cores with FP32 accumulation; activations are FP32.  This is not a
+ * construction of the paper; the solver uses M as a right preconditioner of
+ * its inner BiCGStab (qcd_ir_params.precond).
+ */
+typedef struct qcd_ptc qcd_ptc;
+
+/* Create a network of nlayers layers with channels[0..nlayers] spinor fields
+ * per layer boundary (channels[0] = channels[nlayers] = 1, others 1 or 2) on
+ * the lattice of g (which must hold FP32 links; the handle keeps a pointer
+ * to g, which must outlive it), for batches of up to max_batch fields.
+ * Weights start at zero.  Device buffers are owned by the handle. */
+qcd_status qcd_ptc_create(qcd_ptc** net, const qcd_gauge* g, int nlayers, const int* channels, int max_batch,
+                          void* stream);
+qcd_status qcd_ptc_free(qcd_ptc* net);
+/* Complex weights in total: sum over layers of 9 * C_out * C_in * 16. */
+size_t qcd_ptc_num_weights(const qcd_ptc* net);
+/* Host complex128 weights, layers concatenated, each [9][C_out][C_in][4][4];
+ * setting them resets the optimiser state.  Synchronise. */
+qcd_status qcd_ptc_set_weights(qcd_ptc* net, const double* w_host, void* stream);
+qcd_status qcd_ptc_get_weights(const qcd_ptc* net, double* w_host, void* stream);
+/* out = M(in) for nbatch canonical complex128 fields (device). */
+qcd_status qcd_ptc_apply(qcd_ptc* net, int nbatch, void* out_dev, const void* in_dev, void* stream);
+/* Loss (1/B) sum_b |M(r_b) - e_b|^2 / |e_b|^2 and, if grad_host is not NULL,
+ * its gradient dL/dRe W + i dL/dIm W (host complex128, layout of the
+ * weights).  r_dev, e_dev: nbatch canonical complex128 fields.  Synchronises. */
+qcd_status qcd_ptc_loss_grad(qcd_ptc* net, int nbatch, const void* r_dev, const void* e_dev, double* loss,
+                             double* grad_host, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights with
+ * learning rate lr; loss (may be NULL) receives the loss before the step. */
+qcd_status qcd_ptc_train_step(qcd_ptc* net, int nbatch, const void* r_dev, const void* e_dev, double lr, double* loss,
+                              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

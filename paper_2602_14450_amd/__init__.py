@@ -72,12 +72,25 @@ _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRPara
 _lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
 _lib.qcd_autotune_dslash.argtypes = [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_d), _vp]
 _lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
-for _f in ("qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
+_lib.qcd_ptc_create.argtypes = [ctypes.POINTER(_vp), _vp, _i, ctypes.POINTER(_i), _i, _vp]
+_lib.qcd_ptc_free.argtypes = [_vp]
+_lib.qcd_ptc_num_weights.argtypes = [_vp]
+_lib.qcd_ptc_num_weights.restype = _sz
+_lib.qcd_ptc_set_weights.argtypes = [_vp, _vp, _vp]
+_lib.qcd_ptc_get_weights.argtypes = [_vp, _vp, _vp]
+_lib.qcd_ptc_apply.argtypes = [_vp, _i, _vp, _vp, _vp]
+_lib.qcd_ptc_loss_grad.argtypes = [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp, _vp]
+_lib.qcd_ptc_train_step.argtypes = [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_d), _vp]
+for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get_weights", "qcd_ptc_apply",
+           "qcd_ptc_loss_grad", "qcd_ptc_train_step",
+           "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
 
 EXPORTED = ["qcd_last_error", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
-            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"]
+            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir",
+            "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
+            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step"]
 
 
 class QcdError(RuntimeError):
@@ -292,3 +305,78 @@ def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec
     if raise_on_error:
         _check(code, allow=(0, 1))
     return _infos_out(code, infos, keep)
+
+
+class PTC:
+    """Gauge-covariant parallel-transport network on the lattice of a Gauge
+    (which must hold FP32 links), usable as a right preconditioner.
+
+    channels: fields per layer boundary, e.g. (1, 2, 2, 1).  Weights are a
+    list of complex arrays (9, C_out, C_in, 4, 4), one per layer."""
+
+    def __init__(self, g: Gauge, channels=(1, 2, 2, 1), max_batch=1):
+        self.gauge = g
+        self.channels = tuple(int(c) for c in channels)
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        ch = (ctypes.c_int * len(self.channels))(*self.channels)
+        _check(_lib.qcd_ptc_create(ctypes.byref(h), g.handle, len(self.channels) - 1, ch, self.max_batch, _stream()))
+        self.handle = h
+        self.nweights = int(_lib.qcd_ptc_num_weights(h))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.qcd_ptc_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _shapes(self):
+        return [(9, co, ci, 4, 4) for ci, co in zip(self.channels[:-1], self.channels[1:])]
+
+    def set_weights(self, Ws):
+        import numpy as np
+        flat = np.concatenate([np.asarray(W, dtype=np.complex128).reshape(-1) for W in Ws])
+        assert flat.size == self.nweights, (flat.size, self.nweights)
+        flat = np.ascontiguousarray(flat)
+        _check(_lib.qcd_ptc_set_weights(self.handle, flat.ctypes.data, _stream()))
+
+    def _unflatten(self, flat):
+        out, o = [], 0
+        for sh in self._shapes():
+            n = 9 * sh[1] * sh[2] * 16
+            out.append(flat[o:o + n].reshape(sh).copy())
+            o += n
+        return out
+
+    def get_weights(self):
+        import numpy as np
+        flat = np.empty(self.nweights, dtype=np.complex128)
+        _check(_lib.qcd_ptc_get_weights(self.handle, flat.ctypes.data, _stream()))
+        return self._unflatten(flat)
+
+    def apply(self, out: torch.Tensor, inp: torch.Tensor):
+        """out = M(inp) for one field (V, 4, 3) or a batch (B, V, 4, 3), complex128."""
+        nb = 1 if inp.dim() == 3 else inp.shape[0]
+        _check(_lib.qcd_ptc_apply(self.handle, nb, _ptr(out), _ptr(_as_c128(inp)), _stream()))
+        return out
+
+    def loss_grad(self, r: torch.Tensor, e: torch.Tensor, want_grad=True):
+        import numpy as np
+        nb = 1 if r.dim() == 3 else r.shape[0]
+        loss = ctypes.c_double()
+        flat = np.empty(self.nweights, dtype=np.complex128) if want_grad else None
+        _check(_lib.qcd_ptc_loss_grad(self.handle, nb, _ptr(_as_c128(r)), _ptr(_as_c128(e)), ctypes.byref(loss),
+                                      flat.ctypes.data if want_grad else None, _stream()))
+        return (loss.value, self._unflatten(flat)) if want_grad else loss.value
+
+    def train_step(self, r: torch.Tensor, e: torch.Tensor, lr=1e-3):
+        nb = 1 if r.dim() == 3 else r.shape[0]
+        loss = ctypes.c_double()
+        _check(_lib.qcd_ptc_train_step(self.handle, nb, _ptr(_as_c128(r)), _ptr(_as_c128(e)), float(lr),
+                                       ctypes.byref(loss), _stream()))
+        return loss.value

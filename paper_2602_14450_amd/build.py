@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqcd.so")
-SOURCES = ["dslash.hip", "blas.hip", "api.hip"]
+SOURCES = ["dslash.hip", "blas.hip", "api.hip", "ptc.hip"]
 ARCH = os.environ.get("QCD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -15,25 +15,12 @@
 
 using namespace qcd;
 
-struct qcd_gauge {
-  Geom g;
-  int dims[4];
-  void* U[3];
-  void* ws;          // cached workspace used when the caller passes none
-  size_t ws_bytes;
-  Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
-  DslashTune tune[3];
-  // one captured BiCGStab iteration, reused while its key is unchanged
-  hipStream_t cap_stream;
-  hipGraphExec_t graph_exec;
-  unsigned long long graph_key[6];
-};
+// struct qcd_gauge is defined in internal.h (shared with the network code).
 
-namespace {
+static thread_local std::string g_err;
 
-thread_local std::string g_err;
-
-qcd_status fail(qcd_status code, const char* fmt, ...) {
+// Record an error message for qcd_last_error() and return code.
+int qcd::set_error(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -41,6 +28,12 @@ qcd_status fail(qcd_status code, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return code;
+}
+
+namespace {
+
+template <typename... A> qcd_status fail(qcd_status code, const char* fmt, A... a) {
+  return (qcd_status)qcd::set_error((int)code, fmt, a...);
 }
 
 #define HIP_TRY(expr)                                                                     \

@@ -13,6 +13,10 @@ enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3 };
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4 };
 
 constexpr int kMaxRhs = 64;  // right-hand sides per call
+constexpr int kPtcMaxLayers = 4;  // layers of the parallel-transport network
+
+// Record an error message for qcd_last_error(); returns code.
+int set_error(int code, const char* fmt, ...);
 
 inline size_t prec_complex_bytes(int prec) { return prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4); }
 
@@ -109,3 +113,28 @@ void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, co
 void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st);
 
 }  // namespace qcd
+
+struct qcd_ptc;
+struct qcd_gauge;
+namespace qcd {
+// network applied to nb native FP16 fields: out = M(in_scale * in) (ptc.hip)
+void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scale, int ftz, hipStream_t st);
+int ptc_max_batch(const qcd_ptc* n);
+const qcd_gauge* ptc_gauge(const qcd_ptc* n);
+}  // namespace qcd
+
+// The gauge handle behind the C ABI's opaque qcd_gauge.
+struct qcd_gauge {
+  qcd::Geom g;
+  int dims[4];
+  void* U[3];        // native links per precision (FP64, FP32, FP16)
+  void* ws;          // cached workspace used when the caller passes none
+  size_t ws_bytes;
+  qcd::Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
+  qcd::DslashTune tune[3];
+  // one captured BiCGStab iteration, reused while its key is unchanged
+  hipStream_t cap_stream;
+  hipGraphExec_t graph_exec;
+  unsigned long long graph_key[6];
+};
+

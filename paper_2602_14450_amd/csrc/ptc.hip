@@ -1,0 +1,763 @@
+// Gauge-covariant parallel-transport network (learned right preconditioner).
+//
+// A layer maps C_in spinor fields to C_out fields,
+//   out_j(x) = sum_i sum_p W[p][j][i] (T_p psi_i)(x),
+// over nine paths p = 0, +x, -x, +y, -y, +z, -z, +t, -t with
+//   (T_{+mu} psi)(x) = U_mu(x) psi(x + mu),  (T_{-mu} psi)(x) = U_mu(x - mu)^dag psi(x - mu),
+// and W[p][j][i] a complex 4x4 spin matrix; the network composes its layers
+// linearly, so it is gauge covariant and a fixed linear operator.
+//
+// GPU form.  For every (site, colour) column n the transported inputs are
+// written once as a real vector X[n][k], k = (re/im, p, i, spin), in BF16.
+// The channel mixing is then the real GEMM
+//   [out_re; out_im](16 x N) = A (16 x Kp) X^T,  A = [[Wr, -Wi], [Wi, Wr]],
+// run on MFMA 16x16x16 BF16 tiles with FP32 accumulation (rows padded to 16,
+// Kp = 2K rounded up to 16).  The backward pass uses A^T for dX (MFMA), the
+// adjoint transports (T_{+mu}^dag = T_{-mu} for unitary links) as a gather,
+// and an MFMA reduction over columns for dW = dOut X^H.  Activations are
+// native FP32 spinor fields; links are the handle's native FP32 copy.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "qcd.h"
+#include "internal.h"
+
+namespace qcd {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
+
+struct PtcLayerDev {
+  int cin, cout, K, M, Kp;  // K = 9*cin*4 complex inputs, M = cout*4 complex outputs, Kp = 2K rounded to 16
+};
+
+// neighbour half index of (par, h) one step along +mu (dir > 0) or -mu
+__device__ __forceinline__ int nbr(const Geom& g, int h, const Coord& c, int mu, int dir) {
+  if (mu == 0) {
+    const int base = h - (c.x >> 1);
+    const int xn = dir > 0 ? ((c.x + 1 == g.L[0]) ? 0 : c.x + 1) : ((c.x == 0) ? g.L[0] - 1 : c.x - 1);
+    return base + (xn >> 1);
+  }
+  const int cm = mu == 1 ? c.y : (mu == 2 ? c.z : c.t);
+  const int st = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+  if (dir > 0) return (cm + 1 == g.L[mu]) ? h - (g.L[mu] - 1) * st : h + st;
+  return (cm == 0) ? h + (g.L[mu] - 1) * st : h - st;
+}
+
+__device__ __forceinline__ void load_link32(const Geom& g, const float2* U, int mu, int par, int h, cx<float> (&u)[9]) {
+  const float2* b = U + lk_block(g, mu, par, h);
+  const int lane = h & 63;
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    float2 v = b[lk_off<float2>(k, lane)];
+    u[k] = cx<float>(v.x, v.y);
+  }
+}
+
+// out = U f (dag = 0) or U^dag f (dag = 1), colour index of f[s][c]
+__device__ __forceinline__ void su3_apply(const cx<float> (&u)[9], const cx<float> (&f)[12], bool dag,
+                                          cx<float> (&o)[12]) {
+#pragma unroll
+  for (int s = 0; s < 4; s++)
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      cx<float> acc(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; b++) acc = acc + (dag ? cmulc(u[3 * b + a], f[3 * s + b]) : u[3 * a + b] * f[3 * s + b]);
+      o[3 * s + a] = acc;
+    }
+}
+
+__device__ __forceinline__ size_t col_of(const Geom& g, int par, int h) { return ((size_t)par * g.nb * 64 + h) * 3; }
+__device__ __forceinline__ size_t ncols(const Geom& g) { return (size_t)2 * g.nb * 64 * 3; }
+
+// ---------------------------------------------------------------------------
+// Forward transport: X[b][n][k] (BF16), n = column (site, colour),
+// k = reim*K + (p*cin + i)*4 + spin; rows [2K, Kp) and padding sites are zero.
+__global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, const float2* __restrict__ act,
+                                                       const float2* __restrict__ U, short* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;  // over 2 * nb * 64 (padding included)
+  const int per = g.nb * 64;
+  if (i_site >= 2 * per) return;
+  const int par = i_site >= per, h = i_site - par * per;
+  short* Xb = X + ((size_t)b * ncols(g) + col_of(g, par, h)) * L.Kp;
+  if (h >= g.Vh) {  // padding site: zero columns
+    for (int c = 0; c < 3; c++)
+      for (int k = 0; k < L.Kp; k++) Xb[(size_t)c * L.Kp + k] = 0;
+    return;
+  }
+  const Coord c = decode(g, par, h);
+  const size_t fstride = spinor_elems(g);
+  for (int k = 2 * L.K; k < L.Kp; k++)
+    for (int cc = 0; cc < 3; cc++) Xb[(size_t)cc * L.Kp + k] = 0;
+  for (int i = 0; i < L.cin; i++) {
+    const float2* f = act + ((size_t)b * L.cin + i) * fstride;
+    for (int p = 0; p < 9; p++) {
+      cx<float> in[12], t[12];
+      if (p == 0) {
+        load_site(f, g, par, h, t);
+      } else {
+        const int mu = (p - 1) >> 1;
+        const bool fwd = ((p - 1) & 1) == 0;
+        const int hn = nbr(g, h, c, mu, fwd ? 1 : -1);
+        load_site(f, g, par ^ 1, hn, in);
+        cx<float> u[9];
+        if (fwd) load_link32(g, U, mu, par, h, u);       // U_mu(x)
+        else load_link32(g, U, mu, par ^ 1, hn, u);      // U_mu(x - mu)^dag
+        su3_apply(u, in, !fwd, t);
+      }
+      const int k0 = (p * L.cin + i) * 4;
+      for (int cc = 0; cc < 3; cc++) {
+        short* col = Xb + (size_t)cc * L.Kp;
+        bf16x4 re, im;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          re[s] = to_bf16(t[3 * s + cc].re);
+          im[s] = to_bf16(t[3 * s + cc].im);
+        }
+        *reinterpret_cast<bf16x4*>(col + k0) = re;
+        *reinterpret_cast<bf16x4*>(col + L.K + k0) = im;
+      }
+    }
+  }
+}
+
+// A[16][Kp] (BF16) from the complex weights W[p][j][i][s'][s] of one layer.
+__global__ void k_ptc_prep_A(PtcLayerDev L, const float2* __restrict__ W, short* __restrict__ A) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 16 * L.Kp) return;
+  const int r = idx / L.Kp, k = idx % L.Kp;
+  float v = 0.0f;
+  const bool rre = r < L.M, rim = r >= L.M && r < 2 * L.M;
+  const bool kre = k < L.K, kim = k >= L.K && k < 2 * L.K;
+  if ((rre || rim) && (kre || kim)) {
+    const int row = rre ? r : r - L.M;       // (j, s')
+    const int kk = kre ? k : k - L.K;         // (p, i, s)
+    const int j = row >> 2, sp = row & 3;
+    const int p = kk / (L.cin * 4), i = (kk / 4) % L.cin, s = kk & 3;
+    const float2 w = W[(((size_t)(p * L.cout + j) * L.cin + i) * 4 + sp) * 4 + s];
+    if (rre && kre) v = w.x;
+    else if (rre && kim) v = -w.y;
+    else if (rim && kre) v = w.y;
+    else v = w.x;
+  }
+  A[idx] = to_bf16(v);
+}
+
+// Channel mixing: out[b][j] (native FP32 fields) = layer(X).  One wave per
+// tile of 16 columns; A fragments stay in registers.
+__global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const short* __restrict__ X,
+                                                 const short* __restrict__ A, float2* __restrict__ out, int nbatch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
+  const size_t N = ncols(g);
+  const size_t ntiles = (N * nbatch) / 16;  // N is a multiple of 192
+  const int nk = L.Kp / 16;
+  bf16x4 af[9];
+#pragma unroll
+  for (int kt = 0; kt < 9; kt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) af[kt][q] = kt < nk ? A[(lane % 16) * L.Kp + kt * 16 + 4 * (lane / 16) + q] : 0;
+  const size_t fstride = spinor_elems(g);
+  for (size_t tile = wave; tile < ntiles; tile += nwaves) {
+    const size_t n = tile * 16 + (lane % 16);
+    const short* xc = X + n * L.Kp + 4 * (lane / 16);
+    f32x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kt = 0; kt < 9; kt++) {
+      if (kt >= nk) break;
+      const bf16x4 bf = *reinterpret_cast<const bf16x4*>(xc + kt * 16);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kt], bf, acc, 0, 0, 0);
+    }
+    // lane holds rows 4*(lane/16) + q of column n
+    const int b = (int)(n / N);
+    const size_t nn = n - (size_t)b * N;
+    const int site = (int)(nn / 3), cc = (int)(nn % 3);
+    const int per = g.nb * 64;
+    const int par = site >= per, h = site - par * per;
+    if (h >= g.Vh) continue;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int r = 4 * (lane / 16) + q;
+      if (r >= 2 * L.M) continue;
+      const int row = r < L.M ? r : r - L.M;
+      const int j = row >> 2, sp = row & 3;
+      float* dst = reinterpret_cast<float*>(out + ((size_t)b * L.cout + j) * fstride + sp_block(g, par, h) +
+                                            sp_off<float2>(3 * sp + cc, h & 63));
+      dst[r < L.M ? 0 : 1] = acc[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward.
+
+// dOut (native FP32 fields) -> DO[b][n][16] BF16 real form (re rows, im rows, zeros).
+__global__ __launch_bounds__(256) void k_ptc_dout_bf16(Geom g, PtcLayerDev L, const float2* __restrict__ dout,
+                                                       short* __restrict__ DO) {
+  const int b = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  const int per = g.nb * 64;
+  if (i_site >= 2 * per) return;
+  const int par = i_site >= per, h = i_site - par * per;
+  short* d = DO + ((size_t)b * ncols(g) + col_of(g, par, h)) * 16;
+  const size_t fstride = spinor_elems(g);
+  for (int cc = 0; cc < 3; cc++) {
+    short row[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) row[r] = 0;
+    if (h < g.Vh) {
+      for (int j = 0; j < L.cout; j++) {
+        cx<float> f[12];
+        load_site(dout + ((size_t)b * L.cout + j) * fstride, g, par, h, f);
+        for (int sp = 0; sp < 4; sp++) {
+          row[4 * j + sp] = to_bf16(f[3 * sp + cc].re);
+          row[L.M + 4 * j + sp] = to_bf16(f[3 * sp + cc].im);
+        }
+      }
+    }
+    for (int r = 0; r < 16; r += 4) {
+      bf16x4 v = {row[r], row[r + 1], row[r + 2], row[r + 3]};
+      *reinterpret_cast<bf16x4*>(d + (size_t)cc * 16 + r) = v;
+    }
+  }
+}
+
+// DX[b][n][k] (FP32) = sum_r A[r][k] DO[b][n][r]: one MFMA per (k tile, column tile).
+__global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const short* __restrict__ DO,
+                                                    const short* __restrict__ A, float* __restrict__ DX, int nbatch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
+  const size_t N = ncols(g) * nbatch;
+  const size_t ntiles = N / 16;
+  const int nk = L.Kp / 16;
+  for (size_t tile = wave; tile < ntiles; tile += nwaves) {
+    const size_t n = tile * 16 + (lane % 16);
+    const bf16x4 bf = *reinterpret_cast<const bf16x4*>(DO + n * 16 + 4 * (lane / 16));
+    for (int kt = 0; kt < nk; kt++) {
+      bf16x4 at;  // A^T tile: row = k, column = r
+#pragma unroll
+      for (int q = 0; q < 4; q++) at[q] = A[(4 * (lane / 16) + q) * L.Kp + kt * 16 + (lane % 16)];
+      f32x4 acc = {0, 0, 0, 0};
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bf, acc, 0, 0, 0);
+      // lane holds rows k = kt*16 + 4*(lane/16) + q of column n
+      *reinterpret_cast<f32x4*>(DX + n * L.Kp + kt * 16 + 4 * (lane / 16)) = acc;
+    }
+  }
+}
+
+// dIn_i(y) = sum_p (T_p^dag dX_{p,i})(y): p = 0 identity; +mu: U_mu(y-mu)^dag dX(y-mu); -mu: U_mu(y) dX(y+mu).
+__global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L, const float* __restrict__ DX,
+                                                           const float2* __restrict__ U, float2* __restrict__ din) {
+  const int b = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  if (i_site >= 2 * g.Vh) return;
+  const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+  const Coord c = decode(g, par, h);
+  const size_t fstride = spinor_elems(g);
+  const float* DXb = DX + (size_t)b * ncols(g) * L.Kp;
+  for (int i = 0; i < L.cin; i++) {
+    cx<float> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = cx<float>(0, 0);
+    for (int p = 0; p < 9; p++) {
+      int sp = par, sh = h;  // site whose dX column is read
+      bool dag = false;
+      int mu = -1;
+      if (p > 0) {
+        mu = (p - 1) >> 1;
+        const bool fwd = ((p - 1) & 1) == 0;
+        sp = par ^ 1;
+        sh = nbr(g, h, c, mu, fwd ? -1 : 1);  // +mu path reads y - mu, -mu path reads y + mu
+        dag = fwd;
+      }
+      cx<float> f[12];
+      const int k0 = (p * L.cin + i) * 4;
+      const float* col = DXb + col_of(g, sp, sh) * L.Kp;
+#pragma unroll
+      for (int cc = 0; cc < 3; cc++)
+#pragma unroll
+        for (int s = 0; s < 4; s++)
+          f[3 * s + cc] = cx<float>(col[(size_t)cc * L.Kp + k0 + s], col[(size_t)cc * L.Kp + L.K + k0 + s]);
+      if (p == 0) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = acc[k] + f[k];
+      } else {
+        cx<float> u[9], t[12];
+        if (dag) load_link32(g, U, mu, sp, sh, u);   // U_mu(y - mu)^dag
+        else load_link32(g, U, mu, par, h, u);       // U_mu(y)
+        su3_apply(u, f, dag, t);
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[k] = acc[k] + t[k];
+      }
+    }
+    float2* dst = din + ((size_t)b * L.cin + i) * fstride;
+    float2* bb = dst + sp_block(g, par, h);
+#pragma unroll
+    for (int k = 0; k < 12; k++) bb[sp_off<float2>(k, h & 63)] = make_float2(acc[k].re, acc[k].im);
+  }
+}
+
+// G partials: Gp[wave][16][Kp] = sum over the wave's columns of DO[n][r] X[n][k].
+__global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const short* __restrict__ DO,
+                                                    const short* __restrict__ X, float* __restrict__ Gp, int nbatch) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
+  const size_t N = ncols(g) * nbatch;
+  const size_t ntiles = N / 16;
+  const int nk = L.Kp / 16;
+  f32x4 acc[9];
+#pragma unroll
+  for (int kt = 0; kt < 9; kt++) acc[kt] = (f32x4){0, 0, 0, 0};
+  for (size_t tile = wave; tile < ntiles; tile += nwaves) {
+    const size_t n0 = tile * 16;
+    bf16x4 a;  // A[r][nn] = DO[n0 + nn][r]: row r = lane % 16, nn = 4*(lane/16) + q
+#pragma unroll
+    for (int q = 0; q < 4; q++) a[q] = DO[(n0 + 4 * (lane / 16) + q) * 16 + (lane % 16)];
+#pragma unroll
+    for (int kt = 0; kt < 9; kt++) {
+      if (kt >= nk) break;
+      bf16x4 bb;  // B[nn][k] = X[n0 + nn][kt*16 + lane % 16]
+#pragma unroll
+      for (int q = 0; q < 4; q++) bb[q] = X[(n0 + 4 * (lane / 16) + q) * L.Kp + kt * 16 + (lane % 16)];
+      acc[kt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[kt], 0, 0, 0);
+    }
+  }
+  // lane holds G[4*(lane/16) + q][kt*16 + lane % 16]
+  float* dst = Gp + (size_t)wave * 16 * L.Kp;
+#pragma unroll
+  for (int kt = 0; kt < 9; kt++) {
+    if (kt >= nk) break;
+#pragma unroll
+    for (int q = 0; q < 4; q++) dst[(size_t)(4 * (lane / 16) + q) * L.Kp + kt * 16 + (lane % 16)] = acc[kt][q];
+  }
+}
+
+// Sum the wave partials (fixed order) and form the complex gradient
+// dW = (G00 + G11) + i (G10 - G01) in the layout of W; accumulate into grad.
+__global__ void k_ptc_dw_finish(PtcLayerDev L, const float* __restrict__ Gp, int nwaves, float2* __restrict__ grad) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over M*K complex weights
+  if (idx >= L.M * L.K) return;
+  const int row = idx / L.K, kk = idx % L.K;
+  double g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+  for (int w = 0; w < nwaves; w++) {
+    const float* G = Gp + (size_t)w * 16 * L.Kp;
+    g00 += G[(size_t)row * L.Kp + kk];
+    g01 += G[(size_t)row * L.Kp + L.K + kk];
+    g10 += G[(size_t)(L.M + row) * L.Kp + kk];
+    g11 += G[(size_t)(L.M + row) * L.Kp + L.K + kk];
+  }
+  const int j = row >> 2, sp = row & 3;
+  const int p = kk / (L.cin * 4), i = (kk / 4) % L.cin, s = kk & 3;
+  float2& d = grad[(((size_t)(p * L.cout + j) * L.cin + i) * 4 + sp) * 4 + s];
+  d.x += (float)(g00 + g11);
+  d.y += (float)(g10 - g01);
+}
+
+// ---------------------------------------------------------------------------
+// Loss |M(r_b) - e_b|^2 / |e_b|^2 (mean over the batch) and its output gradient.
+
+__global__ __launch_bounds__(256) void k_ptc_loss_parts(Geom g, const float2* __restrict__ out,
+                                                        const float2* __restrict__ e, double* __restrict__ partials) {
+  const int b = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  double red[2] = {0, 0};
+  if (i_site < 2 * g.Vh) {
+    const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+    const size_t fo = (size_t)b * spinor_elems(g);
+    cx<float> o[12], t[12];
+    load_site(out + fo, g, par, h, o);
+    load_site(e + fo, g, par, h, t);
+    float a = 0, n = 0;
+    for (int k = 0; k < 12; k++) {
+      a += norm2(o[k] - t[k]);
+      n += norm2(t[k]);
+    }
+    red[0] = a;
+    red[1] = n;
+  }
+  block_reduce_store<2>(red, partials + (size_t)b * gridDim.x * 2, blockIdx.x);
+}
+
+__global__ void k_ptc_loss_finish(const double* __restrict__ partials, int nrows, int nbatch, double* __restrict__ sums) {
+  // sums[b] = (|out-e|^2, |e|^2) for sample blockIdx.x
+  double s[2];
+  finish_sum<2>(partials + (size_t)blockIdx.x * nrows * 2, nrows, s);
+  if (threadIdx.x == 0) {
+    sums[2 * blockIdx.x] = s[0];
+    sums[2 * blockIdx.x + 1] = s[1];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ptc_dout(Geom g, const float2* __restrict__ out, const float2* __restrict__ e,
+                                                  const double* __restrict__ sums, int nbatch,
+                                                  float2* __restrict__ dout) {
+  const int b = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  if (i_site >= 2 * g.Vh) return;
+  const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+  const size_t fo = (size_t)b * spinor_elems(g);
+  const float c = (float)(2.0 / (nbatch * sums[2 * b + 1]));
+  cx<float> o[12], t[12], d[12];
+  load_site(out + fo, g, par, h, o);
+  load_site(e + fo, g, par, h, t);
+  for (int k = 0; k < 12; k++) d[k] = c * (o[k] - t[k]);
+  store_site(dout + fo, g, par, h, d, 0);
+}
+
+// Adam on FP32 weights (Kingma & Ba 2015), bias-corrected.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ grad, float* __restrict__ m,
+                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gr = grad[i];
+  const float mi = b1 * m[i] + (1 - b1) * gr;
+  const float vi = b2 * v[i] + (1 - b2) * gr * gr;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// FP16 native -> FP32 native and back (for applying the network inside the FP16 solver).
+__global__ __launch_bounds__(256) void k_h2f(Geom g, const __half2* __restrict__ src, float2* __restrict__ dst,
+                                             float scale) {
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  if (i_site >= 2 * g.Vh) return;
+  const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+  const size_t o = (size_t)blockIdx.y * spinor_elems(g);
+  cx<float> f[12];
+  load_site(src + o, g, par, h, f);
+  for (int k = 0; k < 12; k++) f[k] = scale * f[k];
+  store_site(dst + o, g, par, h, f, 0);
+}
+__global__ __launch_bounds__(256) void k_f2h(Geom g, const float2* __restrict__ src, __half2* __restrict__ dst,
+                                             int ftz) {
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  if (i_site >= 2 * g.Vh) return;
+  const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+  const size_t o = (size_t)blockIdx.y * spinor_elems(g);
+  cx<float> f[12];
+  load_site(src + o, g, par, h, f);
+  store_site(dst + o, g, par, h, f, ftz);
+}
+
+}  // namespace qcd
+
+// ===========================================================================
+// Host side: the network handle and its C ABI.
+
+using namespace qcd;
+
+struct qcd_ptc {
+  const qcd_gauge* gauge;
+  Geom g;
+  int nlayers;
+  int channels[kPtcMaxLayers + 1];
+  PtcLayerDev L[kPtcMaxLayers];
+  int max_batch;
+  size_t nweights;                  // complex weights in total
+  size_t woff[kPtcMaxLayers];       // complex offset of each layer's weights
+  float2* w;                        // FP32 master weights
+  float2* grad;
+  float2* adam_m;
+  float2* adam_v;
+  int adam_step;
+  short* A[kPtcMaxLayers];          // BF16 GEMM operands
+  float2* act[kPtcMaxLayers + 1];   // activations (batch x channels native FP32 fields)
+  float2* target;                   // training targets (batch fields)
+  float2* dact[2];                  // gradient ping-pong buffers
+  short* X[kPtcMaxLayers];          // transported inputs per layer (kept for the backward pass)
+  short* DO;
+  float* DX;
+  float* Gp;
+  double* partials;
+  double* sums;
+  int mix_blocks;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+template <typename... A> qcd_status pfail(qcd_status code, const char* fmt, A... a) {
+  return (qcd_status)set_error((int)code, fmt, a...);
+}
+#define PTC_TRY(expr)                                                                                   \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess) return pfail(QCD_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+#define PTC_LAUNCHED()                                                                                  \
+  do {                                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                                  \
+    if (e_ != hipSuccess) return pfail(QCD_ERR_HIP, "kernel launch: %s", hipGetErrorString(e_));        \
+  } while (0)
+
+size_t fields_bytes(const Geom& g, size_t nf) { return nf * spinor_elems(g) * sizeof(float2); }
+int site_blocks_pad(const Geom& g) { return (2 * g.nb * 64 + 255) / 256; }
+int site_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
+const float2* links32(const qcd_ptc* n) { return (const float2*)n->gauge->U[kFP32]; }
+
+qcd_status alloc(qcd_ptc* n, void** p, size_t bytes) {
+  PTC_TRY(hipMalloc(p, bytes ? bytes : 256));
+  n->allocs.push_back(*p);
+  return QCD_OK;
+}
+
+void prep_weights(qcd_ptc* n, hipStream_t st) {
+  for (int l = 0; l < n->nlayers; l++) {
+    const int cnt = 16 * n->L[l].Kp;
+    hipLaunchKernelGGL(k_ptc_prep_A, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
+                       (const float2*)(n->w + n->woff[l]), n->A[l]);
+  }
+}
+
+// Forward through all layers from act[0]; with train the transported inputs
+// of every layer are kept (else one buffer is reused).
+void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
+  const Geom& g = n->g;
+  for (int l = 0; l < n->nlayers; l++) {
+    short* X = train ? n->X[l] : n->X[0];
+    hipLaunchKernelGGL(k_ptc_transport, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, n->L[l],
+                       (const float2*)n->act[l], links32(n), X);
+    hipLaunchKernelGGL(k_ptc_mix, dim3(n->mix_blocks), dim3(256), 0, st, g, n->L[l], (const short*)X,
+                       (const short*)n->A[l], n->act[l + 1], nb);
+  }
+}
+
+// Loss and gradient of the weights (into n->grad) for the batch in act[0] / target.
+qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
+  const Geom& g = n->g;
+  forward(n, nb, true, st);
+  const int last = n->nlayers;
+  hipLaunchKernelGGL(k_ptc_loss_parts, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[last],
+                     (const float2*)n->target, n->partials);
+  hipLaunchKernelGGL(k_ptc_loss_finish, dim3(nb), dim3(1024), 0, st, (const double*)n->partials, site_blocks(g), nb,
+                     n->sums);
+  hipLaunchKernelGGL(k_ptc_dout, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[last],
+                     (const float2*)n->target, (const double*)n->sums, nb, n->dact[0]);
+  PTC_TRY(hipMemsetAsync(n->grad, 0, n->nweights * sizeof(float2), st));
+  int cur = 0;
+  for (int l = n->nlayers - 1; l >= 0; l--) {
+    const PtcLayerDev& L = n->L[l];
+    hipLaunchKernelGGL(k_ptc_dout_bf16, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, L,
+                       (const float2*)n->dact[cur], n->DO);
+    hipLaunchKernelGGL(k_ptc_mix_dw, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
+                       (const short*)n->X[l], n->Gp, nb);
+    hipLaunchKernelGGL(k_ptc_dw_finish, dim3((L.M * L.K + 255) / 256), dim3(256), 0, st, L, (const float*)n->Gp,
+                       n->mix_blocks * 4, n->grad + n->woff[l]);
+    if (l > 0) {
+      hipLaunchKernelGGL(k_ptc_mix_dx, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
+                         (const short*)n->A[l], n->DX, nb);
+      hipLaunchKernelGGL(k_ptc_transport_adj, dim3(site_blocks(g), nb), dim3(256), 0, st, g, L, (const float*)n->DX,
+                         links32(n), n->dact[cur ^ 1]);
+      cur ^= 1;
+    }
+  }
+  PTC_LAUNCHED();
+  if (loss) {
+    std::vector<double> h(2 * nb);
+    PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    PTC_TRY(hipStreamSynchronize(st));
+    double tot = 0;
+    for (int b = 0; b < nb; b++) tot += h[2 * b] / h[2 * b + 1];
+    *loss = tot / nb;
+  }
+  return QCD_OK;
+}
+
+qcd_status check_batch(const qcd_ptc* n, int nb) {
+  if (!n) return pfail(QCD_ERR_ARG, "null network handle");
+  if (nb < 1 || nb > n->max_batch) return pfail(QCD_ERR_ARG, "batch must be in 1..%d", n->max_batch);
+  return QCD_OK;
+}
+
+}  // namespace
+
+namespace qcd {
+// Apply the network to nb native FP16 fields: out = M(in_scale * in).
+// Used by the preconditioned inner solver (all launches are stream-ordered
+// and capturable).
+void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scale, int ftz, hipStream_t st) {
+  const Geom& g = n->g;
+  hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const __half2*)in, n->act[0], in_scale);
+  forward(n, nb, false, st);
+  hipLaunchKernelGGL(k_f2h, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[n->nlayers],
+                     (__half2*)out, ftz);
+}
+int ptc_max_batch(const qcd_ptc* n) { return n->max_batch; }
+const qcd_gauge* ptc_gauge(const qcd_ptc* n) { return n->gauge; }
+}  // namespace qcd
+
+extern "C" {
+
+qcd_status qcd_ptc_free(qcd_ptc* n) {
+  if (!n) return QCD_OK;
+  for (void* p : n->allocs) (void)hipFree(p);
+  delete n;
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, const int* channels, int max_batch,
+                          void* stream) {
+  if (!out || !gauge || !channels) return pfail(QCD_ERR_ARG, "null argument");
+  if (nlayers < 1 || nlayers > kPtcMaxLayers) return pfail(QCD_ERR_ARG, "nlayers must be in 1..%d", kPtcMaxLayers);
+  if (max_batch < 1 || max_batch > kMaxRhs) return pfail(QCD_ERR_ARG, "max_batch must be in 1..%d", kMaxRhs);
+  if (!gauge->U[kFP32]) return pfail(QCD_ERR_ARG, "the network needs the gauge handle's FP32 links");
+  for (int l = 0; l <= nlayers; l++)
+    if (channels[l] < 1 || channels[l] > 2) return pfail(QCD_ERR_UNSUPPORTED, "channels must be 1 or 2 per layer");
+  if (channels[0] != 1 || channels[nlayers] != 1)
+    return pfail(QCD_ERR_ARG, "the network maps one spinor field to one spinor field");
+  qcd_ptc* n = new qcd_ptc();
+  n->gauge = gauge;
+  n->g = gauge->g;
+  n->nlayers = nlayers;
+  n->max_batch = max_batch;
+  n->nweights = 0;
+  int maxKp = 16, maxc = 1;
+  for (int l = 0; l <= nlayers; l++) n->channels[l] = channels[l];
+  for (int l = 0; l < nlayers; l++) {
+    PtcLayerDev& L = n->L[l];
+    L.cin = channels[l];
+    L.cout = channels[l + 1];
+    L.K = 9 * L.cin * 4;
+    L.M = L.cout * 4;
+    L.Kp = ((2 * L.K + 15) / 16) * 16;
+    n->woff[l] = n->nweights;
+    n->nweights += (size_t)9 * L.cout * L.cin * 16;
+    maxKp = std::max(maxKp, L.Kp);
+    maxc = std::max(maxc, std::max(L.cin, L.cout));
+  }
+  const Geom& g = n->g;
+  const size_t N = (size_t)2 * g.nb * 64 * 3;
+  n->mix_blocks = 1024;
+  qcd_status rc = QCD_OK;
+#define PTC_ALLOC(ptr, bytes) \
+  if (rc == QCD_OK) rc = alloc(n, (void**)&(ptr), (bytes))
+  PTC_ALLOC(n->w, n->nweights * sizeof(float2));
+  PTC_ALLOC(n->grad, n->nweights * sizeof(float2));
+  PTC_ALLOC(n->adam_m, n->nweights * sizeof(float2));
+  PTC_ALLOC(n->adam_v, n->nweights * sizeof(float2));
+  for (int l = 0; l < nlayers; l++) {
+    PTC_ALLOC(n->A[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
+    // inference reuses X[0] for every layer, so it takes the widest layer's size
+    PTC_ALLOC(n->X[l], (size_t)max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * sizeof(short));
+  }
+  for (int l = 0; l <= nlayers; l++) PTC_ALLOC(n->act[l], fields_bytes(g, (size_t)max_batch * channels[l]));
+  PTC_ALLOC(n->target, fields_bytes(g, max_batch));
+  PTC_ALLOC(n->dact[0], fields_bytes(g, (size_t)max_batch * maxc));
+  PTC_ALLOC(n->dact[1], fields_bytes(g, (size_t)max_batch * maxc));
+  PTC_ALLOC(n->DO, (size_t)max_batch * N * 16 * sizeof(short));
+  PTC_ALLOC(n->DX, (size_t)max_batch * N * maxKp * sizeof(float));
+  PTC_ALLOC(n->Gp, (size_t)n->mix_blocks * 4 * 16 * maxKp * sizeof(float));
+  PTC_ALLOC(n->partials, (size_t)max_batch * site_blocks(g) * 2 * sizeof(double));
+  PTC_ALLOC(n->sums, (size_t)max_batch * 2 * sizeof(double));
+#undef PTC_ALLOC
+  hipStream_t st = (hipStream_t)stream;
+  if (rc == QCD_OK) {
+    // activations of padding sites are never written: clear once so they stay finite
+    for (int l = 0; l <= nlayers; l++)
+      (void)hipMemsetAsync(n->act[l], 0, fields_bytes(g, (size_t)max_batch * channels[l]), st);
+    (void)hipMemsetAsync(n->w, 0, n->nweights * sizeof(float2), st);
+    (void)hipMemsetAsync(n->adam_m, 0, n->nweights * sizeof(float2), st);
+    (void)hipMemsetAsync(n->adam_v, 0, n->nweights * sizeof(float2), st);
+    prep_weights(n, st);
+    if (hipStreamSynchronize(st) != hipSuccess) rc = pfail(QCD_ERR_HIP, "synchronise failed");
+  }
+  if (rc != QCD_OK) {
+    qcd_ptc_free(n);
+    return rc;
+  }
+  *out = n;
+  return QCD_OK;
+}
+
+size_t qcd_ptc_num_weights(const qcd_ptc* n) { return n ? n->nweights : 0; }
+
+qcd_status qcd_ptc_set_weights(qcd_ptc* n, const double* w_host, void* stream) {
+  if (!n || !w_host) return pfail(QCD_ERR_ARG, "null argument");
+  std::vector<float2> h(n->nweights);
+  for (size_t i = 0; i < n->nweights; i++) h[i] = make_float2((float)w_host[2 * i], (float)w_host[2 * i + 1]);
+  hipStream_t st = (hipStream_t)stream;
+  PTC_TRY(hipMemcpyAsync(n->w, h.data(), n->nweights * sizeof(float2), hipMemcpyHostToDevice, st));
+  PTC_TRY(hipMemsetAsync(n->adam_m, 0, n->nweights * sizeof(float2), st));
+  PTC_TRY(hipMemsetAsync(n->adam_v, 0, n->nweights * sizeof(float2), st));
+  n->adam_step = 0;
+  prep_weights(n, st);
+  PTC_LAUNCHED();
+  PTC_TRY(hipStreamSynchronize(st));
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_get_weights(const qcd_ptc* n, double* w_host, void* stream) {
+  if (!n || !w_host) return pfail(QCD_ERR_ARG, "null argument");
+  std::vector<float2> h(n->nweights);
+  hipStream_t st = (hipStream_t)stream;
+  PTC_TRY(hipMemcpyAsync(h.data(), n->w, n->nweights * sizeof(float2), hipMemcpyDeviceToHost, st));
+  PTC_TRY(hipStreamSynchronize(st));
+  for (size_t i = 0; i < n->nweights; i++) {
+    w_host[2 * i] = h[i].x;
+    w_host[2 * i + 1] = h[i].y;
+  }
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_apply(qcd_ptc* n, int nbatch, void* out_dev, const void* in_dev, void* stream) {
+  qcd_status rc = check_batch(n, nbatch);
+  if (rc) return rc;
+  if (!out_dev || !in_dev) return pfail(QCD_ERR_ARG, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)in_dev, 1.0, 0, nullptr, st);
+  forward(n, nbatch, false, st);
+  launch_unpack_spinor(n->g, kFP32, nbatch, (double*)out_dev, n->act[n->nlayers], nullptr, 1.0, st);
+  PTC_LAUNCHED();
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_loss_grad(qcd_ptc* n, int nbatch, const void* r_dev, const void* e_dev, double* loss,
+                             double* grad_host, void* stream) {
+  qcd_status rc = check_batch(n, nbatch);
+  if (rc) return rc;
+  if (!r_dev || !e_dev) return pfail(QCD_ERR_ARG, "null vector");
+  hipStream_t st = (hipStream_t)stream;
+  launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)r_dev, 1.0, 0, nullptr, st);
+  launch_pack_spinor(n->g, kFP32, nbatch, n->target, (const double*)e_dev, 1.0, 0, nullptr, st);
+  if ((rc = loss_grad(n, nbatch, loss, st))) return rc;
+  if (grad_host) {
+    std::vector<float2> h(n->nweights);
+    PTC_TRY(hipMemcpyAsync(h.data(), n->grad, n->nweights * sizeof(float2), hipMemcpyDeviceToHost, st));
+    PTC_TRY(hipStreamSynchronize(st));
+    for (size_t i = 0; i < n->nweights; i++) {
+      grad_host[2 * i] = h[i].x;
+      grad_host[2 * i + 1] = h[i].y;
+    }
+  }
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_train_step(qcd_ptc* n, int nbatch, const void* r_dev, const void* e_dev, double lr, double* loss,
+                              void* stream) {
+  qcd_status rc = qcd_ptc_loss_grad(n, nbatch, r_dev, e_dev, loss, nullptr, stream);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  n->adam_step++;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)n->adam_step), c2 = 1.0f - powf(b2, (float)n->adam_step);
+  const int cnt = (int)(2 * n->nweights);
+  hipLaunchKernelGGL(k_adam, dim3((cnt + 255) / 256), dim3(256), 0, st, (float*)n->w, (const float*)n->grad,
+                     (float*)n->adam_m, (float*)n->adam_v, cnt, (float)lr, b1, b2, 1e-8f, c1, c2);
+  prep_weights(n, st);
+  PTC_LAUNCHED();
+  return QCD_OK;
+}
+
+}  // extern "C"

@@ -111,3 +111,20 @@ def splitmix64_sequence(state: int, n: int) -> np.ndarray:
     out = np.empty(n, dtype=np.uint64)
     _load().qi_splitmix_raw(int(state) & (2**64 - 1), out.ctypes.data, int(n))
     return out
+
+
+def ptc_weights(channels, seed, scale=0.3):
+    """Seeded complex weights of the parallel-transport network, one array
+    (9, C_out, C_in, 4, 4) per layer channels[0] -> channels[1] -> ...: complex
+    Gaussian entries of size scale / sqrt(2 * 9 * 4 * C_in), plus the identity
+    on the path p = 0 from input channel j % C_in to output channel j, so that
+    an untrained network is close to a multiple of the identity."""
+    rng = np.random.default_rng(seed)
+    Ws = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        shape = (9, cout, cin, 4, 4)
+        W = (rng.normal(size=shape) + 1j * rng.normal(size=shape)) * (scale / np.sqrt(2 * 9 * 4 * cin))
+        for j in range(cout):
+            W[0, j, j % cin] += np.eye(4)
+        Ws.append(W)
+    return Ws
