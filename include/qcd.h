@@ -58,6 +58,7 @@ typedef enum { QCD_LAYOUT_CANONICAL = 0, QCD_LAYOUT_NATIVE = 1 } qcd_layout;
 typedef enum { QCD_OP_D = 0, QCD_OP_H = 1, QCD_OP_DDAG = 2, QCD_OP_HDAG = 3 } qcd_op;
 
 typedef struct qcd_gauge qcd_gauge; /* opaque handle */
+typedef struct qcd_ptc qcd_ptc;     /* opaque handle of the learned preconditioner (declared below) */
 
 /* Parameters of the rescaled BiCGStab (Alg. 4; Alg. 5 when sigma_lambda > 0). */
 typedef struct {
@@ -82,6 +83,14 @@ typedef struct {
   double s;                 /* the residual is rescaled to norm s before conversion */
   int recalc_shat;          /* 1: correct with s^ = |single(y~)| (Alg. 3); 0: with s */
   qcd_bicgstab_params inner;/* inner.tol is eps_tol (the paper's eps_tol^2 = 1e-4 is tol = 1e-2) */
+  const qcd_ptc* precond;   /* NULL, or a network (built on the same gauge handle, max_batch >= nrhs) used
+                               as right preconditioner M of the FP16 inner solve: the inner BiCGStab solves
+                               (D c M) u = y~ and the refinement step corrects with t = c M u.  A step whose
+                               FP64 residual does not drop, or that goes non-finite, is undone and the call
+                               continues without the network (flexible refinement: the outer FP64 residual
+                               is recomputed every step, so M may differ from D^-1 by any amount) */
+  double precond_scale;     /* c above; 0 = 1 / (largest |M v| / |v| over the first inner right-hand sides),
+                               which keeps the FP16 vectors in the range of the plain solver */
 } qcd_ir_params;
 
 typedef struct {
@@ -101,6 +110,9 @@ typedef struct {
   int outer_history_cap;
   double* zeros;            /* optional: zero reals in y~ per refinement step (Fig. 9 diagnostic),
                                capacity outer_history_cap */
+  int precond_steps;        /* refinement steps whose inner solve used the network */
+  int precond_fallback;     /* refinement step at which the network was dropped, or -1 */
+  double precond_scale;     /* the scale c used (0 without a network) */
 } qcd_solve_info;
 
 /* Message for the last error on this thread ("" if none). */
@@ -144,8 +156,9 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
 /* Bytes of one native spinor field in precision prec. */
 size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 
-/* Workspace bytes that qcd_solve_mixed_ir (what = 0), qcd_bicgstab (what = 1)
- * or qcd_dslash with canonical layout (what = 2) need for inner precision
+/* Workspace bytes that qcd_solve_mixed_ir (what = 0; what = 3 with a network
+ * preconditioner), qcd_bicgstab (what = 1) or qcd_dslash with canonical
+ * layout (what = 2) need for inner precision
  * prec, max_iter history entries and nrhs right-hand sides.  Passing ws =
  * NULL to those calls makes the handle's own cached workspace be used
  * (allocated on first use; a handle is not safe for concurrent calls). */
@@ -216,7 +229,6 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
  * construction of the paper; the solver uses M as a right preconditioner of
  * its inner BiCGStab (qcd_ir_params.precond).
  */
-typedef struct qcd_ptc qcd_ptc;
 
 /* Create a network of nlayers layers with channels[0..nlayers] spinor fields
  * per layer boundary (channels[0] = channels[nlayers] = 1, others 1 or 2) on
@@ -226,6 +238,15 @@ typedef struct qcd_ptc qcd_ptc;
 qcd_status qcd_ptc_create(qcd_ptc** net, const qcd_gauge* g, int nlayers, const int* channels, int max_batch,
                           void* stream);
 qcd_status qcd_ptc_free(qcd_ptc* net);
+/* Point the network at another gauge field with the same extents (training
+ * over several fields with one set of weights and optimiser state). */
+qcd_status qcd_ptc_set_gauge(qcd_ptc* net, const qcd_gauge* g);
+/* Set the weights of a (1, 2, 2, 1) network to the third-order Neumann
+ * series of the Wilson matrix, M = sum_{k=0..3} (kappa H)^k, so that
+ * D M = 1 - (kappa H)^4 (with D = 1 - kappa H, eq. (1)).  Layers: (psi,
+ * kappa H psi) -> (c0 + c1, kappa H (c0 + c1)) -> c0 + kappa H c1.  A
+ * starting point for training.  Synchronises. */
+qcd_status qcd_ptc_init_neumann(qcd_ptc* net, double kappa, void* stream);
 /* Complex weights in total: sum over layers of 9 * C_out * C_in * 16. */
 size_t qcd_ptc_num_weights(const qcd_ptc* net);
 /* Host complex128 weights, layers concatenated, each [9][C_out][C_in][4][4];

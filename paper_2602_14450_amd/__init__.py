@@ -41,7 +41,8 @@ class BicgstabParams(ctypes.Structure):
 
 class IRParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_outer", ctypes.c_int), ("inner_prec", ctypes.c_int),
-                ("s", ctypes.c_double), ("recalc_shat", ctypes.c_int), ("inner", BicgstabParams)]
+                ("s", ctypes.c_double), ("recalc_shat", ctypes.c_int), ("inner", BicgstabParams),
+                ("precond", ctypes.c_void_p), ("precond_scale", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -50,7 +51,9 @@ class SolveInfo(ctypes.Structure):
                 ("inner_status", ctypes.c_int), ("first_shat_over_s", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
                 ("history_len", ctypes.c_int), ("outer_history", ctypes.POINTER(ctypes.c_double)),
-                ("outer_history_cap", ctypes.c_int), ("zeros", ctypes.POINTER(ctypes.c_double))]
+                ("outer_history_cap", ctypes.c_int), ("zeros", ctypes.POINTER(ctypes.c_double)),
+                ("precond_steps", ctypes.c_int), ("precond_fallback", ctypes.c_int),
+                ("precond_scale", ctypes.c_double)]
 
 
 _vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
@@ -81,8 +84,10 @@ _lib.qcd_ptc_get_weights.argtypes = [_vp, _vp, _vp]
 _lib.qcd_ptc_apply.argtypes = [_vp, _i, _vp, _vp, _vp]
 _lib.qcd_ptc_loss_grad.argtypes = [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp, _vp]
 _lib.qcd_ptc_train_step.argtypes = [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_d), _vp]
+_lib.qcd_ptc_set_gauge.argtypes = [_vp, _vp]
+_lib.qcd_ptc_init_neumann.argtypes = [_vp, _d, _vp]
 for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get_weights", "qcd_ptc_apply",
-           "qcd_ptc_loss_grad", "qcd_ptc_train_step",
+           "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
            "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
@@ -90,7 +95,7 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
 EXPORTED = ["qcd_last_error", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
-            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step"]
+            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann"]
 
 
 class QcdError(RuntimeError):
@@ -235,6 +240,9 @@ class Info:
     history: list = field(default_factory=list)
     outer_history: list = field(default_factory=list)
     zeros: list = field(default_factory=list)
+    precond_steps: int = 0
+    precond_fallback: int = -1
+    precond_scale: float = 0.0
 
 
 def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph=False):
@@ -266,7 +274,7 @@ def _infos_out(code, infos, keep):
         out.append(Info(STATUS.get(code, str(code)), info.outer_iters, info.inner_iters, info.matvec_low,
                         info.matvec_fp64, info.true_rel_residual, info.seconds, info.inner_status,
                         info.first_shat_over_s, list(hist[:info.history_len]), list(outer[:n_out]),
-                        list(zeros[:n_out])))
+                        list(zeros[:n_out]), info.precond_steps, info.precond_fallback, info.precond_scale))
     return out[0] if len(out) == 1 else out
 
 
@@ -290,13 +298,16 @@ def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1
 def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
                    s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                    recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None, history=False,
-                   raise_on_error=True, use_graph=False):
+                   raise_on_error=True, use_graph=False, precond=None, precond_scale=0.0):
     """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab,
-    for one or several right-hand sides; returns an Info or a list of them."""
+    for one or several right-hand sides; returns an Info or a list of them.
+    precond: a PTC network used as right preconditioner of the FP16 inner
+    solve (flexible refinement with fallback to the plain step)."""
     n = g.nrhs_of(b)
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
                          use_graph)
-    p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner)
+    p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner,
+                 precond.handle if precond is not None else None, float(precond_scale))
     infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
     ws = _ptr(workspace) if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
@@ -334,6 +345,15 @@ class PTC:
             self.close()
         except Exception:
             pass
+
+    def set_gauge(self, g: Gauge):
+        """Bind the network to another gauge field of the same extents (keeps weights and Adam state)."""
+        _check(_lib.qcd_ptc_set_gauge(self.handle, g.handle))
+        self.gauge = g
+
+    def init_neumann(self, kappa):
+        """Weights of M = sum_{k<=3} (kappa H)^k (channels 1, 2, 2, 1)."""
+        _check(_lib.qcd_ptc_init_neumann(self.handle, float(kappa), _stream()))
 
     def _shapes(self):
         return [(9, co, ci, 4, 4) for ci, co in zip(self.channels[:-1], self.channels[1:])]

@@ -83,6 +83,8 @@ struct Work {
   void* p = nullptr;
   void* v = nullptr;
   void* t = nullptr;
+  void* z = nullptr;        // M p and M s of the preconditioned iteration
+  double2* x64b = nullptr;  // x before a preconditioned refinement step
   double* partials = nullptr;
   Scalars* sc = nullptr;
   double* history = nullptr;
@@ -92,13 +94,13 @@ struct Work {
   size_t bytes = 0;
 };
 
-// what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout
+// what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout, 3 preconditioned refinement
 Work carve(const qcd_gauge* G, int what, int prec, int max_iter, int n, char* base) {
   const Geom& g = G->g;
   Carve c{base};
   Work w;
   w.n = n;
-  if (what == 0 || what == 1) {
+  if (what == 0 || what == 1 || what == 3) {
     w.x64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.r64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
@@ -110,6 +112,10 @@ Work carve(const qcd_gauge* G, int what, int prec, int max_iter, int n, char* ba
     w.t = c.take(n * spinor_bytes(g, prec));
     w.hist_stride = max_iter > 0 ? max_iter : 1;
     w.history = (double*)c.take(sizeof(double) * (size_t)w.hist_stride * n);
+    if (what == 3) {
+      w.z = c.take(n * spinor_bytes(g, prec));
+      w.x64b = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    }
   } else {
     w.x = c.take(n * spinor_bytes(g, prec));
     w.r = c.take(n * spinor_bytes(g, prec));
@@ -193,18 +199,37 @@ qcd_status check_bicg_params(const qcd_bicgstab_params* p) {
   return QCD_OK;
 }
 
+// The right preconditioner of the inner iteration: z = c M v (FP16 fields).
+struct Precond {
+  qcd_ptc* net = nullptr;
+  float scale = 1.0f;
+};
+
 // One BiCGStab iteration of Alg. 4 / Alg. 5 for all right-hand sides, entirely on the device.
-void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, int ftz, hipStream_t st) {
+// With a preconditioner the operator is D c M: v = D (c M p), t = D (c M s), and (t, s) is
+// taken against s itself (the TSAux epilogue), so x accumulates the iterate u of D c M u = y.
+void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, int ftz, const Precond& pc,
+                    hipStream_t st) {
   const Geom& G = g->g;
   const int n = w.n;
   const DslashTune& tu = g->tune[prec];
   const int drows = dslash_partial_rows(G, tu, n), frows = flat_rows(G, prec);
   const void* U = g->U[prec];
   launch_p_update(G, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
-  launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.p, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
+  if (pc.net) {
+    ptc_apply_half(pc.net, n, w.p, w.z, pc.scale, ftz, st);
+    launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.z, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
+  } else {
+    launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.p, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
+  }
   launch_alpha(n, w.sc, w.partials, drows, st);
   launch_s_update(G, prec, n, w.sc, w.r, w.v, ftz, st);
-  launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.r, U, kappa, nullptr, w.partials, w.sc, ftz, st);
+  if (pc.net) {
+    ptc_apply_half(pc.net, n, w.r, w.z, pc.scale, ftz, st);
+    launch_dslash(prec, G, tu, kOpD, kEpiTSAux, n, w.t, w.z, U, kappa, w.r, w.partials, w.sc, ftz, st);
+  } else {
+    launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.r, U, kappa, nullptr, w.partials, w.sc, ftz, st);
+  }
   launch_omega(n, w.sc, w.partials, drows, st);
   launch_xr_update(G, prec, n, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
   launch_iter_end(n, w.sc, w.partials, frows, w.history, w.hist_stride, st);
@@ -221,15 +246,18 @@ void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* 
 // handle's own stream (the null stream cannot be captured); the graph is
 // launched on the caller's stream.  The kernels take every changing value
 // from device memory, so one capture serves every iteration.
-qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Work& w, int ftz,
+qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Work& w, int ftz, const Precond& pc,
                            hipGraphExec_t* out) {
   qcd_gauge* g = const_cast<qcd_gauge*>(gc);
   unsigned long long kbits;
   memcpy(&kbits, &kappa, sizeof kbits);
-  const unsigned long long key[6] = {(unsigned long long)prec, (unsigned long long)w.n, (unsigned long long)w.x,
+  unsigned sbits;
+  memcpy(&sbits, &pc.scale, sizeof sbits);
+  const unsigned long long key[8] = {(unsigned long long)prec, (unsigned long long)w.n, (unsigned long long)w.x,
                                      kbits, (unsigned long long)ftz,
                                      (unsigned long long)(g->tune[prec].sched * 64 + g->tune[prec].variant * 8 +
-                                                          g->tune[prec].rhs_tile)};
+                                                          g->tune[prec].rhs_tile),
+                                     (unsigned long long)(uintptr_t)pc.net, pc.net ? sbits : 0ull};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
     return QCD_OK;
@@ -241,7 +269,7 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
   if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  bicg_iteration(g, prec, kappa, w, ftz, g->cap_stream);
+  bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
   hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
   if (e != hipSuccess) return fail(QCD_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
@@ -268,14 +296,14 @@ bool any_active(const qcd_gauge* g, int n) {
 // iterations the observed convergence rate predicts the slowest right-hand
 // side still needs, plus one.
 qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, const qcd_bicgstab_params& p,
-                     hipStream_t st) {
+                     const Precond& pc, hipStream_t st) {
   const int K0 = p.check_every > 0 ? p.check_every : 4;
   const int n = w.n;
   qcd_status s = read_scalars(g, w, st);
   if (s) return s;
   hipGraphExec_t gexec = nullptr;
   if (p.use_graph && any_active(g, n)) {
-    if ((s = iteration_graph(g, prec, kappa, w, p.ftz, &gexec))) return s;
+    if ((s = iteration_graph(g, prec, kappa, w, p.ftz, pc, &gexec))) return s;
   }
   int launched = 0, chunk = K0;
   double prev_res2[kMaxRhs];
@@ -289,7 +317,7 @@ qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, 
       if (gexec)
         HIP_TRY(hipGraphLaunch(gexec, st));
       else
-        bicg_iteration(g, prec, kappa, w, p.ftz, st);
+        bicg_iteration(g, prec, kappa, w, p.ftz, pc, st);
     }
     HIP_LAUNCHED();
     launched += chunk;
@@ -515,7 +543,7 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec) {
 }
 
 size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs) {
-  if (!g || !valid_prec(prec) || what < 0 || what > 2 || nrhs < 1 || nrhs > kMaxRhs) return 0;
+  if (!g || !valid_prec(prec) || what < 0 || what > 3 || nrhs < 1 || nrhs > kMaxRhs) return 0;
   return carve(g, what, prec, max_iter, nrhs, nullptr).bytes;
 }
 
@@ -634,7 +662,7 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
   HIP_TRY(hipMemcpyAsync(w.rstar, w.r, n * spinor_bytes(G, prec), hipMemcpyDeviceToDevice, st));
   launch_bicg_init(n, w.sc, w.partials, rows, st);
   HIP_LAUNCHED();
-  if ((rc = bicg_loop(g, prec, kappa, w, *p, st))) return rc;
+  if ((rc = bicg_loop(g, prec, kappa, w, *p, Precond{}, st))) return rc;
   Scalars sc[kMaxRhs];
   memcpy(sc, g->host_sc, sizeof(Scalars) * n);
   // x = xscale X / lambda' (zero for a right-hand side that made no step)
@@ -687,9 +715,18 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
   if ((rc = check_bicg_params(&p->inner))) return rc;
   const int prec = p->inner_prec;
   const int n = nrhs;
+  qcd_ptc* net = const_cast<qcd_ptc*>(p->precond);
+  if (net) {
+    if (prec != kFP16) return fail(QCD_ERR_UNSUPPORTED, "the network preconditioner runs with the FP16 inner solve");
+    if (ptc_gauge(net) != g) return fail(QCD_ERR_ARG, "the network is bound to another gauge handle");
+    if (n > ptc_max_batch(net)) return fail(QCD_ERR_ARG, "nrhs %d exceeds the network's max_batch %d", n,
+                                            ptc_max_batch(net));
+    if (!(p->precond_scale >= 0) || !std::isfinite(p->precond_scale))
+      return fail(QCD_ERR_ARG, "precond_scale must be finite and >= 0");
+  }
   hipStream_t st = S(stream);
   Work w;
-  if ((rc = get_work(g, 0, prec, p->inner.max_iter, n, ws, ws_bytes, &w))) return rc;
+  if ((rc = get_work(g, net ? 3 : 0, prec, p->inner.max_iter, n, ws, ws_bytes, &w))) return rc;
   const Geom& G = g->g;
   const int rows = site_grid(G);
   const int drows64 = dslash_partial_rows(G, g->tune[kFP64], n);
@@ -719,10 +756,17 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
     if (info) {
       info[i].history_len = 0;
       info[i].first_shat_over_s = 0;
+      info[i].precond_steps = 0;
+      info[i].precond_fallback = -1;
+      info[i].precond_scale = 0;
     }
     any |= g->host_sc[i].outer_active && std::isfinite(bn[i]);
   }
   if (!std::isfinite(bn[0]) && n == 1) any = false;
+  Precond pc;
+  pc.net = net;
+  pc.scale = (float)p->precond_scale;
+  int pc_steps = 0, pc_fallback = -1;
   int step = 0;
   while (any) {
     if (step >= p->max_outer) {
@@ -730,32 +774,77 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
         if (g->host_sc[i].outer_active) result[i] = worse(result[i], QCD_NOT_CONVERGED);
       break;
     }
+    // keep x so that a preconditioned step that fails can be undone
+    if (pc.net) HIP_TRY(hipMemcpyAsync(w.x64b, w.x64, n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
     // y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start (right-hand
     // sides that met the tolerance are skipped by the kernels)
     launch_convert(G, prec, n, w.sc, (const double*)w.r64, w.r, w.rstar, w.partials, p->inner.ftz, st);
     launch_convert_finish(n, w.sc, w.partials, rows, p->recalc_shat, p->s, st);
     HIP_LAUNCHED();
-    if ((rc = bicg_loop(g, prec, kappa, w, p->inner, st))) return rc;
+    if (pc.net && pc.scale == 0.0f) {  // c = 1 / gain of M, measured on the first y~
+      double gain = 0;
+      if ((rc = ptc_gain(pc.net, n, w.r, &gain, st))) return rc;
+      pc.scale = gain > 0 ? (float)(1.0 / gain) : 1.0f;
+    }
+    if ((rc = bicg_loop(g, prec, kappa, w, p->inner, pc, st))) return rc;
     Scalars sc[kMaxRhs];
     memcpy(sc, g->host_sc, sizeof(Scalars) * n);
+    bool inner_failed[kMaxRhs];
     for (int i = 0; i < n; i++) {
+      inner_failed[i] = false;
       if (!sc[i].outer_active) continue;
       if (info && outer[i] == 0) info[i].first_shat_over_s = sc[i].shat / p->s;
       if (info && info[i].zeros && outer[i] < info[i].outer_history_cap) info[i].zeros[outer[i]] = sc[i].zeros;
       copy_history(info ? info + i : nullptr, w, i, sc[i].iter, sc[i].bnorm2, st);
       inner_total[i] += sc[i].iter;
       last_status[i] = sc[i].status;
-      if (sc[i].status == kNonFinite || sc[i].iter == 0)
+      inner_failed[i] = sc[i].status == kNonFinite || sc[i].iter == 0;
+      if (inner_failed[i] && !pc.net)
         result[i] = fail(sc[i].status == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
                          "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
                          sc[i].status, outer[i]);
     }
-    // x += (|r| / s^) double(t~); r = b - D x in FP64 (skipped where not refining)
-    launch_correct(G, prec, n, w.sc, (double*)w.x64, w.x, st);
+    // x += (|r| / s^) double(t~), with t~ = c M u~ when preconditioned; r = b - D x
+    // in FP64 (skipped where not refining)
+    if (pc.net) {
+      ptc_apply_half(pc.net, n, w.x, w.z, pc.scale, p->inner.ftz, st);
+      launch_correct(G, prec, n, w.sc, (double*)w.x64, w.z, st);
+    } else {
+      launch_correct(G, prec, n, w.sc, (double*)w.x64, w.x, st);
+    }
     residual64(g, kappa, w, nullptr, st);
     launch_outer_residual_norm(n, w.sc, w.partials, drows64, p->s, st);
     HIP_LAUNCHED();
     if ((rc = read_scalars(g, w, st))) return rc;
+    if (pc.net) {
+      // flexible step accepted only if every refining residual dropped and stayed finite
+      bool undo = false;
+      for (int i = 0; i < n; i++) {
+        if (!sc[i].outer_active) continue;
+        const double r_new = g->host_sc[i].out_rnorm;
+        if (inner_failed[i] || !std::isfinite(r_new) || !(r_new < rn[i])) undo = true;
+      }
+      if (undo) {
+        // restore x of the right-hand sides whose step failed, recompute r, and go on without M
+        for (int i = 0; i < n; i++) {
+          if (!sc[i].outer_active) continue;
+          const double r_new = g->host_sc[i].out_rnorm;
+          if (inner_failed[i] || !std::isfinite(r_new) || !(r_new < rn[i]))
+            HIP_TRY(hipMemcpyAsync((char*)w.x64 + i * spinor_bytes(G, kFP64), (char*)w.x64b + i * spinor_bytes(G, kFP64),
+                                   spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
+        }
+        for (int i = 0; i < n; i++) g->host_sc[i].outer_active = sc[i].outer_active;
+        HIP_TRY(hipMemcpyAsync(w.sc, g->host_sc, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
+        residual64(g, kappa, w, nullptr, st);
+        launch_outer_residual_norm(n, w.sc, w.partials, drows64, p->s, st);
+        HIP_LAUNCHED();
+        if ((rc = read_scalars(g, w, st))) return rc;
+        pc_fallback = step;
+        pc.net = nullptr;
+      } else {
+        pc_steps++;
+      }
+    }
     any = false;
     for (int i = 0; i < n; i++) {
       if (!sc[i].outer_active) continue;
@@ -786,6 +875,9 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
       info[i].true_rel_residual = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
       info[i].inner_status = last_status[i];
       info[i].seconds = now_s() - t0;
+      info[i].precond_steps = pc_steps;
+      info[i].precond_fallback = pc_fallback;
+      info[i].precond_scale = net ? pc.scale : 0.0;
     }
     res = worse(res, result[i]);
   }

@@ -325,7 +325,8 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
   out += vo;
   if (aux) aux += vo;
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
-  constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (EPI == kEpiTS ? 4 : 1));
+  constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
+  constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
   double red[NV];
 #pragma unroll
   for (int i = 0; i < NV; i++) red[i] = 0.0;
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     const T_ k = (T_)kappa;
     cx<T_> o[12], ctr[12], ax[12];
     if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(in, g, par, h, ctr);
-    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux) load_site(aux, g, par, h, ax);
+    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(aux, g, par, h, ax);
 #pragma unroll
     for (int i = 0; i < 12; i++) {
       if constexpr (OP == kOpH || OP == kOpHdag) {
@@ -367,11 +368,12 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
           if constexpr (EPI == kEpiDotAux) {  // (aux, out) = sum conj(aux) out
             acc0 += ax[i].re * os.re + ax[i].im * os.im;
             acc1 += ax[i].re * os.im - ax[i].im * os.re;
-          } else if constexpr (EPI == kEpiTS) {  // (t, s) with t = out, s = in; |t|^2, |s|^2
-            acc0 += os.re * ctr[i].re + os.im * ctr[i].im;
-            acc1 += os.re * ctr[i].im - os.im * ctr[i].re;
+          } else if constexpr (TS) {  // (t, s) with t = out, s = in (TS) or aux (TSAux); |t|^2, |s|^2
+            const cx<T_> sv = (EPI == kEpiTSAux) ? ax[i] : ctr[i];
+            acc0 += os.re * sv.re + os.im * sv.im;
+            acc1 += os.re * sv.im - os.im * sv.re;
             acc2 += norm2(os);
-            acc3 += norm2(ctr[i]);
+            acc3 += norm2(sv);
           } else {
             acc0 += norm2(os);
           }
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
       *reinterpret_cast<Gr*>(ob + j * 64 * C) = v;
     }
     if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
-    if constexpr (EPI == kEpiTS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
+    if constexpr (TS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
     if constexpr (EPI == kEpiResid) { red[0] = acc0; }
   }
   if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
@@ -445,6 +447,8 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
     QCD_LAUNCH(kOpD, kEpiDotAux);
   } else if (epi == kEpiTS) {
     QCD_LAUNCH(kOpD, kEpiTS);
+  } else if (epi == kEpiTSAux) {
+    QCD_LAUNCH(kOpD, kEpiTSAux);
   } else {
     QCD_LAUNCH(kOpD, kEpiResid);
   }

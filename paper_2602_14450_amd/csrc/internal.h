@@ -2,12 +2,13 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "common.h"
+#include "qcd.h"
 
 namespace qcd {
 
 enum { kFP64 = 0, kFP32 = 1, kFP16 = 2 };
 enum { kOpD = 0, kOpH = 1, kOpDdag = 2, kOpHdag = 3 };
-enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3 };
+enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3, kEpiTSAux = 4 };
 
 // Inner-solver status codes kept on the device.
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4 };
@@ -119,6 +120,8 @@ struct qcd_gauge;
 namespace qcd {
 // network applied to nb native FP16 fields: out = M(in_scale * in) (ptc.hip)
 void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scale, int ftz, hipStream_t st);
+// largest |M(v)| / |v| over nb native FP16 fields (synchronises)
+qcd_status ptc_gain(qcd_ptc* n, int nb, const void* in, double* gain, hipStream_t st);
 int ptc_max_batch(const qcd_ptc* n);
 const qcd_gauge* ptc_gauge(const qcd_ptc* n);
 }  // namespace qcd
@@ -135,6 +138,6 @@ struct qcd_gauge {
   // one captured BiCGStab iteration, reused while its key is unchanged
   hipStream_t cap_stream;
   hipGraphExec_t graph_exec;
-  unsigned long long graph_key[6];
+  unsigned long long graph_key[8];
 };
 

@@ -17,6 +17,8 @@
 // and an MFMA reduction over columns for dW = dOut X^H.  Activations are
 // native FP32 spinor fields; links are the handle's native FP32 copy.
 #include <algorithm>
+#include <cmath>
+#include <complex>
 #include <cstring>
 #include <vector>
 
@@ -415,6 +417,29 @@ __global__ __launch_bounds__(256) void k_ptc_dout(Geom g, const float2* __restri
   store_site(dout + fo, g, par, h, d, 0);
 }
 
+// Per-field |a|^2 and |b|^2 (for the gain |M(v)| / |v| of the network).
+__global__ __launch_bounds__(256) void k_ptc_norms(Geom g, const float2* __restrict__ a, const float2* __restrict__ b,
+                                                   double* __restrict__ partials) {
+  const int bi = blockIdx.y;
+  const int i_site = blockIdx.x * 256 + threadIdx.x;
+  double red[2] = {0, 0};
+  if (i_site < 2 * g.Vh) {
+    const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
+    const size_t fo = (size_t)bi * spinor_elems(g);
+    cx<float> x[12], y[12];
+    load_site(a + fo, g, par, h, x);
+    load_site(b + fo, g, par, h, y);
+    float na = 0, nb = 0;
+    for (int k = 0; k < 12; k++) {
+      na += norm2(x[k]);
+      nb += norm2(y[k]);
+    }
+    red[0] = na;
+    red[1] = nb;
+  }
+  block_reduce_store<2>(red, partials + (size_t)bi * gridDim.x * 2, blockIdx.x);
+}
+
 // Adam on FP32 weights (Kingma & Ba 2015), bias-corrected.
 __global__ void k_adam(float* __restrict__ w, const float* __restrict__ grad, float* __restrict__ m,
                        float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -594,6 +619,27 @@ void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scal
   hipLaunchKernelGGL(k_f2h, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[n->nlayers],
                      (__half2*)out, ftz);
 }
+// Largest |M(v_b)| / |v_b| over the nb native FP16 fields v_b (zero fields
+// skipped); synchronises.  Returns 0 if every field is zero.
+qcd_status ptc_gain(qcd_ptc* n, int nb, const void* in, double* gain, hipStream_t st) {
+  const Geom& g = n->g;
+  hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const __half2*)in, n->act[0], 1.0f);
+  forward(n, nb, false, st);
+  hipLaunchKernelGGL(k_ptc_norms, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[0],
+                     (const float2*)n->act[n->nlayers], n->partials);
+  hipLaunchKernelGGL(k_ptc_loss_finish, dim3(nb), dim3(1024), 0, st, (const double*)n->partials, site_blocks(g), nb,
+                     n->sums);
+  PTC_LAUNCHED();
+  std::vector<double> h(2 * nb);
+  PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  PTC_TRY(hipStreamSynchronize(st));
+  double best = 0;
+  for (int b = 0; b < nb; b++)
+    if (h[2 * b] > 0 && std::isfinite(h[2 * b + 1])) best = std::max(best, std::sqrt(h[2 * b + 1] / h[2 * b]));
+    else if (h[2 * b] > 0) return pfail(QCD_ERR_NONFINITE, "network output is not finite");
+  *gain = best;
+  return QCD_OK;
+}
 int ptc_max_batch(const qcd_ptc* n) { return n->max_batch; }
 const qcd_gauge* ptc_gauge(const qcd_ptc* n) { return n->gauge; }
 }  // namespace qcd
@@ -758,6 +804,58 @@ qcd_status qcd_ptc_train_step(qcd_ptc* n, int nbatch, const void* r_dev, const v
   prep_weights(n, st);
   PTC_LAUNCHED();
   return QCD_OK;
+}
+
+qcd_status qcd_ptc_set_gauge(qcd_ptc* n, const qcd_gauge* gauge) {
+  if (!n || !gauge) return pfail(QCD_ERR_ARG, "null argument");
+  if (!gauge->U[kFP32]) return pfail(QCD_ERR_ARG, "the network needs the gauge handle's FP32 links");
+  for (int mu = 0; mu < 4; mu++)
+    if (gauge->dims[mu] != n->gauge->dims[mu]) return pfail(QCD_ERR_ARG, "lattice extents differ");
+  n->gauge = gauge;
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_init_neumann(qcd_ptc* n, double kappa, void* stream) {
+  if (!n) return pfail(QCD_ERR_ARG, "null network handle");
+  const int want[4] = {1, 2, 2, 1};
+  if (n->nlayers != 3 || memcmp(n->channels, want, sizeof want) != 0)
+    return pfail(QCD_ERR_UNSUPPORTED, "the Neumann form is defined for channels 1, 2, 2, 1");
+  // Spin matrices of the hops of kappa H: path +mu carries kappa (1 - gamma_mu),
+  // path -mu kappa (1 + gamma_mu), in the Dirac basis of the Wilson kernel
+  // (gamma_1 as printed in Sec. 2; gamma_4 = diag(1, 1, -1, -1)).
+  typedef std::complex<double> C;
+  const C I(0, 1);
+  C gam[4][4][4] = {};
+  gam[0][0][3] = -I; gam[0][1][2] = -I; gam[0][2][1] = I; gam[0][3][0] = I;
+  gam[1][0][3] = -1; gam[1][1][2] = 1;  gam[1][2][1] = 1; gam[1][3][0] = -1;
+  gam[2][0][2] = -I; gam[2][1][3] = I;  gam[2][2][0] = I; gam[2][3][1] = -I;
+  gam[3][0][0] = 1;  gam[3][1][1] = 1;  gam[3][2][2] = -1; gam[3][3][3] = -1;
+  std::vector<double> w(2 * n->nweights, 0.0);
+  // weight W[p][j][i][s'][s] of layer l
+  auto put = [&](int l, int p, int j, int i, int sp, int sv, C v) {
+    const PtcLayerDev& L = n->L[l];
+    const size_t k = n->woff[l] + ((((size_t)p * L.cout + j) * L.cin + i) * 4 + sp) * 4 + sv;
+    w[2 * k] += v.real();
+    w[2 * k + 1] += v.imag();
+  };
+  auto ident = [&](int l, int j, int i) {
+    for (int s = 0; s < 4; s++) put(l, 0, j, i, s, s, 1.0);
+  };
+  auto hop = [&](int l, int j, int i) {  // out_j += kappa H in_i
+    for (int mu = 0; mu < 4; mu++)
+      for (int sp = 0; sp < 4; sp++)
+        for (int sv = 0; sv < 4; sv++) {
+          const C d = sp == sv ? 1.0 : 0.0;
+          put(l, 1 + 2 * mu, j, i, sp, sv, kappa * (d - gam[mu][sp][sv]));
+          put(l, 2 + 2 * mu, j, i, sp, sv, kappa * (d + gam[mu][sp][sv]));
+        }
+  };
+  // layer 0: (psi, kH psi); layer 1: (c0 + c1, kH (c0 + c1)); layer 2: c0 + kH c1
+  // => M = (1 + kH)(1 + (kH)^2) = sum_{k <= 3} (kappa H)^k
+  ident(0, 0, 0); hop(0, 1, 0);
+  ident(1, 0, 0); ident(1, 0, 1); hop(1, 1, 0); hop(1, 1, 1);
+  ident(2, 0, 0); hop(2, 0, 1);
+  return qcd_ptc_set_weights(n, w.data(), stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,178 @@
+"""The network as right preconditioner of the FP16 inner solve (flexible
+refinement), against the oracle and against the plain FP16-inner solver.
+
+The Neumann weights give M = sum_{k<=3} (kappa H)^k exactly (up to BF16
+rounding, tolerance as for the network's forward pass), which pins the
+weight layout and the spin matrices of the hops against the oracle's
+Wilson operator.  Solves must reach the FP64 tolerance whatever M is;
+the solution is compared with the oracle's FP64 solve.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import qcd_inputs as qi  # noqa: E402
+from oracle import solvers as S  # noqa: E402
+from gpu_common import to_dev, to_host  # noqa: E402
+
+CH = (1, 2, 2, 1)
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 8), (6, 4, 4, 6)])
+def test_neumann_weights_match_oracle_series(q, dims):
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 300)
+    psi = qi.gaussian_source(dims, 301)
+    terms = [psi]
+    for _ in range(3):
+        terms.append(kappa * oracle.dslash(U, terms[-1], kappa, dims, oracle.OP_H))
+    want = sum(terms)
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, CH, max_batch=1)
+    net.init_neumann(kappa)
+    out = torch.empty_like(to_dev(psi))
+    net.apply(out, to_dev(psi))
+    got = to_host(out)
+    assert rel(got, want) < 1e-2
+    # D M = 1 - (kappa H)^4
+    dm = oracle.dslash(U, got, kappa, dims, oracle.OP_D)
+    h4 = kappa * oracle.dslash(U, terms[3], kappa, dims, oracle.OP_H)
+    assert rel(dm, psi - h4) < 2e-2
+    net.close()
+    g.close()
+
+
+def test_set_gauge_requires_same_extents(q):
+    U1 = qi.gauge_field((4, 4, 4, 8), 0.3, 310)
+    U2 = qi.gauge_field((4, 4, 8, 4), 0.3, 311)
+    g1 = q.gauge_upload(to_dev(U1), (4, 4, 4, 8))
+    g2 = q.gauge_upload(to_dev(U2), (4, 4, 8, 4))
+    net = q.PTC(g1, CH)
+    with pytest.raises(q.QcdError):
+        net.set_gauge(g2)
+    net.close()
+    g1.close()
+    g2.close()
+
+
+SOLVE_DIMS = (8, 8, 8, 8)
+KAPPA = 0.12
+
+
+@pytest.fixture(scope="module")
+def system():
+    U = qi.gauge_field(SOLVE_DIMS, 0.3, 320)
+    b = qi.gaussian_source(SOLVE_DIMS, 321)
+    x_ref, _ = S.solve_fp64(U, KAPPA, SOLVE_DIMS, b, tol=1e-13)
+    return U, b, x_ref
+
+
+def test_neumann_preconditioned_solve_reaches_fp64_tolerance(q, system):
+    U, b, x_ref = system
+    g = q.gauge_upload(to_dev(U), SOLVE_DIMS)
+    net = q.PTC(g, CH)
+    net.init_neumann(KAPPA)
+    bd = to_dev(b)
+    x0 = torch.zeros_like(bd)
+    plain = q.solve_mixed_ir(g, KAPPA, x0, bd, inner_prec=q.FP16, tol=1e-12)
+    x1 = torch.zeros_like(bd)
+    pre = q.solve_mixed_ir(g, KAPPA, x1, bd, inner_prec=q.FP16, tol=1e-12, precond=net)
+    for info in (plain, pre):
+        assert info.status == "ok" and info.true_rel_residual <= 1e-12
+    assert pre.precond_fallback == -1 and pre.precond_steps == pre.outer_iters
+    assert pre.precond_scale > 0
+    # the residual check is FP64; the solution agrees with the oracle's FP64 solve
+    assert rel(to_host(x1), x_ref) < 1e-10
+    # each inner iteration applies D M, a degree-5 polynomial in H: far fewer iterations
+    assert pre.inner_iters < plain.inner_iters, (pre.inner_iters, plain.inner_iters)
+    net.close()
+    g.close()
+
+
+def test_graph_replay_identical_with_network(q, system):
+    U, b, _ = system
+    g = q.gauge_upload(to_dev(U), SOLVE_DIMS)
+    net = q.PTC(g, CH)
+    net.init_neumann(KAPPA)
+    bd = to_dev(b)
+    xs, infos = [], []
+    for use_graph in (False, True, True):
+        x = torch.zeros_like(bd)
+        infos.append(q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP16, tol=1e-12, precond=net,
+                                      use_graph=use_graph))
+        xs.append(x)
+    assert torch.equal(xs[0], xs[1]) and torch.equal(xs[0], xs[2])
+    assert infos[0].inner_iters == infos[1].inner_iters == infos[2].inner_iters
+    net.close()
+    g.close()
+
+
+def test_zero_network_falls_back_to_plain_step(q, system):
+    # M = 0 makes the first inner solve break down; the step is undone and the
+    # call finishes with the plain FP16 inner solver
+    U, b, x_ref = system
+    g = q.gauge_upload(to_dev(U), SOLVE_DIMS)
+    net = q.PTC(g, CH)   # weights start at zero
+    bd = to_dev(b)
+    x = torch.zeros_like(bd)
+    info = q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP16, tol=1e-12, precond=net)
+    assert info.status == "ok" and info.true_rel_residual <= 1e-12
+    assert info.precond_fallback == 0 and info.precond_steps == 0
+    assert rel(to_host(x), x_ref) < 1e-10
+    net.close()
+    g.close()
+
+
+def test_batched_preconditioned_solve(q):
+    dims = (8, 8, 8, 8)
+    U = qi.gauge_field(dims, 0.3, 330)
+    bs = qi.gaussian_source(dims, 331, nrhs=3)
+    bs[1] *= 1e-3          # different norms in one batch
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, CH, max_batch=3)
+    net.init_neumann(KAPPA)
+    bd = to_dev(bs)
+    x = torch.zeros_like(bd)
+    infos = q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP16, tol=1e-12, precond=net)
+    for i, info in enumerate(infos):
+        assert info.true_rel_residual <= 1e-12
+        r = bs[i] - oracle.dslash(U, to_host(x[i]), KAPPA, dims, oracle.OP_D)
+        assert np.linalg.norm(r) <= 1.01e-12 * np.linalg.norm(bs[i])
+    net.close()
+    g.close()
+
+
+def test_preconditioner_argument_checks(q, system):
+    U, b, _ = system
+    g = q.gauge_upload(to_dev(U), SOLVE_DIMS)
+    other = q.gauge_upload(to_dev(U), SOLVE_DIMS)
+    net = q.PTC(other, CH, max_batch=1)
+    bd = to_dev(b)
+    x = torch.zeros_like(bd)
+    with pytest.raises(q.QcdError):   # bound to another handle
+        q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP16, precond=net)
+    net.set_gauge(g)
+    with pytest.raises(q.QcdError):   # FP32 inner solve
+        q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP32, precond=net)
+    b2 = to_dev(qi.gaussian_source(SOLVE_DIMS, 5, nrhs=2))
+    with pytest.raises(q.QcdError):   # batch above max_batch
+        q.solve_mixed_ir(g, KAPPA, torch.zeros_like(b2), b2, inner_prec=q.FP16, precond=net)
+    net.close()
+    g.close()
+    other.close()
