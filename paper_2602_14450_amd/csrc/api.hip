@@ -217,7 +217,7 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
   const void* U = g->U[prec];
   launch_p_update(G, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
   if (pc.net) {
-    ptc_apply_half(pc.net, n, w.p, w.z, pc.scale, ftz, st);
+    ptc_apply_half(pc.net, n, w.p, w.z, pc.scale, ftz, w.sc, st);
     launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.z, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
   } else {
     launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.p, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
@@ -225,7 +225,7 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
   launch_alpha(n, w.sc, w.partials, drows, st);
   launch_s_update(G, prec, n, w.sc, w.r, w.v, ftz, st);
   if (pc.net) {
-    ptc_apply_half(pc.net, n, w.r, w.z, pc.scale, ftz, st);
+    ptc_apply_half(pc.net, n, w.r, w.z, pc.scale, ftz, w.sc, st);
     launch_dslash(prec, G, tu, kOpD, kEpiTSAux, n, w.t, w.z, U, kappa, w.r, w.partials, w.sc, ftz, st);
   } else {
     launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.r, U, kappa, nullptr, w.partials, w.sc, ftz, st);
@@ -807,7 +807,7 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
     // x += (|r| / s^) double(t~), with t~ = c M u~ when preconditioned; r = b - D x
     // in FP64 (skipped where not refining)
     if (pc.net) {
-      ptc_apply_half(pc.net, n, w.x, w.z, pc.scale, p->inner.ftz, st);
+      ptc_apply_half(pc.net, n, w.x, w.z, pc.scale, p->inner.ftz, nullptr, st);
       launch_correct(G, prec, n, w.sc, (double*)w.x64, w.z, st);
     } else {
       launch_correct(G, prec, n, w.sc, (double*)w.x64, w.x, st);

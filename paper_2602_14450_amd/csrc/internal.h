@@ -118,8 +118,10 @@ void launch_finish_sum(int n, const double* partials, int nrows, int nv, double*
 struct qcd_ptc;
 struct qcd_gauge;
 namespace qcd {
-// network applied to nb native FP16 fields: out = M(in_scale * in) (ptc.hip)
-void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scale, int ftz, hipStream_t st);
+// network applied to nb native FP16 fields: out = scale * M(in), skipping
+// batches whose solver stopped when scal is given (ptc.hip)
+void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float scale, int ftz, const Scalars* scal,
+                    hipStream_t st);
 // largest |M(v)| / |v| over nb native FP16 fields (synchronises)
 qcd_status ptc_gain(qcd_ptc* n, int nb, const void* in, double* gain, hipStream_t st);
 int ptc_max_batch(const qcd_ptc* n);

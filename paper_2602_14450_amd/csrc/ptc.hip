@@ -202,6 +202,131 @@ __global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const sh
 }
 
 // ---------------------------------------------------------------------------
+// Fused forward layer (inference): the transported inputs are formed in
+// registers and fed to the matrix cores directly, so nothing but the
+// activations and links crosses HBM.
+//
+// Column ordering: a wave takes 16 sites (one per lane % 16) and all three
+// colours (three accumulators).  The K index is slot * 4 + e with slot =
+// (p * C_in + i) * 2 + sh (transport path, input channel, spin half) and
+// e = s_lo * 2 + re/im for spin s = 2 sh + s_lo; lane group G = lane / 16
+// supplies slot 4 kt + G of k-tile kt.  Output rows are r = (j * 2 + sh') * 4
+// + s'_lo * 2 + re/im, so lane group G ends up holding channel j = G / 2,
+// spins 2 (G % 2) and 2 (G % 2) + 1 of its site for all three colours.
+
+// A for the fused ordering, from W[p][j][i][s'][s] of one layer.
+__global__ void k_ptc_prep_Af(PtcLayerDev L, const float2* __restrict__ W, short* __restrict__ A) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 16 * L.Kp) return;
+  const int r = idx / L.Kp, k = idx % L.Kp;
+  const int j = r >> 3, spo = ((r >> 2) & 1) * 2 + ((r >> 1) & 1), ro = r & 1;
+  const int slot = k >> 2, e = k & 3;
+  float v = 0.0f;
+  if (j < L.cout && slot < 18 * L.cin) {
+    const int p = slot / (2 * L.cin), i = (slot >> 1) % L.cin, s = (slot & 1) * 2 + (e >> 1), ri = e & 1;
+    const float2 w = W[(((size_t)(p * L.cout + j) * L.cin + i) * 4 + spo) * 4 + s];
+    v = ro == ri ? w.x : (ro == 0 ? -w.y : w.y);
+  }
+  A[idx] = to_bf16(v);
+}
+
+template <typename SL>
+__device__ __forceinline__ cx<float> link_entry(const Geom& g, const SL* U, int mu, int par, int h, int k) {
+  return Traits<SL>::load(U + lk_block(g, mu, par, h) + lk_off<SL>(k, h & 63));
+}
+
+// out[b][j] = oscale * sum_{p,i} W[p][j][i] T_p in[b][i] for batch b = blockIdx.y;
+// grid.x = 2 * nb (one 64-site block of one parity per workgroup).  Batches
+// whose solver has stopped (scal[b].active == 0) are skipped when scal is given.
+template <typename SA, typename SL, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict__ in, SA* __restrict__ out,
+                                                   const SL* __restrict__ U, const short* __restrict__ A, int Kp,
+                                                   float oscale, const Scalars* __restrict__ scal, int ftz) {
+  constexpr int NK = (18 * CIN + 3) / 4;
+  const int b = blockIdx.y;
+  if (scal && !scal[b].active) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int G = lane >> 4, n = lane & 15;
+  const int par = blockIdx.x >= g.nb, hb = blockIdx.x - par * g.nb;
+  const int h_raw = hb * 64 + w * 16 + n;
+  const bool valid = h_raw < g.Vh;
+  const int h = valid ? h_raw : 0;  // padding lanes compute on site 0 and store nothing
+  const Coord c = decode(g, par, h);
+  const size_t fstride = spinor_elems(g);
+  bf16x4 af[NK];
+#pragma unroll
+  for (int kt = 0; kt < NK; kt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) af[kt][q] = A[(lane & 15) * Kp + kt * 16 + 4 * G + q];
+  f32x4 acc[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; cc++) acc[cc] = (f32x4){0, 0, 0, 0};
+#pragma unroll
+  for (int kt = 0; kt < NK; kt++) {
+    const int slot = 4 * kt + G;
+    cx<float> t[2][3];  // transported spins 2 sh, 2 sh + 1, colours 0..2
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+      for (int cc = 0; cc < 3; cc++) t[sl][cc] = cx<float>(0, 0);
+    if (slot < 18 * CIN) {
+      const int p = slot / (2 * CIN), i = (slot >> 1) % CIN, sh = slot & 1;
+      const SA* f = in + ((size_t)b * CIN + i) * fstride;
+      if (p == 0) {
+        const SA* fb = f + sp_block(g, par, h);
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+          for (int cc = 0; cc < 3; cc++) t[sl][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * (2 * sh + sl) + cc, h & 63));
+      } else {
+        const int mu = (p - 1) >> 1;
+        const bool fwd = ((p - 1) & 1) == 0;
+        const int hn = nbr(g, h, c, mu, fwd ? 1 : -1);
+        const SA* fb = f + sp_block(g, par ^ 1, hn);
+        cx<float> v[2][3], u[9];
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+          for (int cc = 0; cc < 3; cc++) v[sl][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * (2 * sh + sl) + cc, hn & 63));
+        const int lp = fwd ? par : par ^ 1, lh = fwd ? h : hn;  // U_mu(x) or U_mu(x - mu)
+#pragma unroll
+        for (int k = 0; k < 9; k++) u[k] = link_entry(g, U, mu, lp, lh, k);
+#pragma unroll
+        for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+          for (int a = 0; a < 3; a++) {
+            cx<float> s_(0, 0);
+#pragma unroll
+            for (int bb = 0; bb < 3; bb++)
+              s_ = s_ + (fwd ? u[3 * a + bb] * v[sl][bb] : cmulc(u[3 * bb + a], v[sl][bb]));
+            t[sl][a] = s_;
+          }
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++) {
+      bf16x4 bv;
+      bv[0] = to_bf16(t[0][cc].re);
+      bv[1] = to_bf16(t[0][cc].im);
+      bv[2] = to_bf16(t[1][cc].re);
+      bv[3] = to_bf16(t[1][cc].im);
+      if (!valid) bv = (bf16x4){0, 0, 0, 0};
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kt], bv, acc[cc], 0, 0, 0);
+    }
+  }
+  const int j = G >> 1, sh = G & 1;
+  if (!valid || j >= COUT) return;
+  SA* ob = out + ((size_t)b * COUT + j) * fstride + sp_block(g, par, h);
+#pragma unroll
+  for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++) {
+      const cx<float> o(oscale * acc[cc][2 * sl], oscale * acc[cc][2 * sl + 1]);
+      ob[sp_off<SA>(3 * (2 * sh + sl) + cc, h & 63)] = Traits<SA>::pack(o, ftz);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward.
 
 // dOut (native FP32 fields) -> DO[b][n][16] BF16 real form (re rows, im rows, zeros).
@@ -497,7 +622,9 @@ struct qcd_ptc {
   float2* adam_m;
   float2* adam_v;
   int adam_step;
-  short* A[kPtcMaxLayers];          // BF16 GEMM operands
+  short* A[kPtcMaxLayers];          // BF16 GEMM operands (training ordering)
+  short* Af[kPtcMaxLayers];         // BF16 GEMM operands (fused inference ordering)
+  __half2* act16[kPtcMaxLayers + 1];  // FP16 hidden activations of the solver's applications
   float2* act[kPtcMaxLayers + 1];   // activations (batch x channels native FP32 fields)
   float2* target;                   // training targets (batch fields)
   float2* dact[2];                  // gradient ping-pong buffers
@@ -543,15 +670,38 @@ void prep_weights(qcd_ptc* n, hipStream_t st) {
     const int cnt = 16 * n->L[l].Kp;
     hipLaunchKernelGGL(k_ptc_prep_A, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
                        (const float2*)(n->w + n->woff[l]), n->A[l]);
+    hipLaunchKernelGGL(k_ptc_prep_Af, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
+                       (const float2*)(n->w + n->woff[l]), n->Af[l]);
   }
 }
 
-// Forward through all layers from act[0]; with train the transported inputs
-// of every layer are kept (else one buffer is reused).
+template <typename SA, typename SL>
+void fused_layer(const qcd_ptc* n, int l, int nb, const SA* in, SA* out, const SL* U, float oscale,
+                 const Scalars* scal, int ftz, hipStream_t st) {
+  const Geom& g = n->g;
+  const PtcLayerDev& L = n->L[l];
+  const dim3 grid(2 * g.nb, nb), block(256);
+#define PTC_FUSED(CI, CO)                                                                                    \
+  hipLaunchKernelGGL((k_ptc_fused<SA, SL, CI, CO>), grid, block, 0, st, g, in, out, U, (const short*)n->Af[l], \
+                     L.Kp, oscale, scal, ftz)
+  if (L.cin == 1 && L.cout == 1) PTC_FUSED(1, 1);
+  else if (L.cin == 1) PTC_FUSED(1, 2);
+  else if (L.cout == 1) PTC_FUSED(2, 1);
+  else PTC_FUSED(2, 2);
+#undef PTC_FUSED
+}
+
+// Forward through all layers from act[0].  With train, the two-pass form
+// keeps the transported inputs of every layer for the backward pass; else
+// each layer is one fused kernel.
 void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
   const Geom& g = n->g;
   for (int l = 0; l < n->nlayers; l++) {
-    short* X = train ? n->X[l] : n->X[0];
+    if (!train) {
+      fused_layer<float2, float2>(n, l, nb, n->act[l], n->act[l + 1], links32(n), 1.0f, nullptr, 0, st);
+      continue;
+    }
+    short* X = n->X[l];
     hipLaunchKernelGGL(k_ptc_transport, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, n->L[l],
                        (const float2*)n->act[l], links32(n), X);
     hipLaunchKernelGGL(k_ptc_mix, dim3(n->mix_blocks), dim3(256), 0, st, g, n->L[l], (const short*)X,
@@ -609,20 +759,27 @@ qcd_status check_batch(const qcd_ptc* n, int nb) {
 }  // namespace
 
 namespace qcd {
-// Apply the network to nb native FP16 fields: out = M(in_scale * in).
-// Used by the preconditioned inner solver (all launches are stream-ordered
-// and capturable).
-void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float in_scale, int ftz, hipStream_t st) {
-  const Geom& g = n->g;
-  hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const __half2*)in, n->act[0], in_scale);
-  forward(n, nb, false, st);
-  hipLaunchKernelGGL(k_f2h, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[n->nlayers],
-                     (__half2*)out, ftz);
+// Apply the network to nb native FP16 fields: out = scale * M(in), FP16
+// activations and FP16 links (the inner solver's), one fused kernel per
+// layer.  Used by the preconditioned inner solver (all launches are
+// stream-ordered and capturable); batches whose solver has stopped are
+// skipped when scal is given.
+void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float scale, int ftz, const Scalars* scal,
+                    hipStream_t st) {
+  const __half2* U = (const __half2*)n->gauge->U[kFP16];
+  const __half2* src = (const __half2*)in;
+  for (int l = 0; l < n->nlayers; l++) {
+    const bool last = l == n->nlayers - 1;
+    __half2* dst = last ? (__half2*)out : n->act16[l + 1];
+    fused_layer<__half2, __half2>(n, l, nb, src, dst, U, last ? scale : 1.0f, scal, ftz, st);
+    src = dst;
+  }
 }
 // Largest |M(v_b)| / |v_b| over the nb native FP16 fields v_b (zero fields
 // skipped); synchronises.  Returns 0 if every field is zero.
 qcd_status ptc_gain(qcd_ptc* n, int nb, const void* in, double* gain, hipStream_t st) {
   const Geom& g = n->g;
+  if (!n->gauge->U[kFP16]) return pfail(QCD_ERR_ARG, "the gauge handle holds no FP16 links");
   hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const __half2*)in, n->act[0], 1.0f);
   forward(n, nb, false, st);
   hipLaunchKernelGGL(k_ptc_norms, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[0],
@@ -695,10 +852,13 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
   PTC_ALLOC(n->adam_v, n->nweights * sizeof(float2));
   for (int l = 0; l < nlayers; l++) {
     PTC_ALLOC(n->A[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
+    PTC_ALLOC(n->Af[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
     // inference reuses X[0] for every layer, so it takes the widest layer's size
     PTC_ALLOC(n->X[l], (size_t)max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * sizeof(short));
   }
   for (int l = 0; l <= nlayers; l++) PTC_ALLOC(n->act[l], fields_bytes(g, (size_t)max_batch * channels[l]));
+  for (int l = 1; l < nlayers; l++)
+    PTC_ALLOC(n->act16[l], (size_t)max_batch * channels[l] * spinor_elems(g) * sizeof(__half2));
   PTC_ALLOC(n->target, fields_bytes(g, max_batch));
   PTC_ALLOC(n->dact[0], fields_bytes(g, (size_t)max_batch * maxc));
   PTC_ALLOC(n->dact[1], fields_bytes(g, (size_t)max_batch * maxc));
@@ -713,6 +873,8 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
     // activations of padding sites are never written: clear once so they stay finite
     for (int l = 0; l <= nlayers; l++)
       (void)hipMemsetAsync(n->act[l], 0, fields_bytes(g, (size_t)max_batch * channels[l]), st);
+    for (int l = 1; l < nlayers; l++)
+      (void)hipMemsetAsync(n->act16[l], 0, (size_t)max_batch * channels[l] * spinor_elems(g) * sizeof(__half2), st);
     (void)hipMemsetAsync(n->w, 0, n->nweights * sizeof(float2), st);
     (void)hipMemsetAsync(n->adam_m, 0, n->nweights * sizeof(float2), st);
     (void)hipMemsetAsync(n->adam_v, 0, n->nweights * sizeof(float2), st);
