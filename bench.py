@@ -8,14 +8,20 @@ full solve D x = b from x = 0 with the FP64 iterative refinement around the
 rescaled FP16-storage BiCGStab (s = 128, sigma = 64), with all inputs
 resident in device memory.  The FP64 BiCGStab and the FP32-inner refinement
 are timed beside it, the Wilson operator is timed on its own with HIP events
-for the roofline, and the CPU oracle is timed on a bounded sample.
+for the roofline, and the CPU oracle is timed on a bounded sample.  Two more
+forms are measured and reported beside the headline number: the 12
+spin-colour point sources solved as one batch, and the learned
+preconditioner on 16^4 (trained here on pairs the solver makes) against the
+plain FP16-inner solver at the same tolerance.
 
 Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -39,7 +45,9 @@ def parse():
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
+    ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Wilson operator and the calibration copy (for counter runs)")
@@ -54,6 +62,94 @@ def calibration_copy(torch, nbytes=1 << 30):
     b.copy_(a)
     torch.cuda.synchronize()
     return nbytes
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """GB/s of a plain device copy (read + write), for context."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def measured_traffic(prec_name):
+    """HBM bytes per launch of the Wilson operator from the committed counter
+    summary, or None if the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_dslash_32x32x32x64.md")
+    src = os.path.join(ROOT, "paper_2602_14450_amd", "csrc", "dslash.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m = re.search(r"dslash\.hip sha256: ([0-9a-f]{64})", text)
+    t = re.search(rf"traffic bytes per launch {prec_name}: (\d+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return int(t.group(1))
+
+
+def learned_form(q, torch, np, qi, kappa, pairs_per_field, max_iter):
+    """16^4, kappa = 0.124: train the network on 8 seeded fields (pairs from the
+    FP32 solver), then solve on a held-out field with the plain FP16-inner
+    refinement, with the Neumann-initialised network, and with the trained
+    one, all to 1e-12 with hip-graph replay."""
+    from paper_2602_14450_amd import ptc_train as T
+    dims = (16, 16, 16, 16)
+    net, sets, tinfo = T.train_preconditioner(dims, kappa, nfields=8, pairs_per_field=pairs_per_field, epochs=1,
+                                              batch=16, lr=1e-3)
+    held = T.make_pairs(dims, kappa, 999, 64, 777)
+    tinfo["heldout_loss_trained"] = T.evaluate(net, held)
+    neu = q.PTC(held.gauge, (1, 2, 2, 1), max_batch=16)
+    neu.init_neumann(kappa)
+    tinfo["heldout_loss_neumann"] = T.evaluate(neu, held)
+    g = held.gauge
+    net.set_gauge(g)
+    b = torch.from_numpy(qi.gaussian_source(dims, 4242)).cuda()
+    res = {}
+    for name, pc in (("plain", None), ("neumann", neu), ("trained", net)):
+        times = []
+        for rep in range(3):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            info = q.solve_mixed_ir(g, kappa, x, b, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12,
+                                    inner_tol=1e-2, inner_max_iter=max_iter, use_graph=True, precond=pc)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+        res[name] = dict(seconds=min(times), outer=info.outer_iters, inner_iters=info.inner_iters,
+                         true_rel_residual=info.true_rel_residual, precond_steps=info.precond_steps,
+                         precond_fallback=info.precond_fallback, precond_scale=info.precond_scale)
+        print(f"[bench] learned form {name}: {min(times)*1e3:.2f} ms inner={info.inner_iters} "
+              f"res={info.true_rel_residual:.2e}", file=sys.stderr, flush=True)
+    # one network application (FP32 canonical in/out through the C ABI)
+    psi = torch.from_numpy(qi.gaussian_source(dims, 7)).cuda()
+    out = torch.empty_like(psi)
+    for _ in range(3):
+        net.apply(out, psi)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        net.apply(out, psi)
+    e1.record()
+    e1.synchronize()
+    res["network_apply_us"] = e0.elapsed_time(e1) / 20 * 1e3
+    res["training"] = tinfo
+    res["workload"] = ("16^4, eps=0.3 links, kappa=0.124; network 1->2->2->1 spinor fields, BF16 MFMA mixing; "
+                       f"trained 1 epoch on {8 * pairs_per_field} (r, FP32-solver D^-1 r) pairs from 8 seeded "
+                       "fields; solves on a held-out field, tol 1e-12")
+    net.close()
+    neu.close()
+    del sets, held
+    torch.cuda.empty_cache()
+    return res
 
 
 def time_dslash(q, torch, g, prec, reps, V, nrhs=1):
@@ -217,9 +313,14 @@ def main():
               f"12-rhs dslash {ms12*1e3:.1f} us {bytes12 / ms12 / 1e6:.0f} GB/s", file=sys.stderr, flush=True)
         del xb, bpd, wsb
 
+    traffic = measured_traffic("fp16") if dims == (32, 32, 32, 64) else None
     roof = dict(bound="hbm", achieved=dsl["fp16"]["GBps"], peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=dsl["fp16"]["frac"], traffic=None, kernel="k_dslash<__half2, D>",
-                bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V)
+                frac=dsl["fp16"]["frac"], traffic=traffic, kernel="k_dslash<__half2, D>",
+                bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V,
+                algorithmic_bytes_per_launch=DSLASH_BYTES[2] * V, copy_GBps=copy_bandwidth(torch))
+    learned = None
+    if not args.no_learned:
+        learned = learned_form(q, torch, np, qi, 0.124, args.learned_pairs, max_iter)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -244,7 +345,7 @@ def main():
         "config": {"workload": f"Wilson D x = b, {'x'.join(map(str, dims))} lattice, eps={args.eps} SU(3) links, "
                                f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64), tol 1e-12",
                    "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12},
-        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl, "batched": batched,
+        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl, "batched": batched, "learned": learned,
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,

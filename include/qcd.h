@@ -53,6 +53,9 @@ typedef enum {
 } qcd_status;
 
 typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2 } qcd_prec;
+/* Flag for qcd_gauge_upload's prec_mask: store all 18 reals of every link
+ * even when the field is in SU(3). */
+enum { QCD_LINKS_FULL = 1 << 8 };
 typedef enum { QCD_LAYOUT_CANONICAL = 0, QCD_LAYOUT_NATIVE = 1 } qcd_layout;
 /* D = 1 - kappa H (eq. (1)); H is the hopping sum; D^dag = gamma_5 D gamma_5. */
 typedef enum { QCD_OP_D = 0, QCD_OP_H = 1, QCD_OP_DDAG = 2, QCD_OP_HDAG = 3 } qcd_op;
@@ -129,6 +132,12 @@ const char* qcd_last_error(void);
  * null pointer or an odd / < 2 extent, QCD_ERR_HIP on allocation failure. */
 qcd_status qcd_gauge_upload(qcd_gauge** g, const int dims[4], const void* U_dev, int prec_mask, void* stream);
 qcd_status qcd_gauge_free(qcd_gauge* g);
+/* Reals stored per link in precision prec: 12 when every link passed the
+ * SU(3) check at upload (row 2 equals conj(row0 x row1) to within 1e-14,
+ * 1e-7, 1e-4 for FP64, FP32, FP16; the kernels rebuild row 2, which saves a
+ * third of the link bytes), 18 otherwise or with QCD_LINKS_FULL; 0 if the
+ * handle holds no links in prec. */
+int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
 
 /* Launch shape of the Wilson operator for precision prec (picked by a tuner):
  * sched 0 orders thread blocks by half-lattice index; sched m = 1..3 gives

@@ -28,6 +28,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FP64, FP32, FP16 = 0, 1, 2
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
 CANONICAL, NATIVE = 0, 1
+LINKS_FULL = 1 << 8
 OP_D, OP_H, OP_DDAG, OP_HDAG = 0, 1, 2, 3
 STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_hip", -3: "err_nonfinite", -4: "err_workspace",
           -5: "err_unsupported", -6: "err_breakdown"}
@@ -60,6 +61,8 @@ _vp, _i, _d, _sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size
 _lib.qcd_last_error.restype = ctypes.c_char_p
 _lib.qcd_gauge_upload.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_i), _vp, _i, _vp]
 _lib.qcd_gauge_free.argtypes = [_vp]
+_lib.qcd_gauge_link_reals.argtypes = [_vp, _i]
+_lib.qcd_gauge_link_reals.restype = _i
 _lib.qcd_spinor_bytes.argtypes = [_vp, _i]
 _lib.qcd_spinor_bytes.restype = _sz
 _lib.qcd_workspace_bytes.argtypes = [_vp, _i, _i, _i, _i]
@@ -92,7 +95,7 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
 
-EXPORTED = ["qcd_last_error", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
+EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann"]
@@ -128,10 +131,10 @@ class Gauge:
     """A gauge field uploaded to the device in the native layout (FP64 plus
     the selected low-precision copies)."""
 
-    def __init__(self, U: torch.Tensor, dims, precs=(FP64, FP32, FP16)):
+    def __init__(self, U: torch.Tensor, dims, precs=(FP64, FP32, FP16), full_links=False):
         U = _as_c128(U)
         self.dims = tuple(int(d) for d in dims)
-        mask = 0
+        mask = LINKS_FULL if full_links else 0
         for p in precs:
             mask |= 1 << PREC[p]
         h = ctypes.c_void_p()
@@ -150,6 +153,10 @@ class Gauge:
             self.close()
         except Exception:
             pass
+
+    def link_reals(self, prec) -> int:
+        """Reals stored per link in prec: 12 (SU(3) rows 0, 1; row 2 rebuilt) or 18."""
+        return int(_lib.qcd_gauge_link_reals(self.handle, PREC[prec]))
 
     def set_tuning(self, prec, sched: int, variant: int, rhs_tile: int = 0):
         _check(_lib.qcd_set_dslash_tuning(self.handle, PREC[prec], int(sched), int(variant), int(rhs_tile)))
@@ -187,8 +194,8 @@ class Gauge:
         return torch.empty(self.spinor_bytes(prec) * nrhs, dtype=torch.uint8, device="cuda")
 
 
-def gauge_upload(U, dims, precs=(FP64, FP32, FP16)) -> Gauge:
-    return Gauge(U, dims, precs)
+def gauge_upload(U, dims, precs=(FP64, FP32, FP16), full_links=False) -> Gauge:
+    return Gauge(U, dims, precs, full_links)
 
 
 def _one_or_list(vals, n):

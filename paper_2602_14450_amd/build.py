@@ -17,7 +17,12 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqcd.so")
-SOURCES = ["dslash.hip", "blas.hip", "api.hip", "ptc.hip"]
+# (source, object, extra flags): the Wilson operator is built once per storage
+# precision so that its many kernel instantiations compile in parallel
+SOURCES = [("dslash.hip", "dslash_f16.o", ["-DQCD_DSLASH_PREC=2"]),
+           ("dslash.hip", "dslash_f32.o", ["-DQCD_DSLASH_PREC=1"]),
+           ("dslash.hip", "dslash_f64.o", ["-DQCD_DSLASH_PREC=0"]),
+           ("blas.hip", "blas.o", []), ("api.hip", "api.o", []), ("ptc.hip", "ptc.o", [])]
 ARCH = os.environ.get("QCD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -25,9 +30,10 @@ FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Wno-
          "-I", INCLUDE, "-I", CSRC]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(spec) -> str:
+    src, objname, extra = spec
+    obj = os.path.join(BUILD, objname)
+    cmd = ["hipcc", *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

@@ -372,21 +372,44 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
     if (dims[i] < 2 || dims[i] % 2) return fail(QCD_ERR_ARG, "extent %d of direction %d must be even and >= 2", dims[i], i);
   const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
   if (V / 2 >= (1ll << 30)) return fail(QCD_ERR_ARG, "lattice too large");
+  const int flags = prec_mask & ~7;
+  prec_mask &= 7;
   if (prec_mask == 0) prec_mask = 7;
   prec_mask |= 1 << kFP64;
   qcd_gauge* g = new qcd_gauge();
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
   // defaults measured on MI355X at 32^3 x 64 (the tuner may override them)
-  g->tune[kFP64] = DslashTune{1, 0, 0};
-  g->tune[kFP32] = DslashTune{1, 1, 0};
-  g->tune[kFP16] = DslashTune{1, 1, 0};
+  g->tune[kFP64] = DslashTune{1, 0, 0, 0};
+  g->tune[kFP32] = DslashTune{1, 1, 0, 0};
+  g->tune[kFP16] = DslashTune{1, 1, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
+  // Links whose row 2 equals conj(row0 x row1) to within the rounding of a
+  // precision are stored as rows 0 and 1 only in that precision.
+  g->su3_dev = INFINITY;
+  if (!(flags & QCD_LINKS_FULL)) {
+    const int rows = site_grid(g->g);
+    double* part = nullptr;
+    if (hipMalloc(&part, (rows + 1) * sizeof(double)) != hipSuccess) {
+      delete g;
+      return fail(QCD_ERR_HIP, "hipMalloc failed");
+    }
+    launch_link_su3_dev(g->g, (const double*)U_dev, part, part + rows, st);
+    hipError_t e = hipMemcpyAsync(&g->su3_dev, part + rows, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (e != hipSuccess) {
+      delete g;
+      return fail(QCD_ERR_HIP, "link check failed: %s", hipGetErrorString(e));
+    }
+    const double thr[3] = {1e-14, 1e-7, 1e-4};
+    for (int p = 0; p < 3; p++) g->tune[p].recon = g->su3_dev <= thr[p];
+  }
   for (int p = 0; p < 3 && rc == QCD_OK; p++) {
     if (!(prec_mask & (1 << p))) continue;
-    size_t bytes = link_elems(g->g) * prec_complex_bytes(p);
+    size_t bytes = link_elems(g->g, g->tune[p].recon ? 6 : 9) * prec_complex_bytes(p);
     if (hipMalloc(&g->U[p], bytes) != hipSuccess) {
       g->U[p] = nullptr;
       rc = fail(QCD_ERR_HIP, "hipMalloc of %zu bytes for links failed", bytes);
@@ -394,7 +417,7 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
     }
     // the padding of the last 64-site block stays zero
     if (hipMemsetAsync(g->U[p], 0, bytes, st) != hipSuccess) rc = fail(QCD_ERR_HIP, "hipMemsetAsync failed");
-    launch_pack_links(g->g, p, g->U[p], (const double*)U_dev, st);
+    launch_pack_links(g->g, p, g->U[p], (const double*)U_dev, g->tune[p].recon, st);
     if (hipGetLastError() != hipSuccess) rc = fail(QCD_ERR_HIP, "link packing launch failed");
   }
   if (rc == QCD_OK && hipHostMalloc((void**)&g->host_sc, sizeof(Scalars) * kMaxRhs, 0) != hipSuccess)
@@ -426,8 +449,13 @@ qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int var
     return fail(QCD_ERR_ARG, "sched must be 0..%d and variant 0..%d", kDslashScheds - 1, kDslashVariants - 1);
   if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4)
     return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2 or 4");
-  g->tune[prec] = DslashTune{sched, variant, rhs_tile};
+  g->tune[prec] = DslashTune{sched, variant, rhs_tile, g->tune[prec].recon};
   return QCD_OK;
+}
+
+int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec) {
+  if (!g || !valid_prec(prec) || !g->U[prec]) return 0;
+  return g->tune[prec].recon ? 12 : 18;
 }
 
 qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile) {
@@ -457,8 +485,8 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
   for (char* c = arch; *c; c++)
     if (*c == ':') { *c = 0; break; }
   char key[256];
-  snprintf(key, sizeof key, "\"dims\": \"%dx%dx%dx%d\", \"prec\": %d, \"nrhs\": %d, \"arch\": \"%s\"", g->dims[0],
-           g->dims[1], g->dims[2], g->dims[3], (int)prec, nrhs, arch);
+  snprintf(key, sizeof key, "\"dims\": \"%dx%dx%dx%d\", \"prec\": %d, \"nrhs\": %d, \"links\": %d, \"arch\": \"%s\"",
+           g->dims[0], g->dims[1], g->dims[2], g->dims[3], (int)prec, nrhs, g->tune[prec].recon ? 12 : 18, arch);
   if (cache_path && cache_path[0]) {
     FILE* f = fopen(cache_path, "r");
     if (f) {
@@ -471,7 +499,7 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
         if (q) sscanf(q, "\"sched\": %d, \"variant\": %d, \"rhs_tile\": %d, \"us\": %lf", &sc, &va, &rt, &us);
         if (sc >= 0 && va >= 0 && rt >= 0) {
           fclose(f);
-          g->tune[prec] = DslashTune{sc, va, rt};
+          g->tune[prec] = DslashTune{sc, va, rt, g->tune[prec].recon};
           if (best_us) *best_us = us;
           return QCD_OK;
         }
@@ -481,13 +509,19 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
   }
   hipStream_t st = S(stream);
   const size_t bytes = (size_t)nrhs * spinor_bytes(g->g, prec);
-  void *in = nullptr, *out = nullptr;
-  HIP_TRY(hipMalloc(&in, bytes));
-  if (hipMalloc(&out, bytes) != hipSuccess) {
-    (void)hipFree(in);
-    return fail(QCD_ERR_HIP, "hipMalloc failed");
+  // Rotate input/output pairs whose total exceeds the last-level cache
+  // (256 MB on MI355X), as the vectors of a solve do; a single pair would stay
+  // cache-resident and favour the wrong launch shape.
+  const int npair = (int)std::min<size_t>(4, std::max<size_t>(1, ((size_t)512 << 20) / (2 * bytes) + 1));
+  void* buf[8] = {};
+  for (int i = 0; i < 2 * npair; i++) {
+    if (hipMalloc(&buf[i], bytes) != hipSuccess) {
+      for (int j = 0; j < i; j++) (void)hipFree(buf[j]);
+      return fail(QCD_ERR_HIP, "hipMalloc failed");
+    }
+    // finite, normal values in every precision (bytes 0x3c)
+    (void)hipMemsetAsync(buf[i], 0x3c, bytes, st);
   }
-  (void)hipMemsetAsync(in, 0, bytes, st);  // any finite input times the same
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
@@ -500,14 +534,14 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
     for (int sched = 0; sched < kDslashScheds; sched++)
       for (int var = 0; var < (T == 1 ? kDslashVariants : 1); var++) {
         if (sched > 1 && make_sched(g->g, sched, T, nrhs).mode != sched) continue;  // not applicable
-        const DslashTune tu{sched, var, T};
+        const DslashTune tu{sched, var, T, g->tune[prec].recon};
         for (int i = 0; i < 2; i++)
-          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, out, in, g->U[prec], 0.1, nullptr, nullptr, nullptr, 0,
-                        st);
+          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, buf[2 * (i % npair) + 1], buf[2 * (i % npair)],
+                        g->U[prec], 0.1, nullptr, nullptr, nullptr, 0, st);
         (void)hipEventRecord(e0, st);
         for (int i = 0; i < reps; i++)
-          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, out, in, g->U[prec], 0.1, nullptr, nullptr, nullptr, 0,
-                        st);
+          launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, buf[2 * (i % npair) + 1], buf[2 * (i % npair)],
+                        g->U[prec], 0.1, nullptr, nullptr, nullptr, 0, st);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0;
@@ -521,8 +555,7 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(in);
-  (void)hipFree(out);
+  for (int i = 0; i < 2 * npair; i++) (void)hipFree(buf[i]);
   HIP_LAUNCHED();
   g->tune[prec] = best;
   if (best_us) *best_us = best_ms * 1e3;

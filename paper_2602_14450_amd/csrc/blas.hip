@@ -43,18 +43,61 @@ __device__ __forceinline__ int64_t volume(const Geom& g) { return 2 * (int64_t)g
 // ---------------------------------------------------------------------------
 // Layout conversions
 
-template <typename S>
+template <typename S, int NE>
 __global__ __launch_bounds__(256) void k_pack_links(Geom g, S* __restrict__ dst, const double* __restrict__ Uc) {
   SiteId id = site_id(g);
   if (!id.valid) return;
   const int64_t s = lex_site(g, id.par, id.h);
   const int lane = id.h & 63;
   for (int mu = 0; mu < 4; mu++) {
-    S* b = dst + lk_block(g, mu, id.par, id.h);
-    for (int k = 0; k < 9; k++) {
+    S* b = dst + lk_block<NE>(g, mu, id.par, id.h);
+    for (int k = 0; k < NE; k++) {
       const double* src = Uc + ((s * 4 + mu) * 9 + k) * 2;
-      b[lk_off<S>(k, lane)] = pack_from_double<S>(src[0], src[1], 0);
+      b[lk_off<S, NE>(k, lane)] = pack_from_double<S>(src[0], src[1], 0);
     }
+  }
+}
+
+// Largest |row2 - conj(row0 x row1)| over the links of each block's sites
+// (FP64, canonical layout): zero up to rounding exactly when every link is
+// in SU(3), so that row 2 need not be stored.
+__global__ __launch_bounds__(256) void k_link_su3_dev(Geom g, const double* __restrict__ Uc,
+                                                      double* __restrict__ partials) {
+  SiteId id = site_id(g);
+  double m = 0.0;
+  if (id.valid) {
+    const int64_t s = lex_site(g, id.par, id.h);
+    for (int mu = 0; mu < 4; mu++) {
+      const double* u = Uc + (s * 4 + mu) * 18;
+      cx<double> e[9];
+      for (int k = 0; k < 9; k++) e[k] = cx<double>(u[2 * k], u[2 * k + 1]);
+      cx<double> r[9];
+      for (int k = 0; k < 6; k++) r[k] = e[k];
+      su3_third_row(r);
+      for (int k = 6; k < 9; k++) {
+        const double dr = r[k].re - e[k].re, di = r[k].im - e[k].im;
+        m = fmax(m, sqrt(dr * dr + di * di));
+      }
+      if (!(m == m)) m = INFINITY;  // NaN input: not SU(3)
+    }
+  }
+  __shared__ double red[4];
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+__global__ void k_max_finish(const double* __restrict__ partials, int nrows, double* __restrict__ out) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) m = fmax(m, partials[r]);
+  for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, red[w]);
+    *out = fmax(red[0], m);
   }
 }
 
@@ -501,11 +544,18 @@ __global__ void k_finish_sum_any(const double* partials, int nrows, int nv, doub
     else FN<__half2>(__VA_ARGS__);                      \
   } while (0)
 
-template <typename S> static void pack_links_t(const Geom& g, void* dst, const double* U, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_links<S>, dim3(site_grid(g)), dim3(256), 0, st, g, (S*)dst, U);
+template <typename S> static void pack_links_t(const Geom& g, void* dst, const double* U, int recon, hipStream_t st) {
+  if (recon)
+    hipLaunchKernelGGL((k_pack_links<S, 6>), dim3(site_grid(g)), dim3(256), 0, st, g, (S*)dst, U);
+  else
+    hipLaunchKernelGGL((k_pack_links<S, 9>), dim3(site_grid(g)), dim3(256), 0, st, g, (S*)dst, U);
 }
-void launch_pack_links(const Geom& g, int prec, void* dst, const double* U, hipStream_t st) {
-  QCD_DISPATCH(prec, pack_links_t, g, dst, U, st);
+void launch_pack_links(const Geom& g, int prec, void* dst, const double* U, int recon, hipStream_t st) {
+  QCD_DISPATCH(prec, pack_links_t, g, dst, U, recon, st);
+}
+void launch_link_su3_dev(const Geom& g, const double* U, double* partials, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_link_su3_dev, dim3(site_grid(g)), dim3(256), 0, st, g, U, partials);
+  hipLaunchKernelGGL(k_max_finish, dim3(1), dim3(1024), 0, st, (const double*)partials, site_grid(g), out);
 }
 
 template <typename S>

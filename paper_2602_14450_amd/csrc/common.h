@@ -142,8 +142,10 @@ inline Geom make_geom(const int dims[4]) {
 }
 
 // Elements (stored complex numbers) of one full native spinor / link field.
+// A link field stores ne complex entries per link: 9 (the full matrix) or 6
+// (rows 0 and 1 of an SU(3) matrix; row 2 is rebuilt as conj(row0 x row1)).
 __host__ __device__ inline size_t spinor_elems(const Geom& g) { return (size_t)2 * g.nb * 12 * 64; }
-__host__ __device__ inline size_t link_elems(const Geom& g) { return (size_t)4 * 2 * g.nb * 9 * 64; }
+__host__ __device__ inline size_t link_elems(const Geom& g, int ne = 9) { return (size_t)4 * 2 * g.nb * ne * 64; }
 
 template <typename S> struct Lay {
   static constexpr int C = 16 / (int)sizeof(S);  // components per granule
@@ -151,21 +153,57 @@ template <typename S> struct Lay {
   static constexpr int F = (9 / C) * C;          // link entries in full granule rows
   struct alignas(16) Gran { S s[C]; };
 };
+// Link block of NE entries: the first F in granule rows, the remaining TAIL
+// either as one plane per entry (NE = 9) or packed per lane (NE = 6).
+template <typename S, int NE> struct LkLay {
+  static constexpr int C = Lay<S>::C;
+  static constexpr int F = (NE / C) * C;
+  static constexpr int TAIL = NE - F;
+};
 
 __device__ __forceinline__ size_t sp_block(const Geom& g, int par, int h) {
   return (size_t)(par * g.nb + (h >> 6)) * (12 * 64);
 }
-__device__ __forceinline__ size_t lk_block(const Geom& g, int mu, int par, int h) {
-  return (size_t)((mu * 2 + par) * g.nb + (h >> 6)) * (9 * 64);
+template <int NE = 9> __device__ __forceinline__ size_t lk_block(const Geom& g, int mu, int par, int h) {
+  return (size_t)((mu * 2 + par) * g.nb + (h >> 6)) * (NE * 64);
 }
 // element offset of spinor component k of lane `lane` within its block
 template <typename S> __device__ __forceinline__ int sp_off(int k, int lane) {
   constexpr int C = Lay<S>::C;
   return (k / C) * 64 * C + lane * C + (k % C);
 }
-template <typename S> __device__ __forceinline__ int lk_off(int k, int lane) {
-  constexpr int C = Lay<S>::C, F = Lay<S>::F;
-  return k < F ? (k / C) * 64 * C + lane * C + (k % C) : F * 64 + (k - F) * 64 + lane;
+template <typename S, int NE = 9> __device__ __forceinline__ int lk_off(int k, int lane) {
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F, TAIL = LkLay<S, NE>::TAIL;
+  if (k < F) return (k / C) * 64 * C + lane * C + (k % C);
+  return NE == 9 ? F * 64 + (k - F) * 64 + lane : F * 64 + lane * TAIL + (k - F);
+}
+
+// Row 2 of an SU(3) matrix from rows 0 and 1: u[6..8] = conj(row0 x row1)
+// (unit rows orthogonal to both, with the phase that makes det = 1).
+template <typename T> __device__ __forceinline__ void su3_third_row(cx<T> (&u)[9]) {
+  const cx<T> a = u[1] * u[5] - u[2] * u[4];
+  const cx<T> b = u[2] * u[3] - u[0] * u[5];
+  const cx<T> c = u[0] * u[4] - u[1] * u[3];
+  u[6] = cx<T>(a.re, -a.im);
+  u[7] = cx<T>(b.re, -b.im);
+  u[8] = cx<T>(c.re, -c.im);
+}
+
+// The link U_mu at (par, h) in either storage form (recon != 0: 6 entries).
+template <typename S>
+__device__ __forceinline__ void load_link_any(const Geom& g, const S* __restrict__ U, int recon, int mu, int par,
+                                              int h, cx<typename Traits<S>::T> (&u)[9]) {
+  const int lane = h & 63;
+  if (recon) {
+    const S* b = U + lk_block<6>(g, mu, par, h);
+#pragma unroll
+    for (int k = 0; k < 6; k++) u[k] = Traits<S>::load(b + lk_off<S, 6>(k, lane));
+    su3_third_row(u);
+  } else {
+    const S* b = U + lk_block<9>(g, mu, par, h);
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = Traits<S>::load(b + lk_off<S, 9>(k, lane));
+  }
 }
 
 struct Coord { int x, y, z, t; };

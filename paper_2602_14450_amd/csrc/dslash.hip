@@ -97,30 +97,15 @@ __device__ __forceinline__ void load_spinor(const Geom& g, const S* __restrict__
   }
 }
 
-template <typename S, typename T>
-__device__ __forceinline__ void load_link(const Geom& g, const S* __restrict__ U, int mu, int par, int h,
-                                          cx<T> (&u)[9]) {
-  using Gr = typename Lay<S>::Gran;
-  constexpr int C = Lay<S>::C, F = Lay<S>::F;
-  const int lane = h & 63;
-  const S* b = U + lk_block(g, mu, par, h);
-#pragma unroll
-  for (int j = 0; j < F / C; j++) {
-    const Gr v = *reinterpret_cast<const Gr*>(b + j * 64 * C + lane * C);
-#pragma unroll
-    for (int c = 0; c < C; c++) u[j * C + c] = Traits<S>::load(&v.s[c]);
-  }
-#pragma unroll
-  for (int k = F; k < 9; k++) u[k] = Traits<S>::load(b + F * 64 + (k - F) * 64 + lane);
-}
-
 // Raw (still packed) data of one hop: the neighbour's spinor granules and
-// the link granules.  Hops are numbered HOP = 2*mu + (0 forward, 1 backward).
-template <typename S> struct HopRaw {
+// the link granules (NE = 9 stored entries, or 6 with row 2 rebuilt).  Hops
+// are numbered HOP = 2*mu + (0 forward, 1 backward).
+template <typename S, int NE> struct HopRaw {
   typename Lay<S>::Gran sp[Lay<S>::G];
-  typename Lay<S>::Gran lk[Lay<S>::F / Lay<S>::C];
-  S tail[9 - Lay<S>::F > 0 ? 9 - Lay<S>::F : 1];
+  typename Lay<S>::Gran lk[LkLay<S, NE>::F / Lay<S>::C];
+  S tail[LkLay<S, NE>::TAIL > 0 ? LkLay<S, NE>::TAIL : 1];
 };
+template <typename S> struct alignas(2 * sizeof(S)) Pair { S s[2]; };
 
 // Spin pair a hop needs: the t-direction projectors keep spins (2,3) for
 // (1 - g4) and (0,1) for (1 + g4); the others need all four.
@@ -129,13 +114,13 @@ template <int MU, bool MINUS, typename S> __device__ __forceinline__ constexpr b
   return (MU != 3) || (MINUS ? (j * C + C - 1) / 3 >= 2 : (j * C) / 3 < 2);
 }
 
-template <int HOP, bool DAG, typename S>
+template <int HOP, bool DAG, int NE, typename S>
 __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
-                                         int h, const Coord& c, HopRaw<S>& d, int dep = 0) {
+                                         int h, const Coord& c, HopRaw<S, NE>& d, int dep = 0) {
   constexpr int MU = HOP >> 1;
   constexpr bool BWD = HOP & 1;
   constexpr bool MINUS = BWD ? DAG : !DAG;  // forward hop of D uses (1 - gamma)
-  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F, TAIL = LkLay<S, NE>::TAIL;
   using Gr = typename Lay<S>::Gran;
   int hn;
   if constexpr (MU == 0) {
@@ -157,20 +142,28 @@ __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in
     if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = *reinterpret_cast<const Gr*>(sb + j * 64 * C);
   // forward: U_mu(x) stored at x; backward: U_mu(x - mu) stored at the neighbour
   const int lp = BWD ? npar : par, lh = BWD ? hn : h + dep;
-  const S* lb = U + lk_block(g, MU, lp, lh);
+  const S* lb = U + lk_block<NE>(g, MU, lp, lh);
   const int lane = lh & 63;
 #pragma unroll
   for (int j = 0; j < F / C; j++) d.lk[j] = *reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C);
+  if constexpr (NE == 9) {
 #pragma unroll
-  for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
+    for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
+  } else if constexpr (TAIL == 2) {  // the two remaining entries of this lane, one 2-element load
+    const Pair<S> v = *reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2);
+    d.tail[0] = v.s[0];
+    d.tail[1] = v.s[1];
+  } else {
+    static_assert(TAIL == 0, "unsupported link layout");
+  }
 }
 
-template <int HOP, bool DAG, typename S, typename T>
-__device__ __forceinline__ T hop_compute(const HopRaw<S>& d, cx<T> (&a)[4][3]) {
+template <int HOP, bool DAG, int NE, typename S, typename T>
+__device__ __forceinline__ T hop_compute(const HopRaw<S, NE>& d, cx<T> (&a)[4][3]) {
   constexpr int MU = HOP >> 1;
   constexpr bool BWD = HOP & 1;
   constexpr bool MINUS = BWD ? DAG : !DAG;
-  constexpr int C = Lay<S>::C, F = Lay<S>::F;
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F;
   cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
 #pragma unroll
   for (int j = 0; j < Lay<S>::G; j++)
@@ -186,7 +179,8 @@ __device__ __forceinline__ T hop_compute(const HopRaw<S>& d, cx<T> (&a)[4][3]) {
 #pragma unroll
     for (int cc = 0; cc < C; cc++) u[j * C + cc] = Traits<S>::load(&d.lk[j].s[cc]);
 #pragma unroll
-  for (int k = F; k < 9; k++) u[k] = Traits<S>::load(&d.tail[k - F]);
+  for (int k = F; k < NE; k++) u[k] = Traits<S>::load(&d.tail[k - F]);
+  if constexpr (NE == 6) su3_third_row(u);
   project<MU, MINUS>(f, h1, h2);
   if constexpr (!BWD) {  // U_mu(x) h
 #pragma unroll
@@ -228,38 +222,38 @@ struct PipeArgs {
   Coord c;
 };
 
-template <int I, int DEPTH, bool DAG, typename S, typename T>
+template <int I, int DEPTH, bool DAG, int NE, typename S, typename T>
 __device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
-                                         const PipeArgs& pa, HopRaw<S> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
+                                         const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
   if constexpr (I < 8) {
-    hop_compute<I, DAG>(buf[I % (DEPTH + 1)], a);
+    hop_compute<I, DAG, NE>(buf[I % (DEPTH + 1)], a);
     reg_barrier(a);
     if constexpr (I + DEPTH + 1 < 8) {
       int dep = 0;
       asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
-      hop_load<I + DEPTH + 1, DAG>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
+      hop_load<I + DEPTH + 1, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
     }
     QCD_FENCE();
-    hop_pipe<I + 1, DEPTH, DAG>(g, in, U, pa, buf, a);
+    hop_pipe<I + 1, DEPTH, DAG, NE>(g, in, U, pa, buf, a);
   }
 }
 
-template <int I, int DEPTH, bool DAG, typename S>
+template <int I, int DEPTH, bool DAG, int NE, typename S>
 __device__ __forceinline__ void hop_prologue(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
-                                             const PipeArgs& pa, HopRaw<S> (&buf)[DEPTH + 1]) {
+                                             const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1]) {
   if constexpr (I <= DEPTH) {
-    hop_load<I, DAG>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
-    hop_prologue<I + 1, DEPTH, DAG>(g, in, U, pa, buf);
+    hop_load<I, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
+    hop_prologue<I + 1, DEPTH, DAG, NE>(g, in, U, pa, buf);
   }
 }
 
-template <int DEPTH, bool DAG, typename S, typename T>
+template <int DEPTH, bool DAG, int NE, typename S, typename T>
 __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
                                         int h, const Coord& c, cx<T> (&a)[4][3]) {
-  HopRaw<S> buf[DEPTH + 1];
+  HopRaw<S, NE> buf[DEPTH + 1];
   const PipeArgs pa{par, h, c};
-  hop_prologue<0, DEPTH, DAG>(g, in, U, pa, buf);
-  hop_pipe<0, DEPTH, DAG>(g, in, U, pa, buf, a);
+  hop_prologue<0, DEPTH, DAG, NE>(g, in, U, pa, buf);
+  hop_pipe<0, DEPTH, DAG, NE>(g, in, U, pa, buf, a);
 }
 
 // Thread -> (site, right-hand side).  A block of 256 threads is four waves:
@@ -271,12 +265,25 @@ __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in,
 // With sched.mode 1 the blocks are ordered so that the eight XCDs (which
 // receive consecutive workgroups in turn) each sweep their own slab of z in t
 // order, all right-hand-side tiles of a site block back to back; this keeps
-// t-neighbours and links inside that XCD's L2.
+// t-neighbours and links inside that XCD's L2.  Mode 4 gives each XCD a slab
+// of t instead, swept in z order (half the foreign faces when Lt = 2 Lz).
 struct BlockPos { int h0, tile, sb; };
 __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
   const int b = blockIdx.x;
   BlockPos p;
-  if (sc.mode >= 1) {
+  if (sc.mode == 4) {
+    // XCD xcd owns time slices [xcd*zc, (xcd+1)*zc) and sweeps them in z
+    // order, all slices of one z plane (and all right-hand-side tiles) back
+    // to back: z-neighbours stay in its L2 from the previous step, t-neighbours
+    // are in the same step, and only the two slab faces in t are foreign
+    const int xcd = b & 7, j = b >> 3;
+    p.tile = j % sc.ntiles;
+    const int js = j / sc.ntiles;
+    const int per_z = sc.zc * sc.bp;
+    const int z = js / per_z, rem = js - z * per_z;
+    const int tl = rem / sc.bp, yb = rem - tl * sc.bp;
+    p.sb = ((xcd * sc.zc + tl) * sc.Lz + z) * sc.bp + yb;
+  } else if (sc.mode >= 1) {
     // XCD xcd owns z planes [xcd*zc, (xcd+1)*zc), swept as `sub` thinner
     // slabs one after the other, each in t order
     const int xcd = b & 7, j = b >> 3;
@@ -300,7 +307,7 @@ __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
 // out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues,
 // for T right-hand sides per wave (vectors of right-hand side r start at
 // r * vstride elements).
-template <typename S, int OP, int EPI, int DEPTH, int OCC, int T>
+template <typename S, int OP, int EPI, int DEPTH, int OCC, int T, int NE>
 __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, S* __restrict__ out,
                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                      const S* __restrict__ aux, double* __restrict__ partials,
@@ -337,7 +344,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     for (int s = 0; s < 4; s++)
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T_>(0, 0);
-    hop_all<DEPTH, DAG>(g, in, U, par, h, c, a);
+    hop_all<DEPTH, DAG, NE>(g, in, U, par, h, c, a);
     const T_ k = (T_)kappa;
     cx<T_> o[12], ctr[12], ax[12];
     if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(in, g, par, h, ctr);
@@ -388,6 +395,106 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
   if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
 }
 
+// One translation unit per storage precision (QCD_DSLASH_PREC = 0, 1, 2 for
+// FP64, FP32, FP16) keeps the kernel instantiations of a build parallel; the
+// FP16 unit also holds the precision-independent helpers and the dispatcher.
+#ifndef QCD_DSLASH_PREC
+#define QCD_DSLASH_PREC 2
+#endif
+
+template <typename S, int DEPTH, int OCC, int T, int NE>
+static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                            int ftz, hipStream_t st) {
+  dim3 grid(sc.nsb * sc.ntiles), block(256);
+  S* o = (S*)out;
+  const S* i = (const S*)in;
+  const S* u = (const S*)U;
+  const S* x = (const S*)aux;
+#define QCD_LAUNCH(OPV, EPIV)                                                                                  \
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
+                     partials, scal, ftz)
+  if (epi == kEpiNone) {
+    switch (op) {
+      case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
+      case kOpH: QCD_LAUNCH(kOpH, kEpiNone); break;
+      case kOpDdag: QCD_LAUNCH(kOpDdag, kEpiNone); break;
+      default: QCD_LAUNCH(kOpHdag, kEpiNone); break;
+    }
+  } else if (epi == kEpiDotAux) {
+    QCD_LAUNCH(kOpD, kEpiDotAux);
+  } else if (epi == kEpiTS) {
+    QCD_LAUNCH(kOpD, kEpiTS);
+  } else if (epi == kEpiTSAux) {
+    QCD_LAUNCH(kOpD, kEpiTSAux);
+  } else {
+    QCD_LAUNCH(kOpD, kEpiResid);
+  }
+#undef QCD_LAUNCH
+}
+
+template <typename S, int T, int NE>
+static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
+                               const void* in, const void* U, double kappa, const void* aux, double* partials,
+                               const Scalars* scal, int ftz, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched, T, n);
+  if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
+    launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st);
+    return;
+  }
+  switch (tune.variant) {
+    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 5: launch_dslash_v<S, 1, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    default: launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+  }
+}
+
+template <typename S, int NE>
+static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                            int ftz, hipStream_t st) {
+  const int T = rhs_tile_for(tune, n);
+  if (T == 4)
+    launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else if (T == 2)
+    launch_dslash_tile<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else
+    launch_dslash_tile<S, 1, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
+
+template <typename S>
+static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                            int ftz, hipStream_t st) {
+  if (tune.recon)
+    launch_dslash_r<S, 6>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  else
+    launch_dslash_r<S, 9>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
+
+#define QCD_DSLASH_ARGS                                                                                          \
+  const Geom &g, const DslashTune &tune, int op, int epi, int n, void *out, const void *in, const void *U, \
+      double kappa, const void *aux, double *partials, const Scalars *scal, int ftz, hipStream_t st
+void launch_dslash_f64(QCD_DSLASH_ARGS);
+void launch_dslash_f32(QCD_DSLASH_ARGS);
+void launch_dslash_f16(QCD_DSLASH_ARGS);
+
+#if QCD_DSLASH_PREC == 0
+void launch_dslash_f64(QCD_DSLASH_ARGS) {
+  launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
+#elif QCD_DSLASH_PREC == 1
+void launch_dslash_f32(QCD_DSLASH_ARGS) {
+  launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
+#else
+void launch_dslash_f16(QCD_DSLASH_ARGS) {
+  launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+}
+
 int rhs_tile_for(const DslashTune& tune, int n) {
   int T = tune.rhs_tile;
   if (T <= 0) T = 1;  // measured fastest at 32^3 x 64 with 12 right-hand sides (T = 2 ties, T = 4 is slower)
@@ -408,7 +515,16 @@ DslashSched make_sched(const Geom& g, int mode, int T, int n) {
   s.zc = 1;
   s.sub = 1;
   const int plane = g.Lxh * g.L[1];
-  // mode m >= 1: XCD slabs of Lz/8 planes, each swept as 2^(m-1) sub-slabs
+  if (mode == 4) {
+    // XCD slabs of Lt/8 time slices, each swept in z order
+    if (plane % s.H == 0 && g.L[3] % 8 == 0) {
+      s.mode = 4;
+      s.bp = plane / s.H;
+      s.zc = g.L[3] / 8;
+    }
+    return s;
+  }
+  // mode m = 1..3: XCD slabs of Lz/8 planes, each swept as 2^(m-1) sub-slabs in t order
   const int sub = mode >= 1 ? 1 << (mode - 1) : 1;
   if (mode >= 1 && plane % s.H == 0 && g.L[2] % (8 * sub) == 0) {
     s.mode = mode;
@@ -424,78 +540,17 @@ int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n) {
   return (g.Vh + 128 / T - 1) / (128 / T);
 }
 
-template <typename S, int DEPTH, int OCC, int T>
-static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
-                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, hipStream_t st) {
-  dim3 grid(sc.nsb * sc.ntiles), block(256);
-  S* o = (S*)out;
-  const S* i = (const S*)in;
-  const S* u = (const S*)U;
-  const S* x = (const S*)aux;
-#define QCD_LAUNCH(OPV, EPIV)                                                                                      \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
-                     scal, ftz)
-  if (epi == kEpiNone) {
-    switch (op) {
-      case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
-      case kOpH: QCD_LAUNCH(kOpH, kEpiNone); break;
-      case kOpDdag: QCD_LAUNCH(kOpDdag, kEpiNone); break;
-      default: QCD_LAUNCH(kOpHdag, kEpiNone); break;
-    }
-  } else if (epi == kEpiDotAux) {
-    QCD_LAUNCH(kOpD, kEpiDotAux);
-  } else if (epi == kEpiTS) {
-    QCD_LAUNCH(kOpD, kEpiTS);
-  } else if (epi == kEpiTSAux) {
-    QCD_LAUNCH(kOpD, kEpiTSAux);
-  } else {
-    QCD_LAUNCH(kOpD, kEpiResid);
-  }
-#undef QCD_LAUNCH
-}
-
-template <typename S, int T>
-static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
-                               const void* in, const void* U, double kappa, const void* aux, double* partials,
-                               const Scalars* scal, int ftz, hipStream_t st) {
-  const DslashSched sc = make_sched(g, tune.sched, T, n);
-  if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
-    launch_dslash_v<S, 1, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st);
-    return;
-  }
-  switch (tune.variant) {
-    case 1: launch_dslash_v<S, 2, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 2: launch_dslash_v<S, 0, 3, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 3: launch_dslash_v<S, 1, 3, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 4: launch_dslash_v<S, 0, 4, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 5: launch_dslash_v<S, 1, 4, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    default: launch_dslash_v<S, 1, 2, T>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-  }
-}
-
-template <typename S>
-static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
-                            const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, hipStream_t st) {
-  const int T = rhs_tile_for(tune, n);
-  if (T == 4)
-    launch_dslash_tile<S, 4>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
-  else if (T == 2)
-    launch_dslash_tile<S, 2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
-  else
-    launch_dslash_tile<S, 1>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
-}
-
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                    const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
                    hipStream_t st) {
   if (prec == kFP64)
-    launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
   else if (prec == kFP32)
-    launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
   else
-    launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
 }
+#endif
+#undef QCD_DSLASH_ARGS
 
 }  // namespace qcd

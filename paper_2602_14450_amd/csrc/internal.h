@@ -61,15 +61,17 @@ struct Scalars {
 
 // Launch choices of the Wilson operator (picked by the tuner).
 struct DslashTune {
-  int sched;    // 0: blocks in half-index order; m = 1..3: XCD slabs (each swept as 2^(m-1) sub-slabs)
+  int sched;    // 0: blocks in half-index order; m = 1..3: XCD z slabs (each swept as 2^(m-1) sub-slabs);
+                // 4: XCD t slabs swept in z order
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
   int rhs_tile; // right-hand sides sharing a wave's link loads: 0 = automatic, or 1, 2, 4
+  int recon;    // links stored as 6 entries (rows 0, 1; row 2 rebuilt) instead of 9: a property of the data
 };
 constexpr int kDslashVariants = 6;
 struct DslashSched {
   int mode, nsb, ntiles, Lz, Lt, bp, zc, sub, H;  // H: half-sites per parity per block
 };
-constexpr int kDslashScheds = 4;
+constexpr int kDslashScheds = 5;
 DslashSched make_sched(const Geom& g, int mode, int T, int n);
 int rhs_tile_for(const DslashTune& tune, int n);
 
@@ -86,7 +88,9 @@ int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n);  // rows 
 // launchers (blas.hip)
 int site_grid(const Geom& g);              // blocks (and partial rows) per right-hand side, site-ordered kernels
 int flat_rows(const Geom& g, int prec);    // blocks (and partial rows) per right-hand side, BLAS-1 kernels
-void launch_pack_links(const Geom& g, int prec, void* dst, const double* Ucanon, hipStream_t st);
+void launch_pack_links(const Geom& g, int prec, void* dst, const double* Ucanon, int recon, hipStream_t st);
+// out = largest deviation of a link's row 2 from conj(row0 x row1); partials: site_grid(g) doubles
+void launch_link_su3_dev(const Geom& g, const double* Ucanon, double* partials, double* out, hipStream_t st);
 void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double* canon, double scale, int ftz,
                         double* partials, hipStream_t st);
 void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
@@ -141,5 +145,6 @@ struct qcd_gauge {
   hipStream_t cap_stream;
   hipGraphExec_t graph_exec;
   unsigned long long graph_key[8];
+  double su3_dev;  // largest |row2 - conj(row0 x row1)| of the uploaded links (INFINITY if not checked)
 };
 

@@ -55,16 +55,6 @@ __device__ __forceinline__ int nbr(const Geom& g, int h, const Coord& c, int mu,
   return (cm == 0) ? h + (g.L[mu] - 1) * st : h - st;
 }
 
-__device__ __forceinline__ void load_link32(const Geom& g, const float2* U, int mu, int par, int h, cx<float> (&u)[9]) {
-  const float2* b = U + lk_block(g, mu, par, h);
-  const int lane = h & 63;
-#pragma unroll
-  for (int k = 0; k < 9; k++) {
-    float2 v = b[lk_off<float2>(k, lane)];
-    u[k] = cx<float>(v.x, v.y);
-  }
-}
-
 // out = U f (dag = 0) or U^dag f (dag = 1), colour index of f[s][c]
 __device__ __forceinline__ void su3_apply(const cx<float> (&u)[9], const cx<float> (&f)[12], bool dag,
                                           cx<float> (&o)[12]) {
@@ -86,7 +76,7 @@ __device__ __forceinline__ size_t ncols(const Geom& g) { return (size_t)2 * g.nb
 // Forward transport: X[b][n][k] (BF16), n = column (site, colour),
 // k = reim*K + (p*cin + i)*4 + spin; rows [2K, Kp) and padding sites are zero.
 __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, const float2* __restrict__ act,
-                                                       const float2* __restrict__ U, short* __restrict__ X) {
+                                                       const float2* __restrict__ U, int recon, short* __restrict__ X) {
   const int b = blockIdx.y;
   const int i_site = blockIdx.x * 256 + threadIdx.x;  // over 2 * nb * 64 (padding included)
   const int per = g.nb * 64;
@@ -114,8 +104,8 @@ __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, co
         const int hn = nbr(g, h, c, mu, fwd ? 1 : -1);
         load_site(f, g, par ^ 1, hn, in);
         cx<float> u[9];
-        if (fwd) load_link32(g, U, mu, par, h, u);       // U_mu(x)
-        else load_link32(g, U, mu, par ^ 1, hn, u);      // U_mu(x - mu)^dag
+        if (fwd) load_link_any(g, U, recon, mu, par, h, u);       // U_mu(x)
+        else load_link_any(g, U, recon, mu, par ^ 1, hn, u);      // U_mu(x - mu)^dag
         su3_apply(u, in, !fwd, t);
       }
       const int k0 = (p * L.cin + i) * 4;
@@ -230,18 +220,13 @@ __global__ void k_ptc_prep_Af(PtcLayerDev L, const float2* __restrict__ W, short
   A[idx] = to_bf16(v);
 }
 
-template <typename SL>
-__device__ __forceinline__ cx<float> link_entry(const Geom& g, const SL* U, int mu, int par, int h, int k) {
-  return Traits<SL>::load(U + lk_block(g, mu, par, h) + lk_off<SL>(k, h & 63));
-}
-
 // out[b][j] = oscale * sum_{p,i} W[p][j][i] T_p in[b][i] for batch b = blockIdx.y;
 // grid.x = 2 * nb (one 64-site block of one parity per workgroup).  Batches
 // whose solver has stopped (scal[b].active == 0) are skipped when scal is given.
 template <typename SA, typename SL, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict__ in, SA* __restrict__ out,
-                                                   const SL* __restrict__ U, const short* __restrict__ A, int Kp,
-                                                   float oscale, const Scalars* __restrict__ scal, int ftz) {
+                                                   const SL* __restrict__ U, int recon, const short* __restrict__ A,
+                                                   int Kp, float oscale, const Scalars* __restrict__ scal, int ftz) {
   constexpr int NK = (18 * CIN + 3) / 4;
   const int b = blockIdx.y;
   if (scal && !scal[b].active) return;
@@ -289,8 +274,7 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
 #pragma unroll
           for (int cc = 0; cc < 3; cc++) v[sl][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * (2 * sh + sl) + cc, hn & 63));
         const int lp = fwd ? par : par ^ 1, lh = fwd ? h : hn;  // U_mu(x) or U_mu(x - mu)
-#pragma unroll
-        for (int k = 0; k < 9; k++) u[k] = link_entry(g, U, mu, lp, lh, k);
+        load_link_any(g, U, recon, mu, lp, lh, u);
 #pragma unroll
         for (int sl = 0; sl < 2; sl++)
 #pragma unroll
@@ -385,7 +369,8 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const
 
 // dIn_i(y) = sum_p (T_p^dag dX_{p,i})(y): p = 0 identity; +mu: U_mu(y-mu)^dag dX(y-mu); -mu: U_mu(y) dX(y+mu).
 __global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L, const float* __restrict__ DX,
-                                                           const float2* __restrict__ U, float2* __restrict__ din) {
+                                                           const float2* __restrict__ U, int recon,
+                                                           float2* __restrict__ din) {
   const int b = blockIdx.y;
   const int i_site = blockIdx.x * 256 + threadIdx.x;
   if (i_site >= 2 * g.Vh) return;
@@ -421,8 +406,8 @@ __global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L
         for (int k = 0; k < 12; k++) acc[k] = acc[k] + f[k];
       } else {
         cx<float> u[9], t[12];
-        if (dag) load_link32(g, U, mu, sp, sh, u);   // U_mu(y - mu)^dag
-        else load_link32(g, U, mu, par, h, u);       // U_mu(y)
+        if (dag) load_link_any(g, U, recon, mu, sp, sh, u);   // U_mu(y - mu)^dag
+        else load_link_any(g, U, recon, mu, par, h, u);       // U_mu(y)
         su3_apply(u, f, dag, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = acc[k] + t[k];
@@ -658,6 +643,7 @@ size_t fields_bytes(const Geom& g, size_t nf) { return nf * spinor_elems(g) * si
 int site_blocks_pad(const Geom& g) { return (2 * g.nb * 64 + 255) / 256; }
 int site_blocks(const Geom& g) { return (2 * g.Vh + 255) / 256; }
 const float2* links32(const qcd_ptc* n) { return (const float2*)n->gauge->U[kFP32]; }
+int recon_of(const qcd_ptc* n, int prec) { return n->gauge->tune[prec].recon; }
 
 qcd_status alloc(qcd_ptc* n, void** p, size_t bytes) {
   PTC_TRY(hipMalloc(p, bytes ? bytes : 256));
@@ -681,8 +667,9 @@ void fused_layer(const qcd_ptc* n, int l, int nb, const SA* in, SA* out, const S
   const Geom& g = n->g;
   const PtcLayerDev& L = n->L[l];
   const dim3 grid(2 * g.nb, nb), block(256);
-#define PTC_FUSED(CI, CO)                                                                                    \
-  hipLaunchKernelGGL((k_ptc_fused<SA, SL, CI, CO>), grid, block, 0, st, g, in, out, U, (const short*)n->Af[l], \
+  const int recon = recon_of(n, sizeof(SL) == sizeof(float2) ? kFP32 : kFP16);
+#define PTC_FUSED(CI, CO)                                                                                          \
+  hipLaunchKernelGGL((k_ptc_fused<SA, SL, CI, CO>), grid, block, 0, st, g, in, out, U, recon, (const short*)n->Af[l], \
                      L.Kp, oscale, scal, ftz)
   if (L.cin == 1 && L.cout == 1) PTC_FUSED(1, 1);
   else if (L.cin == 1) PTC_FUSED(1, 2);
@@ -703,7 +690,7 @@ void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
     }
     short* X = n->X[l];
     hipLaunchKernelGGL(k_ptc_transport, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, n->L[l],
-                       (const float2*)n->act[l], links32(n), X);
+                       (const float2*)n->act[l], links32(n), recon_of(n, kFP32), X);
     hipLaunchKernelGGL(k_ptc_mix, dim3(n->mix_blocks), dim3(256), 0, st, g, n->L[l], (const short*)X,
                        (const short*)n->A[l], n->act[l + 1], nb);
   }
@@ -734,7 +721,7 @@ qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
       hipLaunchKernelGGL(k_ptc_mix_dx, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
                          (const short*)n->A[l], n->DX, nb);
       hipLaunchKernelGGL(k_ptc_transport_adj, dim3(site_blocks(g), nb), dim3(256), 0, st, g, L, (const float*)n->DX,
-                         links32(n), n->dact[cur ^ 1]);
+                         links32(n), recon_of(n, kFP32), n->dact[cur ^ 1]);
       cur ^= 1;
     }
   }

@@ -44,11 +44,11 @@ def test_multi_rhs_dslash(q, dims, nrhs, prec):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(8, 16, 32, 4), (8, 32, 8, 16)])
 @pytest.mark.parametrize("rhs_tile", [1, 2, 4])
-def test_rhs_tile_choices_agree_bitwise(q, rhs_tile):
-    # every launch shape (schedule incl. the sub-slab orders, right-hand-side
-    # tile) gives bit-identical output
-    dims = (8, 16, 32, 4)
+def test_rhs_tile_choices_agree_bitwise(q, rhs_tile, dims):
+    # every launch shape (schedule incl. the sub-slab and t-slab orders,
+    # right-hand-side tile) gives bit-identical output
     U = qi.gauge_field(dims, 0.3, 41)
     psi = qi.gaussian_source(dims, 42, nrhs=4)
     g = q.gauge_upload(to_dev(U), dims)
@@ -57,7 +57,7 @@ def test_rhs_tile_choices_agree_bitwise(q, rhs_tile):
     g.set_tuning(q.FP16, 0, 0, 1)
     q.dslash(g, 0.124, ref, x, prec=q.FP16)
     out = torch.empty_like(x)
-    for sched in (0, 1, 2, 3):
+    for sched in (0, 1, 2, 3, 4):
         g.set_tuning(q.FP16, sched, 0, rhs_tile)
         q.dslash(g, 0.124, out, x, prec=q.FP16)
         torch.cuda.synchronize()

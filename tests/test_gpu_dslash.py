@@ -127,3 +127,43 @@ def test_dslash_full_size_sampled(q, prec):
     want = oracle.dslash_sites(U, psi, 0.124, dims, sites)
     compare(got, want, TOL[prec], f"32^3x64 prec={prec}")
     g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_su3_links_stored_as_two_rows(q, prec):
+    # generated links are SU(3): 12 reals per link, same operator as the
+    # full 18-real storage within the precision's tolerance, both against the oracle
+    dims = (4, 6, 8, 10)
+    U, psi = fields(dims, gseed=71, sseed=72)
+    g12 = q.gauge_upload(to_dev(U), dims)
+    g18 = q.gauge_upload(to_dev(U), dims, full_links=True)
+    assert g12.link_reals(prec) == 12 and g18.link_reals(prec) == 18
+    x = to_dev(psi)
+    for op in OPS:
+        want = oracle.dslash(U, psi, 0.124, dims, op)
+        for g in (g12, g18):
+            out = torch.empty_like(x)
+            q.dslash(g, 0.124, out, x, op=op, prec=prec)
+            torch.cuda.synchronize()
+            compare(to_host(out), want, TOL[prec], f"links={g.link_reals(prec)} prec={prec} op={op}")
+    g12.close()
+    g18.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_u3_links_keep_all_entries(q, prec):
+    # a U(3) field (SU(3) times a site-dependent phase) fails the SU(3) check:
+    # all 18 reals are kept and the operator still matches the oracle
+    dims = (4, 4, 6, 8)
+    U, psi = fields(dims, gseed=73, sseed=74)
+    phase = np.exp(1j * 2 * np.pi * qi.uniform(U.shape[0] * 4, 75)).reshape(-1, 4, 1, 1)
+    U = U * phase
+    g = q.gauge_upload(to_dev(U), dims)
+    assert g.link_reals(prec) == 18
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    for op in OPS:
+        q.dslash(g, 0.124, out, x, op=op, prec=prec)
+        torch.cuda.synchronize()
+        compare(to_host(out), oracle.dslash(U, psi, 0.124, dims, op), TOL[prec], f"U(3) prec={prec} op={op}")
+    g.close()
