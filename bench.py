@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the launch-shape tuner first (default: the library's measured defaults)")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Wilson operator and the calibration copy (for counter runs)")
     return ap.parse_args()
@@ -79,9 +81,10 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
-def measured_traffic(prec_name):
-    """HBM bytes per launch of the Wilson operator from the committed counter
-    summary, or None if the kernel source changed since it was taken."""
+def measured_counter(label):
+    """A per-launch counter figure of the Wilson operator from the committed
+    counter summary ("<label>: <integer>"), or None if the kernel source changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_dslash_32x32x32x64.md")
     src = os.path.join(ROOT, "paper_2602_14450_amd", "csrc", "dslash.hip")
     try:
@@ -90,7 +93,7 @@ def measured_traffic(prec_name):
     except OSError:
         return None
     m = re.search(r"dslash\.hip sha256: ([0-9a-f]{64})", text)
-    t = re.search(rf"traffic bytes per launch {prec_name}: (\d+)", text)
+    t = re.search(rf"{re.escape(label)}: (\d+)", text)
     if not m or not t or m.group(1) != sha:
         return None
     return int(t.group(1))
@@ -152,6 +155,50 @@ def learned_form(q, torch, np, qi, kappa, pairs_per_field, max_iter):
     return res
 
 
+def mixed_lattices(q, torch, qi, kappa, max_iter):
+    """16^4, 24^3 x 48 and 32^3 x 64 with 4 Gaussian sources each: one batched
+    call (inner solves of the three lattices concurrent, hip-graph replay)
+    against the three lattices solved one after another."""
+    specs = [((16, 16, 16, 16), 301), ((24, 24, 24, 48), 302), ((32, 32, 32, 64), 303)]
+    gauges, bs, xs = [], [], []
+    for dims, seed in specs:
+        gauges.append(q.gauge_upload(torch.from_numpy(qi.gauge_field(dims, 0.3, seed)).cuda(), dims))
+        bs.append(torch.from_numpy(qi.gaussian_source(dims, seed + 1000, nrhs=4)).cuda())
+        xs.append(torch.zeros_like(bs[-1]))
+    kw = dict(inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter,
+              use_graph=True)
+
+    def batched():
+        for x in xs:
+            x.zero_()
+        return q.solve_mixed_ir_batched(gauges, [kappa] * 3, xs, bs, **kw)
+
+    def sequential():
+        out = []
+        for g, x, b in zip(gauges, xs, bs):
+            x.zero_()
+            out.append(q.solve_mixed_ir(g, kappa, x, b, **kw))
+        return out
+
+    res = {}
+    for name, fn in (("batched", batched), ("sequential", sequential)):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        infos = fn()
+        torch.cuda.synchronize()
+        res[name + "_seconds"] = time.perf_counter() - ts
+        res[name + "_inner_iters"] = [[i.inner_iters for i in lat] for lat in infos]
+        res[name + "_max_true_rel_residual"] = max(i.true_rel_residual for lat in infos for i in lat)
+    res["speedup"] = res["sequential_seconds"] / res["batched_seconds"]
+    res["workload"] = "16^4 + 24^3x48 + 32^3x64, eps=0.3, kappa=%g, 4 Gaussian sources each, FP16-inner IR to 1e-12" % kappa
+    print(f"[bench] mixed lattices: {res['batched_seconds']*1e3:.1f} ms batched vs "
+          f"{res['sequential_seconds']*1e3:.1f} ms sequential", file=sys.stderr, flush=True)
+    for g in gauges:
+        g.close()
+    return res
+
+
 def time_dslash(q, torch, g, prec, reps, V, nrhs=1):
     """Average duration of the native-layout Wilson operator, HIP events on
     the launch stream; three buffer pairs rotate so repeats are not served
@@ -205,21 +252,29 @@ def main():
     bd = torch.from_numpy(b).cuda()
     x = torch.zeros_like(bd)
     max_iter = 20000
-    ws = torch.empty(g.workspace_bytes(0, q.FP16, max_iter), dtype=torch.uint8, device="cuda")
-    ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
-    ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
 
     tuned = {}
     for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
-        tuned[name] = g.autotune(prec, nrhs=1, reps=10)
+        if args.autotune:
+            g.autotune(prec, nrhs=1, reps=10)
+        tuned[name] = list(g.get_tuning(prec)) + [g.link_reals(prec)]
     calib_bytes = calibration_copy(torch)
+    # Wilson operator roofline (dominant kernel of the inner solve), timed
+    # before the solver workspaces are allocated
+    dsl = {}
+    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+        ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
+        gbs = DSLASH_BYTES[prec] * V / (ms * 1e-3) / 1e9
+        dsl[name] = dict(us=ms * 1e3, GBps=gbs, frac=gbs / PEAK_HBM_GBS,
+                         GFLOPs=DSLASH_FLOP_PER_SITE * V / (ms * 1e-3) / 1e9)
+        print(f"[bench] dslash {name}: {ms*1e3:.1f} us {gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.only_dslash:
-        for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
-            ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
-            print(f"[bench] dslash {name}: {ms*1e3:.1f} us {DSLASH_BYTES[prec] * V / ms / 1e6:.0f} GB/s", flush=True)
-        print(f"[bench] calibration copy: {calib_bytes} bytes read and written", flush=True)
+        print(f"[bench] calibration copy: {calib_bytes} bytes read and written", file=sys.stderr, flush=True)
         g.close()
         return
+    ws = torch.empty(g.workspace_bytes(0, q.FP16, max_iter), dtype=torch.uint8, device="cuda")
+    ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
+    ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
 
     def solve_fp16():
         return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,
@@ -262,20 +317,13 @@ def main():
                                    matvec_low=i16.matvec_low, matvec_fp64=i16.matvec_fp64,
                                    true_rel_residual=i16.true_rel_residual)
 
-    # Wilson operator roofline (dominant kernel of the inner solve)
-    dsl = {}
-    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
-        ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
-        gbs = DSLASH_BYTES[prec] * V / (ms * 1e-3) / 1e9
-        dsl[name] = dict(us=ms * 1e3, GBps=gbs, frac=gbs / PEAK_HBM_GBS,
-                         GFLOPs=DSLASH_FLOP_PER_SITE * V / (ms * 1e-3) / 1e9)
-        print(f"[bench] dslash {name}: {ms*1e3:.1f} us {gbs:.0f} GB/s", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batched:
         # the 12 spin-colour point sources of a propagator, one batched solve
         # against 12 sequential solves at the same tolerance
         nb = 12
-        tuned["fp16_12rhs"] = g.autotune(q.FP16, nrhs=nb, reps=5)
+        if args.autotune:
+            tuned["fp16_12rhs"] = g.autotune(q.FP16, nrhs=nb, reps=5)
         ms12 = time_dslash(q, torch, g, q.FP16, max(5, args.dslash_reps // 5), V, nrhs=nb)
         bytes12 = (144 + nb * 96) * V
         bp = np.stack([qi.point_source(dims, sp, c) for sp in range(4) for c in range(3)])
@@ -312,12 +360,18 @@ def main():
         print(f"[bench] batched 12 rhs: {t_batched*1e3:.1f} ms vs {t_seq*1e3:.1f} ms sequential; "
               f"12-rhs dslash {ms12*1e3:.1f} us {bytes12 / ms12 / 1e6:.0f} GB/s", file=sys.stderr, flush=True)
         del xb, bpd, wsb
+        batched["mixed_lattices"] = mixed_lattices(q, torch, qi, k, max_iter)
 
-    traffic = measured_traffic("fp16") if dims == (32, 32, 32, 64) else None
+    at_size = dims == (32, 32, 32, 64)
+    traffic = measured_counter("traffic bytes per launch fp16") if at_size else None
+    valu = measured_counter("valu wave-instructions per launch fp16") if at_size else None
+    # VALU issue: a wave64 instruction occupies a 16-lane SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+    valu_frac = valu * 4 / (1024 * 2.4e9) / (dsl["fp16"]["us"] * 1e-6) if valu else None
     roof = dict(bound="hbm", achieved=dsl["fp16"]["GBps"], peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=dsl["fp16"]["frac"], traffic=traffic, kernel="k_dslash<__half2, D>",
                 bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V,
-                algorithmic_bytes_per_launch=DSLASH_BYTES[2] * V, copy_GBps=copy_bandwidth(torch))
+                algorithmic_bytes_per_launch=DSLASH_BYTES[2] * V, copy_GBps=copy_bandwidth(torch),
+                valu_issue_frac=valu_frac, link_reals=tuned["fp16"][3])
     learned = None
     if not args.no_learned:
         learned = learned_form(q, torch, np, qi, 0.124, args.learned_pairs, max_iter)

@@ -226,6 +226,22 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
 qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
                               const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Several lattices in one call (the batched form of Alg. 3): nlat gauge
+ * handles (distinct, possibly of different extents), each with its own kappa,
+ * nrhs right-hand sides b_dev[i] and solutions x_dev[i] (canonical complex128,
+ * device), solved with the same parameters p.  Every refinement step converts
+ * all lattices, runs their inner BiCGStab iterations together (each lattice
+ * on its handle's own stream, forked from and joined to `stream`, so small
+ * lattices run concurrently; with p->inner.use_graph each lattice replays its
+ * captured iteration) and corrects them; the host polls all lattices' device
+ * scalars with one synchronisation.  Per right-hand side results match
+ * qcd_solve_mixed_ir on that lattice alone.  info may be NULL or hold nlat
+ * arrays of nrhs[i] entries.  Workspaces are the handles' own; p->precond
+ * must be NULL (QCD_ERR_UNSUPPORTED otherwise).  nlat in 1..64. */
+qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const double* kappa, const int* nrhs,
+                                      void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
+                                      qcd_solve_info* const* info, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned preconditioner: a gauge-covariant parallel-transport network.
  * A layer maps C_in spinor fields to C_out fields,

@@ -75,6 +75,10 @@ _lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _i, _vp, _vp, ctypes.POINTER(Bicgstab
                               _vp, _sz, _vp]
 _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
                                     _sz, _vp]
+_lib.qcd_solve_mixed_ir_batched.argtypes = [_i, ctypes.POINTER(_vp), ctypes.POINTER(_d), ctypes.POINTER(_i),
+                                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(IRParams),
+                                            ctypes.POINTER(ctypes.POINTER(SolveInfo)), _vp]
+_lib.qcd_solve_mixed_ir_batched.restype = _i
 _lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
 _lib.qcd_autotune_dslash.argtypes = [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_d), _vp]
 _lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
@@ -96,7 +100,7 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
     getattr(_lib, _f).restype = _i
 
 EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
-            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir",
+            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann"]
 
@@ -407,3 +411,33 @@ class PTC:
         _check(_lib.qcd_ptc_train_step(self.handle, nb, _ptr(_as_c128(r)), _ptr(_as_c128(e)), float(lr),
                                        ctypes.byref(loss), _stream()))
         return loss.value
+
+
+def solve_mixed_ir_batched(gauges, kappas, xs, bs, inner_prec=FP16, tol=1e-12, max_outer=100, s=128.0,
+                           recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
+                           recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, history=False,
+                           raise_on_error=True, use_graph=False):
+    """Several lattices (distinct Gauge handles, any extents) solved together:
+    one refinement whose inner solves run concurrently.  xs[i], bs[i] hold one
+    or several canonical fields of lattice i.  Returns a list (per lattice) of
+    Info or lists of Info."""
+    nl = len(gauges)
+    ns = [g.nrhs_of(b) for g, b in zip(gauges, bs)]
+    inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
+                         use_graph)
+    p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner, None, 0.0)
+    made = [_make_infos(n, inner_max_iter * 4 if history else 0, max_outer) for n in ns]
+    gh = (ctypes.c_void_p * nl)(*[g.handle.value for g in gauges])
+    kp = (ctypes.c_double * nl)(*[float(k) for k in kappas])
+    npp = (ctypes.c_int * nl)(*ns)
+    bcs = [_as_c128(b) for b in bs]
+    xp = (ctypes.c_void_p * nl)(*[_ptr(x).value for x in xs])
+    bp = (ctypes.c_void_p * nl)(*[_ptr(b).value for b in bcs])
+    ip = (ctypes.POINTER(SolveInfo) * nl)(*[ctypes.cast(m[0], ctypes.POINTER(SolveInfo)) for m in made])
+    code = _lib.qcd_solve_mixed_ir_batched(nl, gh, kp, npp, xp, bp, ctypes.byref(p), ip, _stream())
+    if raise_on_error:
+        _check(code, allow=(0, 1))
+    out = []
+    for (infos, keep) in made:
+        out.append(_infos_out(code, infos, keep))
+    return out

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "qcd.h"
 #include "internal.h"
@@ -289,59 +290,118 @@ bool any_active(const qcd_gauge* g, int n) {
   return false;
 }
 
-// Run the inner loop from initialised scalars until the device reports a
-// stop for every right-hand side; fills the host mirror.  Iterations are
-// queued in chunks without host synchronisation (kernels of a stopped solve
-// return at once).  After the first chunk, the chunk length is the number of
-// iterations the observed convergence rate predicts the slowest right-hand
-// side still needs, plus one.
-qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, const qcd_bicgstab_params& p,
-                     const Precond& pc, hipStream_t st) {
+// One inner solve in progress: a handle, its workspace and its preconditioner.
+struct InnerRun {
+  const qcd_gauge* g;
+  int prec;
+  double kappa;
+  const Work* w;
+  Precond pc;
+};
+
+// Copy every run's device scalars to its handle's host mirror, one synchronisation.
+qcd_status read_scalars_all(const InnerRun* runs, int nrun, hipStream_t st) {
+  for (int r = 0; r < nrun; r++)
+    HIP_TRY(hipMemcpyAsync(runs[r].g->host_sc, runs[r].w->sc, sizeof(Scalars) * runs[r].w->n, hipMemcpyDeviceToHost,
+                           st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return QCD_OK;
+}
+
+// Run the inner loops of several solves (one per run) from initialised
+// scalars until the device reports a stop for every right-hand side of every
+// run; fills the host mirrors.  Iterations are queued in chunks without host
+// synchronisation (kernels of a stopped solve return at once).  After the
+// first chunk, the chunk length is the number of iterations the observed
+// convergence rate predicts the slowest right-hand side still needs, plus
+// one.  With several runs each chunk forks from st onto every run's own
+// stream (runs on different lattices proceed concurrently) and joins back.
+qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_params& p, hipStream_t st) {
   const int K0 = p.check_every > 0 ? p.check_every : 4;
-  const int n = w.n;
-  qcd_status s = read_scalars(g, w, st);
+  qcd_status s = read_scalars_all(runs, nrun, st);
   if (s) return s;
-  hipGraphExec_t gexec = nullptr;
-  if (p.use_graph && any_active(g, n)) {
-    if ((s = iteration_graph(g, prec, kappa, w, p.ftz, pc, &gexec))) return s;
+  std::vector<hipGraphExec_t> gexec(nrun, nullptr);
+  std::vector<hipStream_t> rs(nrun, st);
+  std::vector<hipEvent_t> done(nrun, nullptr);
+  hipEvent_t fork = nullptr;
+  struct Cleanup {
+    std::vector<hipEvent_t>& d;
+    hipEvent_t& f;
+    ~Cleanup() {
+      for (auto e : d)
+        if (e) (void)hipEventDestroy(e);
+      if (f) (void)hipEventDestroy(f);
+    }
+  } cleanup{done, fork};
+  for (int r = 0; r < nrun; r++) {
+    qcd_gauge* g = const_cast<qcd_gauge*>(runs[r].g);
+    if (p.use_graph && any_active(g, runs[r].w->n))
+      if ((s = iteration_graph(g, runs[r].prec, runs[r].kappa, *runs[r].w, p.ftz, runs[r].pc, &gexec[r]))) return s;
+    if (nrun > 1) {
+      if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+      rs[r] = g->cap_stream;
+      HIP_TRY(hipEventCreateWithFlags(&done[r], hipEventDisableTiming));
+    }
   }
+  if (nrun > 1) HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  auto anyrun = [&]() {
+    for (int r = 0; r < nrun; r++)
+      if (any_active(runs[r].g, runs[r].w->n)) return true;
+    return false;
+  };
+  std::vector<double> prev_res2((size_t)nrun * kMaxRhs);
+  std::vector<int> prev_iter((size_t)nrun * kMaxRhs, 0);
+  for (int r = 0; r < nrun; r++)
+    for (int i = 0; i < runs[r].w->n; i++) prev_res2[(size_t)r * kMaxRhs + i] = runs[r].g->host_sc[i].bnorm2;
   int launched = 0, chunk = K0;
-  double prev_res2[kMaxRhs];
-  int prev_iter[kMaxRhs];
-  for (int i = 0; i < n; i++) {
-    prev_res2[i] = g->host_sc[i].bnorm2;
-    prev_iter[i] = 0;
-  }
-  while (any_active(g, n) && launched <= p.max_iter + K0) {
-    for (int j = 0; j < chunk; j++) {
-      if (gexec)
-        HIP_TRY(hipGraphLaunch(gexec, st));
-      else
-        bicg_iteration(g, prec, kappa, w, p.ftz, pc, st);
+  while (anyrun() && launched <= p.max_iter + K0) {
+    if (nrun > 1) HIP_TRY(hipEventRecord(fork, st));
+    for (int r = 0; r < nrun; r++) {
+      const InnerRun& R = runs[r];
+      if (!any_active(R.g, R.w->n)) continue;
+      if (nrun > 1) HIP_TRY(hipStreamWaitEvent(rs[r], fork, 0));
+      for (int j = 0; j < chunk; j++) {
+        if (gexec[r])
+          HIP_TRY(hipGraphLaunch(gexec[r], rs[r]));
+        else
+          bicg_iteration(R.g, R.prec, R.kappa, *R.w, p.ftz, R.pc, rs[r]);
+      }
+      if (nrun > 1) {
+        HIP_TRY(hipEventRecord(done[r], rs[r]));
+        HIP_TRY(hipStreamWaitEvent(st, done[r], 0));
+      }
     }
     HIP_LAUNCHED();
     launched += chunk;
-    s = read_scalars(g, w, st);
-    if (s) return s;
+    if ((s = read_scalars_all(runs, nrun, st))) return s;
     chunk = K0;
     if (p.check_every > 0) continue;
     int need_max = 0;
-    for (int i = 0; i < n; i++) {
-      const Scalars& h = g->host_sc[i];
-      if (!h.active || h.iter <= prev_iter[i]) continue;
-      const double res2 = h.rnorm2 / (h.gamma_cum * h.gamma_cum);
-      const double target = h.tol2 * h.bnorm2;
-      const double rate = std::pow(res2 / prev_res2[i], 1.0 / (h.iter - prev_iter[i]));  // per iteration
-      int need = K0;
-      if (rate > 0.0 && rate < 0.999 && res2 > target)
-        need = (int)std::min(64.0, std::max(1.0, std::ceil(std::log(target / res2) / std::log(rate)) + 1.0));
-      need_max = std::max(need_max, need);
-      prev_res2[i] = res2;
-      prev_iter[i] = h.iter;
-    }
+    for (int r = 0; r < nrun; r++)
+      for (int i = 0; i < runs[r].w->n; i++) {
+        const Scalars& h = runs[r].g->host_sc[i];
+        double& pr = prev_res2[(size_t)r * kMaxRhs + i];
+        int& pi = prev_iter[(size_t)r * kMaxRhs + i];
+        if (!h.active || h.iter <= pi) continue;
+        const double res2 = h.rnorm2 / (h.gamma_cum * h.gamma_cum);
+        const double target = h.tol2 * h.bnorm2;
+        const double rate = std::pow(res2 / pr, 1.0 / (h.iter - pi));  // per iteration
+        int need = K0;
+        if (rate > 0.0 && rate < 0.999 && res2 > target)
+          need = (int)std::min(64.0, std::max(1.0, std::ceil(std::log(target / res2) / std::log(rate)) + 1.0));
+        need_max = std::max(need_max, need);
+        pr = res2;
+        pi = h.iter;
+      }
     if (need_max > 0) chunk = need_max;
   }
   return QCD_OK;
+}
+
+qcd_status bicg_loop(const qcd_gauge* g, int prec, double kappa, const Work& w, const qcd_bicgstab_params& p,
+                     const Precond& pc, hipStream_t st) {
+  const InnerRun run{g, prec, kappa, &w, pc};
+  return bicg_loop_multi(&run, 1, p, st);
 }
 
 void copy_history(qcd_solve_info* info, const Work& w, int rhs, int niter, double bn2, hipStream_t st) {
@@ -379,10 +439,12 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   qcd_gauge* g = new qcd_gauge();
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
-  // defaults measured on MI355X at 32^3 x 64 (the tuner may override them)
+  // defaults measured on MI355X at 32^3 x 64 with rotating buffers (the tuner
+  // may override them): z slabs per XCD; prefetch 1 hop at 4 waves per SIMD
+  // (FP16), 2 hops at 2 (FP32), 1 hop at 2 (FP64)
   g->tune[kFP64] = DslashTune{1, 0, 0, 0};
   g->tune[kFP32] = DslashTune{1, 1, 0, 0};
-  g->tune[kFP16] = DslashTune{1, 1, 0, 0};
+  g->tune[kFP16] = DslashTune{1, 5, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
@@ -735,186 +797,311 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
   return result;
 }
 
-qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
-                              const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
-  const double t0 = now_s();
-  if (!p) return fail(QCD_ERR_ARG, "null parameters");
-  qcd_status rc = check_gauge(g, p->inner_prec);
-  if (rc) return rc;
-  if ((rc = check_nrhs(nrhs))) return rc;
-  if (!x_dev || !b_dev) return fail(QCD_ERR_ARG, "null vector");
-  if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
-  if (!(p->tol > 0) || p->max_outer <= 0 || !(p->s > 0)) return fail(QCD_ERR_ARG, "tol > 0, max_outer > 0, s > 0 required");
-  if ((rc = check_bicg_params(&p->inner))) return rc;
-  const int prec = p->inner_prec;
-  const int n = nrhs;
-  qcd_ptc* net = const_cast<qcd_ptc*>(p->precond);
-  if (net) {
-    if (prec != kFP16) return fail(QCD_ERR_UNSUPPORTED, "the network preconditioner runs with the FP16 inner solve");
-    if (ptc_gauge(net) != g) return fail(QCD_ERR_ARG, "the network is bound to another gauge handle");
-    if (n > ptc_max_batch(net)) return fail(QCD_ERR_ARG, "nrhs %d exceeds the network's max_batch %d", n,
-                                            ptc_max_batch(net));
-    if (!(p->precond_scale >= 0) || !std::isfinite(p->precond_scale))
-      return fail(QCD_ERR_ARG, "precond_scale must be finite and >= 0");
-  }
-  hipStream_t st = S(stream);
+}  // extern "C"
+
+namespace {
+
+// One lattice's refinement (Alg. 3) in progress.
+struct IrRun {
+  const qcd_gauge* g = nullptr;
+  double kappa = 0;
+  int n = 0;
+  void* x_dev = nullptr;
+  const void* b_dev = nullptr;
+  qcd_solve_info* info = nullptr;
+  qcd_ptc* net = nullptr;
   Work w;
-  if ((rc = get_work(g, net ? 3 : 0, prec, p->inner.max_iter, n, ws, ws_bytes, &w))) return rc;
-  const Geom& G = g->g;
-  const int rows = site_grid(G);
-  const int drows64 = dslash_partial_rows(G, g->tune[kFP64], n);
-  Scalars hs[kMaxRhs];
-  for (int i = 0; i < n; i++) {
-    init_params(&hs[i], p->inner);
-    hs[i].out_tol = p->tol;
-  }
-  HIP_TRY(hipMemcpyAsync(w.sc, hs, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
-  // b in the native FP64 layout; r = b, x = 0
-  launch_pack_spinor(G, kFP64, n, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
-  launch_outer_residual_norm(n, w.sc, w.partials, rows, p->s, st);
-  HIP_TRY(hipMemcpyAsync(w.r64, w.b64, n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
-  launch_zero(G, kFP64, n, w.x64, st);
-  HIP_LAUNCHED();
-  if ((rc = read_scalars(g, w, st))) return rc;
+  Precond pc;
   double bn[kMaxRhs], rn[kMaxRhs];
   int outer[kMaxRhs], inner_total[kMaxRhs], last_status[kMaxRhs];
   qcd_status result[kMaxRhs];
+  bool inner_failed[kMaxRhs];
+  Scalars sc[kMaxRhs];  // snapshot after an inner solve
   bool any = false;
-  for (int i = 0; i < n; i++) {
-    bn[i] = rn[i] = g->host_sc[i].out_rnorm;
-    outer[i] = inner_total[i] = 0;
-    last_status[i] = kConverged;
-    result[i] = QCD_OK;
-    if (!std::isfinite(bn[i])) result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
-    if (info) {
-      info[i].history_len = 0;
-      info[i].first_shat_over_s = 0;
-      info[i].precond_steps = 0;
-      info[i].precond_fallback = -1;
-      info[i].precond_scale = 0;
-    }
-    any |= g->host_sc[i].outer_active && std::isfinite(bn[i]);
-  }
-  if (!std::isfinite(bn[0]) && n == 1) any = false;
-  Precond pc;
-  pc.net = net;
-  pc.scale = (float)p->precond_scale;
   int pc_steps = 0, pc_fallback = -1;
-  int step = 0;
-  while (any) {
+};
+
+qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
+  qcd_status rc = check_gauge(R.g, p->inner_prec);
+  if (rc) return rc;
+  if ((rc = check_nrhs(R.n))) return rc;
+  if (!R.x_dev || !R.b_dev) return fail(QCD_ERR_ARG, "null vector");
+  if (!(R.kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
+  if (R.net) {
+    if (p->inner_prec != kFP16) return fail(QCD_ERR_UNSUPPORTED, "the network preconditioner runs with the FP16 inner solve");
+    if (ptc_gauge(R.net) != R.g) return fail(QCD_ERR_ARG, "the network is bound to another gauge handle");
+    if (R.n > ptc_max_batch(R.net))
+      return fail(QCD_ERR_ARG, "nrhs %d exceeds the network's max_batch %d", R.n, ptc_max_batch(R.net));
+    if (!(p->precond_scale >= 0) || !std::isfinite(p->precond_scale))
+      return fail(QCD_ERR_ARG, "precond_scale must be finite and >= 0");
+  }
+  return QCD_OK;
+}
+
+// b in the native FP64 layout; r = b, x = 0; |b| and the first rescaling on the device.
+void ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+  const Geom& G = R.g->g;
+  Scalars hs[kMaxRhs];
+  for (int i = 0; i < R.n; i++) {
+    init_params(&hs[i], p->inner);
+    hs[i].out_tol = p->tol;
+  }
+  (void)hipMemcpyAsync(R.w.sc, hs, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st);
+  launch_pack_spinor(G, kFP64, R.n, R.w.b64, (const double*)R.b_dev, 1.0, 0, R.w.partials, st);
+  launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(G), p->s, st);
+  (void)hipMemcpyAsync(R.w.r64, R.w.b64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st);
+  launch_zero(G, kFP64, R.n, R.w.x64, st);
+}
+
+void ir_after_start(IrRun& R) {
+  R.any = false;
+  for (int i = 0; i < R.n; i++) {
+    const Scalars& h = R.g->host_sc[i];
+    R.bn[i] = R.rn[i] = h.out_rnorm;
+    R.outer[i] = R.inner_total[i] = 0;
+    R.last_status[i] = kConverged;
+    R.result[i] = QCD_OK;
+    if (!std::isfinite(R.bn[i])) R.result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
+    if (R.info) {
+      R.info[i].history_len = 0;
+      R.info[i].first_shat_over_s = 0;
+      R.info[i].precond_steps = 0;
+      R.info[i].precond_fallback = -1;
+      R.info[i].precond_scale = 0;
+    }
+    R.any |= h.outer_active && std::isfinite(R.bn[i]);
+  }
+  if (R.n == 1 && !std::isfinite(R.bn[0])) R.any = false;
+  R.pc.net = R.net;
+}
+
+// y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start (right-hand sides
+// that met the tolerance are skipped by the kernels); x is saved first when a
+// preconditioned step may have to be undone.
+qcd_status ir_begin_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+  const Geom& G = R.g->g;
+  const int prec = p->inner_prec;
+  if (R.pc.net) HIP_TRY(hipMemcpyAsync(R.w.x64b, R.w.x64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
+  launch_convert(G, prec, R.n, R.w.sc, (const double*)R.w.r64, R.w.r, R.w.rstar, R.w.partials, p->inner.ftz, st);
+  launch_convert_finish(R.n, R.w.sc, R.w.partials, site_grid(G), p->recalc_shat, p->s, st);
+  HIP_LAUNCHED();
+  if (R.pc.net && R.pc.scale == 0.0f) {  // c = 1 / gain of M, measured on the first y~
+    double gain = 0;
+    qcd_status rc = ptc_gain(R.pc.net, R.n, R.w.r, &gain, st);
+    if (rc) return rc;
+    R.pc.scale = gain > 0 ? (float)(1.0 / gain) : 1.0f;
+  }
+  return QCD_OK;
+}
+
+// After the inner solve: bookkeeping, x += (|r| / s^) double(t~) (t~ = c M u~
+// when preconditioned), r = b - D x in FP64 (skipped where not refining).
+qcd_status ir_end_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+  const Geom& G = R.g->g;
+  const int prec = p->inner_prec;
+  memcpy(R.sc, R.g->host_sc, sizeof(Scalars) * R.n);
+  for (int i = 0; i < R.n; i++) {
+    R.inner_failed[i] = false;
+    if (!R.sc[i].outer_active) continue;
+    if (R.info && R.outer[i] == 0) R.info[i].first_shat_over_s = R.sc[i].shat / p->s;
+    if (R.info && R.info[i].zeros && R.outer[i] < R.info[i].outer_history_cap)
+      R.info[i].zeros[R.outer[i]] = R.sc[i].zeros;
+    copy_history(R.info ? R.info + i : nullptr, R.w, i, R.sc[i].iter, R.sc[i].bnorm2, st);
+    R.inner_total[i] += R.sc[i].iter;
+    R.last_status[i] = R.sc[i].status;
+    R.inner_failed[i] = R.sc[i].status == kNonFinite || R.sc[i].iter == 0;
+    if (R.inner_failed[i] && !R.pc.net)
+      R.result[i] = fail(R.sc[i].status == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
+                         "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
+                         R.sc[i].status, R.outer[i]);
+  }
+  if (R.pc.net) {
+    ptc_apply_half(R.pc.net, R.n, R.w.x, R.w.z, R.pc.scale, p->inner.ftz, nullptr, st);
+    launch_correct(G, prec, R.n, R.w.sc, (double*)R.w.x64, R.w.z, st);
+  } else {
+    launch_correct(G, prec, R.n, R.w.sc, (double*)R.w.x64, R.w.x, st);
+  }
+  residual64(R.g, R.kappa, R.w, nullptr, st);
+  launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, dslash_partial_rows(G, R.g->tune[kFP64], R.n), p->s, st);
+  HIP_LAUNCHED();
+  return QCD_OK;
+}
+
+// With the new residual norms in the host mirror: the flexible step is kept
+// only if every refining residual dropped and stayed finite (else x is
+// restored for the right-hand sides that failed and the run continues
+// without the network); then the outer counters and stop flags.
+qcd_status ir_after_step(IrRun& R, const qcd_ir_params* p, int step, hipStream_t st) {
+  const Geom& G = R.g->g;
+  qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
+  if (R.pc.net) {
+    bool undo = false;
+    bool bad[kMaxRhs];
+    for (int i = 0; i < R.n; i++) {
+      bad[i] = false;
+      if (!R.sc[i].outer_active) continue;
+      const double r_new = g->host_sc[i].out_rnorm;
+      bad[i] = R.inner_failed[i] || !std::isfinite(r_new) || !(r_new < R.rn[i]);
+      undo |= bad[i];
+    }
+    if (undo) {
+      for (int i = 0; i < R.n; i++)
+        if (bad[i])
+          HIP_TRY(hipMemcpyAsync((char*)R.w.x64 + i * spinor_bytes(G, kFP64),
+                                 (char*)R.w.x64b + i * spinor_bytes(G, kFP64), spinor_bytes(G, kFP64),
+                                 hipMemcpyDeviceToDevice, st));
+      for (int i = 0; i < R.n; i++) g->host_sc[i].outer_active = R.sc[i].outer_active;
+      HIP_TRY(hipMemcpyAsync(R.w.sc, g->host_sc, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
+      residual64(R.g, R.kappa, R.w, nullptr, st);
+      launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, dslash_partial_rows(G, R.g->tune[kFP64], R.n), p->s,
+                                 st);
+      HIP_LAUNCHED();
+      qcd_status rc = read_scalars(R.g, R.w, st);
+      if (rc) return rc;
+      R.pc_fallback = step;
+      R.pc.net = nullptr;
+    } else {
+      R.pc_steps++;
+    }
+  }
+  R.any = false;
+  for (int i = 0; i < R.n; i++) {
+    if (!R.sc[i].outer_active) continue;
+    R.outer[i]++;
+    R.rn[i] = g->host_sc[i].out_rnorm;
+    if (R.info && R.info[i].outer_history && R.outer[i] - 1 < R.info[i].outer_history_cap)
+      R.info[i].outer_history[R.outer[i] - 1] = R.rn[i] / R.bn[i];
+    if (!std::isfinite(R.rn[i])) R.result[i] = fail(QCD_ERR_NONFINITE, "non-finite outer residual");
+    if (R.result[i] < 0) {  // stop refining this right-hand side
+      g->host_sc[i].outer_active = 0;
+      HIP_TRY(hipMemcpyAsync(&R.w.sc[i].outer_active, &g->host_sc[i].outer_active, sizeof(int), hipMemcpyHostToDevice,
+                             st));
+    }
+    R.any |= g->host_sc[i].outer_active != 0;
+  }
+  return QCD_OK;
+}
+
+qcd_status ir_finish(IrRun& R, double t0) {
+  qcd_status res = QCD_OK;
+  for (int i = 0; i < R.n; i++) {
+    if (R.info) {
+      qcd_solve_info& in = R.info[i];
+      in.outer_iters = R.outer[i];
+      in.inner_iters = R.inner_total[i];
+      in.matvec_low = 2 * R.inner_total[i];
+      in.matvec_fp64 = R.outer[i];
+      in.true_rel_residual = R.bn[i] > 0 ? R.rn[i] / R.bn[i] : 0.0;
+      in.inner_status = R.last_status[i];
+      in.seconds = now_s() - t0;
+      in.precond_steps = R.pc_steps;
+      in.precond_fallback = R.pc_fallback;
+      in.precond_scale = R.net ? R.pc.scale : 0.0;
+    }
+    res = worse(res, R.result[i]);
+  }
+  return res;
+}
+
+// The refinement of Alg. 3 for several lattices at once: every refinement
+// step converts all of them, runs their inner solves together
+// (bicg_loop_multi) and corrects them.  runs[r].w must be set.
+qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream_t st, double t0) {
+  qcd_status rc;
+  for (int r = 0; r < nrun; r++) ir_start(runs[r], p, st);
+  HIP_LAUNCHED();
+  {
+    std::vector<InnerRun> ir(nrun);
+    for (int r = 0; r < nrun; r++) ir[r] = InnerRun{runs[r].g, p->inner_prec, runs[r].kappa, &runs[r].w, Precond{}};
+    if ((rc = read_scalars_all(ir.data(), nrun, st))) return rc;
+  }
+  for (int r = 0; r < nrun; r++) {
+    runs[r].pc.scale = (float)p->precond_scale;
+    ir_after_start(runs[r]);
+  }
+  for (int step = 0;; step++) {
+    std::vector<IrRun*> act;
+    for (int r = 0; r < nrun; r++)
+      if (runs[r].any) act.push_back(&runs[r]);
+    if (act.empty()) break;
     if (step >= p->max_outer) {
-      for (int i = 0; i < n; i++)
-        if (g->host_sc[i].outer_active) result[i] = worse(result[i], QCD_NOT_CONVERGED);
+      for (IrRun* R : act)
+        for (int i = 0; i < R->n; i++)
+          if (R->g->host_sc[i].outer_active) R->result[i] = worse(R->result[i], QCD_NOT_CONVERGED);
       break;
     }
-    // keep x so that a preconditioned step that fails can be undone
-    if (pc.net) HIP_TRY(hipMemcpyAsync(w.x64b, w.x64, n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
-    // y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start (right-hand
-    // sides that met the tolerance are skipped by the kernels)
-    launch_convert(G, prec, n, w.sc, (const double*)w.r64, w.r, w.rstar, w.partials, p->inner.ftz, st);
-    launch_convert_finish(n, w.sc, w.partials, rows, p->recalc_shat, p->s, st);
-    HIP_LAUNCHED();
-    if (pc.net && pc.scale == 0.0f) {  // c = 1 / gain of M, measured on the first y~
-      double gain = 0;
-      if ((rc = ptc_gain(pc.net, n, w.r, &gain, st))) return rc;
-      pc.scale = gain > 0 ? (float)(1.0 / gain) : 1.0f;
-    }
-    if ((rc = bicg_loop(g, prec, kappa, w, p->inner, pc, st))) return rc;
-    Scalars sc[kMaxRhs];
-    memcpy(sc, g->host_sc, sizeof(Scalars) * n);
-    bool inner_failed[kMaxRhs];
-    for (int i = 0; i < n; i++) {
-      inner_failed[i] = false;
-      if (!sc[i].outer_active) continue;
-      if (info && outer[i] == 0) info[i].first_shat_over_s = sc[i].shat / p->s;
-      if (info && info[i].zeros && outer[i] < info[i].outer_history_cap) info[i].zeros[outer[i]] = sc[i].zeros;
-      copy_history(info ? info + i : nullptr, w, i, sc[i].iter, sc[i].bnorm2, st);
-      inner_total[i] += sc[i].iter;
-      last_status[i] = sc[i].status;
-      inner_failed[i] = sc[i].status == kNonFinite || sc[i].iter == 0;
-      if (inner_failed[i] && !pc.net)
-        result[i] = fail(sc[i].status == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
-                         "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
-                         sc[i].status, outer[i]);
-    }
-    // x += (|r| / s^) double(t~), with t~ = c M u~ when preconditioned; r = b - D x
-    // in FP64 (skipped where not refining)
-    if (pc.net) {
-      ptc_apply_half(pc.net, n, w.x, w.z, pc.scale, p->inner.ftz, nullptr, st);
-      launch_correct(G, prec, n, w.sc, (double*)w.x64, w.z, st);
-    } else {
-      launch_correct(G, prec, n, w.sc, (double*)w.x64, w.x, st);
-    }
-    residual64(g, kappa, w, nullptr, st);
-    launch_outer_residual_norm(n, w.sc, w.partials, drows64, p->s, st);
-    HIP_LAUNCHED();
-    if ((rc = read_scalars(g, w, st))) return rc;
-    if (pc.net) {
-      // flexible step accepted only if every refining residual dropped and stayed finite
-      bool undo = false;
-      for (int i = 0; i < n; i++) {
-        if (!sc[i].outer_active) continue;
-        const double r_new = g->host_sc[i].out_rnorm;
-        if (inner_failed[i] || !std::isfinite(r_new) || !(r_new < rn[i])) undo = true;
-      }
-      if (undo) {
-        // restore x of the right-hand sides whose step failed, recompute r, and go on without M
-        for (int i = 0; i < n; i++) {
-          if (!sc[i].outer_active) continue;
-          const double r_new = g->host_sc[i].out_rnorm;
-          if (inner_failed[i] || !std::isfinite(r_new) || !(r_new < rn[i]))
-            HIP_TRY(hipMemcpyAsync((char*)w.x64 + i * spinor_bytes(G, kFP64), (char*)w.x64b + i * spinor_bytes(G, kFP64),
-                                   spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
-        }
-        for (int i = 0; i < n; i++) g->host_sc[i].outer_active = sc[i].outer_active;
-        HIP_TRY(hipMemcpyAsync(w.sc, g->host_sc, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
-        residual64(g, kappa, w, nullptr, st);
-        launch_outer_residual_norm(n, w.sc, w.partials, drows64, p->s, st);
-        HIP_LAUNCHED();
-        if ((rc = read_scalars(g, w, st))) return rc;
-        pc_fallback = step;
-        pc.net = nullptr;
-      } else {
-        pc_steps++;
-      }
-    }
-    any = false;
-    for (int i = 0; i < n; i++) {
-      if (!sc[i].outer_active) continue;
-      outer[i]++;
-      rn[i] = g->host_sc[i].out_rnorm;
-      if (info && info[i].outer_history && outer[i] - 1 < info[i].outer_history_cap)
-        info[i].outer_history[outer[i] - 1] = rn[i] / bn[i];
-      if (!std::isfinite(rn[i])) result[i] = fail(QCD_ERR_NONFINITE, "non-finite outer residual");
-      if (result[i] < 0) {  // stop refining this right-hand side
-        g->host_sc[i].outer_active = 0;
-        HIP_TRY(hipMemcpyAsync(&w.sc[i].outer_active, &g->host_sc[i].outer_active, sizeof(int),
-                               hipMemcpyHostToDevice, st));
-      }
-      any |= g->host_sc[i].outer_active != 0;
-    }
-    step++;
+    for (IrRun* R : act)
+      if ((rc = ir_begin_step(*R, p, st))) return rc;
+    std::vector<InnerRun> ir;
+    for (IrRun* R : act) ir.push_back(InnerRun{R->g, p->inner_prec, R->kappa, &R->w, R->pc});
+    if ((rc = bicg_loop_multi(ir.data(), (int)ir.size(), p->inner, st))) return rc;
+    for (IrRun* R : act)
+      if ((rc = ir_end_step(*R, p, st))) return rc;
+    if ((rc = read_scalars_all(ir.data(), (int)ir.size(), st))) return rc;
+    for (IrRun* R : act)
+      if ((rc = ir_after_step(*R, p, step, st))) return rc;
   }
-  launch_unpack_spinor(G, kFP64, n, (double*)x_dev, w.x64, nullptr, 1.0, st);
+  for (int r = 0; r < nrun; r++)
+    launch_unpack_spinor(runs[r].g->g, kFP64, runs[r].n, (double*)runs[r].x_dev, runs[r].w.x64, nullptr, 1.0, st);
   HIP_LAUNCHED();
   HIP_TRY(hipStreamSynchronize(st));
   qcd_status res = QCD_OK;
-  for (int i = 0; i < n; i++) {
-    if (info) {
-      info[i].outer_iters = outer[i];
-      info[i].inner_iters = inner_total[i];
-      info[i].matvec_low = 2 * inner_total[i];
-      info[i].matvec_fp64 = outer[i];
-      info[i].true_rel_residual = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
-      info[i].inner_status = last_status[i];
-      info[i].seconds = now_s() - t0;
-      info[i].precond_steps = pc_steps;
-      info[i].precond_fallback = pc_fallback;
-      info[i].precond_scale = net ? pc.scale : 0.0;
-    }
-    res = worse(res, result[i]);
-  }
+  for (int r = 0; r < nrun; r++) res = worse(res, ir_finish(runs[r], t0));
   return res;
+}
+
+qcd_status check_ir_params(const qcd_ir_params* p) {
+  if (!p) return fail(QCD_ERR_ARG, "null parameters");
+  if (!(p->tol > 0) || p->max_outer <= 0 || !(p->s > 0)) return fail(QCD_ERR_ARG, "tol > 0, max_outer > 0, s > 0 required");
+  return check_bicg_params(&p->inner);
+}
+
+}  // namespace
+
+extern "C" {
+
+qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
+                              const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
+  const double t0 = now_s();
+  qcd_status rc = check_ir_params(p);
+  if (rc) return rc;
+  IrRun R;
+  R.g = g;
+  R.kappa = kappa;
+  R.n = nrhs;
+  R.x_dev = x_dev;
+  R.b_dev = b_dev;
+  R.info = info;
+  R.net = const_cast<qcd_ptc*>(p->precond);
+  if ((rc = check_ir_run(R, p))) return rc;
+  if ((rc = get_work(g, R.net ? 3 : 0, p->inner_prec, p->inner.max_iter, nrhs, ws, ws_bytes, &R.w))) return rc;
+  return solve_ir_runs(&R, 1, p, S(stream), t0);
+}
+
+qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const double* kappa, const int* nrhs,
+                                      void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
+                                      qcd_solve_info* const* info, void* stream) {
+  const double t0 = now_s();
+  qcd_status rc = check_ir_params(p);
+  if (rc) return rc;
+  if (nlat < 1 || nlat > 64 || !g || !kappa || !nrhs || !x_dev || !b_dev)
+    return fail(QCD_ERR_ARG, "nlat must be in 1..64 and the arrays non-null");
+  if (p->precond) return fail(QCD_ERR_UNSUPPORTED, "a network preconditioner serves one lattice; use qcd_solve_mixed_ir");
+  std::vector<IrRun> runs(nlat);
+  for (int r = 0; r < nlat; r++) {
+    for (int q = 0; q < r; q++)
+      if (g[q] == g[r]) return fail(QCD_ERR_ARG, "lattice %d repeats the gauge handle of lattice %d", r, q);
+    IrRun& R = runs[r];
+    R.g = g[r];
+    R.kappa = kappa[r];
+    R.n = nrhs[r];
+    R.x_dev = x_dev[r];
+    R.b_dev = b_dev[r];
+    R.info = info ? info[r] : nullptr;
+    if ((rc = check_ir_run(R, p))) return rc;
+    if ((rc = get_work(g[r], 0, p->inner_prec, p->inner.max_iter, nrhs[r], nullptr, 0, &R.w))) return rc;
+  }
+  return solve_ir_runs(runs.data(), nlat, p, S(stream), t0);
 }
 
 }  // extern "C"
