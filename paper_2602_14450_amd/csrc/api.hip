@@ -440,11 +440,11 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
   // defaults measured on MI355X at 32^3 x 64 with rotating buffers (the tuner
-  // may override them): z slabs per XCD; prefetch 1 hop at 4 waves per SIMD
-  // (FP16), 2 hops at 2 (FP32), 1 hop at 2 (FP64)
+  // may override them): z slabs per XCD; prefetch 2 hops at 2 waves per SIMD
+  // (FP16, FP32), 1 hop at 2 (FP64)
   g->tune[kFP64] = DslashTune{1, 0, 0, 0};
   g->tune[kFP32] = DslashTune{1, 1, 0, 0};
-  g->tune[kFP16] = DslashTune{1, 5, 0, 0};
+  g->tune[kFP16] = DslashTune{1, 1, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
@@ -509,8 +509,8 @@ qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int var
   if (!g || !valid_prec(prec)) return fail(QCD_ERR_ARG, "invalid handle or precision");
   if (sched < 0 || sched >= kDslashScheds || variant < 0 || variant >= kDslashVariants)
     return fail(QCD_ERR_ARG, "sched must be 0..%d and variant 0..%d", kDslashScheds - 1, kDslashVariants - 1);
-  if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4)
-    return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2 or 4");
+  if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4 && !(rhs_tile >= -4 && rhs_tile <= -2))
+    return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2, 4 (lanes) or -2, -3, -4 (per thread)");
   g->tune[prec] = DslashTune{sched, variant, rhs_tile, g->tune[prec].recon};
   return QCD_OK;
 }
@@ -589,13 +589,15 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
   (void)hipEventCreate(&e1);
   DslashTune best = g->tune[prec];
   float best_ms = 1e30f;
-  const int tiles[3] = {1, 2, 4};
-  for (int ti = 0; ti < 3; ti++) {
+  const int tiles[6] = {1, 2, 4, -2, -3, -4};
+  for (int ti = 0; ti < 6; ti++) {
     const int T = tiles[ti];
-    if (nrhs % T || (T > 1 && nrhs == 1)) continue;
+    const int A = T < 0 ? -T : T;
+    if (nrhs % A || (A > 1 && nrhs == 1)) continue;
     for (int sched = 0; sched < kDslashScheds; sched++)
       for (int var = 0; var < (T == 1 ? kDslashVariants : 1); var++) {
-        if (sched > 1 && make_sched(g->g, sched, T, nrhs).mode != sched) continue;  // not applicable
+        if (sched > 1 && make_sched(g->g, sched, T > 0 ? T : 1, T > 0 ? nrhs : nrhs / A).mode != sched)
+          continue;  // not applicable
         const DslashTune tu{sched, var, T, g->tune[prec].recon};
         for (int i = 0; i < 2; i++)
           launch_dslash(prec, g->g, tu, kOpD, kEpiNone, nrhs, buf[2 * (i % npair) + 1], buf[2 * (i % npair)],

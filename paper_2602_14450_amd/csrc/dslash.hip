@@ -22,6 +22,8 @@
 // One thread computes one output site; partial sums for the solver's dot
 // products are formed from the values in registers (epilogues), so that the
 // vectors they need are not read a second time.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -70,6 +72,85 @@ __device__ __forceinline__ void accumulate(cx<T> (&a)[4][3], const cx<T> (&u1)[3
         else { a[2][c] = a[2][c] + mul_i(u1[c]); a[3][c] = a[3][c] + mul_mi(u2[c]); }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP16 storage: the hop's arithmetic in native binary16 form.  The projection
+// onto half-spinors is one packed binary16 add per complex component (one
+// rounding, as the storage itself), and the SU(3) products use v_dot2_f32_f16:
+// two binary16 products, exact, summed into an FP32 accumulator.  The
+// reconstruction accumulates in FP32.  No spinor component is converted to
+// FP32 before the link product.
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v h2_of(__half2 x) { return __builtin_bit_cast(h2v, x); }
+__device__ __forceinline__ h2v h_conjv(h2v x) {  // (re, -im)
+  return __builtin_bit_cast(h2v, __builtin_bit_cast(uint32_t, x) ^ 0x80000000u);
+}
+__device__ __forceinline__ h2v h_swap(h2v x) { return h2v{x.y, x.x}; }     // (im, re)
+__device__ __forceinline__ h2v h_muli(h2v x) { return h2v{-x.y, x.x}; }    // i x
+__device__ __forceinline__ float hdot(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
+
+// conj(x y - z w) from binary16 entries: exact products, FP32 sums, one
+// round-to-nearest-even conversion back to binary16
+__device__ __forceinline__ h2v h_rebuild(h2v x, h2v y, h2v z, h2v w) {
+  const h2v zn = -z;
+  const float re = hdot(zn, h_conjv(w), hdot(x, h_conjv(y), 0.0f));
+  const float im = hdot(zn, h_swap(w), hdot(x, h_swap(y), 0.0f));
+  return h2v{(_Float16)re, (_Float16)(-im)};
+}
+// row 2 = conj(row0 x row1), as su3_third_row
+__device__ __forceinline__ void h_third_row(h2v (&u)[9]) {
+  u[6] = h_rebuild(u[1], u[5], u[2], u[4]);
+  u[7] = h_rebuild(u[2], u[3], u[0], u[5]);
+  u[8] = h_rebuild(u[0], u[4], u[1], u[3]);
+}
+
+// the projection of project<MU, MINUS> in binary16
+template <int MU, bool MINUS>
+__device__ __forceinline__ void project_h(const h2v (&f)[4][3], h2v (&h1)[3], h2v (&h2)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; c++) {
+    if constexpr (MU == 0) {
+      h1[c] = MINUS ? f[0][c] + h_muli(f[3][c]) : f[0][c] - h_muli(f[3][c]);
+      h2[c] = MINUS ? f[1][c] + h_muli(f[2][c]) : f[1][c] - h_muli(f[2][c]);
+    } else if constexpr (MU == 1) {
+      h1[c] = MINUS ? f[0][c] + f[3][c] : f[0][c] - f[3][c];
+      h2[c] = MINUS ? f[1][c] - f[2][c] : f[1][c] + f[2][c];
+    } else if constexpr (MU == 2) {
+      h1[c] = MINUS ? f[0][c] + h_muli(f[2][c]) : f[0][c] - h_muli(f[2][c]);
+      h2[c] = MINUS ? f[1][c] - h_muli(f[3][c]) : f[1][c] + h_muli(f[3][c]);
+    } else {
+      h1[c] = MINUS ? f[2][c] + f[2][c] : f[0][c] + f[0][c];
+      h2[c] = MINUS ? f[3][c] + f[3][c] : f[1][c] + f[1][c];
+    }
+  }
+}
+
+// The link in the form its products need: forward hops use (re, -im) and
+// (im, re) of U_ab (Re and Im of U h), backward hops U_ab and i U_ab (Re and
+// Im of U^dag h).
+template <bool BWD> struct HLink { h2v p[9], q[9]; };
+template <bool BWD> __device__ __forceinline__ void h_link_prep(const h2v (&u)[9], HLink<BWD>& L) {
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    if constexpr (!BWD) {
+      L.p[k] = h_conjv(u[k]);
+      L.q[k] = h_swap(u[k]);
+    } else {
+      L.p[k] = u[k];
+      L.q[k] = h_muli(u[k]);
+    }
+  }
+}
+// w = U h (forward) or U^dag h (backward) in FP32
+template <bool BWD>
+__device__ __forceinline__ void h_mult(const HLink<BWD>& L, const h2v (&h)[3], cx<float> (&w)[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    const int k0 = BWD ? r : 3 * r, dk = BWD ? 3 : 1;
+    w[r].re = hdot(L.p[k0 + 2 * dk], h[2], hdot(L.p[k0 + dk], h[1], hdot(L.p[k0], h[0], 0.0f)));
+    w[r].im = hdot(L.q[k0 + 2 * dk], h[2], hdot(L.q[k0 + dk], h[1], hdot(L.q[k0], h[0], 0.0f)));
   }
 }
 
@@ -164,6 +245,33 @@ __device__ __forceinline__ T hop_compute(const HopRaw<S, NE>& d, cx<T> (&a)[4][3
   constexpr bool BWD = HOP & 1;
   constexpr bool MINUS = BWD ? DAG : !DAG;
   constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F;
+  if constexpr (std::is_same<S, __half2>::value) {
+    h2v f[4][3], u[9], h1[3], h2[3];
+#pragma unroll
+    for (int j = 0; j < Lay<S>::G; j++)
+      if (gran_needed<MU, MINUS, S>(j)) {
+#pragma unroll
+        for (int cc = 0; cc < C; cc++) {
+          const int k = j * C + cc;
+          f[k / 3][k % 3] = h2_of(d.sp[j].s[cc]);
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < F / C; j++)
+#pragma unroll
+      for (int cc = 0; cc < C; cc++) u[j * C + cc] = h2_of(d.lk[j].s[cc]);
+#pragma unroll
+    for (int k = F; k < NE; k++) u[k] = h2_of(d.tail[k - F]);
+    if constexpr (NE == 6) h_third_row(u);
+    project_h<MU, MINUS>(f, h1, h2);
+    HLink<BWD> L;
+    h_link_prep<BWD>(u, L);
+    cx<float> w1[3], w2[3];
+    h_mult<BWD>(L, h1, w1);
+    h_mult<BWD>(L, h2, w2);
+    accumulate<MU, MINUS>(a, w1, w2);
+    return w1[0].re + w2[2].im;
+  }
   cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
 #pragma unroll
   for (int j = 0; j < Lay<S>::G; j++)
@@ -395,6 +503,282 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
   if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides per thread: the thread of a site applies the link
+// it loaded (and rebuilt) once to R right-hand sides, so the link conversion,
+// the row-2 rebuild and the neighbour addressing are paid once per site
+// rather than once per site and right-hand side (the FP16 operator is bound by
+// instruction issue, not bytes).
+
+template <typename S, int NE, int R> struct HopRawR {
+  typename Lay<S>::Gran sp[R][Lay<S>::G];
+  typename Lay<S>::Gran lk[LkLay<S, NE>::F / Lay<S>::C];
+  S tail[LkLay<S, NE>::TAIL > 0 ? LkLay<S, NE>::TAIL : 1];
+};
+
+template <int MU, bool BWD>
+__device__ __forceinline__ int hop_neighbour(const Geom& g, int h, const Coord& c) {
+  if constexpr (MU == 0) {
+    const int base = h - (c.x >> 1);
+    const int xn = BWD ? ((c.x == 0) ? g.L[0] - 1 : c.x - 1) : ((c.x + 1 == g.L[0]) ? 0 : c.x + 1);
+    return base + (xn >> 1);
+  } else if constexpr (MU == 1) {
+    return BWD ? ((c.y == 0) ? h + (g.L[1] - 1) * g.sy : h - g.sy) : ((c.y + 1 == g.L[1]) ? h - (g.L[1] - 1) * g.sy : h + g.sy);
+  } else if constexpr (MU == 2) {
+    return BWD ? ((c.z == 0) ? h + (g.L[2] - 1) * g.sz : h - g.sz) : ((c.z + 1 == g.L[2]) ? h - (g.L[2] - 1) * g.sz : h + g.sz);
+  } else {
+    return BWD ? ((c.t == 0) ? h + (g.L[3] - 1) * g.st : h - g.st) : ((c.t + 1 == g.L[3]) ? h - (g.L[3] - 1) * g.st : h + g.st);
+  }
+}
+
+template <int HOP, bool DAG, int NE, int R, typename S>
+__device__ __forceinline__ void hop_load_r(const Geom& g, const S* __restrict__ in, size_t vstride,
+                                           const S* __restrict__ U, int par, int h, const Coord& c,
+                                           HopRawR<S, NE, R>& d, int dep = 0) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr bool MINUS = BWD ? DAG : !DAG;
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F, TAIL = LkLay<S, NE>::TAIL;
+  using Gr = typename Lay<S>::Gran;
+  const int hn = hop_neighbour<MU, BWD>(g, h, c) + dep;
+  const int npar = par ^ 1;
+  const S* sb = in + sp_block(g, npar, hn) + (hn & 63) * C;
+#pragma unroll
+  for (int r = 0; r < R; r++)
+#pragma unroll
+    for (int j = 0; j < Lay<S>::G; j++)
+      if (gran_needed<MU, MINUS, S>(j)) d.sp[r][j] = *reinterpret_cast<const Gr*>(sb + r * vstride + j * 64 * C);
+  const int lp = BWD ? npar : par, lh = BWD ? hn : h + dep;
+  const S* lb = U + lk_block<NE>(g, MU, lp, lh);
+  const int lane = lh & 63;
+#pragma unroll
+  for (int j = 0; j < F / C; j++) d.lk[j] = *reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C);
+  if constexpr (NE == 9) {
+#pragma unroll
+    for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
+  } else if constexpr (TAIL == 2) {
+    const Pair<S> v = *reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2);
+    d.tail[0] = v.s[0];
+    d.tail[1] = v.s[1];
+  }
+}
+
+template <int HOP, bool DAG, int NE, int R, typename S, typename T>
+__device__ __forceinline__ void hop_compute_r(const HopRawR<S, NE, R>& d, cx<T> (&a)[R][4][3]) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr bool MINUS = BWD ? DAG : !DAG;
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F;
+  if constexpr (std::is_same<S, __half2>::value) {
+    h2v u[9];
+#pragma unroll
+    for (int j = 0; j < F / C; j++)
+#pragma unroll
+      for (int cc = 0; cc < C; cc++) u[j * C + cc] = h2_of(d.lk[j].s[cc]);
+#pragma unroll
+    for (int k = F; k < NE; k++) u[k] = h2_of(d.tail[k - F]);
+    if constexpr (NE == 6) h_third_row(u);
+    HLink<BWD> L;
+    h_link_prep<BWD>(u, L);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      h2v f[4][3], h1[3], h2[3];
+#pragma unroll
+      for (int j = 0; j < Lay<S>::G; j++)
+        if (gran_needed<MU, MINUS, S>(j)) {
+#pragma unroll
+          for (int cc = 0; cc < C; cc++) {
+            const int k = j * C + cc;
+            f[k / 3][k % 3] = h2_of(d.sp[r][j].s[cc]);
+          }
+        }
+      project_h<MU, MINUS>(f, h1, h2);
+      cx<float> w1[3], w2[3];
+      h_mult<BWD>(L, h1, w1);
+      h_mult<BWD>(L, h2, w2);
+      accumulate<MU, MINUS>(a[r], w1, w2);
+    }
+    return;
+  }
+  cx<T> u[9];
+#pragma unroll
+  for (int j = 0; j < F / C; j++)
+#pragma unroll
+    for (int cc = 0; cc < C; cc++) u[j * C + cc] = Traits<S>::load(&d.lk[j].s[cc]);
+#pragma unroll
+  for (int k = F; k < NE; k++) u[k] = Traits<S>::load(&d.tail[k - F]);
+  if constexpr (NE == 6) su3_third_row(u);
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    cx<T> f[4][3], h1[3], h2[3], w1[3], w2[3];
+#pragma unroll
+    for (int j = 0; j < Lay<S>::G; j++)
+      if (gran_needed<MU, MINUS, S>(j)) {
+#pragma unroll
+        for (int cc = 0; cc < C; cc++) {
+          const int k = j * C + cc;
+          f[k / 3][k % 3] = Traits<S>::load(&d.sp[r][j].s[cc]);
+        }
+      }
+    project<MU, MINUS>(f, h1, h2);
+    if constexpr (!BWD) {
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        w1[q] = u[3 * q] * h1[0] + u[3 * q + 1] * h1[1] + u[3 * q + 2] * h1[2];
+        w2[q] = u[3 * q] * h2[0] + u[3 * q + 1] * h2[1] + u[3 * q + 2] * h2[2];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        w1[q] = cmulc(u[q], h1[0]) + cmulc(u[3 + q], h1[1]) + cmulc(u[6 + q], h1[2]);
+        w2[q] = cmulc(u[q], h2[0]) + cmulc(u[3 + q], h2[1]) + cmulc(u[6 + q], h2[2]);
+      }
+    }
+    accumulate<MU, MINUS>(a[r], w1, w2);
+  }
+}
+
+template <int R, typename T> __device__ __forceinline__ void reg_barrier_r(cx<T> (&a)[R][4][3]) {
+#pragma unroll
+  for (int r = 0; r < R; r++) reg_barrier(a[r]);
+}
+
+// The eight hops one after the other; the loads of hop i+1 are issued after
+// hop i is computed (dependency through an empty asm statement).
+template <int I, bool DAG, int NE, int R, typename S, typename T>
+__device__ __forceinline__ void hop_seq_r(const Geom& g, const S* __restrict__ in, size_t vstride,
+                                          const S* __restrict__ U, int par, int h, const Coord& c,
+                                          cx<T> (&a)[R][4][3], int dep) {
+  if constexpr (I < 8) {
+    HopRawR<S, NE, R> d;
+    hop_load_r<I, DAG, NE, R>(g, in, vstride, U, par, h, c, d, dep);
+    hop_compute_r<I, DAG, NE, R>(d, a);
+    reg_barrier_r<R>(a);
+    int dep2 = 0;
+    asm volatile("" : "+v"(dep2) : "v"(a[0][0][0].re));
+    QCD_FENCE();
+    hop_seq_r<I + 1, DAG, NE, R>(g, in, vstride, U, par, h, c, a, dep2);
+  }
+}
+
+// Per-right-hand-side block reduction for R right-hand sides per thread:
+// value i of right-hand side r0 + r goes to partials[((r0 + r) * rstride + row) * NV + i].
+template <int NV, int R>
+__device__ __forceinline__ void block_reduce_store_R(double (&v)[R][NV], double* partials, int r0, int rstride,
+                                                     int row) {
+  __shared__ double red[R * NV][4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < R; r++)
+#pragma unroll
+    for (int i = 0; i < NV; i++) {
+      double a = v[r][i];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+      if (lane == 0) red[r * NV + i][wid] = a;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < R * NV) {
+    const int r = threadIdx.x / NV, i = threadIdx.x % NV;
+    const double s = ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) + red[threadIdx.x][3];
+    partials[((size_t)(r0 + r) * rstride + row) * NV + i] = s;
+  }
+}
+
+template <typename S, int OP, int EPI, int R, int NE>
+__global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched, S* __restrict__ out,
+                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
+                                                      const S* __restrict__ aux, double* __restrict__ partials,
+                                                      const Scalars* __restrict__ scal, int ftz) {
+  using T_ = typename Traits<S>::T;
+  const BlockPos bp = block_pos(sched);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int r0 = bp.tile * R;
+  bool live[R];
+  bool any = false;
+#pragma unroll
+  for (int r = 0; r < R; r++) {
+    live[r] = !scal || scal[r0 + r].active != 0;
+    any |= live[r];
+  }
+  if (!any) return;  // uniform over the block
+  const int par = wid & 1;
+  const int h = bp.h0 + (wid >> 1) * 64 + lane;
+  const size_t vs = spinor_elems(g);
+  const size_t vo = (size_t)r0 * vs;
+  constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
+  constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
+  constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
+  double red[R][NV];
+#pragma unroll
+  for (int r = 0; r < R; r++)
+#pragma unroll
+    for (int i = 0; i < NV; i++) red[r][i] = 0.0;
+  if (h < g.Vh) {
+    const Coord c = decode(g, par, h);
+    cx<T_> a[R][4][3];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+      for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) a[r][sp][cc] = cx<T_>(0, 0);
+    hop_seq_r<0, DAG, NE, R>(g, in + vo, vs, U, par, h, c, a, 0);
+    const T_ k = (T_)kappa;
+    using Gr = typename Lay<S>::Gran;
+    constexpr int C = Lay<S>::C;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (!live[r]) continue;
+      const S* inr = in + vo + r * vs;
+      const S* axr = aux ? aux + vo + r * vs : nullptr;
+      cx<T_> o[12], ctr[12], ax[12];
+      if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(inr, g, par, h, ctr);
+      if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(axr, g, par, h, ax);
+#pragma unroll
+      for (int i = 0; i < 12; i++) {
+        if constexpr (OP == kOpH || OP == kOpHdag) {
+          o[i] = a[r][i / 3][i % 3];
+        } else {
+          o[i] = ctr[i] - k * a[r][i / 3][i % 3];
+          if constexpr (EPI == kEpiResid) o[i] = ax[i] - o[i];
+        }
+      }
+      S* ob = out + vo + r * vs + sp_block(g, par, h) + (h & 63) * C;
+      T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+#pragma unroll
+      for (int j = 0; j < Lay<S>::G; j++) {
+        Gr v;
+#pragma unroll
+        for (int cc = 0; cc < C; cc++) {
+          const int i = j * C + cc;
+          v.s[cc] = Traits<S>::pack(o[i], ftz);
+          if constexpr (EPI != kEpiNone) {
+            const cx<T_> os = Traits<S>::load(&v.s[cc]);
+            if constexpr (EPI == kEpiDotAux) {
+              acc0 += ax[i].re * os.re + ax[i].im * os.im;
+              acc1 += ax[i].re * os.im - ax[i].im * os.re;
+            } else if constexpr (TS) {
+              const cx<T_> sv = (EPI == kEpiTSAux) ? ax[i] : ctr[i];
+              acc0 += os.re * sv.re + os.im * sv.im;
+              acc1 += os.re * sv.im - os.im * sv.re;
+              acc2 += norm2(os);
+              acc3 += norm2(sv);
+            } else {
+              acc0 += norm2(os);
+            }
+          }
+        }
+        *reinterpret_cast<Gr*>(ob + j * 64 * C) = v;
+      }
+      if constexpr (EPI == kEpiDotAux) { red[r][0] = acc0; red[r][1] = acc1; }
+      if constexpr (TS) { red[r][0] = acc0; red[r][1] = acc1; red[r][2] = acc2; red[r][3] = acc3; }
+      if constexpr (EPI == kEpiResid) { red[r][0] = acc0; }
+    }
+  }
+  if constexpr (EPI != kEpiNone) block_reduce_store_R<NV, R>(red, partials, r0, sched.nsb, bp.sb);
+}
+
 // One translation unit per storage precision (QCD_DSLASH_PREC = 0, 1, 2 for
 // FP64, FP32, FP16) keeps the kernel instantiations of a build parallel; the
 // FP16 unit also holds the precision-independent helpers and the dispatcher.
@@ -452,10 +836,46 @@ static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, in
   }
 }
 
+template <typename S, int R, int NE>
+static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
+                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                             int ftz, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched, 1, n / R);
+  dim3 grid(sc.nsb * sc.ntiles), block(256);
+  S* o = (S*)out;
+  const S* i = (const S*)in;
+  const S* u = (const S*)U;
+  const S* x = (const S*)aux;
+#define QCD_LAUNCH(OPV, EPIV)                                                                                   \
+  hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
+                     scal, ftz)
+  if (epi == kEpiNone) {
+    switch (op) {
+      case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
+      case kOpH: QCD_LAUNCH(kOpH, kEpiNone); break;
+      case kOpDdag: QCD_LAUNCH(kOpDdag, kEpiNone); break;
+      default: QCD_LAUNCH(kOpHdag, kEpiNone); break;
+    }
+  } else if (epi == kEpiDotAux) {
+    QCD_LAUNCH(kOpD, kEpiDotAux);
+  } else if (epi == kEpiTS) {
+    QCD_LAUNCH(kOpD, kEpiTS);
+  } else if (epi == kEpiTSAux) {
+    QCD_LAUNCH(kOpD, kEpiTSAux);
+  } else {
+    QCD_LAUNCH(kOpD, kEpiResid);
+  }
+#undef QCD_LAUNCH
+}
+
 template <typename S, int NE>
 static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                             int ftz, hipStream_t st) {
+  const int R = reg_tile_for(tune, n);
+  if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
   const int T = rhs_tile_for(tune, n);
   if (T == 4)
     launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
@@ -501,6 +921,11 @@ int rhs_tile_for(const DslashTune& tune, int n) {
   if (T != 1 && T != 2 && T != 4) T = 1;
   if (n % T) T = 1;
   return T;
+}
+
+int reg_tile_for(const DslashTune& tune, int n) {
+  const int R = -tune.rhs_tile;
+  return (R >= 2 && R <= 4 && n % R == 0) ? R : 1;
 }
 
 DslashSched make_sched(const Geom& g, int mode, int T, int n) {

@@ -64,7 +64,8 @@ struct DslashTune {
   int sched;    // 0: blocks in half-index order; m = 1..3: XCD z slabs (each swept as 2^(m-1) sub-slabs);
                 // 4: XCD t slabs swept in z order
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
-  int rhs_tile; // right-hand sides sharing a wave's link loads: 0 = automatic, or 1, 2, 4
+  int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
+                // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers)
   int recon;    // links stored as 6 entries (rows 0, 1; row 2 rebuilt) instead of 9: a property of the data
 };
 constexpr int kDslashVariants = 6;
@@ -74,6 +75,8 @@ struct DslashSched {
 constexpr int kDslashScheds = 5;
 DslashSched make_sched(const Geom& g, int mode, int T, int n);
 int rhs_tile_for(const DslashTune& tune, int n);
+// right-hand sides per thread (rhs_tile = -R, R = 2..4, n divisible by R), else 1
+int reg_tile_for(const DslashTune& tune, int n);
 
 // Every launcher takes n, the number of right-hand sides: vector arguments
 // hold n native spinors back to back (stride spinor_elems), sc points to

@@ -45,7 +45,7 @@ def test_multi_rhs_dslash(q, dims, nrhs, prec):
 
 
 @pytest.mark.parametrize("dims", [(8, 16, 32, 4), (8, 32, 8, 16)])
-@pytest.mark.parametrize("rhs_tile", [1, 2, 4])
+@pytest.mark.parametrize("rhs_tile", [1, 2, 4, -2, -4])
 def test_rhs_tile_choices_agree_bitwise(q, rhs_tile, dims):
     # every launch shape (schedule incl. the sub-slab and t-slab orders,
     # right-hand-side tile) gives bit-identical output
@@ -61,8 +61,21 @@ def test_rhs_tile_choices_agree_bitwise(q, rhs_tile, dims):
         g.set_tuning(q.FP16, sched, 0, rhs_tile)
         q.dslash(g, 0.124, out, x, prec=q.FP16)
         torch.cuda.synchronize()
-        assert torch.equal(out, ref), (sched, rhs_tile)
+        if rhs_tile > 0:
+            assert torch.equal(out, ref), (sched, rhs_tile)
+        else:
+            same_to_one_fp16_ulp(out, ref)
     g.close()
+
+
+def same_to_one_fp16_ulp(out, ref):
+    # A thread holding several right-hand sides evaluates the same expressions,
+    # but the compiler may fuse a multiply-add differently: the FP32 sum can then
+    # round to the neighbouring binary16 value (seen at 2 of 1.6e6 outputs).
+    d = (out - ref).abs()
+    ulp = ref.abs() * 2.0 ** -10 + 2.0 ** -24
+    assert bool((d <= ulp).all())
+    assert int((d > 0).sum()) <= max(4, out.numel() // 10000)
 
 
 @pytest.fixture(scope="module")
@@ -224,4 +237,48 @@ def test_batched_lattices_reject_repeated_handle(q):
     b = to_dev(qi.gaussian_source(dims, 511))
     with pytest.raises(q.QcdError):
         q.solve_mixed_ir_batched([g, g], [0.12, 0.12], [torch.zeros_like(b), torch.zeros_like(b)], [b, b])
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("op", [0, 1, 2, 3])
+def test_register_tile_of_three_matches_single(q, prec, op):
+    # 6 right-hand sides as two tiles of 3 per thread: bit-identical to one per thread
+    dims = (4, 6, 8, 10)
+    U = qi.gauge_field(dims, 0.3, 81)
+    psi = qi.gaussian_source(dims, 82, nrhs=6)
+    g = q.gauge_upload(to_dev(U), dims)
+    x = to_dev(psi)
+    ref, out = torch.empty_like(x), torch.empty_like(x)
+    g.set_tuning(prec, 1, 0, 1)
+    q.dslash(g, 0.124, ref, x, op=op, prec=prec)
+    g.set_tuning(prec, 1, 0, -3)
+    q.dslash(g, 0.124, out, x, op=op, prec=prec)
+    torch.cuda.synchronize()
+    if prec == 2:
+        same_to_one_fp16_ulp(out, ref)
+    else:
+        assert torch.equal(out, ref)
+    compare(to_host(out)[5], oracle.dslash(U, psi[5], 0.124, dims, op), TOL[prec], "tile 3")
+    g.close()
+
+
+def test_register_tiles_in_the_batched_solver(q):
+    # the epilogues (reductions per right-hand side) and the stopped-RHS masks
+    # of the register-tiled operator inside a batched FP16 refinement
+    dims = (8, 8, 8, 8)
+    U = qi.gauge_field(dims, 0.3, 91)
+    bs = qi.gaussian_source(dims, 92, nrhs=6)
+    bs[2] *= 1e-4
+    g = q.gauge_upload(to_dev(U), dims)
+    b = to_dev(bs)
+    xs = []
+    for tile in (1, -2, -3):
+        g.set_tuning(q.FP16, 1, 0, tile)
+        x = torch.zeros_like(b)
+        infos = q.solve_mixed_ir(g, 0.12, x, b, inner_prec=q.FP16, tol=1e-12)
+        assert all(i.true_rel_residual <= 1e-12 for i in infos)
+        xs.append(x)
+    for x in xs[1:]:
+        assert float((x - xs[0]).norm() / xs[0].norm()) < 1e-10
     g.close()
