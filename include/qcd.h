@@ -58,7 +58,9 @@ typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2 } qcd_prec;
 enum { QCD_LINKS_FULL = 1 << 8 };
 typedef enum { QCD_LAYOUT_CANONICAL = 0, QCD_LAYOUT_NATIVE = 1 } qcd_layout;
 /* D = 1 - kappa H (eq. (1)); H is the hopping sum; D^dag = gamma_5 D gamma_5. */
-typedef enum { QCD_OP_D = 0, QCD_OP_H = 1, QCD_OP_DDAG = 2, QCD_OP_HDAG = 3 } qcd_op;
+/* QCD_OP_SCHUR: the even-odd matrix of eq. (5), out_e = in_e - kappa^2 H_eo H_oe in_e on even sites,
+ * out_o = 0 (in_o is not read). */
+typedef enum { QCD_OP_D = 0, QCD_OP_H = 1, QCD_OP_DDAG = 2, QCD_OP_HDAG = 3, QCD_OP_SCHUR = 4 } qcd_op;
 
 typedef struct qcd_gauge qcd_gauge; /* opaque handle */
 typedef struct qcd_ptc qcd_ptc;     /* opaque handle of the learned preconditioner (declared below) */
@@ -76,6 +78,13 @@ typedef struct {
                           (first poll after 4, then after the number the convergence rate predicts) */
   int use_graph;       /* 1: one iteration is captured in a hip graph (on a stream the handle owns) and
                           replayed; results are identical to plain launches */
+  int even_odd;        /* 1: solve the even-odd preconditioned system of eq. (4)-(6) (the paper's form):
+                          (1 - kappa^2 H_eo H_oe) x_e = b_e + kappa H_eo b_o on even sites, then
+                          x_o = b_o + kappa H_oe x_e; vectors of the iteration are half-size.  In
+                          qcd_solve_mixed_ir (through its inner parameters) the refinement runs on the
+                          even system too, with its stop test taken relative to the full |b|; the
+                          reported residual is always the full |b - D x| / |b|.  tol in qcd_bicgstab
+                          is relative to |b_e + kappa H_eo b_o|. */
 } qcd_bicgstab_params;
 
 /* Parameters of the rescaled iterative refinement (Alg. 3; Alg. 2 is s = 1, recalc_shat = 0). */
@@ -167,7 +176,7 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 
 /* Workspace bytes that qcd_solve_mixed_ir (what = 0; what = 3 with a network
  * preconditioner), qcd_bicgstab (what = 1) or qcd_dslash with canonical
- * layout (what = 2) need for inner precision
+ * layout (what = 2) need, what = 0 or 1 plus 8 for the even-odd form, for inner precision
  * prec, max_iter history entries and nrhs right-hand sides.  Passing ws =
  * NULL to those calls makes the handle's own cached workspace be used
  * (allocated on first use; a handle is not safe for concurrent calls). */

@@ -29,7 +29,7 @@ FP64, FP32, FP16 = 0, 1, 2
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
 CANONICAL, NATIVE = 0, 1
 LINKS_FULL = 1 << 8
-OP_D, OP_H, OP_DDAG, OP_HDAG = 0, 1, 2, 3
+OP_D, OP_H, OP_DDAG, OP_HDAG, OP_SCHUR = 0, 1, 2, 3, 4
 STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_hip", -3: "err_nonfinite", -4: "err_workspace",
           -5: "err_unsupported", -6: "err_breakdown"}
 
@@ -37,7 +37,8 @@ STATUS = {0: "ok", 1: "not_converged", -1: "err_arg", -2: "err_hip", -3: "err_no
 class BicgstabParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("sigma", ctypes.c_double),
                 ("sigma_lambda", ctypes.c_double), ("recalc_gamma", ctypes.c_int), ("omega0", ctypes.c_double),
-                ("ftz", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int)]
+                ("ftz", ctypes.c_int), ("check_every", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("even_odd", ctypes.c_int)]
 
 
 class IRParams(ctypes.Structure):
@@ -256,10 +257,11 @@ class Info:
     precond_scale: float = 0.0
 
 
-def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph=False):
+def _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph=False,
+                 even_odd=False):
     return BicgstabParams(float(tol), int(max_iter), float(sigma or 0.0), float(sigma_lambda or 0.0),
                           int(bool(recalc_gamma)), float(omega0), int(bool(ftz)), int(check_every),
-                          int(bool(use_graph)))
+                          int(bool(use_graph)), int(bool(even_odd)))
 
 
 def _make_infos(n, hist_cap, outer_cap):
@@ -291,11 +293,12 @@ def _infos_out(code, infos, keep):
 
 def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1e-12, max_iter=10000, sigma=0.0,
              sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None,
-             history=True, raise_on_error=True, use_graph=False):
+             history=True, raise_on_error=True, use_graph=False, even_odd=False):
     """Rescaled BiCGStab (Alg. 4 / 5) on canonical complex128 device vectors
-    (one or several right-hand sides); returns an Info or a list of them."""
+    (one or several right-hand sides); returns an Info or a list of them.
+    even_odd: solve the even-odd system of eq. (4)-(6)."""
     n = g.nrhs_of(b)
-    p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph)
+    p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph, even_odd)
     infos, keep = _make_infos(n, max_iter if history else 0, 1)
     ws = _ptr(workspace) if workspace is not None else None
     wsb = workspace.numel() if workspace is not None else 0
@@ -309,14 +312,14 @@ def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1
 def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12, max_outer=100,
                    s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                    recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, workspace=None, history=False,
-                   raise_on_error=True, use_graph=False, precond=None, precond_scale=0.0):
+                   raise_on_error=True, use_graph=False, precond=None, precond_scale=0.0, even_odd=False):
     """FP64 iterative refinement (Alg. 3 / 2) around the rescaled BiCGStab,
     for one or several right-hand sides; returns an Info or a list of them.
     precond: a PTC network used as right preconditioner of the FP16 inner
     solve (flexible refinement with fallback to the plain step)."""
     n = g.nrhs_of(b)
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
-                         use_graph)
+                         use_graph, even_odd)
     p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner,
                  precond.handle if precond is not None else None, float(precond_scale))
     infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
@@ -416,7 +419,7 @@ class PTC:
 def solve_mixed_ir_batched(gauges, kappas, xs, bs, inner_prec=FP16, tol=1e-12, max_outer=100, s=128.0,
                            recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                            recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, history=False,
-                           raise_on_error=True, use_graph=False):
+                           raise_on_error=True, use_graph=False, even_odd=False):
     """Several lattices (distinct Gauge handles, any extents) solved together:
     one refinement whose inner solves run concurrently.  xs[i], bs[i] hold one
     or several canonical fields of lattice i.  Returns a list (per lattice) of
@@ -424,7 +427,7 @@ def solve_mixed_ir_batched(gauges, kappas, xs, bs, inner_prec=FP16, tol=1e-12, m
     nl = len(gauges)
     ns = [g.nrhs_of(b) for g, b in zip(gauges, bs)]
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
-                         use_graph)
+                         use_graph, even_odd)
     p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner, None, 0.0)
     made = [_make_infos(n, inner_max_iter * 4 if history else 0, max_outer) for n in ns]
     gh = (ctypes.c_void_p * nl)(*[g.handle.value for g in gauges])

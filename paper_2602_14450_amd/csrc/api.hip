@@ -86,6 +86,12 @@ struct Work {
   void* t = nullptr;
   void* z = nullptr;        // M p and M s of the preconditioned iteration
   double2* x64b = nullptr;  // x before a preconditioned refinement step
+  // even-odd solve (eq. (4)-(6)): inner vectors, r64, x64 (= x_e) are even-parity
+  // fields; t1 / t64 hold H_oe of a vector (odd parity); b64 and xf64 are full fields
+  bool eo = false;
+  void* t1 = nullptr;
+  double2 *eta_e = nullptr, *eta_o = nullptr, *bp64 = nullptr, *t64 = nullptr, *x64o = nullptr, *xf64 = nullptr,
+          *rf64 = nullptr;
   double* partials = nullptr;
   Scalars* sc = nullptr;
   double* history = nullptr;
@@ -95,13 +101,39 @@ struct Work {
   size_t bytes = 0;
 };
 
-// what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout, 3 preconditioned refinement
-Work carve(const qcd_gauge* G, int what, int prec, int max_iter, int n, char* base) {
+// what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout, 3 preconditioned refinement;
+// | kWhatEO: the even-odd form of 0 or 1
+constexpr int kWhatEO = 8;
+Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char* base) {
   const Geom& g = G->g;
+  const bool eo = (what_in & kWhatEO) != 0;
+  const int what = what_in & 7;
   Carve c{base};
   Work w;
   w.n = n;
-  if (what == 0 || what == 1 || what == 3) {
+  if (eo && (what == 0 || what == 1)) {
+    const Geom gh = half_geom(g);
+    w.eo = true;
+    w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.xf64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.rf64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
+    w.eta_e = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.eta_o = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.bp64 = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.t64 = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.x64 = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.x64o = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.r64 = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+    w.x = c.take(n * spinor_bytes(gh, prec));
+    w.r = c.take(n * spinor_bytes(gh, prec));
+    w.rstar = c.take(n * spinor_bytes(gh, prec));
+    w.p = c.take(n * spinor_bytes(gh, prec));
+    w.v = c.take(n * spinor_bytes(gh, prec));
+    w.t = c.take(n * spinor_bytes(gh, prec));
+    w.t1 = c.take(n * spinor_bytes(gh, prec));
+    w.hist_stride = max_iter > 0 ? max_iter : 1;
+    w.history = (double*)c.take(sizeof(double) * (size_t)w.hist_stride * n);
+  } else if (what == 0 || what == 1 || what == 3) {
     w.x64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.r64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
@@ -216,6 +248,22 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
   const DslashTune& tu = g->tune[prec];
   const int drows = dslash_partial_rows(G, tu, n), frows = flat_rows(G, prec);
   const void* U = g->U[prec];
+  if (w.eo) {  // A = 1 - kappa^2 H_eo H_oe on even-parity fields, two launches per product
+    const Geom gh = half_geom(G);
+    const int erows = dslash_partial_rows(G, tu, n, true);
+    const double k2 = kappa * kappa;
+    launch_p_update(gh, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
+    launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.p, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
+    launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.t1, U, k2, w.rstar, w.partials, w.sc, ftz, st, w.p, 0);
+    launch_alpha(n, w.sc, w.partials, erows, st);
+    launch_s_update(gh, prec, n, w.sc, w.r, w.v, ftz, st);
+    launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.r, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
+    launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.t1, U, k2, nullptr, w.partials, w.sc, ftz, st, w.r, 0);
+    launch_omega(n, w.sc, w.partials, erows, st);
+    launch_xr_update(gh, prec, n, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
+    launch_iter_end(n, w.sc, w.partials, flat_rows(gh, prec), w.history, w.hist_stride, st);
+    return;
+  }
   launch_p_update(G, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
   if (pc.net) {
     ptc_apply_half(pc.net, n, w.p, w.z, pc.scale, ftz, w.sc, st);
@@ -239,8 +287,43 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
 // FP64 residual r = b - D x with |r|^2 partials for all right-hand sides
 // (only those still refining are computed).
 void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* outer_mask, hipStream_t st) {
+  if (w.eo) {  // r = b' - (x_e - kappa^2 H_eo H_oe x_e)
+    launch_dslash(kFP64, g->g, g->tune[kFP64], kOpH, kEpiNone, w.n, w.t64, w.x64, g->U[kFP64], 1.0, nullptr, nullptr,
+                  outer_mask, 0, st, nullptr, 1);
+    launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.r64, w.t64, g->U[kFP64], kappa * kappa,
+                  w.bp64, w.partials, outer_mask, 0, st, w.x64, 0);
+    return;
+  }
   launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.r64, w.x64, g->U[kFP64], kappa, w.b64,
                 w.partials, outer_mask, 0, st);
+}
+int residual_rows(const qcd_gauge* g, const Work& w) {
+  return dslash_partial_rows(g->g, g->tune[kFP64], w.n, w.eo);
+}
+
+// Even-odd set-up from the full FP64 source in b64: eta_e, eta_o and the
+// right-hand side b' = eta_e + kappa H_eo eta_o of eq. (4)-(6) (D_ee = D_oo = 1,
+// D_eo = -kappa H_eo).
+void eo_setup(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
+  const size_t half = spinor_bytes(half_geom(g->g), kFP64), full = spinor_bytes(g->g, kFP64);
+  (void)hipMemcpy2DAsync(w.eta_e, half, w.b64, full, half, w.n, hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpy2DAsync(w.eta_o, half, (const char*)w.b64 + half, full, half, w.n, hipMemcpyDeviceToDevice, st);
+  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiNone, w.n, w.bp64, w.eta_o, g->U[kFP64], -kappa, nullptr,
+                nullptr, nullptr, 0, st, w.eta_e, 0);
+}
+// x_o = eta_o + kappa H_oe x_e, and the full solution [x_e | x_o] in xf64.
+void eo_reconstruct(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
+  const size_t half = spinor_bytes(half_geom(g->g), kFP64), full = spinor_bytes(g->g, kFP64);
+  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiNone, w.n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr,
+                nullptr, nullptr, 0, st, w.eta_o, 1);
+  (void)hipMemcpy2DAsync(w.xf64, full, w.x64, half, half, w.n, hipMemcpyDeviceToDevice, st);
+  (void)hipMemcpy2DAsync((char*)w.xf64 + half, full, w.x64o, half, half, w.n, hipMemcpyDeviceToDevice, st);
+}
+// |b - D x|^2 partials per right-hand side for the full solution xf64, with
+// the full operator (residual written to rf64).
+void eo_full_residual(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
+  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.rf64, w.xf64, g->U[kFP64], kappa, w.b64,
+                w.partials, nullptr, 0, st);
 }
 
 // Capture one iteration (8 kernels) into a hip graph.  Capture runs on the
@@ -256,8 +339,10 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
   memcpy(&sbits, &pc.scale, sizeof sbits);
   const unsigned long long key[8] = {(unsigned long long)prec, (unsigned long long)w.n, (unsigned long long)w.x,
                                      kbits, (unsigned long long)ftz,
-                                     (unsigned long long)(g->tune[prec].sched * 64 + g->tune[prec].variant * 8 +
-                                                          g->tune[prec].rhs_tile),
+                                     ((unsigned long long)(unsigned)g->tune[prec].sched << 16) |
+                                         ((unsigned long long)(unsigned)g->tune[prec].variant << 8) |
+                                         ((unsigned long long)(g->tune[prec].rhs_tile & 0xff)) |
+                                         ((unsigned long long)w.eo << 24),
                                      (unsigned long long)(uintptr_t)pc.net, pc.net ? sbits : 0ull};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
@@ -640,7 +725,8 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec) {
 }
 
 size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs) {
-  if (!g || !valid_prec(prec) || what < 0 || what > 3 || nrhs < 1 || nrhs > kMaxRhs) return 0;
+  if (!g || !valid_prec(prec) || (what & ~(7 | kWhatEO)) || (what & 7) > 3 || nrhs < 1 || nrhs > kMaxRhs) return 0;
+  if ((what & kWhatEO) && (what & 7) > 1) return 0;
   return carve(g, what, prec, max_iter, nrhs, nullptr).bytes;
 }
 
@@ -680,9 +766,37 @@ qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec
   if (rc) return rc;
   if ((rc = check_nrhs(nrhs))) return rc;
   if (!out_dev || !in_dev || out_dev == in_dev) return fail(QCD_ERR_ARG, "out and in must be distinct non-null buffers");
-  if (op < QCD_OP_D || op > QCD_OP_HDAG) return fail(QCD_ERR_ARG, "invalid op %d", (int)op);
+  if (op < QCD_OP_D || op > QCD_OP_SCHUR) return fail(QCD_ERR_ARG, "invalid op %d", (int)op);
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   hipStream_t st = S(stream);
+  if (op == QCD_OP_SCHUR) {
+    // out_e = in_e - kappa^2 H_eo H_oe in_e, out_o = 0; the odd half of out holds H_oe in_e meanwhile
+    const void* src = in_dev;
+    void* dst = out_dev;
+    Work w;
+    if (layout == QCD_LAYOUT_CANONICAL) {
+      if ((rc = get_work(g, 2, prec, 0, nrhs, nullptr, 0, &w))) return rc;
+      launch_pack_spinor(g->g, prec, nrhs, w.x, (const double*)in_dev, 1.0, 0, nullptr, st);
+      src = w.x;
+      dst = w.r;
+    } else if (layout != QCD_LAYOUT_NATIVE) {
+      return fail(QCD_ERR_ARG, "invalid layout");
+    }
+    const Geom gh = half_geom(g->g);
+    const size_t full = spinor_bytes(g->g, prec), half = spinor_bytes(gh, prec);
+    for (int r = 0; r < nrhs; r++) {
+      const char* xe = (const char*)src + r * full;
+      char* ye = (char*)dst + r * full;
+      launch_dslash(prec, g->g, g->tune[prec], kOpH, kEpiNone, 1, ye + half, xe, g->U[prec], 1.0, nullptr, nullptr,
+                    nullptr, 0, st, nullptr, 1);
+      launch_dslash(prec, g->g, g->tune[prec], kOpD, kEpiNone, 1, ye, ye + half, g->U[prec], kappa * kappa, nullptr,
+                    nullptr, nullptr, 0, st, xe, 0);
+      launch_zero(gh, prec, 1, ye + half, st);
+    }
+    if (layout == QCD_LAYOUT_CANONICAL) launch_unpack_spinor(g->g, prec, nrhs, (double*)out_dev, w.r, nullptr, 1.0, st);
+    HIP_LAUNCHED();
+    return QCD_OK;
+  }
   if (layout == QCD_LAYOUT_NATIVE) {
     launch_dslash(prec, g->g, g->tune[prec], op, kEpiNone, nrhs, out_dev, in_dev, g->U[prec], kappa, nullptr, nullptr,
                   nullptr, 0, st);
@@ -736,6 +850,68 @@ static qcd_status worse(qcd_status a, qcd_status b) {
   return a > b ? a : b;
 }
 
+}  // extern "C"
+
+namespace {
+// Even-odd BiCGStab (eq. (4)-(6)): b' = eta_e + kappa H_eo eta_o in FP64,
+// Alg. 4 / 5 on A = 1 - kappa^2 H_eo H_oe in precision prec, then
+// x_o = eta_o + kappa H_oe x_e in FP64; the reported residual is the full
+// |b - D x| / |b|.
+qcd_status bicgstab_eo(const qcd_gauge* g, double kappa, int prec, int n, void* x_dev, const void* b_dev,
+                       const qcd_bicgstab_params& p, qcd_solve_info* info, const Work& w, hipStream_t st, double t0) {
+  const Geom& G = g->g;
+  const Geom gh = half_geom(G);
+  qcd_status rc;
+  Scalars hs[kMaxRhs];
+  for (int i = 0; i < n; i++) init_params(&hs[i], p);
+  HIP_TRY(hipMemcpyAsync(w.sc, hs, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
+  double b2[kMaxRhs], r2[kMaxRhs];
+  launch_pack_spinor(G, kFP64, n, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
+  if ((rc = read_sum(w, site_grid(G), 1, b2, st))) return rc;
+  eo_setup(g, kappa, w, st);
+  // r = r* = low(b'), x0 = 0
+  launch_narrow(gh, prec, n, w.r, (const double*)w.bp64, w.partials, p.ftz, st);
+  HIP_TRY(hipMemcpyAsync(w.rstar, w.r, n * spinor_bytes(gh, prec), hipMemcpyDeviceToDevice, st));
+  launch_bicg_init(n, w.sc, w.partials, site_grid(gh), st);
+  HIP_LAUNCHED();
+  if ((rc = bicg_loop(g, prec, kappa, w, p, Precond{}, st))) return rc;
+  Scalars sc[kMaxRhs];
+  memcpy(sc, g->host_sc, sizeof(Scalars) * n);
+  double scales[kMaxRhs];
+  for (int i = 0; i < n; i++) {
+    scales[i] = sc[i].iter > 0 ? sc[i].xscale / sc[i].lambda_cum : 0.0;
+    if (sc[i].iter == 0) launch_zero(gh, prec, 1, (char*)w.x + i * spinor_bytes(gh, prec), st);
+  }
+  HIP_TRY(hipMemcpyAsync(w.scale, scales, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  launch_widen(gh, prec, n, (double*)w.x64, w.x, w.scale, st);
+  eo_reconstruct(g, kappa, w, st);
+  launch_unpack_spinor(G, kFP64, n, (double*)x_dev, w.xf64, nullptr, 1.0, st);
+  eo_full_residual(g, kappa, w, st);
+  HIP_LAUNCHED();
+  if ((rc = read_sum(w, dslash_partial_rows(G, g->tune[kFP64], n), 1, r2, st))) return rc;
+  qcd_status result = QCD_OK;
+  for (int i = 0; i < n; i++) {
+    if (info) {
+      qcd_solve_info* in = info + i;
+      in->outer_iters = 0;
+      in->inner_iters = sc[i].iter;
+      in->matvec_low = 2 * sc[i].iter;
+      in->matvec_fp64 = 1;
+      in->true_rel_residual = b2[i] > 0 ? sqrt(r2[i] / b2[i]) : 0.0;
+      in->inner_status = sc[i].status;
+      in->first_shat_over_s = 1.0;
+      in->history_len = 0;
+      copy_history(in, w, i, sc[i].iter, sc[i].bnorm2, st);
+      in->seconds = now_s() - t0;
+    }
+    result = worse(result, status_of(sc[i].status, sc[i].iter));
+  }
+  return result;
+}
+}  // namespace
+
+extern "C" {
+
 qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrhs, void* x_dev, const void* b_dev,
                         const qcd_bicgstab_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream) {
   const double t0 = now_s();
@@ -747,7 +923,9 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
   if ((rc = check_bicg_params(p))) return rc;
   hipStream_t st = S(stream);
   Work w;
-  if ((rc = get_work(g, 1, prec, p->max_iter, nrhs, ws, ws_bytes, &w))) return rc;
+  const bool eo = p->even_odd != 0;
+  if ((rc = get_work(g, eo ? (1 | kWhatEO) : 1, prec, p->max_iter, nrhs, ws, ws_bytes, &w))) return rc;
+  if (eo) return bicgstab_eo(g, kappa, prec, nrhs, x_dev, b_dev, *p, info, w, st, t0);
   const Geom& G = g->g;
   const int n = nrhs;
   const int rows = site_grid(G);
@@ -821,6 +999,7 @@ struct IrRun {
   Scalars sc[kMaxRhs];  // snapshot after an inner solve
   bool any = false;
   int pc_steps = 0, pc_fallback = -1;
+  double bfull[kMaxRhs];  // |b| of the full system (even-odd: the stop test is scaled to it)
 };
 
 qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
@@ -829,6 +1008,7 @@ qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
   if ((rc = check_nrhs(R.n))) return rc;
   if (!R.x_dev || !R.b_dev) return fail(QCD_ERR_ARG, "null vector");
   if (!(R.kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
+  if (R.net && p->inner.even_odd) return fail(QCD_ERR_UNSUPPORTED, "the network preconditions the full operator only");
   if (R.net) {
     if (p->inner_prec != kFP16) return fail(QCD_ERR_UNSUPPORTED, "the network preconditioner runs with the FP16 inner solve");
     if (ptc_gauge(R.net) != R.g) return fail(QCD_ERR_ARG, "the network is bound to another gauge handle");
@@ -841,18 +1021,32 @@ qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
 }
 
 // b in the native FP64 layout; r = b, x = 0; |b| and the first rescaling on the device.
-void ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
   const Geom& G = R.g->g;
   Scalars hs[kMaxRhs];
   for (int i = 0; i < R.n; i++) {
     init_params(&hs[i], p->inner);
     hs[i].out_tol = p->tol;
   }
-  (void)hipMemcpyAsync(R.w.sc, hs, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st);
+  HIP_TRY(hipMemcpyAsync(R.w.sc, hs, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
   launch_pack_spinor(G, kFP64, R.n, R.w.b64, (const double*)R.b_dev, 1.0, 0, R.w.partials, st);
+  if (R.w.eo) {
+    // |b| of the full system, then b' (eq. (4)-(6)), r = b', x_e = 0
+    double b2[kMaxRhs];
+    qcd_status rc = read_sum(R.w, site_grid(G), 1, b2, st);
+    if (rc) return rc;
+    for (int i = 0; i < R.n; i++) R.bfull[i] = sqrt(b2[i]);
+    const Geom gh = half_geom(G);
+    eo_setup(R.g, R.kappa, R.w, st);
+    launch_narrow(gh, kFP64, R.n, R.w.r64, (const double*)R.w.bp64, R.w.partials, 0, st);
+    launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(gh), p->s, st);
+    launch_zero(gh, kFP64, R.n, R.w.x64, st);
+    return QCD_OK;
+  }
   launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(G), p->s, st);
-  (void)hipMemcpyAsync(R.w.r64, R.w.b64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st);
+  HIP_TRY(hipMemcpyAsync(R.w.r64, R.w.b64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
   launch_zero(G, kFP64, R.n, R.w.x64, st);
+  return QCD_OK;
 }
 
 void ir_after_start(IrRun& R) {
@@ -877,11 +1071,25 @@ void ir_after_start(IrRun& R) {
   R.pc.net = R.net;
 }
 
+// Even-odd: the refinement stops on the residual of the even system, whose
+// norm equals that of b - D x after the odd half is reconstructed (its odd
+// rows vanish), so the tolerance is taken relative to |b| rather than |b'|.
+qcd_status ir_eo_scale_tol(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+  qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
+  for (int i = 0; i < R.n; i++) {
+    const double bp = g->host_sc[i].out_rnorm;
+    if (bp > 0 && std::isfinite(bp)) g->host_sc[i].out_tol = p->tol * R.bfull[i] / bp;
+    R.bn[i] = R.bfull[i];
+  }
+  HIP_TRY(hipMemcpyAsync(R.w.sc, g->host_sc, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
+  return QCD_OK;
+}
+
 // y~ = low(r s/|r|), s^ = |single(y~)|, inner solver start (right-hand sides
 // that met the tolerance are skipped by the kernels); x is saved first when a
 // preconditioned step may have to be undone.
 qcd_status ir_begin_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
-  const Geom& G = R.g->g;
+  const Geom G = R.w.eo ? half_geom(R.g->g) : R.g->g;  // geometry of the refined vectors
   const int prec = p->inner_prec;
   if (R.pc.net) HIP_TRY(hipMemcpyAsync(R.w.x64b, R.w.x64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
   launch_convert(G, prec, R.n, R.w.sc, (const double*)R.w.r64, R.w.r, R.w.rstar, R.w.partials, p->inner.ftz, st);
@@ -899,7 +1107,7 @@ qcd_status ir_begin_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
 // After the inner solve: bookkeeping, x += (|r| / s^) double(t~) (t~ = c M u~
 // when preconditioned), r = b - D x in FP64 (skipped where not refining).
 qcd_status ir_end_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
-  const Geom& G = R.g->g;
+  const Geom G = R.w.eo ? half_geom(R.g->g) : R.g->g;  // geometry of the refined vectors
   const int prec = p->inner_prec;
   memcpy(R.sc, R.g->host_sc, sizeof(Scalars) * R.n);
   for (int i = 0; i < R.n; i++) {
@@ -924,7 +1132,7 @@ qcd_status ir_end_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
     launch_correct(G, prec, R.n, R.w.sc, (double*)R.w.x64, R.w.x, st);
   }
   residual64(R.g, R.kappa, R.w, nullptr, st);
-  launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, dslash_partial_rows(G, R.g->tune[kFP64], R.n), p->s, st);
+  launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, residual_rows(R.g, R.w), p->s, st);
   HIP_LAUNCHED();
   return QCD_OK;
 }
@@ -1010,7 +1218,8 @@ qcd_status ir_finish(IrRun& R, double t0) {
 // (bicg_loop_multi) and corrects them.  runs[r].w must be set.
 qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream_t st, double t0) {
   qcd_status rc;
-  for (int r = 0; r < nrun; r++) ir_start(runs[r], p, st);
+  for (int r = 0; r < nrun; r++)
+    if ((rc = ir_start(runs[r], p, st))) return rc;
   HIP_LAUNCHED();
   {
     std::vector<InnerRun> ir(nrun);
@@ -1020,6 +1229,7 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
   for (int r = 0; r < nrun; r++) {
     runs[r].pc.scale = (float)p->precond_scale;
     ir_after_start(runs[r]);
+    if (runs[r].w.eo && (rc = ir_eo_scale_tol(runs[r], p, st))) return rc;
   }
   for (int step = 0;; step++) {
     std::vector<IrRun*> act;
@@ -1043,8 +1253,22 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
     for (IrRun* R : act)
       if ((rc = ir_after_step(*R, p, step, st))) return rc;
   }
-  for (int r = 0; r < nrun; r++)
-    launch_unpack_spinor(runs[r].g->g, kFP64, runs[r].n, (double*)runs[r].x_dev, runs[r].w.x64, nullptr, 1.0, st);
+  for (int r = 0; r < nrun; r++) {
+    IrRun& R = runs[r];
+    if (R.w.eo) {
+      // x_o from x_e, the full solution, and |b - D x| of the full system for the report
+      eo_reconstruct(R.g, R.kappa, R.w, st);
+      launch_unpack_spinor(R.g->g, kFP64, R.n, (double*)R.x_dev, R.w.xf64, nullptr, 1.0, st);
+      eo_full_residual(R.g, R.kappa, R.w, st);
+      HIP_LAUNCHED();
+      double r2[kMaxRhs];
+      if ((rc = read_sum(R.w, dslash_partial_rows(R.g->g, R.g->tune[kFP64], R.n), 1, r2, st))) return rc;
+      for (int i = 0; i < R.n; i++)
+        if (R.outer[i] > 0) R.rn[i] = sqrt(r2[i]);
+    } else {
+      launch_unpack_spinor(R.g->g, kFP64, R.n, (double*)R.x_dev, R.w.x64, nullptr, 1.0, st);
+    }
+  }
   HIP_LAUNCHED();
   HIP_TRY(hipStreamSynchronize(st));
   qcd_status res = QCD_OK;
@@ -1076,7 +1300,8 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
   R.info = info;
   R.net = const_cast<qcd_ptc*>(p->precond);
   if ((rc = check_ir_run(R, p))) return rc;
-  if ((rc = get_work(g, R.net ? 3 : 0, p->inner_prec, p->inner.max_iter, nrhs, ws, ws_bytes, &R.w))) return rc;
+  const int what = R.net ? 3 : (p->inner.even_odd ? kWhatEO : 0);
+  if ((rc = get_work(g, what, p->inner_prec, p->inner.max_iter, nrhs, ws, ws_bytes, &R.w))) return rc;
   return solve_ir_runs(&R, 1, p, S(stream), t0);
 }
 
@@ -1101,7 +1326,9 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
     R.b_dev = b_dev[r];
     R.info = info ? info[r] : nullptr;
     if ((rc = check_ir_run(R, p))) return rc;
-    if ((rc = get_work(g[r], 0, p->inner_prec, p->inner.max_iter, nrhs[r], nullptr, 0, &R.w))) return rc;
+    if ((rc = get_work(g[r], p->inner.even_odd ? kWhatEO : 0, p->inner_prec, p->inner.max_iter, nrhs[r], nullptr, 0,
+                       &R.w)))
+      return rc;
   }
   return solve_ir_runs(runs.data(), nlat, p, S(stream), t0);
 }

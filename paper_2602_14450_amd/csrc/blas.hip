@@ -15,7 +15,7 @@ namespace qcd {
 // 16-byte granules with a fixed grid, so their partial-sum rows number at
 // most kFlatBlocks per right-hand side.
 constexpr int kFlatBlocks = 1024;
-int site_grid(const Geom& g) { return (2 * g.Vh + 255) / 256; }
+int site_grid(const Geom& g) { return (g.npar * g.Vh + 255) / 256; }
 template <typename S> static int flat_grid(const Geom& g) {
   const size_t n = spinor_granules<S>(g);
   const size_t b = (n + 255) / 256;
@@ -29,9 +29,9 @@ struct SiteId { int par, h; bool valid; };
 __device__ __forceinline__ SiteId site_id(const Geom& g) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   SiteId s;
-  s.par = i >= g.Vh;
+  s.par = g.npar == 2 && i >= g.Vh;
   s.h = i - s.par * g.Vh;
-  s.valid = i < 2 * g.Vh;
+  s.valid = i < g.npar * g.Vh;
   return s;
 }
 __device__ __forceinline__ int64_t lex_site(const Geom& g, int par, int h) {
@@ -535,6 +535,49 @@ __global__ void k_finish_sum_any(const double* partials, int nrows, int nv, doub
 }
 
 // ---------------------------------------------------------------------------
+// FP64 native -> storage precision (one RNE conversion), with |stored|^2
+// partials per block; and storage precision -> FP64 times a per-RHS scale.
+template <typename S>
+__global__ __launch_bounds__(256) void k_narrow(Geom g, S* __restrict__ dst, const double2* __restrict__ src,
+                                                double* __restrict__ partials, int ftz) {
+  using T = typename Traits<S>::T;
+  SiteId id = site_id(g);
+  const int rhs = blockIdx.y;
+  dst += (size_t)rhs * spinor_elems(g);
+  src += (size_t)rhs * spinor_elems(g);
+  double red[1] = {0.0};
+  if (id.valid) {
+    cx<double> f[12];
+    load_site(src, g, id.par, id.h, f);
+    S* b = dst + sp_block(g, id.par, id.h);
+    const int lane = id.h & 63;
+    T acc = 0;
+    for (int k = 0; k < 12; k++) {
+      const S v = pack_from_double<S>(f[k].re, f[k].im, ftz);
+      b[sp_off<S>(k, lane)] = v;
+      acc += norm2(Traits<S>::load(&v));
+    }
+    red[0] = acc;
+  }
+  if (partials) block_reduce_store<1>(red, partials + (size_t)rhs * gridDim.x, blockIdx.x);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_widen(Geom g, double2* __restrict__ dst, const S* __restrict__ src,
+                                               const double* __restrict__ scale_dev) {
+  SiteId id = site_id(g);
+  if (!id.valid) return;
+  const int rhs = blockIdx.y;
+  dst += (size_t)rhs * spinor_elems(g);
+  src += (size_t)rhs * spinor_elems(g);
+  const double c = scale_dev[rhs];
+  cx<typename Traits<S>::T> f[12];
+  cx<double> o[12];
+  load_site(src, g, id.par, id.h, f);
+  for (int k = 0; k < 12; k++) o[k] = cx<double>(c * (double)f[k].re, c * (double)f[k].im);
+  store_site(dst, g, id.par, id.h, o, 0);
+}
+
 // launchers
 
 #define QCD_DISPATCH(prec, FN, ...)                     \
@@ -665,4 +708,25 @@ void launch_finish_sum(int n, const double* partials, int nrows, int nv, double*
   hipLaunchKernelGGL(k_finish_sum_any, dim3(n), dim3(1024), 0, st, partials, nrows, nv, out);
 }
 
+}  // namespace qcd
+
+namespace qcd {
+template <typename S>
+static void narrow_t(const Geom& g, int n, void* dst, const double* src, double* partials, int ftz, hipStream_t st) {
+  hipLaunchKernelGGL(k_narrow<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, (S*)dst, (const double2*)src, partials,
+                     ftz);
+}
+void launch_narrow(const Geom& g, int prec, int n, void* dst, const double* src, double* partials, int ftz,
+                   hipStream_t st) {
+  QCD_DISPATCH(prec, narrow_t, g, n, dst, src, partials, ftz, st);
+}
+template <typename S>
+static void widen_t(const Geom& g, int n, double* dst, const void* src, const double* scale_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_widen<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, (double2*)dst, (const S*)src,
+                     scale_dev);
+}
+void launch_widen(const Geom& g, int prec, int n, double* dst, const void* src, const double* scale_dev,
+                  hipStream_t st) {
+  QCD_DISPATCH(prec, widen_t, g, n, dst, src, scale_dev, st);
+}
 }  // namespace qcd

@@ -123,6 +123,7 @@ struct Geom {
   int nb;          // 64-site blocks per parity
   int sy, sz, st;  // half-index strides of y, z, t
   FastDiv dx, dy, dz, dnb;
+  int npar;        // parities a field holds: 2 (full field, even then odd) or 1 (one parity, indexed as parity 0)
 };
 
 inline Geom make_geom(const int dims[4]) {
@@ -138,13 +139,21 @@ inline Geom make_geom(const int dims[4]) {
   g.dy = make_fastdiv(dims[1]);
   g.dz = make_fastdiv(dims[2]);
   g.dnb = make_fastdiv(g.nb);
+  g.npar = 2;
   return g;
+}
+// The same lattice seen through fields of one parity (the even-odd solver's
+// vectors): streaming kernels then run over Vh sites, indexed as parity 0.
+inline Geom half_geom(const Geom& g) {
+  Geom h = g;
+  h.npar = 1;
+  return h;
 }
 
 // Elements (stored complex numbers) of one full native spinor / link field.
 // A link field stores ne complex entries per link: 9 (the full matrix) or 6
 // (rows 0 and 1 of an SU(3) matrix; row 2 is rebuilt as conj(row0 x row1)).
-__host__ __device__ inline size_t spinor_elems(const Geom& g) { return (size_t)2 * g.nb * 12 * 64; }
+__host__ __device__ inline size_t spinor_elems(const Geom& g) { return (size_t)g.npar * g.nb * 12 * 64; }
 __host__ __device__ inline size_t link_elems(const Geom& g, int ne = 9) { return (size_t)4 * 2 * g.nb * ne * 64; }
 
 template <typename S> struct Lay {

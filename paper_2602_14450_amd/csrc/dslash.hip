@@ -195,7 +195,7 @@ template <int MU, bool MINUS, typename S> __device__ __forceinline__ constexpr b
   return (MU != 3) || (MINUS ? (j * C + C - 1) / 3 >= 2 : (j * C) / 3 < 2);
 }
 
-template <int HOP, bool DAG, int NE, typename S>
+template <int HOP, bool DAG, int NE, bool EO, typename S>
 __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
                                          int h, const Coord& c, HopRaw<S, NE>& d, int dep = 0) {
   constexpr int MU = HOP >> 1;
@@ -217,7 +217,8 @@ __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in
   }
   hn += dep;  // dep is an opaque zero that orders these loads after an earlier hop
   const int npar = par ^ 1;
-  const S* sb = in + sp_block(g, npar, hn) + (hn & 63) * C;
+  // a one-parity input field holds only the neighbours' parity, indexed as parity 0
+  const S* sb = in + sp_block(g, EO ? 0 : npar, hn) + (hn & 63) * C;
 #pragma unroll
   for (int j = 0; j < Lay<S>::G; j++)
     if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = *reinterpret_cast<const Gr*>(sb + j * 64 * C);
@@ -330,7 +331,7 @@ struct PipeArgs {
   Coord c;
 };
 
-template <int I, int DEPTH, bool DAG, int NE, typename S, typename T>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, typename S, typename T>
 __device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                          const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
   if constexpr (I < 8) {
@@ -339,29 +340,29 @@ __device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in
     if constexpr (I + DEPTH + 1 < 8) {
       int dep = 0;
       asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
-      hop_load<I + DEPTH + 1, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
+      hop_load<I + DEPTH + 1, DAG, NE, EO>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
     }
     QCD_FENCE();
-    hop_pipe<I + 1, DEPTH, DAG, NE>(g, in, U, pa, buf, a);
+    hop_pipe<I + 1, DEPTH, DAG, NE, EO>(g, in, U, pa, buf, a);
   }
 }
 
-template <int I, int DEPTH, bool DAG, int NE, typename S>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, typename S>
 __device__ __forceinline__ void hop_prologue(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                              const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1]) {
   if constexpr (I <= DEPTH) {
-    hop_load<I, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
-    hop_prologue<I + 1, DEPTH, DAG, NE>(g, in, U, pa, buf);
+    hop_load<I, DAG, NE, EO>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
+    hop_prologue<I + 1, DEPTH, DAG, NE, EO>(g, in, U, pa, buf);
   }
 }
 
-template <int DEPTH, bool DAG, int NE, typename S, typename T>
+template <int DEPTH, bool DAG, int NE, bool EO, typename S, typename T>
 __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
                                         int h, const Coord& c, cx<T> (&a)[4][3]) {
   HopRaw<S, NE> buf[DEPTH + 1];
   const PipeArgs pa{par, h, c};
-  hop_prologue<0, DEPTH, DAG, NE>(g, in, U, pa, buf);
-  hop_pipe<0, DEPTH, DAG, NE>(g, in, U, pa, buf, a);
+  hop_prologue<0, DEPTH, DAG, NE, EO>(g, in, U, pa, buf);
+  hop_pipe<0, DEPTH, DAG, NE, EO>(g, in, U, pa, buf, a);
 }
 
 // Thread -> (site, right-hand side).  A block of 256 threads is four waves:
@@ -414,12 +415,17 @@ __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
 
 // out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues,
 // for T right-hand sides per wave (vectors of right-hand side r start at
-// r * vstride elements).
-template <typename S, int OP, int EPI, int DEPTH, int OCC, int T, int NE>
+// r * vstride elements).  With EO the output covers parity tpar only and every
+// vector is a one-parity field: the hops read `in` (the other parity) and D's
+// centre term comes from `cin` (parity tpar), so out = cin - kappa H in
+// (kappa = kappa^2 gives the Schur complement's second half, kappa < 0 the
+// right-hand side and the reconstruction of the even-odd solve).
+template <typename S, int OP, int EPI, int DEPTH, int OCC, int T, int NE, bool EO>
 __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, S* __restrict__ out,
                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                      const S* __restrict__ aux, double* __restrict__ partials,
-                                                     const Scalars* __restrict__ scal, int ftz) {
+                                                     const Scalars* __restrict__ scal, int ftz,
+                                                     const S* __restrict__ cin, int tpar) {
   using T_ = typename Traits<S>::T;
   const BlockPos bp = block_pos(sched);
   const int tid = threadIdx.x;
@@ -433,12 +439,14 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     if (!any) return;
   }
   const bool live = !scal || scal[rhs].active != 0;
-  const int par = wid & 1;
-  const int h = bp.h0 + (wid >> 1) * (64 / T) + lane / T;
-  const size_t vo = (size_t)rhs * spinor_elems(g);
+  const int par = EO ? tpar : (wid & 1);
+  const int h = EO ? bp.h0 + wid * (64 / T) + lane / T : bp.h0 + (wid >> 1) * (64 / T) + lane / T;
+  const int fpar = EO ? 0 : par;  // parity index of this site in its own fields
+  const size_t vo = (size_t)rhs * (EO ? (size_t)g.nb * 768 : spinor_elems(g));
   in += vo;
   out += vo;
   if (aux) aux += vo;
+  if (EO && cin) cin += vo;
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
   constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
@@ -452,11 +460,11 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     for (int s = 0; s < 4; s++)
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T_>(0, 0);
-    hop_all<DEPTH, DAG, NE>(g, in, U, par, h, c, a);
+    hop_all<DEPTH, DAG, NE, EO>(g, in, U, par, h, c, a);
     const T_ k = (T_)kappa;
     cx<T_> o[12], ctr[12], ax[12];
-    if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(in, g, par, h, ctr);
-    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(aux, g, par, h, ax);
+    if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(EO ? cin : in, g, fpar, h, ctr);
+    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(aux, g, fpar, h, ax);
 #pragma unroll
     for (int i = 0; i < 12; i++) {
       if constexpr (OP == kOpH || OP == kOpHdag) {
@@ -469,7 +477,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     // round to storage; the reductions see the stored values
     using Gr = typename Lay<S>::Gran;
     constexpr int C = Lay<S>::C;
-    S* ob = out + sp_block(g, par, h) + (h & 63) * C;
+    S* ob = out + sp_block(g, fpar, h) + (h & 63) * C;
     T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
 #pragma unroll
     for (int j = 0; j < Lay<S>::G; j++) {
@@ -789,15 +797,28 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
 template <typename S, int DEPTH, int OCC, int T, int NE>
 static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, hipStream_t st) {
+                            int ftz, const void* cin, int eo_par, hipStream_t st) {
   dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
   const S* u = (const S*)U;
   const S* x = (const S*)aux;
-#define QCD_LAUNCH(OPV, EPIV)                                                                                  \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
-                     partials, scal, ftz)
+  const S* ci = (const S*)cin;
+  if (eo_par >= 0) {  // one parity: D form (centre from cin) or H, the epilogues the solvers use
+#define QCD_LAUNCH_EO(OPV, EPIV)                                                                                    \
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
+                     partials, scal, ftz, ci, eo_par)
+    if (op == kOpH) QCD_LAUNCH_EO(kOpH, kEpiNone);
+    else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
+    else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
+    else if (epi == kEpiTS) QCD_LAUNCH_EO(kOpD, kEpiTS);
+    else QCD_LAUNCH_EO(kOpD, kEpiResid);
+#undef QCD_LAUNCH_EO
+    return;
+  }
+#define QCD_LAUNCH(OPV, EPIV)                                                                                         \
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, false>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
+                     partials, scal, ftz, nullptr, 0)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -820,27 +841,27 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 template <typename S, int T, int NE>
 static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
                                const void* in, const void* U, double kappa, const void* aux, double* partials,
-                               const Scalars* scal, int ftz, hipStream_t st) {
-  const DslashSched sc = make_sched(g, tune.sched, T, n);
+                               const Scalars* scal, int ftz, const void* cin, int eo_par, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched, T, n, eo_par >= 0);
   if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
-    launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
     return;
   }
   switch (tune.variant) {
-    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    case 5: launch_dslash_v<S, 1, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
-    default: launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, st); break;
+    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    case 5: launch_dslash_v<S, 1, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    default: launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
   }
 }
 
 template <typename S, int R, int NE>
 static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                              const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                             int ftz, hipStream_t st) {
-  const DslashSched sc = make_sched(g, tune.sched, 1, n / R);
+                             int ftz, const void* cin, int eo_par, hipStream_t st) {
+  const DslashSched sc = make_sched(g, tune.sched, 1, n / R, false);
   dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
@@ -871,48 +892,49 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
 template <typename S, int NE>
 static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, hipStream_t st) {
-  const int R = reg_tile_for(tune, n);
-  if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
-  if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
-  if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+                            int ftz, const void* cin, int eo_par, hipStream_t st) {
+  const int R = eo_par >= 0 ? 1 : reg_tile_for(tune, n);  // one-parity launches use lane tiles only
+  if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   const int T = rhs_tile_for(tune, n);
   if (T == 4)
-    launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else if (T == 2)
-    launch_dslash_tile<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_tile<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else
-    launch_dslash_tile<S, 1, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_tile<S, 1, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 
 template <typename S>
 static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, hipStream_t st) {
+                            int ftz, const void* cin, int eo_par, hipStream_t st) {
   if (tune.recon)
-    launch_dslash_r<S, 6>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_r<S, 6>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else
-    launch_dslash_r<S, 9>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_r<S, 9>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 
 #define QCD_DSLASH_ARGS                                                                                          \
   const Geom &g, const DslashTune &tune, int op, int epi, int n, void *out, const void *in, const void *U, \
-      double kappa, const void *aux, double *partials, const Scalars *scal, int ftz, hipStream_t st
+      double kappa, const void *aux, double *partials, const Scalars *scal, int ftz, const void *cin, int eo_par, \
+      hipStream_t st
 void launch_dslash_f64(QCD_DSLASH_ARGS);
 void launch_dslash_f32(QCD_DSLASH_ARGS);
 void launch_dslash_f16(QCD_DSLASH_ARGS);
 
 #if QCD_DSLASH_PREC == 0
 void launch_dslash_f64(QCD_DSLASH_ARGS) {
-  launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 #elif QCD_DSLASH_PREC == 1
 void launch_dslash_f32(QCD_DSLASH_ARGS) {
-  launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 #else
 void launch_dslash_f16(QCD_DSLASH_ARGS) {
-  launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+  launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 
 int rhs_tile_for(const DslashTune& tune, int n) {
@@ -928,9 +950,9 @@ int reg_tile_for(const DslashTune& tune, int n) {
   return (R >= 2 && R <= 4 && n % R == 0) ? R : 1;
 }
 
-DslashSched make_sched(const Geom& g, int mode, int T, int n) {
+DslashSched make_sched(const Geom& g, int mode, int T, int n, bool eo) {
   DslashSched s;
-  s.H = 128 / T;
+  s.H = (eo ? 256 : 128) / T;  // half sites of one parity (eo) or of each parity per block
   s.nsb = (g.Vh + s.H - 1) / s.H;
   s.ntiles = n / T;
   s.mode = 0;
@@ -960,20 +982,21 @@ DslashSched make_sched(const Geom& g, int mode, int T, int n) {
   return s;
 }
 
-int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n) {
+int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo) {
   const int T = rhs_tile_for(tune, n);
-  return (g.Vh + 128 / T - 1) / (128 / T);
+  const int H = (eo ? 256 : 128) / T;
+  return (g.Vh + H - 1) / H;
 }
 
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                    const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
-                   hipStream_t st) {
+                   hipStream_t st, const void* cin, int eo_par) {
   if (prec == kFP64)
-    launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else if (prec == kFP32)
-    launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else
-    launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, st);
+    launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 #endif
 #undef QCD_DSLASH_ARGS

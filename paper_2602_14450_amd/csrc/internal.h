@@ -73,7 +73,7 @@ struct DslashSched {
   int mode, nsb, ntiles, Lz, Lt, bp, zc, sub, H;  // H: half-sites per parity per block
 };
 constexpr int kDslashScheds = 5;
-DslashSched make_sched(const Geom& g, int mode, int T, int n);
+DslashSched make_sched(const Geom& g, int mode, int T, int n, bool eo = false);
 int rhs_tile_for(const DslashTune& tune, int n);
 // right-hand sides per thread (rhs_tile = -R, R = 2..4, n divisible by R), else 1
 int reg_tile_for(const DslashTune& tune, int n);
@@ -84,9 +84,9 @@ int reg_tile_for(const DslashTune& tune, int n);
 
 // launchers (dslash.hip)
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
-                   const void* U, double kappa, const void* aux, double* partials, const Scalars* sc, int ftz,
-                   hipStream_t st);
-int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n);  // rows per right-hand side
+                   const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
+                   hipStream_t st, const void* cin = nullptr, int eo_par = -1);
+int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo = false);  // rows per right-hand side
 
 // launchers (blas.hip)
 int site_grid(const Geom& g);              // blocks (and partial rows) per right-hand side, site-ordered kernels
@@ -99,6 +99,11 @@ void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double*
 void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
                           double scale, hipStream_t st);
 void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st);
+// native FP64 -> native prec (RNE, |stored|^2 partials if not null); native prec -> FP64 times scale_dev[rhs]
+void launch_narrow(const Geom& g, int prec, int n, void* dst, const double* src, double* partials, int ftz,
+                   hipStream_t st);
+void launch_widen(const Geom& g, int prec, int n, double* dst, const void* src, const double* scale_dev,
+                  hipStream_t st);
 
 void launch_bicg_init(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st);
 void launch_p_update(const Geom& g, int prec, int n, Scalars* sc, void* p, const void* v, const void* r, int ftz,

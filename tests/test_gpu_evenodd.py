@@ -1,0 +1,121 @@
+"""Even-odd form (eq. (4)-(6)) on the GPU against oracle/evenodd.py, through the C ABI."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import qcd_inputs as qi  # noqa: E402
+from oracle import evenodd as EO  # noqa: E402
+from gpu_common import TOL, compare, to_dev, to_host  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+# (4,6,8,10): 960 half sites, a ragged last 256-site block; (8,8,8,8): whole blocks
+SHAPES = [(4, 6, 8, 10), (8, 8, 8, 8), (2, 4, 6, 8)]
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_schur_operator_matches_oracle(q, dims, prec):
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 700 + sum(dims))
+    psi = qi.gaussian_source(dims, 701, nrhs=2)
+    e = EO.even_mask(dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    out = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    q.dslash(g, kappa, out, to_dev(psi), op=q.OP_SCHUR, prec=prec)
+    torch.cuda.synchronize()
+    got = to_host(out)
+    for r in range(2):
+        want = EO.schur(U, psi[r], kappa, dims)
+        assert not np.any(got[r][~e])
+        compare(got[r][e], want[e], TOL[prec], f"schur dims={dims} prec={prec} rhs={r}")
+    g.close()
+
+
+def test_bicgstab_even_odd_fp64(q):
+    dims = (8, 8, 8, 8)
+    kappa = 0.12
+    U = qi.gauge_field(dims, 0.3, 710)
+    b = qi.gaussian_source(dims, 711)
+    x_ref, info_ref = EO.solve_fp64(U, kappa, dims, b, tol=1e-13)
+    g = q.gauge_upload(to_dev(U), dims)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    info = q.bicgstab(g, kappa, x, to_dev(b), prec=q.FP64, tol=1e-12, even_odd=True)
+    assert info.status == "ok" and info.true_rel_residual <= 1.5e-12
+    assert np.linalg.norm(to_host(x) - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    full = q.bicgstab(g, kappa, torch.zeros_like(x), to_dev(b), prec=q.FP64, tol=1e-12)
+    assert info.inner_iters < full.inner_iters
+    assert abs(info.inner_iters - info_ref.iterations) <= 1
+    g.close()
+
+
+@pytest.mark.parametrize("inner_prec", [1, 2])
+def test_refinement_even_odd(q, inner_prec):
+    dims = (8, 8, 8, 8)
+    kappa = 0.12
+    U = qi.gauge_field(dims, 0.3, 720)
+    bs = qi.gaussian_source(dims, 721, nrhs=3)
+    bs[1] = 0.0
+    g = q.gauge_upload(to_dev(U), dims)
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, kappa, x, b, inner_prec=inner_prec, tol=1e-12, even_odd=True)
+    xh = to_host(x)
+    full = q.solve_mixed_ir(g, kappa, torch.zeros_like(b), b, inner_prec=inner_prec, tol=1e-12)
+    for r in (0, 2):
+        assert infos[r].true_rel_residual <= 1e-12
+        res = bs[r] - oracle.dslash(U, xh[r], kappa, dims)
+        assert np.linalg.norm(res) <= 1.01e-12 * np.linalg.norm(bs[r])
+        x_ref, _ = EO.solve_fp64(U, kappa, dims, bs[r], tol=1e-13)
+        assert np.linalg.norm(xh[r] - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+        assert infos[r].inner_iters < full[r].inner_iters
+    assert not np.any(xh[1]) and infos[1].true_rel_residual == 0.0
+    g.close()
+
+
+def test_even_odd_graph_replay_and_batched_lattices(q):
+    specs = [((8, 8, 8, 8), 0.12, 730), ((4, 6, 8, 10), 0.124, 731)]
+    gauges, bs = [], []
+    for dims, k, seed in specs:
+        gauges.append(q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, seed)), dims))
+        bs.append(to_dev(qi.gaussian_source(dims, seed + 1, nrhs=2)))
+    single = []
+    for g, (dims, k, _), b in zip(gauges, specs, bs):
+        xs = []
+        for use_graph in (False, True):
+            x = torch.zeros_like(b)
+            q.solve_mixed_ir(g, k, x, b, inner_prec=q.FP16, tol=1e-12, even_odd=True, use_graph=use_graph)
+            xs.append(x)
+        assert torch.equal(xs[0], xs[1])
+        single.append(xs[0])
+    xb = [torch.zeros_like(b) for b in bs]
+    q.solve_mixed_ir_batched(gauges, [s[1] for s in specs], xb, bs, inner_prec=q.FP16, tol=1e-12, even_odd=True,
+                             use_graph=True)
+    for a, b in zip(xb, single):
+        assert torch.equal(a, b)
+    for g in gauges:
+        g.close()
+
+
+def test_even_odd_rejects_network(q):
+    dims = (4, 4, 4, 8)
+    U = qi.gauge_field(dims, 0.3, 740)
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, (1, 2, 2, 1))
+    net.init_neumann(0.12)
+    b = to_dev(qi.gaussian_source(dims, 741))
+    with pytest.raises(q.QcdError):
+        q.solve_mixed_ir(g, 0.12, torch.zeros_like(b), b, inner_prec=q.FP16, precond=net, even_odd=True)
+    net.close()
+    g.close()
