@@ -45,10 +45,12 @@ def parse():
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--dslash-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-iters", type=int, default=3)
+    ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
+    ap.add_argument("--full-operator", action="store_true",
+                    help="solve with the full Wilson matrix instead of the even-odd system of eq. (5)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the launch-shape tuner first (default: the library's measured defaults)")
     ap.add_argument("--only-dslash", action="store_true",
@@ -155,7 +157,7 @@ def learned_form(q, torch, np, qi, kappa, pairs_per_field, max_iter):
     return res
 
 
-def mixed_lattices(q, torch, qi, kappa, max_iter):
+def mixed_lattices(q, torch, qi, kappa, max_iter, eo):
     """16^4, 24^3 x 48 and 32^3 x 64 with 4 Gaussian sources each: one batched
     call (inner solves of the three lattices concurrent, hip-graph replay)
     against the three lattices solved one after another."""
@@ -166,7 +168,7 @@ def mixed_lattices(q, torch, qi, kappa, max_iter):
         bs.append(torch.from_numpy(qi.gaussian_source(dims, seed + 1000, nrhs=4)).cuda())
         xs.append(torch.zeros_like(bs[-1]))
     kw = dict(inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter,
-              use_graph=True)
+              use_graph=True, even_odd=eo)
 
     def batched():
         for x in xs:
@@ -191,7 +193,8 @@ def mixed_lattices(q, torch, qi, kappa, max_iter):
         res[name + "_inner_iters"] = [[i.inner_iters for i in lat] for lat in infos]
         res[name + "_max_true_rel_residual"] = max(i.true_rel_residual for lat in infos for i in lat)
     res["speedup"] = res["sequential_seconds"] / res["batched_seconds"]
-    res["workload"] = "16^4 + 24^3x48 + 32^3x64, eps=0.3, kappa=%g, 4 Gaussian sources each, FP16-inner IR to 1e-12" % kappa
+    res["workload"] = ("16^4 + 24^3x48 + 32^3x64, eps=0.3, kappa=%g, 4 Gaussian sources each, FP16-inner IR to 1e-12%s"
+                       % (kappa, ", even-odd" if eo else ""))
     print(f"[bench] mixed lattices: {res['batched_seconds']*1e3:.1f} ms batched vs "
           f"{res['sequential_seconds']*1e3:.1f} ms sequential", file=sys.stderr, flush=True)
     for g in gauges:
@@ -272,20 +275,26 @@ def main():
         print(f"[bench] calibration copy: {calib_bytes} bytes read and written", file=sys.stderr, flush=True)
         g.close()
         return
-    ws = torch.empty(g.workspace_bytes(0, q.FP16, max_iter), dtype=torch.uint8, device="cuda")
-    ws64 = torch.empty(g.workspace_bytes(1, q.FP64, max_iter), dtype=torch.uint8, device="cuda")
-    ws32 = torch.empty(g.workspace_bytes(0, q.FP32, max_iter), dtype=torch.uint8, device="cuda")
+    eo = not args.full_operator
+    EOF = 8   # workspace flag of the even-odd form
+    ws = {e: torch.empty(g.workspace_bytes(0 | (EOF if e else 0), q.FP16, max_iter), dtype=torch.uint8,
+                         device="cuda") for e in (False, True)}
+    ws64 = {e: torch.empty(g.workspace_bytes(1 | (EOF if e else 0), q.FP64, max_iter), dtype=torch.uint8,
+                           device="cuda") for e in (False, True)}
+    ws32 = {e: torch.empty(g.workspace_bytes(0 | (EOF if e else 0), q.FP32, max_iter), dtype=torch.uint8,
+                           device="cuda") for e in (False, True)}
 
-    def solve_fp16():
+    def solve_fp16(e=eo):
         return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,
-                                inner_max_iter=max_iter, workspace=ws)
+                                inner_max_iter=max_iter, workspace=ws[e], even_odd=e)
 
-    def solve_fp32():
+    def solve_fp32(e=eo):
         return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP32, s=1.0, recalc_shat=False, sigma=0.0, tol=1e-12,
-                                inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws32)
+                                inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws32[e], even_odd=e)
 
-    def solve_fp64():
-        return q.bicgstab(g, k, x, bd, prec=q.FP64, tol=1e-12, max_iter=max_iter, workspace=ws64, history=False)
+    def solve_fp64(e=eo):
+        return q.bicgstab(g, k, x, bd, prec=q.FP64, tol=1e-12, max_iter=max_iter, workspace=ws64[e], history=False,
+                          even_odd=e)
 
     for _ in range(args.warmup):
         solve_fp16()
@@ -316,6 +325,21 @@ def main():
     others["fp16_inner_ir"] = dict(seconds=s_per_solve, outer=i16.outer_iters, iters=i16.inner_iters,
                                    matvec_low=i16.matvec_low, matvec_fp64=i16.matvec_fp64,
                                    true_rel_residual=i16.true_rel_residual)
+    # the same three solvers on the other form (full matrix if the headline is even-odd)
+    other_form = {}
+    for name, fn in (("fp16_inner_ir", solve_fp16), ("fp64_bicgstab", solve_fp64), ("fp32_inner_ir", solve_fp32)):
+        fn(not eo)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        inf = fn(not eo)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        other_form[name] = dict(seconds=te, outer=inf.outer_iters, iters=inf.inner_iters,
+                                true_rel_residual=inf.true_rel_residual)
+        print(f"[bench] {name} ({'full matrix' if eo else 'even-odd'}): {te*1e3:.2f} ms, iters={inf.inner_iters}",
+              file=sys.stderr, flush=True)
+    del ws, ws64, ws32
+    torch.cuda.empty_cache()
 
     batched = None
     if not args.no_batched:
@@ -330,11 +354,13 @@ def main():
         bpd = torch.from_numpy(bp).cuda()
         del bp
         xb = torch.zeros_like(bpd)
-        wsb = torch.empty(g.workspace_bytes(0, q.FP16, max_iter, nb), dtype=torch.uint8, device="cuda")
+        wsb = torch.empty(g.workspace_bytes(0 | (EOF if eo else 0), q.FP16, max_iter, nb), dtype=torch.uint8,
+                          device="cuda")
 
         def solve_batched():
             return q.solve_mixed_ir(g, k, xb, bpd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12,
-                                    inner_tol=1e-2, inner_max_iter=max_iter, workspace=wsb, use_graph=True)
+                                    inner_tol=1e-2, inner_max_iter=max_iter, workspace=wsb, use_graph=True,
+                                    even_odd=eo)
 
         solve_batched()
         torch.cuda.synchronize()
@@ -347,7 +373,7 @@ def main():
         seq_iters = 0
         for r in range(nb):
             inf = q.solve_mixed_ir(g, k, x1, bpd[r].contiguous(), inner_prec=q.FP16, s=128.0, sigma=64.0,
-                                   tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws)
+                                   tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter, use_graph=True, even_odd=eo)
             seq_iters += inf.inner_iters
         torch.cuda.synchronize()
         t_seq = time.perf_counter() - ts
@@ -360,7 +386,7 @@ def main():
         print(f"[bench] batched 12 rhs: {t_batched*1e3:.1f} ms vs {t_seq*1e3:.1f} ms sequential; "
               f"12-rhs dslash {ms12*1e3:.1f} us {bytes12 / ms12 / 1e6:.0f} GB/s", file=sys.stderr, flush=True)
         del xb, bpd, wsb
-        batched["mixed_lattices"] = mixed_lattices(q, torch, qi, k, max_iter)
+        batched["mixed_lattices"] = mixed_lattices(q, torch, qi, k, max_iter, eo)
 
     at_size = dims == (32, 32, 32, 64)
     traffic = measured_counter("traffic bytes per launch fp16") if at_size else None
@@ -382,14 +408,21 @@ def main():
         from oracle import solvers as S
         n_it = args.cpu_sample_iters
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        A = lambda v: oracle.dslash(U, v, k, dims)
+        if eo:
+            from oracle import evenodd as EO
+            A = lambda v: EO.schur(U, v, k, dims)
+            rhs0 = EO.rhs(U, b, k, dims)
+        else:
+            A = lambda v: oracle.dslash(U, v, k, dims)
+            rhs0 = b
         ts = time.perf_counter()
-        S.bicgstab(A, b, S.FP64, tol2=0.0, maxiter=n_it)
+        S.bicgstab(A, rhs0, S.FP64, tol2=0.0, maxiter=n_it)
         per_it = (time.perf_counter() - ts) / n_it
         it64 = others["fp64_bicgstab"]["iters"]
         cpu = dict(value=per_it * it64, unit="s", cores=threads, kind="oracle",
-                   sample=f"{n_it} iterations of the oracle's FP64 BiCGStab at {dims}, "
-                          f"scaled to the {it64} iterations the FP64 solve needs")
+                   sample=f"{n_it} iterations of the oracle's FP64 BiCGStab on the "
+                          f"{'even-odd system' if eo else 'full matrix'} at {dims}, "
+                          f"scaled to the {it64} iterations the GPU FP64 solve needs")
         print(f"[bench] cpu oracle: {per_it:.2f} s/iteration", file=sys.stderr, flush=True)
 
     out = {
@@ -397,9 +430,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": s_per_solve * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp16-storage/fp32-arith, fp64 refinement", "data": "synthetic",
         "config": {"workload": f"Wilson D x = b, {'x'.join(map(str, dims))} lattice, eps={args.eps} SU(3) links, "
-                               f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64), tol 1e-12",
-                   "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12},
-        "roofline": roof, "cpu_baseline": cpu, "solvers": others, "dslash": dsl, "batched": batched, "learned": learned,
+                               f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64), "
+                               f"{'even-odd system (eq. 5)' if eo else 'full matrix'}, true residual 1e-12",
+                   "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12, "even_odd": eo},
+        "roofline": roof, "cpu_baseline": cpu, "solvers": others,
+        ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched, "learned": learned,
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,
