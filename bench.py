@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
+    ap.add_argument("--no-rescaling-study", action="store_true", help="skip the (s, sigma) grid of Sec. 5")
     ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
     ap.add_argument("--full-operator", action="store_true",
@@ -398,6 +399,23 @@ def main():
                 bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V,
                 algorithmic_bytes_per_launch=DSLASH_BYTES[2] * V, copy_GBps=copy_bandwidth(torch),
                 valu_issue_frac=valu_frac, link_reals=tuned["fp16"][3])
+    rescaling = None
+    if not args.no_rescaling_study and dims == (32, 32, 32, 64):
+        from paper_2602_14450_amd import rescaling_study as RS
+        ts = time.perf_counter()
+        st = RS.study(dims, k, eps=args.eps, seed=201)
+        grid = {}
+        for r in st["records"]:
+            key = f"rescale_x={int(r['rescale_x'])},recalc_gamma={int(r['recalc_gamma'])}"
+            grid.setdefault(key, {})[f"s={r['s']:g},sigma={r['sigma']:g}"] = r["matvecs"]
+        zeros = {f"s={r['s']:g},sigma={r['sigma']:g}": [round(z, 4) for z in r["zero_fraction"]]
+                 for r in st["records"] if not r["rescale_x"] and not r["recalc_gamma"]
+                 and r["s"] in (1.0, 128.0, 4096.0) and r["sigma"] in (0.0, 64.0)}
+        zeros["fp32_inner"] = [round(z, 4) for z in st["fp32_reference"]["zero_fraction"]]
+        rescaling = dict(fp16_matvecs=grid, zero_fraction_per_step=zeros, source=st["source"], ftz=st["ftz"],
+                         seconds=time.perf_counter() - ts)
+        print(f"[bench] rescaling study: {len(st['records'])} solves in {rescaling['seconds']:.1f} s",
+              file=sys.stderr, flush=True)
     learned = None
     if not args.no_learned:
         learned = learned_form(q, torch, np, qi, 0.124, args.learned_pairs, max_iter)
@@ -434,7 +452,7 @@ def main():
                                f"{'even-odd system (eq. 5)' if eo else 'full matrix'}, true residual 1e-12",
                    "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12, "even_odd": eo},
         "roofline": roof, "cpu_baseline": cpu, "solvers": others,
-        ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched, "learned": learned,
+        ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched, "learned": learned, "rescaling_study": rescaling,
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,
