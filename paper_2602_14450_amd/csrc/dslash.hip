@@ -539,7 +539,7 @@ __device__ __forceinline__ int hop_neighbour(const Geom& g, int h, const Coord& 
   }
 }
 
-template <int HOP, bool DAG, int NE, int R, typename S>
+template <int HOP, bool DAG, int NE, int R, bool EO, typename S>
 __device__ __forceinline__ void hop_load_r(const Geom& g, const S* __restrict__ in, size_t vstride,
                                            const S* __restrict__ U, int par, int h, const Coord& c,
                                            HopRawR<S, NE, R>& d, int dep = 0) {
@@ -550,7 +550,7 @@ __device__ __forceinline__ void hop_load_r(const Geom& g, const S* __restrict__ 
   using Gr = typename Lay<S>::Gran;
   const int hn = hop_neighbour<MU, BWD>(g, h, c) + dep;
   const int npar = par ^ 1;
-  const S* sb = in + sp_block(g, npar, hn) + (hn & 63) * C;
+  const S* sb = in + sp_block(g, EO ? 0 : npar, hn) + (hn & 63) * C;
 #pragma unroll
   for (int r = 0; r < R; r++)
 #pragma unroll
@@ -653,19 +653,19 @@ template <int R, typename T> __device__ __forceinline__ void reg_barrier_r(cx<T>
 
 // The eight hops one after the other; the loads of hop i+1 are issued after
 // hop i is computed (dependency through an empty asm statement).
-template <int I, bool DAG, int NE, int R, typename S, typename T>
+template <int I, bool DAG, int NE, int R, bool EO, typename S, typename T>
 __device__ __forceinline__ void hop_seq_r(const Geom& g, const S* __restrict__ in, size_t vstride,
                                           const S* __restrict__ U, int par, int h, const Coord& c,
                                           cx<T> (&a)[R][4][3], int dep) {
   if constexpr (I < 8) {
     HopRawR<S, NE, R> d;
-    hop_load_r<I, DAG, NE, R>(g, in, vstride, U, par, h, c, d, dep);
+    hop_load_r<I, DAG, NE, R, EO>(g, in, vstride, U, par, h, c, d, dep);
     hop_compute_r<I, DAG, NE, R>(d, a);
     reg_barrier_r<R>(a);
     int dep2 = 0;
     asm volatile("" : "+v"(dep2) : "v"(a[0][0][0].re));
     QCD_FENCE();
-    hop_seq_r<I + 1, DAG, NE, R>(g, in, vstride, U, par, h, c, a, dep2);
+    hop_seq_r<I + 1, DAG, NE, R, EO>(g, in, vstride, U, par, h, c, a, dep2);
   }
 }
 
@@ -693,11 +693,13 @@ __device__ __forceinline__ void block_reduce_store_R(double (&v)[R][NV], double*
   }
 }
 
-template <typename S, int OP, int EPI, int R, int NE>
+// EO as in k_dslash: one parity tpar of one-parity fields, centre term from cin.
+template <typename S, int OP, int EPI, int R, int NE, bool EO>
 __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched, S* __restrict__ out,
                                                       const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                       const S* __restrict__ aux, double* __restrict__ partials,
-                                                      const Scalars* __restrict__ scal, int ftz) {
+                                                      const Scalars* __restrict__ scal, int ftz,
+                                                      const S* __restrict__ cin, int tpar) {
   using T_ = typename Traits<S>::T;
   const BlockPos bp = block_pos(sched);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -710,9 +712,10 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
     any |= live[r];
   }
   if (!any) return;  // uniform over the block
-  const int par = wid & 1;
-  const int h = bp.h0 + (wid >> 1) * 64 + lane;
-  const size_t vs = spinor_elems(g);
+  const int par = EO ? tpar : (wid & 1);
+  const int h = EO ? bp.h0 + wid * 64 + lane : bp.h0 + (wid >> 1) * 64 + lane;
+  const int fpar = EO ? 0 : par;
+  const size_t vs = EO ? (size_t)g.nb * 768 : spinor_elems(g);
   const size_t vo = (size_t)r0 * vs;
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
@@ -731,18 +734,18 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
       for (int sp = 0; sp < 4; sp++)
 #pragma unroll
         for (int cc = 0; cc < 3; cc++) a[r][sp][cc] = cx<T_>(0, 0);
-    hop_seq_r<0, DAG, NE, R>(g, in + vo, vs, U, par, h, c, a, 0);
+    hop_seq_r<0, DAG, NE, R, EO>(g, in + vo, vs, U, par, h, c, a, 0);
     const T_ k = (T_)kappa;
     using Gr = typename Lay<S>::Gran;
     constexpr int C = Lay<S>::C;
 #pragma unroll
     for (int r = 0; r < R; r++) {
       if (!live[r]) continue;
-      const S* inr = in + vo + r * vs;
+      const S* inr = (EO ? cin : in) + vo + r * vs;
       const S* axr = aux ? aux + vo + r * vs : nullptr;
       cx<T_> o[12], ctr[12], ax[12];
-      if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(inr, g, par, h, ctr);
-      if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(axr, g, par, h, ax);
+      if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(inr, g, fpar, h, ctr);
+      if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(axr, g, fpar, h, ax);
 #pragma unroll
       for (int i = 0; i < 12; i++) {
         if constexpr (OP == kOpH || OP == kOpHdag) {
@@ -752,7 +755,7 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
           if constexpr (EPI == kEpiResid) o[i] = ax[i] - o[i];
         }
       }
-      S* ob = out + vo + r * vs + sp_block(g, par, h) + (h & 63) * C;
+      S* ob = out + vo + r * vs + sp_block(g, fpar, h) + (h & 63) * C;
       T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
 #pragma unroll
       for (int j = 0; j < Lay<S>::G; j++) {
@@ -861,15 +864,28 @@ template <typename S, int R, int NE>
 static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                              const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                              int ftz, const void* cin, int eo_par, hipStream_t st) {
-  const DslashSched sc = make_sched(g, tune.sched, 1, n / R, false);
+  const DslashSched sc = make_sched(g, tune.sched, 1, n / R, eo_par >= 0);
   dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
   const S* u = (const S*)U;
   const S* x = (const S*)aux;
-#define QCD_LAUNCH(OPV, EPIV)                                                                                   \
-  hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
-                     scal, ftz)
+  const S* ci = (const S*)cin;
+  if (eo_par >= 0) {
+#define QCD_LAUNCH_EO(OPV, EPIV)                                                                                 \
+  hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE, true>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
+                     scal, ftz, ci, eo_par)
+    if (op == kOpH) QCD_LAUNCH_EO(kOpH, kEpiNone);
+    else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
+    else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
+    else if (epi == kEpiTS) QCD_LAUNCH_EO(kOpD, kEpiTS);
+    else QCD_LAUNCH_EO(kOpD, kEpiResid);
+#undef QCD_LAUNCH_EO
+    return;
+  }
+#define QCD_LAUNCH(OPV, EPIV)                                                                                     \
+  hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE, false>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
+                     scal, ftz, nullptr, 0)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -893,7 +909,7 @@ template <typename S, int NE>
 static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                             int ftz, const void* cin, int eo_par, hipStream_t st) {
-  const int R = eo_par >= 0 ? 1 : reg_tile_for(tune, n);  // one-parity launches use lane tiles only
+  const int R = reg_tile_for(tune, n);
   if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
@@ -950,6 +966,16 @@ int reg_tile_for(const DslashTune& tune, int n) {
   return (R >= 2 && R <= 4 && n % R == 0) ? R : 1;
 }
 
+// The automatic choice (rhs_tile = 0) for n right-hand sides in precision
+// prec: FP16 is bound by instruction issue per site-RHS, so several
+// right-hand sides per thread pay (3 measured best at 32^3 x 64, then 2); FP32
+// and FP64 are bound by bandwidth and keep one per thread.
+DslashTune resolve_rhs_tile(const DslashTune& tune, int prec, int n) {
+  DslashTune t = tune;
+  if (t.rhs_tile == 0 && prec == kFP16 && n > 1) t.rhs_tile = (n % 3 == 0) ? -3 : ((n % 2 == 0) ? -2 : 1);
+  return t;
+}
+
 DslashSched make_sched(const Geom& g, int mode, int T, int n, bool eo) {
   DslashSched s;
   s.H = (eo ? 256 : 128) / T;  // half sites of one parity (eo) or of each parity per block
@@ -988,9 +1014,10 @@ int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo) {
   return (g.Vh + H - 1) / H;
 }
 
-void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
-                   const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
-                   hipStream_t st, const void* cin, int eo_par) {
+void launch_dslash(int prec, const Geom& g, const DslashTune& tune_in, int op, int epi, int n, void* out,
+                   const void* in, const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                   int ftz, hipStream_t st, const void* cin, int eo_par) {
+  const DslashTune tune = resolve_rhs_tile(tune_in, prec, n);
   if (prec == kFP64)
     launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else if (prec == kFP32)

@@ -10,6 +10,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import qcd_inputs as qi  # noqa: E402
+from oracle import evenodd as EO  # noqa: E402
 from oracle import solvers as S  # noqa: E402
 from gpu_common import TOL, compare, to_dev, to_host  # noqa: E402
 
@@ -177,7 +178,7 @@ def test_autotune_and_cache(q, tmp_path):
     g = q.gauge_upload(to_dev(U), dims)
     cache = str(tmp_path / "tune.jsonl")
     r1 = g.autotune(q.FP16, nrhs=4, reps=5, cache_path=cache)
-    assert r1[2] in (1, 2, 4) and r1[3] > 0
+    assert r1[2] in (1, 2, 4, -2, -4) and r1[3] > 0
     g.set_tuning(q.FP16, 0, 0, 1)
     r2 = g.autotune(q.FP16, nrhs=4, reps=5, cache_path=cache)   # read from the cache
     assert r2[:3] == r1[:3] and abs(r2[3] - r1[3]) < 1e-3
@@ -281,4 +282,74 @@ def test_register_tiles_in_the_batched_solver(q):
         xs.append(x)
     for x in xs[1:]:
         assert float((x - xs[0]).norm() / xs[0].norm()) < 1e-10
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_register_tiles_on_one_parity(q, prec):
+    # the Schur operator of the even-odd form (one-parity fields) with 6
+    # right-hand sides as tiles of 3 and of 2 per thread, against one per thread
+    # and the oracle
+    dims = (4, 6, 8, 10)
+    U = qi.gauge_field(dims, 0.3, 85)
+    psi = qi.gaussian_source(dims, 86, nrhs=6)
+    e = EO.even_mask(dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    x = to_dev(psi)
+    ref = torch.empty_like(x)
+    g.set_tuning(prec, 1, 0, 1)
+    q.dslash(g, 0.124, ref, x, op=q.OP_SCHUR, prec=prec)
+    for tile in (-3, -2):
+        out = torch.empty_like(x)
+        g.set_tuning(prec, 1, 0, tile)
+        q.dslash(g, 0.124, out, x, op=q.OP_SCHUR, prec=prec)
+        torch.cuda.synchronize()
+        if prec == 2:
+            same_to_one_fp16_ulp(out, ref)
+        else:
+            assert torch.equal(out, ref), tile
+        got = to_host(out)
+        for r in (0, 5):
+            compare(got[r][e], EO.schur(U, psi[r], 0.124, dims)[e], TOL[prec], f"schur tile {tile} rhs {r}")
+    g.close()
+
+
+def test_automatic_tile_is_a_register_tile_for_fp16(q):
+    # rhs_tile 0 (automatic) takes 3 per thread for FP16 when the count allows,
+    # else 2, else 1; FP32 keeps one per thread
+    dims = (8, 8, 8, 8)
+    U = qi.gauge_field(dims, 0.3, 87)
+    g = q.gauge_upload(to_dev(U), dims)
+    for n, tile in ((6, -3), (4, -2), (5, 1)):
+        x = to_dev(qi.gaussian_source(dims, 88 + n, nrhs=n))
+        auto, fixed = torch.empty_like(x), torch.empty_like(x)
+        g.set_tuning(q.FP16, 1, 0, 0)
+        q.dslash(g, 0.124, auto, x, prec=q.FP16)
+        g.set_tuning(q.FP16, 1, 0, tile)
+        q.dslash(g, 0.124, fixed, x, prec=q.FP16)
+        torch.cuda.synchronize()
+        assert torch.equal(auto, fixed), n
+    g.close()
+
+
+def test_register_tiles_in_the_even_odd_solver(q):
+    dims = (8, 8, 8, 8)
+    U = qi.gauge_field(dims, 0.3, 93)
+    bs = qi.gaussian_source(dims, 94, nrhs=6)
+    bs[4] *= 1e-4
+    g = q.gauge_upload(to_dev(U), dims)
+    b = to_dev(bs)
+    xs = []
+    for tile in (1, -2, -3):
+        g.set_tuning(q.FP16, 1, 0, tile)
+        x = torch.zeros_like(b)
+        infos = q.solve_mixed_ir(g, 0.12, x, b, inner_prec=q.FP16, tol=1e-12, even_odd=True)
+        assert all(i.true_rel_residual <= 1e-12 for i in infos)
+        xs.append(x)
+    for x in xs[1:]:
+        assert float((x - xs[0]).norm() / xs[0].norm()) < 1e-10
+    xh = to_host(xs[2])
+    for r in (0, 4):
+        res = bs[r] - oracle.dslash(U, xh[r], 0.12, dims)
+        assert np.linalg.norm(res) <= 1.01e-12 * np.linalg.norm(bs[r])
     g.close()
