@@ -24,7 +24,11 @@ reason in the design notes):
   inner right-hand side.
 * Alg. 5 returns the solution divided by the accumulated factor lambda'.
 * FP64 -> FP16 conversion is one round-to-nearest-even step (IEEE 754
-  format conversion), not two roundings through FP32.
+  format conversion), not two roundings through FP32.  The same holds for
+  BF16 (Table 1: 8 exponent bits, 7 fraction bits, e_min = -126), which has
+  no IEEE conversion of its own: the value is rounded once, to nearest even,
+  to 8 significant bits (subnormal below 2^-126), exactly as the other
+  formats are.
 """
 from __future__ import annotations
 
@@ -35,16 +39,39 @@ import numpy as np
 
 from . import OP_D, dslash
 
-FP64, FP32, FP16 = "fp64", "fp32", "fp16"
+FP64, FP32, FP16, BF16 = "fp64", "fp32", "fp16", "bf16"
 FP16_MIN_NORMAL = 2.0 ** -14  # smallest normal binary16 magnitude (Table 1: e_min = -14)
+BF16_MIN_NORMAL = 2.0 ** -126  # Table 1: e_min = -126
+BF16_SIGNIFICAND = 8           # Table 1: 7 fraction bits plus the implicit one
+BF16_EMAX = 127                # Table 1
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Nearest BF16 value of each FP64 number, ties to even mantissa.
+
+    A value in [2^E, 2^(E+1)) is a multiple of 2^(E - 7) in BF16; below
+    2^-126 the spacing stays 2^-133 (subnormals).  Results beyond the largest
+    finite value become infinities, as in IEEE rounding.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    out = x.copy()
+    fin = np.isfinite(x) & (x != 0)
+    v = x[fin]
+    _, e = np.frexp(v)                      # v = m 2^e with 1/2 <= |m| < 1, i.e. E = e - 1
+    q = np.maximum(e - BF16_SIGNIFICAND, -126 - (BF16_SIGNIFICAND - 1))
+    r = np.ldexp(np.rint(np.ldexp(v, -q)), q)   # np.rint rounds halves to even
+    big = np.abs(r) >= 2.0 ** (BF16_EMAX + 1)
+    r[big] = np.copysign(np.inf, r[big])
+    out[fin] = r
+    return out
 
 
 def lowp(v: np.ndarray, prec: str, ftz: bool = False) -> np.ndarray:
     """Round real and imaginary parts to the storage precision (RNE).
 
     Returns complex128 whose parts are exactly representable in ``prec``.
-    With ``ftz`` a binary16 result below the smallest normal becomes zero,
-    as with the flush-to-zero compilation of the paper's runs (Sec. 6).
+    With ``ftz`` a binary16 (BF16) result below the smallest normal becomes
+    zero, as with the flush-to-zero compilation of the paper's runs (Sec. 6).
     """
     v = np.asarray(v, dtype=np.complex128)
     if prec == FP64:
@@ -61,6 +88,12 @@ def lowp(v: np.ndarray, prec: str, ftz: bool = False) -> np.ndarray:
         out.real = re.astype(np.float64)
         out.imag = im.astype(np.float64)
         return out
+    if prec == BF16:
+        re, im = round_bf16(v.real), round_bf16(v.imag)
+        if ftz:
+            re = np.where(np.abs(re) < BF16_MIN_NORMAL, 0.0 * re, re)
+            im = np.where(np.abs(im) < BF16_MIN_NORMAL, 0.0 * im, im)
+        return re + 1j * im
     raise ValueError(f"unknown precision {prec!r}")
 
 

@@ -10,7 +10,11 @@
   correction factor of Alg. 2/3);
 * s^ differs from s by FP16 rounding only, and the zero count of the first
   inner input for b = e_0 is what the paper prints (Sec. 6, Fig. 9 text);
-* storage rounding matches IEEE binary16 values of Table 1.
+* storage rounding matches IEEE binary16 values of Table 1, and BF16
+  rounding (Table 1's format) matches the conversion of a library (torch's
+  bfloat16, float32 inputs) and hand-derived ties;
+* the BF16-inner refinement (the comparison the paper's conclusion proposes)
+  reaches the FP64 solution.
 """
 import math
 import os
@@ -59,6 +63,53 @@ def test_binary16_rounding_matches_table1():
     assert d[0] == 1 + 2.0 ** -10
     e32 = S.lowp(np.array([1 + 2.0 ** -24, 1 + 3 * 2.0 ** -24], complex), S.FP32).real
     assert e32[0] == 1.0 and e32[1] == 1 + 2.0 ** -22
+
+
+def test_bf16_rounding_matches_table1_and_a_library():
+    f = paper_facts()
+    fb = int(f["bf16_fraction_bits"])
+    eps = 2.0 ** -fb
+    # ties to even at 1 + eps/2 and 1 + 3 eps/2; just above a tie rounds up
+    # even when FP32 could not hold the excess (one rounding from FP64)
+    t = S.lowp(np.array([1 + eps / 2, 1 + 3 * eps / 2, 1 + eps / 2 + 2.0 ** -40, -(1 + eps / 2 + 2.0 ** -40)],
+                        complex), S.BF16).real
+    assert t[0] == 1.0 and t[1] == 1 + 2 * eps and t[2] == 1 + eps and t[3] == -(1 + eps)
+    emin, emax = int(f["bf16_emin"]), int(f["bf16_emax"])
+    top = (2 - eps) * 2.0 ** emax
+    r = S.round_bf16(np.array([top, top * (1 + 2.0 ** -10), top + 2.0 ** (emax - fb - 1), 2.0 ** emin,
+                               2.0 ** (emin - fb), 2.0 ** (emin - fb - 1), 3 * 2.0 ** (emin - fb - 1)]))
+    assert r[0] == top and r[1] == top and np.isinf(r[2])    # the tie above the largest value overflows
+    assert r[3] == 2.0 ** emin                                 # smallest normal
+    assert r[4] == 2.0 ** (emin - fb)                          # smallest subnormal
+    assert r[5] == 0.0 and r[6] == 2.0 ** (emin - fb + 1)      # ties to even among subnormals
+    z = S.lowp(np.array([2.0 ** (emin - 1), 2.0 ** emin], complex), S.BF16, ftz=True).real
+    assert z[0] == 0.0 and z[1] == 2.0 ** emin
+    # a library's float32 -> bfloat16 conversion (round to nearest even) on
+    # values exactly representable in float32, ties included
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    v = (rng.standard_normal(20000) * np.exp(rng.uniform(-60, 60, 20000))).astype(np.float32)
+    bits = v.view(np.uint32)
+    v = np.concatenate([v, ((bits & ~np.uint32(0xFFFF)) | np.uint32(0x8000)).view(np.float32)])   # exact ties
+    lib = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    mine = S.round_bf16(v.astype(np.float64))
+    assert np.array_equal(lib, mine)
+
+
+def test_bf16_inner_refinement_matches_fp64():
+    dims = (4, 4, 4, 8)
+    U = qi.gauge_field(dims, 0.3, 97)
+    b = qi.gaussian_source(dims, 98)
+    k = 0.12
+    x64, _ = S.solve_fp64(U, k, dims, b, tol=1e-14)
+    for s, sig in [(1.0, None), (128.0, 64.0)]:
+        x, info = S.solve_mixed_ir(U, k, dims, b, inner_prec=S.BF16, s=s, sigma=sig, recalc_shat=(s != 1.0))
+        assert info.converged and info.true_rel_residual <= 1e-12
+        r = b - oracle.dslash(U, x, k, dims)
+        assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-12
+        assert np.linalg.norm(x - x64) / np.linalg.norm(x64) < 1e-10
+        # the stored inner right-hand side is the BF16 rounding of the rescaled residual
+        assert abs(info.shat_over_s[0] - 1) < 2.0 ** -8
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 3, 4, 5)])
