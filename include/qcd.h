@@ -52,7 +52,11 @@ typedef enum {
   QCD_ERR_BREAKDOWN = -6   /* BiCGStab breakdown: rho = (r*, r) = 0 or (r*, A p) = 0 */
 } qcd_status;
 
-typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2 } qcd_prec;
+/* Storage precisions of fields and links (Table 1).  FP16 and BF16 store a
+ * complex number as two 16-bit halves of one 32-bit word; arithmetic on them
+ * is FP32.  BF16 (8 exponent bits, 7 fraction bits) is the alternative inner
+ * format the paper's conclusion proposes to compare. */
+typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2, QCD_BF16 = 3 } qcd_prec;
 /* Flag for qcd_gauge_upload's prec_mask: store all 18 reals of every link
  * even when the field is in SU(3). */
 enum { QCD_LINKS_FULL = 1 << 8 };
@@ -73,7 +77,7 @@ typedef struct {
   double sigma_lambda; /* rescale the solution to norm sigma_lambda (Alg. 5); 0 = off */
   int recalc_gamma;    /* 1: gamma is the measured ratio |r stored| / |r before rescaling| */
   double omega0;       /* omega prescription threshold; the paper uses 0.7; 0 disables */
-  int ftz;             /* 1: a binary16 store below 2^-14 in magnitude is flushed to zero */
+  int ftz;             /* 1: a binary16 store below 2^-14 (BF16: 2^-126) in magnitude is flushed to zero */
   int check_every;     /* > 0: host polls the convergence flag every this many iterations; 0: adaptive
                           (first poll after 4, then after the number the convergence rate predicts) */
   int use_graph;       /* 1: one iteration is captured in a hip graph (on a stream the handle owns) and
@@ -91,7 +95,7 @@ typedef struct {
 typedef struct {
   double tol;               /* stop when |b - D x|_2 / |b|_2 <= tol, checked in FP64 */
   int max_outer;            /* outer iteration cap (> 0) */
-  qcd_prec inner_prec;      /* storage precision of the inner solve (FP16, FP32 or FP64) */
+  qcd_prec inner_prec;      /* storage precision of the inner solve (FP16, BF16, FP32 or FP64) */
   double s;                 /* the residual is rescaled to norm s before conversion */
   int recalc_shat;          /* 1: correct with s^ = |single(y~)| (Alg. 3); 0: with s */
   qcd_bicgstab_params inner;/* inner.tol is eps_tol (the paper's eps_tol^2 = 1e-4 is tol = 1e-2) */
@@ -132,10 +136,10 @@ const char* qcd_last_error(void);
 
 /* Gauge upload.  Converts the canonical FP64 field U_dev (complex128
  * [V][4][3][3], device) to native copies in the precisions selected by
- * prec_mask (bit (1 << QCD_FP64) etc.; 0 selects all three; the FP64 copy
+ * prec_mask (bit (1 << QCD_FP64) etc.; 0 selects all four; the FP64 copy
  * is always built because the outer refinement needs it).  The handle owns
  * those copies and a reusable workspace; free it with qcd_gauge_free.
- * FP64 -> FP32/FP16 rounding is one round-to-nearest-even step.
+ * FP64 -> FP32/FP16/BF16 rounding is one round-to-nearest-even step.
  * Implements the low-precision matrix A~ of Alg. 3 (links stored in the
  * inner precision).  Synchronises with stream.  Errors: QCD_ERR_ARG for a
  * null pointer or an odd / < 2 extent, QCD_ERR_HIP on allocation failure. */
@@ -143,7 +147,7 @@ qcd_status qcd_gauge_upload(qcd_gauge** g, const int dims[4], const void* U_dev,
 qcd_status qcd_gauge_free(qcd_gauge* g);
 /* Reals stored per link in precision prec: 12 when every link passed the
  * SU(3) check at upload (row 2 equals conj(row0 x row1) to within 1e-14,
- * 1e-7, 1e-4 for FP64, FP32, FP16; the kernels rebuild row 2, which saves a
+ * 1e-7, 1e-4, 1e-3 for FP64, FP32, FP16, BF16; the kernels rebuild row 2, which saves a
  * third of the link bytes), 18 otherwise or with QCD_LINKS_FULL; 0 if the
  * handle holds no links in prec. */
 int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);

@@ -25,8 +25,9 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-FP64, FP32, FP16 = 0, 1, 2
-PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, FP64: FP64, FP32: FP32, FP16: FP16}
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16, FP64: FP64, FP32: FP32, FP16: FP16,
+        BF16: BF16}
 CANONICAL, NATIVE = 0, 1
 LINKS_FULL = 1 << 8
 OP_D, OP_H, OP_DDAG, OP_HDAG, OP_SCHUR = 0, 1, 2, 3, 4
@@ -136,7 +137,7 @@ class Gauge:
     """A gauge field uploaded to the device in the native layout (FP64 plus
     the selected low-precision copies)."""
 
-    def __init__(self, U: torch.Tensor, dims, precs=(FP64, FP32, FP16), full_links=False):
+    def __init__(self, U: torch.Tensor, dims, precs=(FP64, FP32, FP16, BF16), full_links=False):
         U = _as_c128(U)
         self.dims = tuple(int(d) for d in dims)
         mask = LINKS_FULL if full_links else 0
@@ -199,7 +200,7 @@ class Gauge:
         return torch.empty(self.spinor_bytes(prec) * nrhs, dtype=torch.uint8, device="cuda")
 
 
-def gauge_upload(U, dims, precs=(FP64, FP32, FP16), full_links=False) -> Gauge:
+def gauge_upload(U, dims, precs=(FP64, FP32, FP16, BF16), full_links=False) -> Gauge:
     return Gauge(U, dims, precs, full_links)
 
 

@@ -20,6 +20,7 @@ LIB = os.path.join(PKG, "libqcd.so")
 # (source, object, extra flags): the Wilson operator is built once per storage
 # precision so that its many kernel instantiations compile in parallel
 SOURCES = [("dslash.hip", "dslash_f16.o", ["-DQCD_DSLASH_PREC=2"]),
+           ("dslash.hip", "dslash_bf16.o", ["-DQCD_DSLASH_PREC=3"]),
            ("dslash.hip", "dslash_f32.o", ["-DQCD_DSLASH_PREC=1"]),
            ("dslash.hip", "dslash_f64.o", ["-DQCD_DSLASH_PREC=0"]),
            ("blas.hip", "blas.o", []), ("api.hip", "api.o", []), ("ptc.hip", "ptc.o", [])]

@@ -57,8 +57,8 @@ size_t spinor_bytes(const Geom& g, int prec) { return spinor_elems(g) * prec_com
 size_t canon_bytes(const Geom& g) { return (size_t)2 * g.Vh * 12 * 16; }
 int max_rows(const Geom& g, const DslashTune* tune, int n) {
   int rows = site_grid(g);
-  for (int p = 0; p < 3; p++) rows = std::max(rows, flat_rows(g, p));
-  for (int p = 0; p < 3; p++) rows = std::max(rows, dslash_partial_rows(g, tune[p], n));
+  for (int p = 0; p < kNumPrec; p++) rows = std::max(rows, flat_rows(g, p));
+  for (int p = 0; p < kNumPrec; p++) rows = std::max(rows, dslash_partial_rows(g, tune[p], n));
   return rows;
 }
 
@@ -184,7 +184,7 @@ qcd_status get_work(const qcd_gauge* gc, int what, int prec, int max_iter, int n
   return QCD_OK;
 }
 
-bool valid_prec(int p) { return p == kFP64 || p == kFP32 || p == kFP16; }
+bool valid_prec(int p) { return p == kFP64 || p == kFP32 || p == kFP16 || p == kBF16; }
 
 qcd_status check_gauge(const qcd_gauge* g, int prec) {
   if (!g) return fail(QCD_ERR_ARG, "null gauge handle");
@@ -517,9 +517,9 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
     if (dims[i] < 2 || dims[i] % 2) return fail(QCD_ERR_ARG, "extent %d of direction %d must be even and >= 2", dims[i], i);
   const long long V = (long long)dims[0] * dims[1] * dims[2] * dims[3];
   if (V / 2 >= (1ll << 30)) return fail(QCD_ERR_ARG, "lattice too large");
-  const int flags = prec_mask & ~7;
-  prec_mask &= 7;
-  if (prec_mask == 0) prec_mask = 7;
+  const int flags = prec_mask & ~15;
+  prec_mask &= 15;
+  if (prec_mask == 0) prec_mask = 15;
   prec_mask |= 1 << kFP64;
   qcd_gauge* g = new qcd_gauge();
   memset(g, 0, sizeof(*g));
@@ -530,6 +530,7 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   g->tune[kFP64] = DslashTune{1, 0, 0, 0};
   g->tune[kFP32] = DslashTune{1, 1, 0, 0};
   g->tune[kFP16] = DslashTune{1, 1, 0, 0};
+  g->tune[kBF16] = DslashTune{1, 1, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);
   qcd_status rc = QCD_OK;
@@ -551,10 +552,10 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
       delete g;
       return fail(QCD_ERR_HIP, "link check failed: %s", hipGetErrorString(e));
     }
-    const double thr[3] = {1e-14, 1e-7, 1e-4};
-    for (int p = 0; p < 3; p++) g->tune[p].recon = g->su3_dev <= thr[p];
+    const double thr[kNumPrec] = {1e-14, 1e-7, 1e-4, 1e-3};
+    for (int p = 0; p < kNumPrec; p++) g->tune[p].recon = g->su3_dev <= thr[p];
   }
-  for (int p = 0; p < 3 && rc == QCD_OK; p++) {
+  for (int p = 0; p < kNumPrec && rc == QCD_OK; p++) {
     if (!(prec_mask & (1 << p))) continue;
     size_t bytes = link_elems(g->g, g->tune[p].recon ? 6 : 9) * prec_complex_bytes(p);
     if (hipMalloc(&g->U[p], bytes) != hipSuccess) {
@@ -580,7 +581,7 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
 
 qcd_status qcd_gauge_free(qcd_gauge* g) {
   if (!g) return QCD_OK;
-  for (int p = 0; p < 3; p++)
+  for (int p = 0; p < kNumPrec; p++)
     if (g->U[p]) (void)hipFree(g->U[p]);
   if (g->ws) (void)hipFree(g->ws);
   if (g->host_sc) (void)hipHostFree(g->host_sc);

@@ -22,7 +22,7 @@ template <typename S> static int flat_grid(const Geom& g) {
   return (int)(b < (size_t)kFlatBlocks ? b : (size_t)kFlatBlocks);
 }
 int flat_rows(const Geom& g, int prec) {
-  return prec == kFP64 ? flat_grid<double2>(g) : (prec == kFP32 ? flat_grid<float2>(g) : flat_grid<__half2>(g));
+  return prec == kFP64 ? flat_grid<double2>(g) : (prec == kFP32 ? flat_grid<float2>(g) : flat_grid<__half2>(g));  // BF16 as FP16
 }
 
 struct SiteId { int par, h; bool valid; };
@@ -584,6 +584,7 @@ __global__ __launch_bounds__(256) void k_widen(Geom g, double2* __restrict__ dst
   do {                                                  \
     if ((prec) == kFP64) FN<double2>(__VA_ARGS__);      \
     else if ((prec) == kFP32) FN<float2>(__VA_ARGS__);  \
+    else if ((prec) == kBF16) FN<bf2>(__VA_ARGS__);     \
     else FN<__half2>(__VA_ARGS__);                      \
   } while (0)
 

@@ -66,12 +66,46 @@ template <> struct Traits<__half2> {
   }
 };
 
+// BF16 storage (Table 1: 8 exponent bits, 7 fraction bits): one complex is
+// two bfloat16 halves of a 32-bit word, like FP16; arithmetic on it is FP32.
+struct alignas(4) bf2 {
+  __bf16 x, y;
+};
+constexpr float kBf16MinNormal = 1.17549435e-38f;  // 2^-126
+template <> struct Traits<bf2> {
+  using T = float;
+  static __device__ __forceinline__ cx<float> load(const bf2* p) {
+    const bf2 v = *p;
+    return {(float)v.x, (float)v.y};
+  }
+  // Round to nearest even; with ftz set, a result below 2^-126 in magnitude
+  // is replaced by a zero of the same sign.
+  static __device__ __forceinline__ bf2 pack(cx<float> v, int ftz) {
+    bf2 b{(__bf16)v.re, (__bf16)v.im};
+    if (ftz) {
+      if (fabsf((float)b.x) < kBf16MinNormal) b.x = (__bf16)copysignf(0.0f, v.re);
+      if (fabsf((float)b.y) < kBf16MinNormal) b.y = (__bf16)copysignf(0.0f, v.im);
+    }
+    return b;
+  }
+};
+
 // FP64 value -> stored format: one round-to-nearest-even conversion
 // (for FP16 the compiler emits a correctly rounded FP64 -> FP16 sequence).
 template <typename S> __device__ __forceinline__ S pack_from_double(double re, double im, int ftz);
 template <> __device__ __forceinline__ double2 pack_from_double<double2>(double re, double im, int) { return make_double2(re, im); }
 template <> __device__ __forceinline__ float2 pack_from_double<float2>(double re, double im, int) {
   return make_float2((float)re, (float)im);
+}
+// FP64 -> BF16 in one rounding (the compiler rounds to FP32 with the
+// round-to-odd rule first, which makes the second rounding exact).
+template <> __device__ __forceinline__ bf2 pack_from_double<bf2>(double re, double im, int ftz) {
+  bf2 b{(__bf16)re, (__bf16)im};
+  if (ftz) {
+    if (fabsf((float)b.x) < kBf16MinNormal) b.x = (__bf16)copysignf(0.0f, (float)re);
+    if (fabsf((float)b.y) < kBf16MinNormal) b.y = (__bf16)copysignf(0.0f, (float)im);
+  }
+  return b;
 }
 template <> __device__ __forceinline__ __half2 pack_from_double<__half2>(double re, double im, int ftz) {
   __half2 h = __half2{_Float16_2{static_cast<_Float16>(re), static_cast<_Float16>(im)}};
@@ -108,7 +142,7 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return (__umul
 // (x,y,z,t) has half index h = (x>>1) + Lx/2*(y + Ly*(z + Lz*t)).  Half
 // indices are grouped in blocks of 64 (one wavefront).  Each block stores its
 // complex components in 16-byte granules: with C = 16 / sizeof(stored
-// complex) components per granule (4 for FP16, 2 for FP32, 1 for FP64),
+// complex) components per granule (4 for FP16 and BF16, 2 for FP32, 1 for FP64),
 // granule row j holds components [jC, jC+C) of the 64 sites, lane-major, so
 // that lane i of a wave reading row j issues one 16-byte load at
 // (block*12*64 + j*64*C + i*C) and the wave reads one contiguous 1 KB

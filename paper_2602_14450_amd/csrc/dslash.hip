@@ -790,8 +790,8 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
   if constexpr (EPI != kEpiNone) block_reduce_store_R<NV, R>(red, partials, r0, sched.nsb, bp.sb);
 }
 
-// One translation unit per storage precision (QCD_DSLASH_PREC = 0, 1, 2 for
-// FP64, FP32, FP16) keeps the kernel instantiations of a build parallel; the
+// One translation unit per storage precision (QCD_DSLASH_PREC = 0, 1, 2, 3 for
+// FP64, FP32, FP16, BF16) keeps the kernel instantiations of a build parallel; the
 // FP16 unit also holds the precision-independent helpers and the dispatcher.
 #ifndef QCD_DSLASH_PREC
 #define QCD_DSLASH_PREC 2
@@ -939,6 +939,7 @@ static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int e
 void launch_dslash_f64(QCD_DSLASH_ARGS);
 void launch_dslash_f32(QCD_DSLASH_ARGS);
 void launch_dslash_f16(QCD_DSLASH_ARGS);
+void launch_dslash_bf16(QCD_DSLASH_ARGS);
 
 #if QCD_DSLASH_PREC == 0
 void launch_dslash_f64(QCD_DSLASH_ARGS) {
@@ -947,6 +948,10 @@ void launch_dslash_f64(QCD_DSLASH_ARGS) {
 #elif QCD_DSLASH_PREC == 1
 void launch_dslash_f32(QCD_DSLASH_ARGS) {
   launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+}
+#elif QCD_DSLASH_PREC == 3
+void launch_dslash_bf16(QCD_DSLASH_ARGS) {
+  launch_dslash_t<bf2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }
 #else
 void launch_dslash_f16(QCD_DSLASH_ARGS) {
@@ -1022,6 +1027,8 @@ void launch_dslash(int prec, const Geom& g, const DslashTune& tune_in, int op, i
     launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else if (prec == kFP32)
     launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  else if (prec == kBF16)
+    launch_dslash_bf16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else
     launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
 }

@@ -6,7 +6,8 @@
 
 namespace qcd {
 
-enum { kFP64 = 0, kFP32 = 1, kFP16 = 2 };
+enum { kFP64 = 0, kFP32 = 1, kFP16 = 2, kBF16 = 3 };
+constexpr int kNumPrec = 4;
 enum { kOpD = 0, kOpH = 1, kOpDdag = 2, kOpHdag = 3 };
 enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3, kEpiTSAux = 4 };
 
@@ -19,7 +20,7 @@ constexpr int kPtcMaxLayers = 4;  // layers of the parallel-transport network
 // Record an error message for qcd_last_error(); returns code.
 int set_error(int code, const char* fmt, ...);
 
-inline size_t prec_complex_bytes(int prec) { return prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4); }
+inline size_t prec_complex_bytes(int prec) { return prec == kFP64 ? 16 : (prec == kFP32 ? 8 : 4); }  // FP16, BF16: 4
 
 // Scalars of the rescaled BiCGStab (Alg. 4 / Alg. 5) and of the outer
 // refinement (Alg. 2 / Alg. 3), all FP64, resident in device memory.
@@ -144,11 +145,11 @@ const qcd_gauge* ptc_gauge(const qcd_ptc* n);
 struct qcd_gauge {
   qcd::Geom g;
   int dims[4];
-  void* U[3];        // native links per precision (FP64, FP32, FP16)
+  void* U[qcd::kNumPrec];  // native links per precision (FP64, FP32, FP16, BF16)
   void* ws;          // cached workspace used when the caller passes none
   size_t ws_bytes;
   qcd::Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
-  qcd::DslashTune tune[3];
+  qcd::DslashTune tune[qcd::kNumPrec];
   // one captured BiCGStab iteration, reused while its key is unchanged
   hipStream_t cap_stream;
   hipGraphExec_t graph_exec;

@@ -25,7 +25,7 @@ OPS = [0, 1, 2, 3]
 
 
 @pytest.mark.parametrize("dims", SHAPES)
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_dslash_all_ops(q, dims, prec):
     U, psi = fields(dims, gseed=11 + sum(dims), sseed=12)
     g = q.gauge_upload(to_dev(U), dims)
@@ -44,7 +44,7 @@ def test_dslash_native_layout_and_bitwise_rerun(q):
     dims = (4, 6, 8, 10)
     U, psi = fields(dims)
     g = q.gauge_upload(to_dev(U), dims)
-    for prec in (0, 1, 2):
+    for prec in (0, 1, 2, 3):
         a = g.native_spinor(prec)
         b1 = g.native_spinor(prec)
         b2 = g.native_spinor(prec)
@@ -59,7 +59,7 @@ def test_dslash_native_layout_and_bitwise_rerun(q):
     g.close()
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_convert_is_bit_exact(q, prec):
     dims = (2, 4, 6, 10)
     U, psi = fields(dims)
@@ -71,7 +71,7 @@ def test_convert_is_bit_exact(q, prec):
         back = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
         q.unconvert(g, prec, back, nat)
         torch.cuda.synchronize()
-        want = S.lowp(scale * psi, S.FP32 if prec == 1 else S.FP16, ftz=ftz)
+        want = S.lowp(scale * psi, {1: S.FP32, 2: S.FP16, 3: S.BF16}[prec], ftz=ftz)
         got = to_host(back)
         assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), f"scale={scale} ftz={ftz}"
         assert abs(n2 - S.norm2(want)) <= 1e-6 * S.norm2(want)
@@ -106,7 +106,7 @@ def test_invalid_arguments(q):
     g.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_dslash_full_size_sampled(q, prec):
     # The benchmark lattice 32^3 x 64 in the launch configuration the
     # benchmark times (native layout); outputs compared at sampled sites.
@@ -129,7 +129,7 @@ def test_dslash_full_size_sampled(q, prec):
     g.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_su3_links_stored_as_two_rows(q, prec):
     # generated links are SU(3): 12 reals per link, same operator as the
     # full 18-real storage within the precision's tolerance, both against the oracle
@@ -150,7 +150,7 @@ def test_su3_links_stored_as_two_rows(q, prec):
     g18.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_u3_links_keep_all_entries(q, prec):
     # a U(3) field (SU(3) times a site-dependent phase) fails the SU(3) check:
     # all 18 reals are kept and the operator still matches the oracle
@@ -166,4 +166,30 @@ def test_u3_links_keep_all_entries(q, prec):
         q.dslash(g, 0.124, out, x, op=op, prec=prec)
         torch.cuda.synchronize()
         compare(to_host(out), oracle.dslash(U, psi, 0.124, dims, op), TOL[prec], f"U(3) prec={prec} op={op}")
+    g.close()
+
+
+def test_bf16_operator_is_the_rounded_exact_operator(q):
+    # With all 18 reals stored, the BF16 operator computes in FP32 on the
+    # BF16-rounded links and input and rounds the result once: every element
+    # is the oracle's FP64 operator on the same rounded inputs, rounded to BF16,
+    # or (where FP32 summation decides a near-tie) its neighbour.
+    dims = (4, 6, 8, 10)
+    U, psi = fields(dims, gseed=77, sseed=78)
+    Ub, pb = S.lowp(U, S.BF16), S.lowp(psi, S.BF16)
+    g = q.gauge_upload(to_dev(U), dims, full_links=True)
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    for op in OPS:
+        q.dslash(g, 0.124, out, x, op=op, prec=q.BF16)
+        torch.cuda.synchronize()
+        got = to_host(out).reshape(-1)
+        want = S.lowp(oracle.dslash(Ub, pb, 0.124, dims, op), S.BF16).reshape(-1)
+        rms = np.sqrt(np.mean(np.abs(want) ** 2))
+        for a, b in ((got.real, want.real), (got.imag, want.imag)):
+            ulp = np.ldexp(1.0, np.frexp(np.abs(b))[1] - 8)
+            d = np.abs(a - b)
+            # FP32 sums of terms of size ~rms: 1e-6 rms absolute on top of one BF16 unit
+            assert np.all(d <= ulp + 1e-6 * rms), f"op={op}: {np.max(d / ulp):.2f} ulp"
+            assert np.count_nonzero(d) <= max(4, a.size // 200), f"op={op}: {np.count_nonzero(d)} of {a.size} differ"
     g.close()

@@ -25,7 +25,7 @@ SHAPES = [(4, 6, 8, 10), (8, 8, 8, 8), (2, 4, 6, 8)]
 
 
 @pytest.mark.parametrize("dims", SHAPES)
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_schur_operator_matches_oracle(q, dims, prec):
     kappa = 0.124
     U = qi.gauge_field(dims, 0.3, 700 + sum(dims))
@@ -60,7 +60,7 @@ def test_bicgstab_even_odd_fp64(q):
     g.close()
 
 
-@pytest.mark.parametrize("inner_prec", [1, 2])
+@pytest.mark.parametrize("inner_prec", [1, 2, 3])
 def test_refinement_even_odd(q, inner_prec):
     dims = (8, 8, 8, 8)
     kappa = 0.12
