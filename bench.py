@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-12 residual + Dslash HBM GB/s at 32^3x64, FP16-inner vs FP64 BiCGStab"
 PEAK_HBM_GBS = 8000.0
-DSLASH_BYTES = {0: 960, 1: 480, 2: 240}    # algorithmic bytes per site: links + input + output
+DSLASH_BYTES = {0: 960, 1: 480, 2: 240, 3: 240}    # algorithmic bytes per site: links + input + output
 DSLASH_FLOP_PER_SITE = 1368                 # 8 hops x 168 - 24 + 48 for 1 - kappa H
 
 
@@ -258,7 +258,7 @@ def main():
     max_iter = 20000
 
     tuned = {}
-    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+    for prec, name in ((q.FP16, "fp16"), (q.BF16, "bf16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
         if args.autotune:
             g.autotune(prec, nrhs=1, reps=10)
         tuned[name] = list(g.get_tuning(prec)) + [g.link_reals(prec)]
@@ -266,7 +266,7 @@ def main():
     # Wilson operator roofline (dominant kernel of the inner solve), timed
     # before the solver workspaces are allocated
     dsl = {}
-    for prec, name in ((q.FP16, "fp16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
+    for prec, name in ((q.FP16, "fp16"), (q.BF16, "bf16"), (q.FP32, "fp32"), (q.FP64, "fp64")):
         ms = time_dslash(q, torch, g, prec, args.dslash_reps, V)
         gbs = DSLASH_BYTES[prec] * V / (ms * 1e-3) / 1e9
         dsl[name] = dict(us=ms * 1e3, GBps=gbs, frac=gbs / PEAK_HBM_GBS,
@@ -292,6 +292,12 @@ def main():
     def solve_fp32(e=eo):
         return q.solve_mixed_ir(g, k, x, bd, inner_prec=q.FP32, s=1.0, recalc_shat=False, sigma=0.0, tol=1e-12,
                                 inner_tol=1e-2, inner_max_iter=max_iter, workspace=ws32[e], even_odd=e)
+
+    def solve_lowp(prec, s_, sigma, e=eo):
+        wsl = ws[e] if prec in (q.FP16, q.BF16) else ws32[e]
+        return q.solve_mixed_ir(g, k, x, bd, inner_prec=prec, s=s_, recalc_shat=(s_ != 1.0), sigma=sigma,
+                                tol=1e-12, inner_tol=1e-2, inner_max_iter=max_iter, workspace=wsl, even_odd=e,
+                                raise_on_error=False)
 
     def solve_fp64(e=eo):
         return q.bicgstab(g, k, x, bd, prec=q.FP64, tol=1e-12, max_iter=max_iter, workspace=ws64[e], history=False,
@@ -326,6 +332,21 @@ def main():
     others["fp16_inner_ir"] = dict(seconds=s_per_solve, outer=i16.outer_iters, iters=i16.inner_iters,
                                    matvec_low=i16.matvec_low, matvec_fp64=i16.matvec_fp64,
                                    true_rel_residual=i16.true_rel_residual)
+    # BF16 storage in the inner solve (the comparison the paper's conclusion
+    # proposes), with the headline's rescaling and with none, beside FP16 without
+    for name, prec, s_, sigma in (("bf16_inner_ir", q.BF16, 128.0, 64.0), ("bf16_inner_ir_s1_nosigma", q.BF16, 1.0, 0.0),
+                                  ("fp16_inner_ir_s1_nosigma", q.FP16, 1.0, 0.0)):
+        solve_lowp(prec, s_, sigma)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        inf = solve_lowp(prec, s_, sigma)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - ts
+        others[name] = dict(seconds=te, outer=inf.outer_iters, iters=inf.inner_iters, matvec_low=inf.matvec_low,
+                            matvec_fp64=inf.matvec_fp64, true_rel_residual=inf.true_rel_residual, status=inf.status,
+                            s=s_, sigma=sigma)
+        print(f"[bench] {name}: {te*1e3:.2f} ms, outer={inf.outer_iters} iters={inf.inner_iters} "
+              f"status={inf.status}", file=sys.stderr, flush=True)
     # the same three solvers on the other form (full matrix if the headline is even-odd)
     other_form = {}
     for name, fn in (("fp16_inner_ir", solve_fp16), ("fp64_bicgstab", solve_fp64), ("fp32_inner_ir", solve_fp32)):
@@ -413,6 +434,10 @@ def main():
                  and r["s"] in (1.0, 128.0, 4096.0) and r["sigma"] in (0.0, 64.0)}
         zeros["fp32_inner"] = [round(z, 4) for z in st["fp32_reference"]["zero_fraction"]]
         rescaling = dict(fp16_matvecs=grid, zero_fraction_per_step=zeros, source=st["source"], ftz=st["ftz"],
+                         bf16_matvecs={f"s={r['s']:g},sigma={r['sigma']:g}": r["matvecs"] for r in st["bf16"]},
+                         bf16_zero_fraction_per_step={f"s={r['s']:g},sigma={r['sigma']:g}":
+                                                      [round(z, 4) for z in (r.get("zero_fraction") or [])]
+                                                      for r in st["bf16"]},
                          seconds=time.perf_counter() - ts)
         print(f"[bench] rescaling study: {len(st['records'])} solves in {rescaling['seconds']:.1f} s",
               file=sys.stderr, flush=True)
