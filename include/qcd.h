@@ -161,8 +161,10 @@ int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
  * computed and the minimum waves per SIMD the kernel is compiled for:
  * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4).
  * rhs_tile (0 = automatic, 1, 2, 4) is the number of right-hand sides whose
- * lanes share one wave's link loads in a multi-RHS application (it must divide
- * nrhs, else 1 is used).  Results do not depend on these choices. */
+ * lanes share one wave's link loads in a multi-RHS application, -2, -3, -4 the
+ * number a thread applies one loaded link to (it must divide nrhs, else 1 is
+ * used; automatic takes 3 or 2 per thread for FP16 and 1 otherwise).  Results
+ * do not depend on these choices beyond FP16 rounding of the register tiles. */
 qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile);
 qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile);
 

@@ -86,12 +86,12 @@ struct Work {
   void* t = nullptr;
   void* z = nullptr;        // M p and M s of the preconditioned iteration
   double2* x64b = nullptr;  // x before a preconditioned refinement step
-  // even-odd solve (eq. (4)-(6)): inner vectors, r64, x64 (= x_e) are even-parity
-  // fields; t1 / t64 hold H_oe of a vector (odd parity); b64 and xf64 are full fields
+  // even-odd solve (eq. (4)-(6)): every vector is a one-parity field; inner
+  // vectors, r64, x64 (= x_e) and eta_e are even, eta_o and x64o (= x_o) odd;
+  // t1 / t64 hold H_oe of a vector
   bool eo = false;
   void* t1 = nullptr;
-  double2 *eta_e = nullptr, *eta_o = nullptr, *bp64 = nullptr, *t64 = nullptr, *x64o = nullptr, *xf64 = nullptr,
-          *rf64 = nullptr;
+  double2 *eta_e = nullptr, *eta_o = nullptr, *bp64 = nullptr, *t64 = nullptr, *x64o = nullptr;
   double* partials = nullptr;
   Scalars* sc = nullptr;
   double* history = nullptr;
@@ -114,9 +114,6 @@ Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char*
   if (eo && (what == 0 || what == 1)) {
     const Geom gh = half_geom(g);
     w.eo = true;
-    w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
-    w.xf64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
-    w.rf64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.eta_e = (double2*)c.take(n * spinor_bytes(gh, kFP64));
     w.eta_o = (double2*)c.take(n * spinor_bytes(gh, kFP64));
     w.bp64 = (double2*)c.take(n * spinor_bytes(gh, kFP64));
@@ -301,29 +298,39 @@ int residual_rows(const qcd_gauge* g, const Work& w) {
   return dslash_partial_rows(g->g, g->tune[kFP64], w.n, w.eo);
 }
 
-// Even-odd set-up from the full FP64 source in b64: eta_e, eta_o and the
-// right-hand side b' = eta_e + kappa H_eo eta_o of eq. (4)-(6) (D_ee = D_oo = 1,
-// D_eo = -kappa H_eo).
-void eo_setup(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
-  const size_t half = spinor_bytes(half_geom(g->g), kFP64), full = spinor_bytes(g->g, kFP64);
-  (void)hipMemcpy2DAsync(w.eta_e, half, w.b64, full, half, w.n, hipMemcpyDeviceToDevice, st);
-  (void)hipMemcpy2DAsync(w.eta_o, half, (const char*)w.b64 + half, full, half, w.n, hipMemcpyDeviceToDevice, st);
+// Even-odd set-up: the canonical FP64 source goes straight to eta_e and eta_o
+// (|b|^2 partials of the full field, site_grid rows), then the right-hand side
+// b' = eta_e + kappa H_eo eta_o of eq. (4)-(6) (D_ee = D_oo = 1, D_eo = -kappa H_eo).
+void eo_setup(const qcd_gauge* g, double kappa, const Work& w, const void* b_dev, hipStream_t st) {
+  launch_pack_spinor_split(g->g, w.n, w.eta_e, w.eta_o, (const double*)b_dev, w.partials, st);
   launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiNone, w.n, w.bp64, w.eta_o, g->U[kFP64], -kappa, nullptr,
                 nullptr, nullptr, 0, st, w.eta_e, 0);
 }
-// x_o = eta_o + kappa H_oe x_e, and the full solution [x_e | x_o] in xf64.
-void eo_reconstruct(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
-  const size_t half = spinor_bytes(half_geom(g->g), kFP64), full = spinor_bytes(g->g, kFP64);
-  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiNone, w.n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr,
-                nullptr, nullptr, 0, st, w.eta_o, 1);
-  (void)hipMemcpy2DAsync(w.xf64, full, w.x64, half, half, w.n, hipMemcpyDeviceToDevice, st);
-  (void)hipMemcpy2DAsync((char*)w.xf64 + half, full, w.x64o, half, half, w.n, hipMemcpyDeviceToDevice, st);
-}
-// |b - D x|^2 partials per right-hand side for the full solution xf64, with
-// the full operator (residual written to rf64).
-void eo_full_residual(const qcd_gauge* g, double kappa, const Work& w, hipStream_t st) {
-  launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.rf64, w.xf64, g->U[kFP64], kappa, w.b64,
-                w.partials, nullptr, 0, st);
+// x_o = eta_o + kappa H_oe x_e, the canonical solution, and |b - D x|^2 of the
+// full system per right-hand side in r2 (synchronises): the odd rows come from
+// the reconstruction launch itself, the even rows eta_e - (x_e - kappa H_eo x_o)
+// from one more one-parity launch (residual vector left in r64).
+qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_dev, double* r2, hipStream_t st) {
+  const Geom& G = g->g;
+  const int n = w.n;
+  DslashTune one = g->tune[kFP64];
+  one.rhs_tile = 1;
+  const int rows_o = dslash_partial_rows(G, one, n, true), rows_e = dslash_partial_rows(G, g->tune[kFP64], n, true);
+  double* po = w.partials;
+  double* pe = w.partials + (size_t)n * rows_o;
+  launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiRecon, n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr, po,
+                nullptr, 0, st, w.eta_o, 1);
+  launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
+                nullptr, 0, st, w.x64, 0);
+  launch_unpack_spinor_split(G, n, (double*)x_dev, w.x64, w.x64o, st);
+  launch_finish_sum(n, po, rows_o, 1, w.sums, st);
+  launch_finish_sum(n, pe, rows_e, 1, w.sums + n, st);
+  HIP_LAUNCHED();
+  double h[2 * kMaxRhs];
+  HIP_TRY(hipMemcpyAsync(h, w.sums, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int i = 0; i < n; i++) r2[i] = h[i] + h[n + i];
+  return QCD_OK;
 }
 
 // Capture one iteration (8 kernels) into a hip graph.  Capture runs on the
@@ -401,10 +408,19 @@ qcd_status read_scalars_all(const InnerRun* runs, int nrun, hipStream_t st) {
 // convergence rate predicts the slowest right-hand side still needs, plus
 // one.  With several runs each chunk forks from st onto every run's own
 // stream (runs on different lattices proceed concurrently) and joins back.
-qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_params& p, hipStream_t st) {
+// Without entry_read the first chunk is queued for every right-hand side the
+// host mirror shows as refining (outer_active), without a synchronisation;
+// the kernels skip those the device has already stopped.
+qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_params& p, hipStream_t st,
+                           bool entry_read = true) {
   const int K0 = p.check_every > 0 ? p.check_every : 4;
-  qcd_status s = read_scalars_all(runs, nrun, st);
-  if (s) return s;
+  qcd_status s = QCD_OK;
+  if (entry_read) {
+    if ((s = read_scalars_all(runs, nrun, st))) return s;
+  } else {
+    for (int r = 0; r < nrun; r++)
+      for (int i = 0; i < runs[r].w->n; i++) runs[r].g->host_sc[i].active = runs[r].g->host_sc[i].outer_active;
+  }
   std::vector<hipGraphExec_t> gexec(nrun, nullptr);
   std::vector<hipStream_t> rs(nrun, st);
   std::vector<hipEvent_t> done(nrun, nullptr);
@@ -434,10 +450,9 @@ qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_pa
       if (any_active(runs[r].g, runs[r].w->n)) return true;
     return false;
   };
+  // residual^2 at the last poll (at iteration 0: |b|^2, set when the run started)
   std::vector<double> prev_res2((size_t)nrun * kMaxRhs);
   std::vector<int> prev_iter((size_t)nrun * kMaxRhs, 0);
-  for (int r = 0; r < nrun; r++)
-    for (int i = 0; i < runs[r].w->n; i++) prev_res2[(size_t)r * kMaxRhs + i] = runs[r].g->host_sc[i].bnorm2;
   int launched = 0, chunk = K0;
   while (anyrun() && launched <= p.max_iter + K0) {
     if (nrun > 1) HIP_TRY(hipEventRecord(fork, st));
@@ -468,6 +483,7 @@ qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_pa
         double& pr = prev_res2[(size_t)r * kMaxRhs + i];
         int& pi = prev_iter[(size_t)r * kMaxRhs + i];
         if (!h.active || h.iter <= pi) continue;
+        if (pi == 0) pr = h.bnorm2;
         const double res2 = h.rnorm2 / (h.gamma_cum * h.gamma_cum);
         const double target = h.tol2 * h.bnorm2;
         const double rate = std::pow(res2 / pr, 1.0 / (h.iter - pi));  // per iteration
@@ -867,9 +883,8 @@ qcd_status bicgstab_eo(const qcd_gauge* g, double kappa, int prec, int n, void* 
   for (int i = 0; i < n; i++) init_params(&hs[i], p);
   HIP_TRY(hipMemcpyAsync(w.sc, hs, sizeof(Scalars) * n, hipMemcpyHostToDevice, st));
   double b2[kMaxRhs], r2[kMaxRhs];
-  launch_pack_spinor(G, kFP64, n, w.b64, (const double*)b_dev, 1.0, 0, w.partials, st);
+  eo_setup(g, kappa, w, b_dev, st);
   if ((rc = read_sum(w, site_grid(G), 1, b2, st))) return rc;
-  eo_setup(g, kappa, w, st);
   // r = r* = low(b'), x0 = 0
   launch_narrow(gh, prec, n, w.r, (const double*)w.bp64, w.partials, p.ftz, st);
   HIP_TRY(hipMemcpyAsync(w.rstar, w.r, n * spinor_bytes(gh, prec), hipMemcpyDeviceToDevice, st));
@@ -885,11 +900,7 @@ qcd_status bicgstab_eo(const qcd_gauge* g, double kappa, int prec, int n, void* 
   }
   HIP_TRY(hipMemcpyAsync(w.scale, scales, sizeof(double) * n, hipMemcpyHostToDevice, st));
   launch_widen(gh, prec, n, (double*)w.x64, w.x, w.scale, st);
-  eo_reconstruct(g, kappa, w, st);
-  launch_unpack_spinor(G, kFP64, n, (double*)x_dev, w.xf64, nullptr, 1.0, st);
-  eo_full_residual(g, kappa, w, st);
-  HIP_LAUNCHED();
-  if ((rc = read_sum(w, dslash_partial_rows(G, g->tune[kFP64], n), 1, r2, st))) return rc;
+  if ((rc = eo_finish(g, kappa, w, x_dev, r2, st))) return rc;
   qcd_status result = QCD_OK;
   for (int i = 0; i < n; i++) {
     if (info) {
@@ -1030,20 +1041,20 @@ qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
     hs[i].out_tol = p->tol;
   }
   HIP_TRY(hipMemcpyAsync(R.w.sc, hs, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
-  launch_pack_spinor(G, kFP64, R.n, R.w.b64, (const double*)R.b_dev, 1.0, 0, R.w.partials, st);
   if (R.w.eo) {
-    // |b| of the full system, then b' (eq. (4)-(6)), r = b', x_e = 0
+    // eta_e, eta_o and b' (eq. (4)-(6)), |b| of the full system, r = b', x_e = 0
+    eo_setup(R.g, R.kappa, R.w, R.b_dev, st);
     double b2[kMaxRhs];
     qcd_status rc = read_sum(R.w, site_grid(G), 1, b2, st);
     if (rc) return rc;
     for (int i = 0; i < R.n; i++) R.bfull[i] = sqrt(b2[i]);
     const Geom gh = half_geom(G);
-    eo_setup(R.g, R.kappa, R.w, st);
     launch_narrow(gh, kFP64, R.n, R.w.r64, (const double*)R.w.bp64, R.w.partials, 0, st);
     launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(gh), p->s, st);
     launch_zero(gh, kFP64, R.n, R.w.x64, st);
     return QCD_OK;
   }
+  launch_pack_spinor(G, kFP64, R.n, R.w.b64, (const double*)R.b_dev, 1.0, 0, R.w.partials, st);
   launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(G), p->s, st);
   HIP_TRY(hipMemcpyAsync(R.w.r64, R.w.b64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
   launch_zero(G, kFP64, R.n, R.w.x64, st);
@@ -1247,7 +1258,7 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
       if ((rc = ir_begin_step(*R, p, st))) return rc;
     std::vector<InnerRun> ir;
     for (IrRun* R : act) ir.push_back(InnerRun{R->g, p->inner_prec, R->kappa, &R->w, R->pc});
-    if ((rc = bicg_loop_multi(ir.data(), (int)ir.size(), p->inner, st))) return rc;
+    if ((rc = bicg_loop_multi(ir.data(), (int)ir.size(), p->inner, st, false))) return rc;
     for (IrRun* R : act)
       if ((rc = ir_end_step(*R, p, st))) return rc;
     if ((rc = read_scalars_all(ir.data(), (int)ir.size(), st))) return rc;
@@ -1257,13 +1268,9 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
   for (int r = 0; r < nrun; r++) {
     IrRun& R = runs[r];
     if (R.w.eo) {
-      // x_o from x_e, the full solution, and |b - D x| of the full system for the report
-      eo_reconstruct(R.g, R.kappa, R.w, st);
-      launch_unpack_spinor(R.g->g, kFP64, R.n, (double*)R.x_dev, R.w.xf64, nullptr, 1.0, st);
-      eo_full_residual(R.g, R.kappa, R.w, st);
-      HIP_LAUNCHED();
+      // x_o from x_e, the canonical solution, and |b - D x| of the full system for the report
       double r2[kMaxRhs];
-      if ((rc = read_sum(R.w, dslash_partial_rows(R.g->g, R.g->tune[kFP64], R.n), 1, r2, st))) return rc;
+      if ((rc = eo_finish(R.g, R.kappa, R.w, R.x_dev, r2, st))) return rc;
       for (int i = 0; i < R.n; i++)
         if (R.outer[i] > 0) R.rn[i] = sqrt(r2[i]);
     } else {

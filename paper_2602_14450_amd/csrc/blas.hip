@@ -103,19 +103,22 @@ __global__ void k_max_finish(const double* __restrict__ partials, int nrows, dou
 
 // dst = round(scale * canon) for right-hand side blockIdx.y; partial
 // |dst|^2 per block from the stored values.
+// With `odd` set the destination is split by parity: even sites go to the
+// one-parity fields at dst, odd sites to those at odd.
 template <typename S>
 __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst, const double* __restrict__ src,
-                                                     double scale, int ftz, double* __restrict__ partials) {
+                                                     double scale, int ftz, double* __restrict__ partials,
+                                                     S* __restrict__ odd) {
   using T = typename Traits<S>::T;
   SiteId id = site_id(g);
   const int rhs = blockIdx.y;
-  dst += (size_t)rhs * spinor_elems(g);
   src += (size_t)rhs * volume(g) * 24;
   double red[1] = {0.0};
   if (id.valid) {
     const int64_t s = lex_site(g, id.par, id.h);
     const int lane = id.h & 63;
-    S* b = dst + sp_block(g, id.par, id.h);
+    S* b = odd ? (id.par ? odd : dst) + (size_t)rhs * g.nb * 768 + sp_block(g, 0, id.h)
+               : dst + (size_t)rhs * spinor_elems(g) + sp_block(g, id.par, id.h);
     T acc = 0;
     for (int k = 0; k < 12; k++) {
       const S v = pack_from_double<S>(scale * src[(s * 12 + k) * 2], scale * src[(s * 12 + k) * 2 + 1], ftz);
@@ -128,18 +131,22 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst
 }
 
 // canon = scale * double(src) with scale = scale_dev[rhs] (if given) or scale.
+// With `odd` set the source is split by parity as in k_pack_spinor.
 template <typename S>
 __global__ __launch_bounds__(256) void k_unpack_spinor(Geom g, double* __restrict__ dst, const S* __restrict__ src,
-                                                       const double* __restrict__ scale_dev, double scale) {
+                                                       const double* __restrict__ scale_dev, double scale,
+                                                       const S* __restrict__ odd) {
   SiteId id = site_id(g);
   if (!id.valid) return;
   const int rhs = blockIdx.y;
-  src += (size_t)rhs * spinor_elems(g);
   dst += (size_t)rhs * volume(g) * 24;
   if (scale_dev) scale = scale_dev[rhs];
   const int64_t s = lex_site(g, id.par, id.h);
   cx<typename Traits<S>::T> f[12];
-  load_site(src, g, id.par, id.h, f);
+  if (odd)
+    load_site((id.par ? odd : src) + (size_t)rhs * g.nb * 768, g, 0, id.h, f);
+  else
+    load_site(src + (size_t)rhs * spinor_elems(g), g, id.par, id.h, f);
   for (int k = 0; k < 12; k++) {
     dst[(s * 12 + k) * 2] = scale * (double)f[k].re;
     dst[(s * 12 + k) * 2 + 1] = scale * (double)f[k].im;
@@ -605,7 +612,8 @@ void launch_link_su3_dev(const Geom& g, const double* U, double* partials, doubl
 template <typename S>
 static void pack_spinor_t(const Geom& g, int n, void* dst, const double* c, double scale, int ftz, double* partials,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, (S*)dst, c, scale, ftz, partials);
+  hipLaunchKernelGGL(k_pack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, (S*)dst, c, scale, ftz, partials,
+                     nullptr);
 }
 void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double* canon, double scale, int ftz,
                         double* partials, hipStream_t st) {
@@ -615,11 +623,23 @@ void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double*
 template <typename S>
 static void unpack_spinor_t(const Geom& g, int n, double* c, const void* src, const double* sd, double scale,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, c, (const S*)src, sd, scale);
+  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, c, (const S*)src, sd, scale,
+                     nullptr);
 }
 void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
                           double scale, hipStream_t st) {
   QCD_DISPATCH(prec, unpack_spinor_t, g, n, canon, src, scale_dev, scale, st);
+}
+
+void launch_pack_spinor_split(const Geom& g, int n, void* even, void* odd, const double* canon, double* partials,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_spinor<double2>, dim3(site_grid(g), n), dim3(256), 0, st, g, (double2*)even, canon, 1.0,
+                     0, partials, (double2*)odd);
+}
+void launch_unpack_spinor_split(const Geom& g, int n, double* canon, const void* even, const void* odd,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_unpack_spinor<double2>, dim3(site_grid(g), n), dim3(256), 0, st, g, canon,
+                     (const double2*)even, nullptr, 1.0, (const double2*)odd);
 }
 
 template <typename S> static void zero_t(const Geom& g, int n, void* dst, hipStream_t st) {

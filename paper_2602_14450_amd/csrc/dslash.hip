@@ -450,6 +450,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
   constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
+  static_assert(EPI != kEpiRecon || (EO && OP == kOpD), "the reconstruction epilogue is a one-parity D form");
   double red[NV];
 #pragma unroll
   for (int i = 0; i < NV; i++) red[i] = 0.0;
@@ -497,6 +498,9 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
             acc1 += os.re * sv.im - os.im * sv.re;
             acc2 += norm2(os);
             acc3 += norm2(sv);
+          } else if constexpr (EPI == kEpiRecon) {  // cin - (out - |kappa| H in), as a separate residual launch forms it
+            const cx<T_> dv = os - (-k) * a[i / 3][i % 3];
+            acc0 += norm2(ctr[i] - dv);
           } else {
             acc0 += norm2(os);
           }
@@ -506,7 +510,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     }
     if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
     if constexpr (TS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
-    if constexpr (EPI == kEpiResid) { red[0] = acc0; }
+    if constexpr (EPI == kEpiResid || EPI == kEpiRecon) { red[0] = acc0; }
   }
   if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
 }
@@ -815,7 +819,9 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
     else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
     else if (epi == kEpiTS) QCD_LAUNCH_EO(kOpD, kEpiTS);
-    else QCD_LAUNCH_EO(kOpD, kEpiResid);
+    else if (epi == kEpiRecon) {
+      if constexpr (std::is_same<S, double2>::value && T == 1) QCD_LAUNCH_EO(kOpD, kEpiRecon);
+    } else QCD_LAUNCH_EO(kOpD, kEpiResid);
 #undef QCD_LAUNCH_EO
     return;
   }
@@ -1022,7 +1028,8 @@ int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo) {
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune_in, int op, int epi, int n, void* out,
                    const void* in, const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                    int ftz, hipStream_t st, const void* cin, int eo_par) {
-  const DslashTune tune = resolve_rhs_tile(tune_in, prec, n);
+  DslashTune tune = resolve_rhs_tile(tune_in, prec, n);
+  if (epi == kEpiRecon) tune.rhs_tile = 1;  // built for one right-hand side per thread only
   if (prec == kFP64)
     launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   else if (prec == kFP32)

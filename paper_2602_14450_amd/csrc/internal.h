@@ -9,7 +9,11 @@ namespace qcd {
 enum { kFP64 = 0, kFP32 = 1, kFP16 = 2, kBF16 = 3 };
 constexpr int kNumPrec = 4;
 enum { kOpD = 0, kOpH = 1, kOpDdag = 2, kOpHdag = 3 };
-enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3, kEpiTSAux = 4 };
+enum { kEpiNone = 0, kEpiDotAux = 1, kEpiTS = 2, kEpiResid = 3, kEpiTSAux = 4, kEpiRecon = 5 };
+// kEpiRecon (FP64, one parity, D form with kappa < 0): out = cin - kappa H in is
+// stored, and |cin - (out + kappa H in)|^2 goes to the partials: the residual
+// rows of the stored out, from the same hop sum (the odd rows of b - D x when
+// the even-odd solve rebuilds x_o).
 
 // Inner-solver status codes kept on the device.
 enum { kRunning = 0, kConverged = 1, kMaxIter = 2, kNonFinite = 3, kBreakdown = 4 };
@@ -65,6 +69,7 @@ struct DslashTune {
   int sched;    // 0: blocks in half-index order; m = 1..3: XCD z slabs (each swept as 2^(m-1) sub-slabs);
                 // 4: XCD t slabs swept in z order
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
+                // (prefetching 2 hops at 5 waves spills registers and measured slower in every precision)
   int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
                 // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers)
   int recon;    // links stored as 6 entries (rows 0, 1; row 2 rebuilt) instead of 9: a property of the data
@@ -99,6 +104,12 @@ void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double*
                         double* partials, hipStream_t st);
 void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
                           double scale, hipStream_t st);
+// FP64 only: canonical <-> two one-parity native fields (even sites in `even`,
+// odd sites in `odd`, each with a one-parity field per right-hand side)
+void launch_pack_spinor_split(const Geom& g, int n, void* even, void* odd, const double* canon, double* partials,
+                              hipStream_t st);
+void launch_unpack_spinor_split(const Geom& g, int n, double* canon, const void* even, const void* odd,
+                                hipStream_t st);
 void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st);
 // native FP64 -> native prec (RNE, |stored|^2 partials if not null); native prec -> FP64 times scale_dev[rhs]
 void launch_narrow(const Geom& g, int prec, int n, void* dst, const double* src, double* partials, int ftz,
