@@ -464,8 +464,11 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     hop_all<DEPTH, DAG, NE, EO>(g, in, U, par, h, c, a);
     const T_ k = (T_)kappa;
     cx<T_> o[12], ctr[12], ax[12];
-    if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(EO ? cin : in, g, fpar, h, ctr);
-    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(aux, g, fpar, h, ax);
+    if constexpr (!(OP == kOpH || OP == kOpHdag)) {
+      if constexpr (EO) load_site_stream(cin, g, fpar, h, ctr);  // read once
+      else load_site(EO ? cin : in, g, fpar, h, ctr);  // the full form's centre is also neighbour data
+    }
+    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site_stream(aux, g, fpar, h, ax);
 #pragma unroll
     for (int i = 0; i < 12; i++) {
       if constexpr (OP == kOpH || OP == kOpHdag) {
@@ -506,7 +509,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
           }
         }
       }
-      *reinterpret_cast<Gr*>(ob + j * 64 * C) = v;
+      store_stream(reinterpret_cast<Gr*>(ob + j * 64 * C), v);
     }
     if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
     if constexpr (TS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
@@ -748,8 +751,11 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
       const S* inr = (EO ? cin : in) + vo + r * vs;
       const S* axr = aux ? aux + vo + r * vs : nullptr;
       cx<T_> o[12], ctr[12], ax[12];
-      if constexpr (!(OP == kOpH || OP == kOpHdag)) load_site(inr, g, fpar, h, ctr);
-      if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site(axr, g, fpar, h, ax);
+      if constexpr (!(OP == kOpH || OP == kOpHdag)) {
+        if constexpr (EO) load_site_stream(inr, g, fpar, h, ctr);
+        else load_site(inr, g, fpar, h, ctr);
+      }
+      if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site_stream(axr, g, fpar, h, ax);
 #pragma unroll
       for (int i = 0; i < 12; i++) {
         if constexpr (OP == kOpH || OP == kOpHdag) {
@@ -784,7 +790,7 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
             }
           }
         }
-        *reinterpret_cast<Gr*>(ob + j * 64 * C) = v;
+        store_stream(reinterpret_cast<Gr*>(ob + j * 64 * C), v);
       }
       if constexpr (EPI == kEpiDotAux) { red[r][0] = acc0; red[r][1] = acc1; }
       if constexpr (TS) { red[r][0] = acc0; red[r][1] = acc1; red[r][2] = acc2; red[r][3] = acc3; }
