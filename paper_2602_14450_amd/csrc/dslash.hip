@@ -188,16 +188,18 @@ template <typename S, int NE> struct HopRaw {
 };
 template <typename S> struct alignas(2 * sizeof(S)) Pair { S s[2]; };
 
-// Link loads.  A one-parity launch reads every link of the lattice exactly
-// once (each link joins an even and an odd site), so there the loads are
-// marked non-temporal (3% on the even-odd solve at 32^3 x 64); a full launch
-// reads each link twice and keeps plain loads (the hint costs it 8%).
-template <bool EO, typename Gr> __device__ __forceinline__ Gr load_link_gran(const Gr* p) {
-  if constexpr (EO) return load_stream(p);
+// Link loads.  A one-parity launch for one tile of right-hand sides reads
+// every link of the lattice exactly once (each link joins an even and an odd
+// site), so there the loads are marked non-temporal (LNT; 3% on the even-odd
+// solve at 32^3 x 64).  A full launch reads each link twice, and the tiles of
+// a multi-RHS launch read the same links again: both keep plain loads (the
+// hint costs the full launch 8% and the 12-source batch 4%).
+template <bool LNT, typename Gr> __device__ __forceinline__ Gr load_link_gran(const Gr* p) {
+  if constexpr (LNT) return load_stream(p);
   else return *p;
 }
-template <bool EO, typename S> __device__ __forceinline__ Pair<S> load_link_pair(const Pair<S>* p) {
-  if constexpr (EO && QCD_STREAM_HINTS) {
+template <bool LNT, typename S> __device__ __forceinline__ Pair<S> load_link_pair(const Pair<S>* p) {
+  if constexpr (LNT && QCD_STREAM_HINTS) {
     static_assert(sizeof(Pair<S>) == 8, "a tail pair is 8 bytes");
     using V = unsigned int __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(Pair<S>, __builtin_nontemporal_load(reinterpret_cast<const V*>(p)));
@@ -213,7 +215,7 @@ template <int MU, bool MINUS, typename S> __device__ __forceinline__ constexpr b
   return (MU != 3) || (MINUS ? (j * C + C - 1) / 3 >= 2 : (j * C) / 3 < 2);
 }
 
-template <int HOP, bool DAG, int NE, bool EO, typename S>
+template <int HOP, bool DAG, int NE, bool EO, bool LNT, typename S>
 __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
                                          int h, const Coord& c, HopRaw<S, NE>& d, int dep = 0) {
   constexpr int MU = HOP >> 1;
@@ -245,12 +247,12 @@ __device__ __forceinline__ void hop_load(const Geom& g, const S* __restrict__ in
   const S* lb = U + lk_block<NE>(g, MU, lp, lh);
   const int lane = lh & 63;
 #pragma unroll
-  for (int j = 0; j < F / C; j++) d.lk[j] = load_link_gran<EO>(reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C));
+  for (int j = 0; j < F / C; j++) d.lk[j] = load_link_gran<LNT>(reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C));
   if constexpr (NE == 9) {
 #pragma unroll
     for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
   } else if constexpr (TAIL == 2) {  // the two remaining entries of this lane, one 2-element load
-    const Pair<S> v = load_link_pair<EO>(reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2));
+    const Pair<S> v = load_link_pair<LNT>(reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2));
     d.tail[0] = v.s[0];
     d.tail[1] = v.s[1];
   } else {
@@ -349,7 +351,7 @@ struct PipeArgs {
   Coord c;
 };
 
-template <int I, int DEPTH, bool DAG, int NE, bool EO, typename S, typename T>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, bool LNT, typename S, typename T>
 __device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                          const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
   if constexpr (I < 8) {
@@ -358,29 +360,29 @@ __device__ __forceinline__ void hop_pipe(const Geom& g, const S* __restrict__ in
     if constexpr (I + DEPTH + 1 < 8) {
       int dep = 0;
       asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
-      hop_load<I + DEPTH + 1, DAG, NE, EO>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
+      hop_load<I + DEPTH + 1, DAG, NE, EO, LNT>(g, in, U, pa.par, pa.h, pa.c, buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
     }
     QCD_FENCE();
-    hop_pipe<I + 1, DEPTH, DAG, NE, EO>(g, in, U, pa, buf, a);
+    hop_pipe<I + 1, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, buf, a);
   }
 }
 
-template <int I, int DEPTH, bool DAG, int NE, bool EO, typename S>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, bool LNT, typename S>
 __device__ __forceinline__ void hop_prologue(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                              const PipeArgs& pa, HopRaw<S, NE> (&buf)[DEPTH + 1]) {
   if constexpr (I <= DEPTH) {
-    hop_load<I, DAG, NE, EO>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
-    hop_prologue<I + 1, DEPTH, DAG, NE, EO>(g, in, U, pa, buf);
+    hop_load<I, DAG, NE, EO, LNT>(g, in, U, pa.par, pa.h, pa.c, buf[I]);
+    hop_prologue<I + 1, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, buf);
   }
 }
 
-template <int DEPTH, bool DAG, int NE, bool EO, typename S, typename T>
+template <int DEPTH, bool DAG, int NE, bool EO, bool LNT, typename S, typename T>
 __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in, const S* __restrict__ U, int par,
                                         int h, const Coord& c, cx<T> (&a)[4][3]) {
   HopRaw<S, NE> buf[DEPTH + 1];
   const PipeArgs pa{par, h, c};
-  hop_prologue<0, DEPTH, DAG, NE, EO>(g, in, U, pa, buf);
-  hop_pipe<0, DEPTH, DAG, NE, EO>(g, in, U, pa, buf, a);
+  hop_prologue<0, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, buf);
+  hop_pipe<0, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, buf, a);
 }
 
 // Thread -> (site, right-hand side).  A block of 256 threads is four waves:
@@ -438,7 +440,7 @@ __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
 // centre term comes from `cin` (parity tpar), so out = cin - kappa H in
 // (kappa = kappa^2 gives the Schur complement's second half, kappa < 0 the
 // right-hand side and the reconstruction of the even-odd solve).
-template <typename S, int OP, int EPI, int DEPTH, int OCC, int T, int NE, bool EO>
+template <typename S, int OP, int EPI, int DEPTH, int OCC, int T, int NE, bool EO, bool LNT>
 __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, S* __restrict__ out,
                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                      const S* __restrict__ aux, double* __restrict__ partials,
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
     for (int s = 0; s < 4; s++)
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T_>(0, 0);
-    hop_all<DEPTH, DAG, NE, EO>(g, in, U, par, h, c, a);
+    hop_all<DEPTH, DAG, NE, EO, LNT>(g, in, U, par, h, c, a);
     const T_ k = (T_)kappa;
     cx<T_> o[12], ctr[12], ax[12];
     if constexpr (!(OP == kOpH || OP == kOpHdag)) {
@@ -585,12 +587,12 @@ __device__ __forceinline__ void hop_load_r(const Geom& g, const S* __restrict__ 
   const S* lb = U + lk_block<NE>(g, MU, lp, lh);
   const int lane = lh & 63;
 #pragma unroll
-  for (int j = 0; j < F / C; j++) d.lk[j] = load_link_gran<EO>(reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C));
+  for (int j = 0; j < F / C; j++) d.lk[j] = load_link_gran<false>(reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C));
   if constexpr (NE == 9) {
 #pragma unroll
     for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
   } else if constexpr (TAIL == 2) {
-    const Pair<S> v = load_link_pair<EO>(reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2));
+    const Pair<S> v = load_link_pair<false>(reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2));
     d.tail[0] = v.s[0];
     d.tail[1] = v.s[1];
   }
@@ -836,9 +838,15 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
   const S* x = (const S*)aux;
   const S* ci = (const S*)cin;
   if (eo_par >= 0) {  // one parity: D form (centre from cin) or H, the epilogues the solvers use
-#define QCD_LAUNCH_EO(OPV, EPIV)                                                                                    \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
-                     partials, scal, ftz, ci, eo_par)
+#define QCD_LAUNCH_EO(OPV, EPIV)                                                                                     \
+  do {                                                                                                               \
+    if (T == 1 && sc.ntiles == 1)                                                                                    \
+      hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true, T == 1>), grid, block, 0, st, g, sc, o, i, \
+                         u, kappa, x, partials, scal, ftz, ci, eo_par);                                              \
+    else                                                                                                             \
+      hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true, false>), grid, block, 0, st, g, sc, o, i,  \
+                         u, kappa, x, partials, scal, ftz, ci, eo_par);                                              \
+  } while (0)
     if (op == kOpH) QCD_LAUNCH_EO(kOpH, kEpiNone);
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
     else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
@@ -849,9 +857,9 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 #undef QCD_LAUNCH_EO
     return;
   }
-#define QCD_LAUNCH(OPV, EPIV)                                                                                         \
-  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, false>), grid, block, 0, st, g, sc, o, i, u, kappa, x, \
-                     partials, scal, ftz, nullptr, 0)
+#define QCD_LAUNCH(OPV, EPIV)                                                                                          \
+  hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, false, false>), grid, block, 0, st, g, sc, o, i, u, kappa, \
+                     x, partials, scal, ftz, nullptr, 0)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
