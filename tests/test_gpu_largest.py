@@ -1,0 +1,133 @@
+"""The largest single-GPU form: 48^3 x 96 (10.6M sites), eps = 0.2, kappa = 0.1245.
+
+At this size the oracle cannot solve, so the checks are the oracle's operator
+on sampled sites (every sampled output against eq. (1) evaluated by the
+oracle) and, for solves, the oracle's residual b - D x of the returned x at
+sampled sites: no site may exceed the claimed 1e-12 |b|, and the norm
+estimated from the samples (all sites near the origin, a random sample
+elsewhere) must be within 3x of it; the solver's own FP64 residual must meet
+1e-12 as well.
+
+* the Wilson operator in every storage precision, native layout, in the
+  launch configuration the benchmark times;
+* the 12 spin-colour point sources at the origin in one batched even-odd
+  refinement with the FP16 inner solver (s = 128, sigma = 64, graph replay);
+* a network trained on 16^4 pairs, applied unchanged as right preconditioner
+  of the full-matrix refinement at 48^3 x 96.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import qcd_inputs as qi  # noqa: E402
+from gpu_common import TOL, compare, to_dev, to_host  # noqa: E402
+
+DIMS = (48, 48, 48, 96)
+KAPPA = 0.1245
+V = int(np.prod(DIMS))
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def big(q):
+    U = qi.gauge_field(DIMS, 0.2, 501)
+    Ud = to_dev(U)
+    g = q.gauge_upload(Ud, DIMS)
+    del Ud
+    torch.cuda.empty_cache()
+    # every site within 3 steps of the origin in each direction (periodic), counted
+    # exactly, and 3000 random sites elsewhere standing for the rest of the lattice
+    off = np.arange(-3, 4)
+    co = np.stack(np.meshgrid(off, off, off, off, indexing="ij"), -1).reshape(-1, 4) % np.array(DIMS)
+    near = np.unique(co[:, 0] + DIMS[0] * (co[:, 1] + DIMS[1] * (co[:, 2] + DIMS[2] * co[:, 3])))
+    rng = np.random.default_rng(502)
+    far = np.setdiff1d(rng.choice(V, 3200, replace=False), near)[:3000]
+    yield dict(U=U, g=g, near=near, far=far, sites=np.concatenate([near, far]))
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def residual_checks(U, x, b, near, far):
+    """The oracle's residual b - D x at the sampled sites: no site's residual may
+    exceed the claimed norm 1e-12 |b| (a rigorous consequence), and |b - D x| / |b|
+    estimated as the exact sum over the near sites plus the far sample scaled to
+    the rest of the lattice is returned."""
+    bn = np.linalg.norm(b)
+    rn = b[near] - oracle.dslash_sites(U, x, KAPPA, DIMS, near)
+    rf = b[far] - oracle.dslash_sites(U, x, KAPPA, DIMS, far)
+    site = np.sqrt(np.sum(np.abs(np.concatenate([rn, rf])) ** 2, axis=(1, 2)))
+    assert site.max() <= 1.01e-12 * bn, site.max() / bn
+    est = np.sum(np.abs(rn) ** 2) + np.sum(np.abs(rf) ** 2) * (V - len(near)) / len(far)
+    return np.sqrt(est) / bn
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+def test_operator_sampled(q, big, prec):
+    g = big["g"]
+    psi = qi.gaussian_source(DIMS, 503)
+    a, out = g.native_spinor(prec), g.native_spinor(prec)
+    q.convert(g, prec, a, to_dev(psi), want_norm=False)
+    q.dslash(g, KAPPA, out, a, prec=prec, layout=q.NATIVE)
+    y = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    q.unconvert(g, prec, y, out)
+    torch.cuda.synchronize()
+    sites = big["sites"]
+    got = to_host(y)[sites]
+    compare(got, oracle.dslash_sites(big["U"], psi, KAPPA, DIMS, sites), TOL[prec], f"48^3x96 prec={prec}")
+    del a, out, y
+    torch.cuda.empty_cache()
+
+
+def test_twelve_point_sources_even_odd(q, big):
+    g = big["g"]
+    bs = np.stack([qi.point_source(DIMS, sp, c) for sp in range(4) for c in range(3)])
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, KAPPA, x, b, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, even_odd=True,
+                             use_graph=True)
+    torch.cuda.synchronize()
+    for i in infos:
+        assert i.status == "ok" and i.true_rel_residual <= 1e-12, i
+    for r in (0, 7, 11):
+        rel = residual_checks(big["U"], to_host(x[r]), bs[r], big["near"], big["far"])
+        assert rel <= 3e-12, (r, rel)
+    del b, x
+    torch.cuda.empty_cache()
+
+
+def test_network_trained_on_16_4_applied_unchanged(q, big):
+    from paper_2602_14450_amd import ptc_train as T
+    net16, sets, _ = T.train_preconditioner((16, 16, 16, 16), 0.124, nfields=2, pairs_per_field=64, batch=16)
+    weights = net16.get_weights()
+    net16.close()
+    for s in sets:
+        s.gauge.close()
+    del sets
+    g = big["g"]
+    net = q.PTC(g, (1, 2, 2, 1), max_batch=2)
+    net.set_weights(weights)
+    bs = qi.gaussian_source(DIMS, 504, nrhs=2)
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, KAPPA, x, b, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, precond=net)
+    torch.cuda.synchronize()
+    for i in infos:
+        assert i.status == "ok" and i.true_rel_residual <= 1e-12, i
+        assert i.precond_fallback == -1 and i.precond_steps == i.outer_iters
+    for r in range(2):
+        rel = residual_checks(big["U"], to_host(x[r]), bs[r], big["near"], big["far"])
+        assert rel <= 3e-12, (r, rel)
+    net.close()
+    del b, x
+    torch.cuda.empty_cache()
