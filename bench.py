@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-rescaling-study", action="store_true", help="skip the (s, sigma) grid of Sec. 5")
     ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
+    ap.add_argument("--no-largest", action="store_true", help="skip the 48^3 x 96 form")
     ap.add_argument("--full-operator", action="store_true",
                     help="solve with the full Wilson matrix instead of the even-odd system of eq. (5)")
     ap.add_argument("--autotune", action="store_true",
@@ -148,12 +149,89 @@ def learned_form(q, torch, np, qi, kappa, pairs_per_field, max_iter):
     e1.synchronize()
     res["network_apply_us"] = e0.elapsed_time(e1) / 20 * 1e3
     res["training"] = tinfo
+    res["_weights"] = net.get_weights()   # reused unchanged at 48^3 x 96, not printed
     res["workload"] = ("16^4, eps=0.3 links, kappa=0.124; network 1->2->2->1 spinor fields, BF16 MFMA mixing; "
                        f"trained 1 epoch on {8 * pairs_per_field} (r, FP32-solver D^-1 r) pairs from 8 seeded "
                        "fields; solves on a held-out field, tol 1e-12")
     net.close()
     neu.close()
     del sets, held
+    torch.cuda.empty_cache()
+    return res
+
+
+def largest_form(q, torch, np, qi, weights, max_iter, reps):
+    """48^3 x 96 (10.6M sites), eps = 0.2, kappa = 0.1245: the FP16 Wilson
+    operator's bandwidth, the 12 spin-colour point sources in one batched
+    even-odd FP16-inner refinement against the plain FP64 BiCGStab on the same
+    sources, and the network trained on 16^4 applied unchanged as right
+    preconditioner of the full-matrix refinement (2 Gaussian sources)."""
+    dims, kappa = (48, 48, 48, 96), 0.1245
+    V = int(np.prod(dims))
+    ts = time.perf_counter()
+    g = q.gauge_upload(torch.from_numpy(qi.gauge_field(dims, 0.2, 501)).cuda(), dims)
+    torch.cuda.empty_cache()
+    res = {"input_seconds": time.perf_counter() - ts}
+    ms = time_dslash(q, torch, g, q.FP16, reps, V)
+    res["dslash_fp16_us"] = ms * 1e3
+    res["dslash_fp16_GBps"] = DSLASH_BYTES[2] * V / (ms * 1e-3) / 1e9
+    res["dslash_fp16_frac"] = res["dslash_fp16_GBps"] / PEAK_HBM_GBS
+    bp = torch.from_numpy(np.stack([qi.point_source(dims, sp, c) for sp in range(4) for c in range(3)])).cuda()
+    x = torch.zeros_like(bp)
+
+    def fp16():
+        x.zero_()
+        return q.solve_mixed_ir(g, kappa, x, bp, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,
+                                inner_max_iter=max_iter, use_graph=True, even_odd=True)
+
+    def fp64():   # two calls of 6 right-hand sides (workspace within the HBM budget)
+        x.zero_()
+        out = []
+        for h in (slice(0, 6), slice(6, 12)):
+            xh = torch.zeros_like(bp[h])
+            out += q.bicgstab(g, kappa, xh, bp[h].contiguous(), prec=q.FP64, tol=1e-12, max_iter=max_iter,
+                              history=False, even_odd=True)
+            x[h] = xh
+            del xh
+        return out
+
+    for name, fn in (("fp16_inner_ir_12_sources", fp16), ("fp64_bicgstab_12_sources", fp64)):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        infos = fn()
+        torch.cuda.synchronize()
+        res[name] = dict(seconds=time.perf_counter() - ts, inner_iters=[i.inner_iters for i in infos],
+                         outer=[i.outer_iters for i in infos],
+                         max_true_rel_residual=max(i.true_rel_residual for i in infos))
+        print(f"[bench] 48^3x96 {name}: {res[name]['seconds']:.2f} s", file=sys.stderr, flush=True)
+    res["speedup_vs_fp64"] = res["fp64_bicgstab_12_sources"]["seconds"] / res["fp16_inner_ir_12_sources"]["seconds"]
+    del bp, x
+    torch.cuda.empty_cache()
+    if weights is not None:
+        net = q.PTC(g, (1, 2, 2, 1), max_batch=2)
+        net.set_weights(weights)
+        b2 = torch.from_numpy(qi.gaussian_source(dims, 504, nrhs=2)).cuda()
+        x2 = torch.zeros_like(b2)
+        for name, pc in (("plain", None), ("trained_16_4", net)):
+            x2.zero_()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            infos = q.solve_mixed_ir(g, kappa, x2, b2, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12,
+                                     inner_tol=1e-2, inner_max_iter=max_iter, use_graph=True, precond=pc)
+            torch.cuda.synchronize()
+            res["network_" + name] = dict(seconds=time.perf_counter() - ts, inner_iters=[i.inner_iters for i in infos],
+                                          max_true_rel_residual=max(i.true_rel_residual for i in infos),
+                                          precond_steps=[i.precond_steps for i in infos],
+                                          precond_fallback=[i.precond_fallback for i in infos])
+            print(f"[bench] 48^3x96 full matrix, 2 sources, {name}: {res['network_' + name]['seconds']:.2f} s "
+                  f"inner={res['network_' + name]['inner_iters']}", file=sys.stderr, flush=True)
+        net.close()
+        del b2, x2
+    res["workload"] = ("48^3x96, eps=0.2, kappa=0.1245; 12 spin-colour point sources at the origin, even-odd "
+                       "FP16-inner IR (s=128, sigma=64) against FP64 BiCGStab to 1e-12; the 16^4-trained network "
+                       "as right preconditioner of the full-matrix refinement on 2 Gaussian sources")
+    g.close()
     torch.cuda.empty_cache()
     return res
 
@@ -444,6 +522,10 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_form(q, torch, np, qi, 0.124, args.learned_pairs, max_iter)
+    largest = None
+    if not args.no_largest:
+        largest = largest_form(q, torch, np, qi, learned.pop("_weights") if learned else None, max_iter,
+                               max(5, args.dslash_reps // 5))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -477,7 +559,8 @@ def main():
                                f"{'even-odd system (eq. 5)' if eo else 'full matrix'}, true residual 1e-12",
                    "lattice": list(dims), "kappa": k, "sources": 1, "tol": 1e-12, "even_odd": eo},
         "roofline": roof, "cpu_baseline": cpu, "solvers": others,
-        ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched, "learned": learned, "rescaling_study": rescaling,
+        ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched,
+        "learned": learned, "largest_48x48x48x96": largest, "rescaling_study": rescaling,
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,
