@@ -522,10 +522,10 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_form(q, torch, np, qi, 0.124, args.learned_pairs, max_iter)
+    weights = learned.pop("_weights") if learned else None
     largest = None
     if not args.no_largest:
-        largest = largest_form(q, torch, np, qi, learned.pop("_weights") if learned else None, max_iter,
-                               max(5, args.dslash_reps // 5))
+        largest = largest_form(q, torch, np, qi, weights, max_iter, max(5, args.dslash_reps // 5))
 
     cpu = None
     if not args.no_cpu_baseline:
