@@ -455,19 +455,41 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const
   }
 }
 
-// Sum the wave partials (fixed order) and form the complex gradient
-// dW = (G00 + G11) + i (G10 - G01) in the layout of W; accumulate into grad.
-__global__ void k_ptc_dw_finish(PtcLayerDev L, const float* __restrict__ Gp, int nwaves, float2* __restrict__ grad) {
+// Sum the wave partials in two fixed-order passes: slice sl adds waves
+// sl, sl + kDwSlices, ... for every weight (one thread per weight and slice),
+// then the slices are added in order and the complex gradient
+// dW = (G00 + G11) + i (G10 - G01) is accumulated into grad in the layout of W.
+constexpr int kDwSlices = 64;
+__global__ __launch_bounds__(64) void k_ptc_dw_slices(PtcLayerDev L, const float* __restrict__ Gp, int nwaves,
+                                                      double* __restrict__ part) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;  // over M*K complex weights
   if (idx >= L.M * L.K) return;
   const int row = idx / L.K, kk = idx % L.K;
   double g00 = 0, g01 = 0, g10 = 0, g11 = 0;
-  for (int w = 0; w < nwaves; w++) {
+  for (int w = blockIdx.y; w < nwaves; w += kDwSlices) {
     const float* G = Gp + (size_t)w * 16 * L.Kp;
     g00 += G[(size_t)row * L.Kp + kk];
     g01 += G[(size_t)row * L.Kp + L.K + kk];
     g10 += G[(size_t)(L.M + row) * L.Kp + kk];
     g11 += G[(size_t)(L.M + row) * L.Kp + L.K + kk];
+  }
+  double* o = part + ((size_t)blockIdx.y * L.M * L.K + idx) * 4;
+  o[0] = g00;
+  o[1] = g01;
+  o[2] = g10;
+  o[3] = g11;
+}
+__global__ void k_ptc_dw_finish(PtcLayerDev L, const double* __restrict__ part, float2* __restrict__ grad) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= L.M * L.K) return;
+  const int row = idx / L.K, kk = idx % L.K;
+  double g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+  for (int sl = 0; sl < kDwSlices; sl++) {
+    const double* q = part + ((size_t)sl * L.M * L.K + idx) * 4;
+    g00 += q[0];
+    g01 += q[1];
+    g10 += q[2];
+    g11 += q[3];
   }
   const int j = row >> 2, sp = row & 3;
   const int p = kk / (L.cin * 4), i = (kk / 4) % L.cin, s = kk & 3;
@@ -617,6 +639,7 @@ struct qcd_ptc {
   short* DO;
   float* DX;
   float* Gp;
+  double* dwp;                      // weight-gradient slices [kDwSlices][M*K][4]
   double* partials;
   double* sums;
   int mix_blocks;
@@ -715,8 +738,10 @@ qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
                        (const float2*)n->dact[cur], n->DO);
     hipLaunchKernelGGL(k_ptc_mix_dw, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
                        (const short*)n->X[l], n->Gp, nb);
-    hipLaunchKernelGGL(k_ptc_dw_finish, dim3((L.M * L.K + 255) / 256), dim3(256), 0, st, L, (const float*)n->Gp,
-                       n->mix_blocks * 4, n->grad + n->woff[l]);
+    hipLaunchKernelGGL(k_ptc_dw_slices, dim3((L.M * L.K + 63) / 64, kDwSlices), dim3(64), 0, st, L,
+                       (const float*)n->Gp, n->mix_blocks * 4, n->dwp);
+    hipLaunchKernelGGL(k_ptc_dw_finish, dim3((L.M * L.K + 255) / 256), dim3(256), 0, st, L, (const double*)n->dwp,
+                       n->grad + n->woff[l]);
     if (l > 0) {
       hipLaunchKernelGGL(k_ptc_mix_dx, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
                          (const short*)n->A[l], n->DX, nb);
@@ -852,6 +877,9 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
   PTC_ALLOC(n->DO, (size_t)max_batch * N * 16 * sizeof(short));
   PTC_ALLOC(n->DX, (size_t)max_batch * N * maxKp * sizeof(float));
   PTC_ALLOC(n->Gp, (size_t)n->mix_blocks * 4 * 16 * maxKp * sizeof(float));
+  size_t max_mk = 0;
+  for (int l = 0; l < nlayers; l++) max_mk = std::max(max_mk, (size_t)n->L[l].M * n->L[l].K);
+  PTC_ALLOC(n->dwp, (size_t)kDwSlices * max_mk * 4 * sizeof(double));
   PTC_ALLOC(n->partials, (size_t)max_batch * site_blocks(g) * 2 * sizeof(double));
   PTC_ALLOC(n->sums, (size_t)max_batch * 2 * sizeof(double));
 #undef PTC_ALLOC
