@@ -183,9 +183,13 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 /* Workspace bytes that qcd_solve_mixed_ir (what = 0; what = 3 with a network
  * preconditioner), qcd_bicgstab (what = 1) or qcd_dslash with canonical
  * layout (what = 2) need, what = 0 or 1 plus 8 for the even-odd form, for inner precision
- * prec, max_iter history entries and nrhs right-hand sides.  Passing ws =
- * NULL to those calls makes the handle's own cached workspace be used
- * (allocated on first use; a handle is not safe for concurrent calls). */
+ * prec, max_iter history entries and nrhs right-hand sides.  The size depends
+ * on the handle's current launch tuning (the operator's partial-sum rows per
+ * right-hand side): query it again after qcd_set_dslash_tuning or
+ * qcd_autotune_dslash.  max_iter must be the inner iteration cap the call
+ * uses.  Passing ws = NULL to those calls makes the handle's own cached
+ * workspace be used (allocated on first use, grown when a call needs more;
+ * a handle is not safe for concurrent calls). */
 size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs);
 
 /* Precision conversion with rescaling (Alg. 3, the steps y = alpha r and
