@@ -119,3 +119,52 @@ def test_even_odd_rejects_network(q):
         q.solve_mixed_ir(g, 0.12, torch.zeros_like(b), b, inner_prec=q.FP16, precond=net, even_odd=True)
     net.close()
     g.close()
+
+
+@pytest.mark.parametrize("fp64_tile", [2, -2])
+def test_even_odd_refinement_with_fp64_tiles(q, fp64_tile):
+    # the final residual of the even-odd solve sums two launches with different
+    # partial-sum layouts when the FP64 operator runs with a lane or register
+    # tile; the reported residual must still be the oracle's |b - D x| / |b|
+    dims = (4, 6, 8, 10)
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 750)
+    bs = qi.gaussian_source(dims, 751, nrhs=4)
+    bs[2] = 0.0
+    g = q.gauge_upload(to_dev(U), dims)
+    g.set_tuning(q.FP64, 1, 0, fp64_tile)
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, kappa, x, b, inner_prec=q.FP16, tol=1e-12, even_odd=True)
+    xh = to_host(x)
+    for r in (0, 1, 3):
+        res = np.linalg.norm(bs[r] - oracle.dslash(U, xh[r], kappa, dims)) / np.linalg.norm(bs[r])
+        assert infos[r].true_rel_residual <= 1e-12 and res <= 1.01e-12
+        assert abs(infos[r].true_rel_residual - res) <= 1e-3 * res + 1e-16
+    assert not np.any(xh[2]) and infos[2].true_rel_residual == 0.0
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_even_odd_bicgstab_low_precision_several_sources(q, prec):
+    # qcd_bicgstab on the even-odd system in a storage precision, several
+    # right-hand sides (one zero) on a lattice with a ragged last block: the
+    # reported full residual is the oracle's, and it meets the requested
+    # tolerance relative to |b'| up to the precision's floor
+    dims = (4, 6, 8, 10)
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 760)
+    bs = qi.gaussian_source(dims, 761, nrhs=3)
+    bs[1] = 0.0
+    g = q.gauge_upload(to_dev(U), dims)
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    tol = {1: 1e-5, 2: 1e-2, 3: 5e-2}[prec]
+    infos = q.bicgstab(g, kappa, x, b, prec=prec, tol=tol, even_odd=True, raise_on_error=False)
+    xh = to_host(x)
+    for r in (0, 2):
+        res = np.linalg.norm(bs[r] - oracle.dslash(U, xh[r], kappa, dims)) / np.linalg.norm(bs[r])
+        assert abs(infos[r].true_rel_residual - res) <= 1e-6 * res + 1e-15
+        assert res <= 20 * tol
+    assert not np.any(xh[1])
+    g.close()
