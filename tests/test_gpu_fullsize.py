@@ -1,0 +1,101 @@
+"""The benchmark's workloads at their full sizes, in the configurations the
+benchmark times, checked against the oracle.
+
+* the headline: 32^3 x 64, eps = 0.3, kappa = 0.124, the Gaussian source of
+  seed 202, FP16-inner refinement (s = 128, sigma = 64) on the even-odd system;
+  the oracle's |b - D x| / |b| of the returned x, and x against the FP64
+  BiCGStab solution;
+* the 12 spin-colour point sources at the origin in one batched even-odd call
+  with graph replay;
+* the mixed batch 16^4 + 24^3 x 48 + 32^3 x 64 with 4 Gaussian sources each.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import qcd_inputs as qi  # noqa: E402
+from gpu_common import to_dev, to_host  # noqa: E402
+
+DIMS = (32, 32, 32, 64)
+KAPPA = 0.124
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+@pytest.fixture(scope="module")
+def field(q):
+    U = qi.gauge_field(DIMS, 0.3, 201)
+    g = q.gauge_upload(to_dev(U), DIMS)
+    yield U, g
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def oracle_rel_res(U, x, b, dims, kappa):
+    return np.linalg.norm(b - oracle.dslash(U, x, kappa, dims)) / np.linalg.norm(b)
+
+
+def test_headline_even_odd(q, field):
+    U, g = field
+    b = qi.gaussian_source(DIMS, 202)
+    bd = to_dev(b)
+    x = torch.zeros_like(bd)
+    info = q.solve_mixed_ir(g, KAPPA, x, bd, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=1e-2,
+                            even_odd=True)
+    assert info.status == "ok" and info.true_rel_residual <= 1e-12
+    xh = to_host(x)
+    res = oracle_rel_res(U, xh, b, DIMS, KAPPA)
+    assert res <= 1.01e-12 and abs(res - info.true_rel_residual) <= 1e-3 * res
+    x64 = torch.zeros_like(bd)
+    i64 = q.bicgstab(g, KAPPA, x64, bd, prec=q.FP64, tol=1e-13, even_odd=True)
+    assert i64.true_rel_residual <= 1e-13
+    assert np.linalg.norm(xh - to_host(x64)) <= 1e-10 * np.linalg.norm(xh)
+    # the iteration count stays within 20% of the FP64 solver's (the paper's claim)
+    assert 2 * info.inner_iters <= 1.2 * 2 * i64.inner_iters + 4
+
+
+def test_twelve_point_sources_even_odd(q, field):
+    U, g = field
+    bs = np.stack([qi.point_source(DIMS, sp, c) for sp in range(4) for c in range(3)])
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, KAPPA, x, b, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, even_odd=True,
+                             use_graph=True)
+    for i in infos:
+        assert i.status == "ok" and i.true_rel_residual <= 1e-12
+    for r in (0, 5, 11):
+        assert oracle_rel_res(U, to_host(x[r]), bs[r], DIMS, KAPPA) <= 1.01e-12
+    del b, x
+    torch.cuda.empty_cache()
+
+
+def test_mixed_batch(q):
+    specs = [((16, 16, 16, 16), 301), ((24, 24, 24, 48), 302), ((32, 32, 32, 64), 303)]
+    Us, gauges, bs, xs = [], [], [], []
+    for dims, seed in specs:
+        U = qi.gauge_field(dims, 0.3, seed)
+        Us.append(U)
+        gauges.append(q.gauge_upload(to_dev(U), dims))
+        bs.append(qi.gaussian_source(dims, seed + 1000, nrhs=4))
+        xs.append(torch.zeros(bs[-1].shape, dtype=torch.complex128, device="cuda"))
+    infos = q.solve_mixed_ir_batched(gauges, [KAPPA] * 3, xs, [to_dev(b) for b in bs], inner_prec=q.FP16,
+                                     s=128.0, sigma=64.0, tol=1e-12, even_odd=True, use_graph=True)
+    for (dims, _), U, b, x, lat in zip(specs, Us, bs, xs, infos):
+        for i in lat:
+            assert i.status == "ok" and i.true_rel_residual <= 1e-12
+        xh = to_host(x)
+        for r in (0, 3):
+            assert oracle_rel_res(U, xh[r], b[r], dims, KAPPA) <= 1.01e-12, dims
+    for g in gauges:
+        g.close()
+    torch.cuda.empty_cache()
