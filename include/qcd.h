@@ -36,6 +36,7 @@
 #define QCD_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -191,6 +192,15 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
  * workspace be used (allocated on first use, grown when a call needs more;
  * a handle is not safe for concurrent calls). */
 size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs);
+
+/* Synthetic sources on the device (the right-hand sides of the training pairs
+ * of the learned preconditioner, generated where they are used): ncomplex
+ * complex128 values z = (g0 + i g1) / sqrt(2), E|z|^2 = 1, written to out_dev
+ * in order.  Value j is the Box-Muller pair of draws 2j and 2j + 1 of a
+ * counter-based SplitMix64 stream keyed by seed (Steele, Lea and Flood 2014),
+ * so the values depend only on (seed, j).  Asynchronous on stream.  Errors:
+ * QCD_ERR_ARG for a null pointer or ncomplex < 0. */
+qcd_status qcd_gaussian_spinors(void* out_dev, int64_t ncomplex, uint64_t seed, void* stream);
 
 /* Precision conversion with rescaling (Alg. 3, the steps y = alpha r and
  * y~ = low_prec(y)): native_dev = round_prec(scale * canonical_dev) with

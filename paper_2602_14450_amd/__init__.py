@@ -70,6 +70,7 @@ _lib.qcd_spinor_bytes.restype = _sz
 _lib.qcd_workspace_bytes.argtypes = [_vp, _i, _i, _i, _i]
 _lib.qcd_workspace_bytes.restype = _sz
 _lib.qcd_convert.argtypes = [_vp, _i, _i, _vp, _vp, _d, _i, ctypes.POINTER(_d), _vp]
+_lib.qcd_gaussian_spinors.argtypes = [_vp, ctypes.c_int64, ctypes.c_uint64, _vp]
 _lib.qcd_unconvert.argtypes = [_vp, _i, _i, _vp, _vp, _d, _vp]
 _lib.qcd_dslash.argtypes = [_vp, _d, _i, _i, _i, _i, _vp, _vp, _vp]
 _lib.qcd_residual.argtypes = [_vp, _d, _i, _vp, _vp, _vp, ctypes.POINTER(_d), _vp]
@@ -104,7 +105,8 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
 EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
-            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann"]
+            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
+            "qcd_gaussian_spinors"]
 
 
 class QcdError(RuntimeError):
@@ -206,6 +208,15 @@ def gauge_upload(U, dims, precs=(FP64, FP32, FP16, BF16), full_links=False) -> G
 
 def _one_or_list(vals, n):
     return vals[0] if n == 1 else list(vals)
+
+
+def gaussian_spinors(shape, seed: int) -> torch.Tensor:
+    """A complex128 device tensor of the given shape (e.g. (n, V, 4, 3)) of
+    complex normal values with E|z|^2 = 1, generated on the device from a
+    counter-based stream keyed by seed."""
+    out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+    _check(_lib.qcd_gaussian_spinors(_ptr(out), out.numel(), int(seed) & (2**64 - 1), _stream()))
+    return out
 
 
 def convert(g: Gauge, prec, native: torch.Tensor, canonical: torch.Tensor, scale=1.0, ftz=False, want_norm=True):

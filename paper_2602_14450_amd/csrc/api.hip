@@ -777,6 +777,14 @@ qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* cano
   return QCD_OK;
 }
 
+qcd_status qcd_gaussian_spinors(void* out_dev, int64_t ncomplex, uint64_t seed, void* stream) {
+  if (!out_dev || ncomplex < 0) return fail(QCD_ERR_ARG, "invalid argument");
+  if (ncomplex == 0) return QCD_OK;
+  launch_gaussian((double*)out_dev, ncomplex, seed, S(stream));
+  HIP_LAUNCHED();
+  return QCD_OK;
+}
+
 qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec, qcd_layout layout, int nrhs,
                       void* out_dev, const void* in_dev, void* stream) {
   qcd_status rc = check_gauge(g, prec);

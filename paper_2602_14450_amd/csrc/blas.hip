@@ -8,6 +8,8 @@
 #include "common.h"
 #include "internal.h"
 
+#include <algorithm>
+
 namespace qcd {
 
 // Site-ordered kernels (layout / precision conversions) use one thread per
@@ -640,6 +642,38 @@ void launch_unpack_spinor_split(const Geom& g, int n, double* canon, const void*
                                 hipStream_t st) {
   hipLaunchKernelGGL(k_unpack_spinor<double2>, dim3(site_grid(g), n), dim3(256), 0, st, g, canon,
                      (const double2*)even, nullptr, 1.0, (const double2*)odd);
+}
+
+// Complex normal values z = (g0 + i g1) / sqrt(2) (so E|z|^2 = 1) in
+// canonical complex128 order: component j takes draws 2j and 2j + 1 of a
+// counter-based SplitMix64 stream (Steele, Lea and Flood, OOPSLA 2014: the
+// draw n of the stream with key k is the SplitMix64 finaliser of
+// k + (n + 1) * golden gamma, key = finaliser(seed + gamma)), mapped to (0, 1]
+// with 53 bits and paired by the Box-Muller transform.  Values depend only on
+// (seed, j), not on the launch shape.
+__host__ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+constexpr uint64_t kSm64Gamma = 0x9e3779b97f4a7c15ULL;
+__device__ __forceinline__ double sm64_unit(uint64_t key, uint64_t n) {
+  return (double)((sm64_mix(key + (n + 1) * kSm64Gamma) >> 11) + 1) * (1.0 / 9007199254740992.0);
+}
+__global__ __launch_bounds__(256) void k_gaussian(double2* __restrict__ out, int64_t n, uint64_t key) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+    const double u1 = sm64_unit(key, 2 * (uint64_t)j), u2 = sm64_unit(key, 2 * (uint64_t)j + 1);
+    const double r = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
+    double sn, cs;
+    sincos(6.283185307179586476925286766559 * u2, &sn, &cs);
+    out[j] = make_double2(r * cs, r * sn);
+  }
+}
+void launch_gaussian(double* out, int64_t ncomplex, uint64_t seed, hipStream_t st) {
+  const uint64_t key = sm64_mix(seed + kSm64Gamma);
+  const int64_t blocks = std::min<int64_t>((ncomplex + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_gaussian, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, (double2*)out,
+                     ncomplex, key);
 }
 
 template <typename S> static void zero_t(const Geom& g, int n, void* dst, hipStream_t st) {

@@ -1,7 +1,7 @@
 """Training of the parallel-transport preconditioner on pairs the solver makes.
 
-Each pair is a Gaussian source r and e = D^-1 r from the library's own FP32
-BiCGStab (relative residual 1e-6).  Pairs live on the device as complex64
+Each pair is a Gaussian source r (generated on the device) and e = D^-1 r
+from the library's own FP32 BiCGStab (relative residual 1e-6).  Pairs live on the device as complex64
 (half the bytes of the canonical complex128 that the C ABI takes; a batch is
 widened just before each call).  The network starts from the third-order
 Neumann series of D^-1 and is trained with Adam through qcd_ptc_train_step,
@@ -19,7 +19,7 @@ import torch
 
 import qcd_inputs as qi
 
-from . import FP32, PTC, Gauge, bicgstab, gauge_upload
+from . import FP32, PTC, Gauge, bicgstab, gauge_upload, gaussian_spinors
 
 
 @dataclass
@@ -41,7 +41,7 @@ def make_pairs(dims, kappa, gauge_seed, npairs, source_seed, eps=0.3, batch=16, 
     iters = []
     for b0 in range(0, npairs, batch):
         nb = min(batch, npairs - b0)
-        r = torch.from_numpy(qi.gaussian_source(dims, source_seed + b0, nrhs=nb)).to("cuda")
+        r = gaussian_spinors((nb, V, 4, 3), source_seed + b0)
         x = torch.zeros_like(r)
         infos = bicgstab(g, kappa, x, r, prec=FP32, tol=tol, max_iter=max_iter, history=False)
         infos = infos if isinstance(infos, list) else [infos]

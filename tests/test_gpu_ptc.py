@@ -234,3 +234,16 @@ def test_rejects_bad_configuration(q):
     with pytest.raises(q.QcdError):
         q.PTC(g64, CH)
     g64.close()
+
+
+def test_device_sources_match_the_input_generator(q):
+    # the training pairs' sources are drawn on the device from the same
+    # counter-based recipe as the seeded input generator (SplitMix64 draws
+    # 2j, 2j + 1 and Box-Muller): equal up to the last bits of log / sin / cos
+    dims = (4, 4, 6, 8)
+    for seed, n in ((2_000_000, 3), (7, 1), (2**63 + 5, 2)):
+        got = to_host(q.gaussian_spinors((n, qi.volume(dims), 4, 3), seed))
+        want = qi.gaussian_source(dims, seed, nrhs=n)
+        assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want)), seed
+    big = to_host(q.gaussian_spinors((1 << 20,), 11))
+    assert abs(np.mean(np.abs(big) ** 2) - 1.0) < 1e-2 and abs(np.mean(big)) < 5e-3
