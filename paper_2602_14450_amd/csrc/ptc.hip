@@ -71,10 +71,18 @@ __device__ __forceinline__ void su3_apply(const cx<float> (&u)[9], const cx<floa
 
 __device__ __forceinline__ size_t col_of(const Geom& g, int par, int h) { return ((size_t)par * g.nb * 64 + h) * 3; }
 __device__ __forceinline__ size_t ncols(const Geom& g) { return (size_t)2 * g.nb * 64 * 3; }
+// Element (column n, k) of a column-major operand of the two-pass form (X in
+// BF16, DX in FP32), stored k-tile-major: per batch and k-tile the 16 k-values
+// of each column are contiguous, so the 16 columns x 16 k of one matrix-core
+// tile are one contiguous segment.  nc = columns per batch entry, nk = Kp / 16.
+__device__ __forceinline__ size_t xidx(size_t nc, int nk, size_t n, int k) {
+  const size_t b = n / nc, col = n - b * nc;
+  return ((b * nk + (k >> 4)) * nc + col) * 16 + (k & 15);
+}
 
 // ---------------------------------------------------------------------------
-// Forward transport: X[b][n][k] (BF16), n = column (site, colour),
-// k = reim*K + (p*cin + i)*4 + spin; rows [2K, Kp) and padding sites are zero.
+// Forward transport: X (BF16) at (n, k), n = b * ncols + column (site, colour),
+// k = reim*K + (p*cin + i)*4 + spin; k in [2K, Kp) and padding sites are zero.
 __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, const float2* __restrict__ act,
                                                        const float2* __restrict__ U, int recon, short* __restrict__ X) {
   const int b = blockIdx.y;
@@ -82,16 +90,18 @@ __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, co
   const int per = g.nb * 64;
   if (i_site >= 2 * per) return;
   const int par = i_site >= per, h = i_site - par * per;
-  short* Xb = X + ((size_t)b * ncols(g) + col_of(g, par, h)) * L.Kp;
+  const size_t nc = ncols(g);
+  const int nk = L.Kp / 16;
+  const size_t n0 = (size_t)b * nc + col_of(g, par, h);  // column of colour 0
   if (h >= g.Vh) {  // padding site: zero columns
     for (int c = 0; c < 3; c++)
-      for (int k = 0; k < L.Kp; k++) Xb[(size_t)c * L.Kp + k] = 0;
+      for (int k = 0; k < L.Kp; k++) X[xidx(nc, nk, n0 + c, k)] = 0;
     return;
   }
   const Coord c = decode(g, par, h);
   const size_t fstride = spinor_elems(g);
   for (int k = 2 * L.K; k < L.Kp; k++)
-    for (int cc = 0; cc < 3; cc++) Xb[(size_t)cc * L.Kp + k] = 0;
+    for (int cc = 0; cc < 3; cc++) X[xidx(nc, nk, n0 + cc, k)] = 0;
   for (int i = 0; i < L.cin; i++) {
     const float2* f = act + ((size_t)b * L.cin + i) * fstride;
     for (int p = 0; p < 9; p++) {
@@ -110,15 +120,15 @@ __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, co
       }
       const int k0 = (p * L.cin + i) * 4;
       for (int cc = 0; cc < 3; cc++) {
-        short* col = Xb + (size_t)cc * L.Kp;
         bf16x4 re, im;
 #pragma unroll
         for (int s = 0; s < 4; s++) {
           re[s] = to_bf16(t[3 * s + cc].re);
           im[s] = to_bf16(t[3 * s + cc].im);
         }
-        *reinterpret_cast<bf16x4*>(col + k0) = re;
-        *reinterpret_cast<bf16x4*>(col + L.K + k0) = im;
+        // k0 and K are multiples of 4, so each group of 4 stays in one k-tile
+        *reinterpret_cast<bf16x4*>(X + xidx(nc, nk, n0 + cc, k0)) = re;
+        *reinterpret_cast<bf16x4*>(X + xidx(nc, nk, n0 + cc, L.K + k0)) = im;
       }
     }
   }
@@ -163,12 +173,11 @@ __global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const sh
   const size_t fstride = spinor_elems(g);
   for (size_t tile = wave; tile < ntiles; tile += nwaves) {
     const size_t n = tile * 16 + (lane % 16);
-    const short* xc = X + n * L.Kp + 4 * (lane / 16);
     f32x4 acc = {0, 0, 0, 0};
 #pragma unroll
     for (int kt = 0; kt < 9; kt++) {
       if (kt >= nk) break;
-      const bf16x4 bf = *reinterpret_cast<const bf16x4*>(xc + kt * 16);
+      const bf16x4 bf = *reinterpret_cast<const bf16x4*>(X + xidx(N, nk, n, kt * 16 + 4 * (lane / 16)));
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kt], bf, acc, 0, 0, 0);
     }
     // lane holds rows 4*(lane/16) + q of column n
@@ -354,6 +363,7 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const
   const int nk = L.Kp / 16;
   for (size_t tile = wave; tile < ntiles; tile += nwaves) {
     const size_t n = tile * 16 + (lane % 16);
+    const size_t nc = ncols(g);
     const bf16x4 bf = *reinterpret_cast<const bf16x4*>(DO + n * 16 + 4 * (lane / 16));
     for (int kt = 0; kt < nk; kt++) {
       bf16x4 at;  // A^T tile: row = k, column = r
@@ -362,7 +372,7 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const
       f32x4 acc = {0, 0, 0, 0};
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bf, acc, 0, 0, 0);
       // lane holds rows k = kt*16 + 4*(lane/16) + q of column n
-      *reinterpret_cast<f32x4*>(DX + n * L.Kp + kt * 16 + 4 * (lane / 16)) = acc;
+      *reinterpret_cast<f32x4*>(DX + xidx(nc, nk, n, kt * 16 + 4 * (lane / 16))) = acc;
     }
   }
 }
@@ -377,7 +387,8 @@ __global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L
   const int par = i_site >= g.Vh, h = i_site - par * g.Vh;
   const Coord c = decode(g, par, h);
   const size_t fstride = spinor_elems(g);
-  const float* DXb = DX + (size_t)b * ncols(g) * L.Kp;
+  const size_t nc = ncols(g);
+  const int nk = L.Kp / 16;
   for (int i = 0; i < L.cin; i++) {
     cx<float> acc[12];
 #pragma unroll
@@ -395,12 +406,14 @@ __global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L
       }
       cx<float> f[12];
       const int k0 = (p * L.cin + i) * 4;
-      const float* col = DXb + col_of(g, sp, sh) * L.Kp;
+      const size_t n0 = (size_t)b * nc + col_of(g, sp, sh);
 #pragma unroll
-      for (int cc = 0; cc < 3; cc++)
+      for (int cc = 0; cc < 3; cc++) {
+        const f32x4 re = *reinterpret_cast<const f32x4*>(DX + xidx(nc, nk, n0 + cc, k0));
+        const f32x4 im = *reinterpret_cast<const f32x4*>(DX + xidx(nc, nk, n0 + cc, L.K + k0));
 #pragma unroll
-        for (int s = 0; s < 4; s++)
-          f[3 * s + cc] = cx<float>(col[(size_t)cc * L.Kp + k0 + s], col[(size_t)cc * L.Kp + L.K + k0 + s]);
+        for (int s = 0; s < 4; s++) f[3 * s + cc] = cx<float>(re[s], im[s]);
+      }
       if (p == 0) {
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = acc[k] + f[k];
@@ -428,6 +441,7 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const
   const size_t N = ncols(g) * nbatch;
   const size_t ntiles = N / 16;
   const int nk = L.Kp / 16;
+  const size_t nc = ncols(g);
   f32x4 acc[9];
 #pragma unroll
   for (int kt = 0; kt < 9; kt++) acc[kt] = (f32x4){0, 0, 0, 0};
@@ -439,9 +453,9 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const
 #pragma unroll
     for (int kt = 0; kt < 9; kt++) {
       if (kt >= nk) break;
-      bf16x4 bb;  // B[nn][k] = X[n0 + nn][kt*16 + lane % 16]
+      bf16x4 bb;  // B[nn][k] = X(n0 + nn, kt*16 + lane % 16)
 #pragma unroll
-      for (int q = 0; q < 4; q++) bb[q] = X[(n0 + 4 * (lane / 16) + q) * L.Kp + kt * 16 + (lane % 16)];
+      for (int q = 0; q < 4; q++) bb[q] = X[xidx(nc, nk, n0 + 4 * (lane / 16) + q, kt * 16 + (lane % 16))];
       acc[kt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[kt], 0, 0, 0);
     }
   }
