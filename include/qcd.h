@@ -309,6 +309,14 @@ qcd_status qcd_ptc_set_weights(qcd_ptc* net, const double* w_host, void* stream)
 qcd_status qcd_ptc_get_weights(const qcd_ptc* net, double* w_host, void* stream);
 /* out = M(in) for nbatch canonical complex128 fields (device). */
 qcd_status qcd_ptc_apply(qcd_ptc* net, int nbatch, void* out_dev, const void* in_dev, void* stream);
+/* As qcd_ptc_apply, with the activations stored in prec: QCD_FP32 is
+ * qcd_ptc_apply; QCD_FP16 rounds the input to binary16 and runs the layers as
+ * an FP16 inner solve with qcd_ir_params.precond applies them (FP16 links and
+ * activations, FP32 sums, the weights rounded to BF16 as above).  QCD_ERR_ARG
+ * for another precision or, with QCD_FP16, a gauge handle without FP16
+ * links.  Inputs must lie within the binary16 range. */
+qcd_status qcd_ptc_apply_prec(qcd_ptc* net, qcd_prec prec, int nbatch, void* out_dev, const void* in_dev,
+                              void* stream);
 /* Loss (1/B) sum_b |M(r_b) - e_b|^2 / |e_b|^2 and, if grad_host is not NULL,
  * its gradient dL/dRe W + i dL/dIm W (host complex128, layout of the
  * weights).  r_dev, e_dev: nbatch canonical complex128 fields.  Synchronises. */

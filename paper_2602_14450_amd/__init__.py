@@ -92,11 +92,13 @@ _lib.qcd_ptc_num_weights.restype = _sz
 _lib.qcd_ptc_set_weights.argtypes = [_vp, _vp, _vp]
 _lib.qcd_ptc_get_weights.argtypes = [_vp, _vp, _vp]
 _lib.qcd_ptc_apply.argtypes = [_vp, _i, _vp, _vp, _vp]
+_lib.qcd_ptc_apply_prec.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
 _lib.qcd_ptc_loss_grad.argtypes = [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp, _vp]
 _lib.qcd_ptc_train_step.argtypes = [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_d), _vp]
 _lib.qcd_ptc_set_gauge.argtypes = [_vp, _vp]
 _lib.qcd_ptc_init_neumann.argtypes = [_vp, _d, _vp]
 for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get_weights", "qcd_ptc_apply",
+           "qcd_ptc_apply_prec",
            "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
            "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
@@ -105,7 +107,7 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
 EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
-            "qcd_ptc_apply", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
+            "qcd_ptc_apply", "qcd_ptc_apply_prec", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
             "qcd_gaussian_spinors"]
 
 
@@ -409,6 +411,12 @@ class PTC:
         """out = M(inp) for one field (V, 4, 3) or a batch (B, V, 4, 3), complex128."""
         nb = 1 if inp.dim() == 3 else inp.shape[0]
         _check(_lib.qcd_ptc_apply(self.handle, nb, _ptr(out), _ptr(_as_c128(inp)), _stream()))
+        return out
+
+    def apply_prec(self, out: torch.Tensor, inp: torch.Tensor, prec: int):
+        """out = M(inp) with activations stored in prec (FP32, or FP16 as the inner solver applies it)."""
+        nb = 1 if inp.dim() == 3 else inp.shape[0]
+        _check(_lib.qcd_ptc_apply_prec(self.handle, prec, nb, _ptr(out), _ptr(_as_c128(inp)), _stream()))
         return out
 
     def loss_grad(self, r: torch.Tensor, e: torch.Tensor, want_grad=True):

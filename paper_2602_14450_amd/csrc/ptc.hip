@@ -24,6 +24,7 @@
 
 #include "qcd.h"
 #include "internal.h"
+#include "half_ops.h"
 
 namespace qcd {
 
@@ -229,6 +230,83 @@ __global__ void k_ptc_prep_Af(PtcLayerDev L, const float2* __restrict__ W, short
   A[idx] = to_bf16(v);
 }
 
+// The transported spin half of one k-slot in binary16 form (FP16 activations
+// and links): the two spins' colour vectors come from three 8-byte loads, the
+// link's row 2 is rebuilt in binary16, and U v / U^dag v use exact binary16
+// products summed in FP32 (the Wilson operator's FP16 arithmetic).
+template <int CIN>
+__device__ __forceinline__ void fused_transport_h(const Geom& g, const __half2* __restrict__ in,
+                                                  const __half2* __restrict__ U, int recon, int b, int slot, int par,
+                                                  int h, const Coord& c, size_t fstride, cx<float> (&t)[2][3]) {
+  using Gr = typename Lay<__half2>::Gran;  // 4 complex components
+  const int p = slot / (2 * CIN), i = (slot >> 1) % CIN, sh = slot & 1;
+  const __half2* f = in + ((size_t)b * CIN + i) * fstride;
+  int sp = par, sh_idx = h, mu = 0;
+  bool fwd = true;
+  if (p > 0) {
+    mu = (p - 1) >> 1;
+    fwd = ((p - 1) & 1) == 0;
+    sp = par ^ 1;
+    sh_idx = nbr(g, h, c, mu, fwd ? 1 : -1);
+  }
+  // components 6 sh + 2 m, 6 sh + 2 m + 1 (m = 0..2; spins 2 sh, 2 sh + 1)
+  // share a granule: three 8-byte loads at computed offsets, so the spin
+  // half is never picked out of loaded registers by a run-time index
+  typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+  const __half2* fb = f + sp_block(g, sp, sh_idx) + (sh_idx & 63) * 4;
+  h2v v[2][3];  // v[sl][cc]: component 6 sh + 3 sl + cc
+#pragma unroll
+  for (int m = 0; m < 3; m++) {
+    const int k = 6 * sh + 2 * m;
+    const h4v d = *reinterpret_cast<const h4v*>(fb + (k >> 2) * 64 * 4 + (k & 3));
+    // swizzles, not __builtin_bit_cast of the elements of a two-dword
+    // vector: the compiler (ROCm 7.2 clang) gives element 0 for d.y there
+    v[(2 * m) / 3][(2 * m) % 3] = d.xy;
+    v[(2 * m + 1) / 3][(2 * m + 1) % 3] = d.zw;
+  }
+  if (p == 0) {
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++)
+#pragma unroll
+      for (int cc = 0; cc < 3; cc++) t[sl][cc] = cx<float>((float)v[sl][cc].x, (float)v[sl][cc].y);
+    return;
+  }
+  // U_mu(x) (forward) or U_mu(x - mu) (backward, applied as its adjoint)
+  const int lp = fwd ? par : par ^ 1, lh = fwd ? h : sh_idx, lane = lh & 63;
+  h2v u[9];
+  if (recon) {
+    const __half2* lb = U + lk_block<6>(g, mu, lp, lh);
+    const Gr q = *reinterpret_cast<const Gr*>(lb + lane * 4);
+    const __half2* tl = lb + 4 * 64 + lane * 2;
+#pragma unroll
+    for (int k = 0; k < 4; k++) u[k] = h2_of(q.s[k]);
+    u[4] = h2_of(tl[0]);
+    u[5] = h2_of(tl[1]);
+    h_third_row(u);
+  } else {
+    const __half2* lb = U + lk_block<9>(g, mu, lp, lh);
+    const Gr q0 = *reinterpret_cast<const Gr*>(lb + lane * 4);
+    const Gr q1 = *reinterpret_cast<const Gr*>(lb + 64 * 4 + lane * 4);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      u[k] = h2_of(q0.s[k]);
+      u[4 + k] = h2_of(q1.s[k]);
+    }
+    u[8] = h2_of(lb[8 * 64 + lane]);
+  }
+  if (fwd) {
+    HLink<false> L;
+    h_link_prep<false>(u, L);
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) h_mult<false>(L, v[sl], t[sl]);
+  } else {
+    HLink<true> L;
+    h_link_prep<true>(u, L);
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) h_mult<true>(L, v[sl], t[sl]);
+  }
+}
+
 // out[b][j] = oscale * sum_{p,i} W[p][j][i] T_p in[b][i] for batch b = blockIdx.y;
 // grid.x = 2 * nb (one 64-site block of one parity per workgroup).  Batches
 // whose solver has stopped (scal[b].active == 0) are skipped when scal is given.
@@ -263,7 +341,9 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
     for (int sl = 0; sl < 2; sl++)
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) t[sl][cc] = cx<float>(0, 0);
-    if (slot < 18 * CIN) {
+    if constexpr (std::is_same<SA, __half2>::value && std::is_same<SL, __half2>::value) {
+      if (slot < 18 * CIN) fused_transport_h<CIN>(g, in, U, recon, b, slot, par, h, c, fstride, t);
+    } else if (slot < 18 * CIN) {
       const int p = slot / (2 * CIN), i = (slot >> 1) % CIN, sh = slot & 1;
       const SA* f = in + ((size_t)b * CIN + i) * fstride;
       if (p == 0) {
@@ -883,7 +963,8 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
     PTC_ALLOC(n->X[l], (size_t)max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * sizeof(short));
   }
   for (int l = 0; l <= nlayers; l++) PTC_ALLOC(n->act[l], fields_bytes(g, (size_t)max_batch * channels[l]));
-  for (int l = 1; l < nlayers; l++)
+  // act16[0] and act16[nlayers] hold the input and output of qcd_ptc_apply_prec in FP16
+  for (int l = 0; l <= nlayers; l++)
     PTC_ALLOC(n->act16[l], (size_t)max_batch * channels[l] * spinor_elems(g) * sizeof(__half2));
   PTC_ALLOC(n->target, fields_bytes(g, max_batch));
   PTC_ALLOC(n->dact[0], fields_bytes(g, (size_t)max_batch * maxc));
@@ -902,7 +983,7 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
     // activations of padding sites are never written: clear once so they stay finite
     for (int l = 0; l <= nlayers; l++)
       (void)hipMemsetAsync(n->act[l], 0, fields_bytes(g, (size_t)max_batch * channels[l]), st);
-    for (int l = 1; l < nlayers; l++)
+    for (int l = 0; l <= nlayers; l++)
       (void)hipMemsetAsync(n->act16[l], 0, (size_t)max_batch * channels[l] * spinor_elems(g) * sizeof(__half2), st);
     (void)hipMemsetAsync(n->w, 0, n->nweights * sizeof(float2), st);
     (void)hipMemsetAsync(n->adam_m, 0, n->nweights * sizeof(float2), st);
@@ -956,6 +1037,22 @@ qcd_status qcd_ptc_apply(qcd_ptc* n, int nbatch, void* out_dev, const void* in_d
   launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)in_dev, 1.0, 0, nullptr, st);
   forward(n, nbatch, false, st);
   launch_unpack_spinor(n->g, kFP32, nbatch, (double*)out_dev, n->act[n->nlayers], nullptr, 1.0, st);
+  PTC_LAUNCHED();
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_apply_prec(qcd_ptc* n, qcd_prec prec, int nbatch, void* out_dev, const void* in_dev,
+                              void* stream) {
+  if (prec == QCD_FP32) return qcd_ptc_apply(n, nbatch, out_dev, in_dev, stream);
+  if (prec != QCD_FP16) return pfail(QCD_ERR_ARG, "the network applies in FP32 or FP16");
+  qcd_status rc = check_batch(n, nbatch);
+  if (rc) return rc;
+  if (!out_dev || !in_dev) return pfail(QCD_ERR_ARG, "null vector");
+  if (!n->gauge->U[kFP16]) return pfail(QCD_ERR_ARG, "the gauge handle holds no FP16 links");
+  hipStream_t st = (hipStream_t)stream;
+  launch_pack_spinor(n->g, kFP16, nbatch, n->act16[0], (const double*)in_dev, 1.0, 0, nullptr, st);
+  ptc_apply_half(n, nbatch, n->act16[0], n->act16[n->nlayers], 1.0f, 0, nullptr, st);
+  launch_unpack_spinor(n->g, kFP16, nbatch, (double*)out_dev, n->act16[n->nlayers], nullptr, 1.0, st);
   PTC_LAUNCHED();
   return QCD_OK;
 }

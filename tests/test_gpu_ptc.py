@@ -96,6 +96,54 @@ def test_forward_matches_oracle(q, dims, seed):
     g.close()
 
 
+@pytest.mark.parametrize("dims", DIMS + [(8, 8, 8, 8)])
+@pytest.mark.parametrize("full_links", [False, True])
+def test_fp16_forward_matches_oracle(q, dims, full_links):
+    # The form the FP16 inner solve applies: binary16 input, links and hidden
+    # activations (u = 2^-11 each, well below the BF16 rounding of the channel
+    # mixing), so the FP32 form's tolerances hold.  Both link storages: two
+    # rows with the third rebuilt, and all three rows.
+    U = qi.gauge_field(dims, 0.3, 60)
+    psi = qi.gaussian_source(dims, 61, nrhs=2)
+    Ws = qi.ptc_weights(CH, seed=62, scale=0.5)
+    nb = P.neighbours(dims)
+    g = q.gauge_upload(to_dev(U), dims, full_links=full_links)
+    net = q.PTC(g, CH, max_batch=2)
+    net.set_weights(Ws)
+    out = torch.empty_like(to_dev(psi))
+    net.apply_prec(out, to_dev(psi), q.FP16)
+    got = to_host(out)
+    for b in range(2):
+        want = P.forward(U, psi[b], Ws, nb)
+        check(got[b], want, 1e-2, 5e-2, f"fp16 forward dims={dims} full={full_links} b={b}")
+    # one field alone gives the same bits as its slot in the batch
+    one = torch.empty_like(to_dev(psi[1]))
+    net.apply_prec(one, to_dev(psi[1]), q.FP16)
+    assert torch.equal(one, out[1])
+    # FP32 through the same entry point is qcd_ptc_apply
+    a = torch.empty_like(out)
+    b32 = torch.empty_like(out)
+    net.apply_prec(a, to_dev(psi), q.FP32)
+    net.apply(b32, to_dev(psi))
+    assert torch.equal(a, b32)
+    net.close()
+    g.close()
+
+
+def test_fp16_apply_needs_fp16_links(q):
+    dims = (4, 4, 4, 8)
+    g = q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, 63)), dims, precs=(q.FP64, q.FP32))
+    net = q.PTC(g, CH, max_batch=1)
+    psi = to_dev(qi.gaussian_source(dims, 64))
+    out = torch.empty_like(psi)
+    with pytest.raises(q.QcdError):
+        net.apply_prec(out, psi, q.FP16)
+    with pytest.raises(q.QcdError):
+        net.apply_prec(out, psi, q.BF16)
+    net.close()
+    g.close()
+
+
 def test_single_layer_weights_layout(q):
     # one layer, one channel, only the +t path with a spin matrix S: out = S (U_t(x) psi(x+t))
     dims = (4, 4, 4, 8)
