@@ -85,18 +85,28 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+DSLASH_SOURCES = ("dslash.hip", "half_ops.h", "common.h")
+
+
+def dslash_source_sha():
+    """sha256 over the Wilson operator's kernel sources, in the order of DSLASH_SOURCES."""
+    h = hashlib.sha256()
+    for name in DSLASH_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2602_14450_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_counter(label):
     """A per-launch counter figure of the Wilson operator from the committed
     counter summary ("<label>: <integer>"), or None if the kernel source changed
     since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_dslash_32x32x32x64.md")
-    src = os.path.join(ROOT, "paper_2602_14450_amd", "csrc", "dslash.hip")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = dslash_source_sha()
     except OSError:
         return None
-    m = re.search(r"dslash\.hip sha256: ([0-9a-f]{64})", text)
+    m = re.search(r"dslash sources sha256: ([0-9a-f]{64})", text)
     t = re.search(rf"{re.escape(label)}: (\d+)", text)
     if not m or not t or m.group(1) != sha:
         return None
