@@ -294,7 +294,29 @@ __device__ __forceinline__ void fused_transport_h(const Geom& g, const __half2* 
     }
     u[8] = h2_of(lb[8 * 64 + lane]);
   }
-  if (fwd) {
+  if constexpr (CIN == 1) {
+    // The two lane halves of a wave take a forward and a backward hop here,
+    // so both take one product form: entry (r, b) of U, or of U^dag read as
+    // conj(u[3b + r]), with the sign flips of each form applied per lane.
+    // Same products in the same order as h_mult, without running both forms.
+    const uint32_t pm = fwd ? 0x80000000u : 0u;  // (re, -im) forward, (re, im) backward
+    const uint32_t qm = fwd ? 0u : 0x8000u;      // (im, re) forward, (-im, re) backward
+    HLink<false> L;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+      for (int bb = 0; bb < 3; bb++) {
+        // both entries as values first: a conditional of two array elements
+        // would select an address and index the array at run time
+        const uint32_t ef = __builtin_bit_cast(uint32_t, u[3 * r + bb]);
+        const uint32_t eb = __builtin_bit_cast(uint32_t, u[3 * bb + r]);
+        const uint32_t a = fwd ? ef : eb;
+        L.p[3 * r + bb] = __builtin_bit_cast(h2v, a ^ pm);
+        L.q[3 * r + bb] = __builtin_bit_cast(h2v, ((a >> 16) | (a << 16)) ^ qm);
+      }
+#pragma unroll
+    for (int sl = 0; sl < 2; sl++) h_mult<false>(L, v[sl], t[sl]);
+  } else if (fwd) {  // uniform over the wave: one path per k-tile when C_in = 2
     HLink<false> L;
     h_link_prep<false>(u, L);
 #pragma unroll
