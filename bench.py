@@ -146,18 +146,20 @@ def learned_form(q, torch, np, qi, kappa, pairs_per_field, max_iter):
                          precond_fallback=info.precond_fallback, precond_scale=info.precond_scale)
         print(f"[bench] learned form {name}: {min(times)*1e3:.2f} ms inner={info.inner_iters} "
               f"res={info.true_rel_residual:.2e}", file=sys.stderr, flush=True)
-    # one network application (FP32 canonical in/out through the C ABI)
+    # one network application (canonical FP64 in/out through the C ABI) with FP32
+    # activations, and with FP16 activations and links (the solver's form)
     psi = torch.from_numpy(qi.gaussian_source(dims, 7)).cuda()
     out = torch.empty_like(psi)
-    for _ in range(3):
-        net.apply(out, psi)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(20):
-        net.apply(out, psi)
-    e1.record()
-    e1.synchronize()
-    res["network_apply_us"] = e0.elapsed_time(e1) / 20 * 1e3
+    for key, prec in (("network_apply_us", q.FP32), ("network_apply_fp16_us", q.FP16)):
+        for _ in range(3):
+            net.apply_prec(out, psi, prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            net.apply_prec(out, psi, prec)
+        e1.record()
+        e1.synchronize()
+        res[key] = e0.elapsed_time(e1) / 20 * 1e3
     res["training"] = tinfo
     res["_weights"] = net.get_weights()   # reused unchanged at 48^3 x 96, not printed
     res["workload"] = ("16^4, eps=0.3 links, kappa=0.124; network 1->2->2->1 spinor fields, BF16 MFMA mixing; "
