@@ -295,3 +295,24 @@ def test_device_sources_match_the_input_generator(q):
         assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want)), seed
     big = to_host(q.gaussian_spinors((1 << 20,), 11))
     assert abs(np.mean(np.abs(big) ** 2) - 1.0) < 1e-2 and abs(np.mean(big)) < 5e-3
+
+
+def test_fp16_apply_at_full_size_matches_fp32_apply(q):
+    # 32^3 x 64, the headline lattice: the oracle's whole-lattice forward is
+    # too slow here, so the FP16 form (checked against the oracle above on
+    # small lattices) is compared with the FP32 form of the same weights.
+    # They differ by binary16 roundings (u = 2^-11) of input, links and hidden
+    # activations, and by BF16 roundings of slightly different mixing inputs:
+    # the oracle tolerances hold between them too.
+    dims = (32, 32, 32, 64)
+    V = qi.volume(dims)
+    g = q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, 70)), dims, precs=(q.FP32, q.FP16))
+    net = q.PTC(g, CH, max_batch=1)
+    net.set_weights(qi.ptc_weights(CH, seed=71, scale=0.5))
+    psi = q.gaussian_spinors((V, 4, 3), 72)
+    o16, o32 = torch.empty_like(psi), torch.empty_like(psi)
+    net.apply_prec(o16, psi, q.FP16)
+    net.apply_prec(o32, psi, q.FP32)
+    check(to_host(o16), to_host(o32), 1e-2, 5e-2, "fp16 vs fp32 at 32^3 x 64")
+    net.close()
+    g.close()
