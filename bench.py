@@ -500,6 +500,16 @@ def main():
         del xb, bpd, wsb
         batched["mixed_lattices"] = mixed_lattices(q, torch, qi, k, max_iter, eo)
 
+    # extreme |eigenvalues| of eq. (5)'s matrix (Sec. 6 quotes their ratio for its configuration)
+    ts = time.perf_counter()
+    sp_hi, sp_lo = g.eo_spectrum(k, power_iters=800, inverse_iters=40, seed=3)
+    spectrum = dict(abs_max=sp_hi, abs_min=sp_lo, ratio=sp_hi / sp_lo, power_iters=800, inverse_iters=40,
+                    seconds=time.perf_counter() - ts,
+                    method="power and inverse iteration on 1 - kappa^2 H_eo H_oe (estimates: max from below, "
+                           "min from above as the iterations converge)")
+    print(f"[bench] even-odd spectrum: |lambda| max {sp_hi:.4f} min {sp_lo:.4f} ratio {sp_hi / sp_lo:.2f}",
+          file=sys.stderr, flush=True)
+
     at_size = dims == (32, 32, 32, 64)
     traffic = measured_counter("traffic bytes per launch fp16") if at_size else None
     valu = measured_counter("valu wave-instructions per launch fp16") if at_size else None
@@ -573,6 +583,7 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "solvers": others,
         ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched,
         "learned": learned, "largest_48x48x48x96": largest, "rescaling_study": rescaling,
+        "spectrum_even_odd": spectrum,
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,

@@ -271,6 +271,26 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
                                       void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
                                       qcd_solve_info* const* info, void* stream);
 
+/* Estimates of the largest and smallest |eigenvalue| of the even-odd matrix
+ * A = 1 - kappa^2 H_eo H_oe of eq. (5), the ratio Sec. 6 quotes for its test
+ * configuration (a diagnostic of the conditioning of the synthetic fields).
+ * Largest: power_iters steps of x <- A x / |A x| in FP64 from the even half
+ * of the Gaussian field with the given seed; abs_max is the geometric mean of
+ * |A x_k| over the second half of the steps (a complex-conjugate pair at the
+ * top, which gamma_5-hermiticity allows, makes single ratios oscillate; the
+ * mean then converges as 1 / power_iters).  Smallest: the same with
+ * x <- A^-1 x / |A^-1 x| for inverse_iters steps (seed + 1), where A^-1 x is
+ * the even half of the solution of D y = (x on even sites, 0 on odd sites)
+ * from qcd_solve_mixed_ir (even-odd, FP16 inner if the handle holds FP16
+ * links, else FP64; tolerance 1e-12); abs_min = 1 / the mean, NaN if
+ * inverse_iters = 0.  Needs FP64 links.  Allocates and frees its own buffers
+ * (three one-parity FP64 fields and two canonical fields); synchronises.
+ * Errors: QCD_ERR_ARG (null handle or output, power_iters outside 2..100000,
+ * inverse_iters outside 0..1000), QCD_NOT_CONVERGED if a solve stops short,
+ * QCD_ERR_NONFINITE, QCD_ERR_HIP. */
+qcd_status qcd_eo_spectrum(const qcd_gauge* g, double kappa, int power_iters, int inverse_iters, uint64_t seed,
+                           double* abs_max, double* abs_min, void* stream);
+
 /* ------------------------------------------------------------------------
  * Learned preconditioner: a gauge-covariant parallel-transport network.
  * A layer maps C_in spinor fields to C_out fields,

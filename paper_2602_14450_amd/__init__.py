@@ -93,12 +93,13 @@ _lib.qcd_ptc_set_weights.argtypes = [_vp, _vp, _vp]
 _lib.qcd_ptc_get_weights.argtypes = [_vp, _vp, _vp]
 _lib.qcd_ptc_apply.argtypes = [_vp, _i, _vp, _vp, _vp]
 _lib.qcd_ptc_apply_prec.argtypes = [_vp, _i, _i, _vp, _vp, _vp]
+_lib.qcd_eo_spectrum.argtypes = [_vp, _d, _i, _i, ctypes.c_uint64, ctypes.POINTER(_d), ctypes.POINTER(_d), _vp]
 _lib.qcd_ptc_loss_grad.argtypes = [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp, _vp]
 _lib.qcd_ptc_train_step.argtypes = [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_d), _vp]
 _lib.qcd_ptc_set_gauge.argtypes = [_vp, _vp]
 _lib.qcd_ptc_init_neumann.argtypes = [_vp, _d, _vp]
 for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get_weights", "qcd_ptc_apply",
-           "qcd_ptc_apply_prec",
+           "qcd_ptc_apply_prec", "qcd_eo_spectrum",
            "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
            "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
@@ -108,7 +109,7 @@ EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qc
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_apply_prec", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
-            "qcd_gaussian_spinors"]
+            "qcd_gaussian_spinors", "qcd_eo_spectrum"]
 
 
 class QcdError(RuntimeError):
@@ -176,6 +177,15 @@ class Gauge:
         _check(_lib.qcd_get_dslash_tuning(self.handle, PREC[prec], ctypes.byref(a), ctypes.byref(b),
                                           ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def eo_spectrum(self, kappa, power_iters=1000, inverse_iters=40, seed=1):
+        """(largest, smallest) |eigenvalue| estimates of the even-odd matrix
+        1 - kappa^2 H_eo H_oe (qcd_eo_spectrum); smallest is NaN when
+        inverse_iters = 0."""
+        hi, lo = _d(), _d()
+        _check(_lib.qcd_eo_spectrum(self.handle, float(kappa), int(power_iters), int(inverse_iters),
+                                    int(seed) & (2**64 - 1), ctypes.byref(hi), ctypes.byref(lo), _stream()))
+        return hi.value, lo.value
 
     def autotune(self, prec, nrhs=1, reps=20, cache_path=None):
         """Time the launch choices of the Wilson operator and keep the fastest;

@@ -1349,4 +1349,129 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
   return solve_ir_runs(runs.data(), nlat, p, S(stream), t0);
 }
 
+
+// ---------------------------------------------------------------------------
+// Extreme |eigenvalues| of the even-odd matrix (a diagnostic).
+
+}  // extern "C"
+
+namespace {
+
+// logs[k] = log of sqrt(sums[num] / sums[den]) (den < 0: / 1), scale = 1 / sqrt(sums[num])
+__global__ void k_log_ratio(const double* __restrict__ sums, int num, int den, double* __restrict__ logs, int k,
+                            double* __restrict__ scale) {
+  if (threadIdx.x != 0) return;
+  const double a = sums[num], b = den >= 0 ? sums[den] : 1.0;
+  if (logs) logs[k] = 0.5 * log(a / b);
+  scale[0] = 1.0 / sqrt(a);
+}
+
+struct SpecBufs {
+  void* p[8] = {};
+  ~SpecBufs() {
+    for (void* q : p)
+      if (q) (void)hipFree(q);
+  }
+};
+
+// x = y / |y| for an even-parity FP64 field y (x != y), and log |y| / |x_prev|
+// (|x_prev| = 1) into logs[k] if logs is not null.
+void spec_normalise(const Geom& gh, double* x, const double* y, double* partials, double* sums, double* scale,
+                    double* logs, int k, hipStream_t st) {
+  launch_narrow(gh, kFP64, 1, x, y, partials, 0, st);  // a copy; the partials hold |y|^2
+  launch_finish_sum(1, partials, site_grid(gh), 1, sums, st);
+  hipLaunchKernelGGL(k_log_ratio, dim3(1), dim3(64), 0, st, sums, 0, -1, logs, k, scale);
+  launch_widen(gh, kFP64, 1, x, y, scale, st);
+}
+
+// x = v / |v| for the even half v of a seeded Gaussian field.
+void spec_start(const qcd_gauge* g, uint64_t seed, double* xe, double* tmp, double* to, double* canon,
+                double* partials, double* sums, double* scale, hipStream_t st) {
+  const Geom& G = g->g;
+  launch_gaussian(canon, (int64_t)2 * G.Vh * 12, seed, st);
+  launch_pack_spinor_split(G, 1, tmp, to, canon, nullptr, st);
+  spec_normalise(half_geom(G), xe, tmp, partials, sums, scale, nullptr, 0, st);
+}
+
+double mean_tail(const std::vector<double>& v, int from, int to) {
+  double s = 0;
+  for (int k = from; k < to; k++) s += v[k];
+  return s / (to - from);
+}
+
+}  // namespace
+
+extern "C" {
+
+qcd_status qcd_eo_spectrum(const qcd_gauge* g, double kappa, int power_iters, int inverse_iters, uint64_t seed,
+                           double* abs_max, double* abs_min, void* stream) {
+  qcd_status rc = check_gauge(g, kFP64);
+  if (rc) return rc;
+  if (!abs_max || !abs_min) return fail(QCD_ERR_ARG, "null output");
+  if (power_iters < 2 || power_iters > 100000 || inverse_iters < 0 || inverse_iters > 1000)
+    return fail(QCD_ERR_ARG, "power_iters must be in 2..100000 and inverse_iters in 0..1000");
+  hipStream_t st = S(stream);
+  const Geom& G = g->g;
+  const Geom gh = half_geom(G);
+  const DslashTune& tu = g->tune[kFP64];
+  const int erows = dslash_partial_rows(G, tu, 1, true);
+  const int nrows = std::max(erows, site_grid(gh));
+  const int nlog = power_iters + inverse_iters;
+  const size_t sizes[8] = {spinor_bytes(gh, kFP64), spinor_bytes(gh, kFP64), spinor_bytes(gh, kFP64),
+                           canon_bytes(G), canon_bytes(G), (size_t)nrows * 4 * sizeof(double),
+                           8 * sizeof(double), (size_t)nlog * sizeof(double)};
+  SpecBufs B;
+  for (int i = 0; i < 8; i++) HIP_TRY(hipMalloc(&B.p[i], sizes[i]));
+  double *xe = (double*)B.p[0], *ye = (double*)B.p[1], *to = (double*)B.p[2];
+  double *cb = (double*)B.p[3], *cx = (double*)B.p[4], *partials = (double*)B.p[5];
+  double *sums = (double*)B.p[6], *scale = sums + 4, *logs = (double*)B.p[7];
+  const void* U = g->U[kFP64];
+  const double k2 = kappa * kappa;
+  // power iteration: y = A x, log |y| / |x| recorded, x = y / |y|
+  spec_start(g, seed, xe, ye, to, cx, partials, sums, scale, st);
+  for (int k = 0; k < power_iters; k++) {
+    launch_dslash(kFP64, G, tu, kOpH, kEpiNone, 1, to, xe, U, 1.0, nullptr, nullptr, nullptr, 0, st, nullptr, 1);
+    launch_dslash(kFP64, G, tu, kOpD, kEpiTS, 1, ye, to, U, k2, nullptr, partials, nullptr, 0, st, xe, 0);
+    launch_finish_sum(1, partials, erows, 4, sums, st);
+    hipLaunchKernelGGL(k_log_ratio, dim3(1), dim3(64), 0, st, sums, 2, 3, logs, k, scale);
+    launch_widen(gh, kFP64, 1, xe, ye, scale, st);
+  }
+  HIP_LAUNCHED();
+  // inverse iteration: A^-1 x is the even half of D^-1 (x, 0) (eq. (5) with b_o = 0)
+  if (inverse_iters > 0) {
+    qcd_ir_params p{};
+    p.tol = 1e-12;
+    p.max_outer = 100;
+    p.inner_prec = g->U[kFP16] ? QCD_FP16 : QCD_FP64;
+    p.s = 128.0;
+    p.recalc_shat = 1;
+    p.inner.tol = 1e-2;
+    p.inner.max_iter = 10000;
+    p.inner.sigma = 64.0;
+    p.inner.recalc_gamma = 1;
+    p.inner.omega0 = 0.7;
+    p.inner.even_odd = 1;
+    spec_start(g, seed + 1, xe, ye, to, cx, partials, sums, scale, st);
+    for (int k = 0; k < inverse_iters; k++) {
+      launch_zero(gh, kFP64, 1, to, st);
+      launch_unpack_spinor_split(G, 1, cb, xe, to, st);
+      HIP_LAUNCHED();
+      qcd_solve_info info{};
+      rc = qcd_solve_mixed_ir(g, kappa, 1, cx, cb, &p, &info, nullptr, 0, stream);
+      if (rc != QCD_OK) return rc == QCD_NOT_CONVERGED ? fail(rc, "an inverse-iteration solve did not converge") : rc;
+      launch_pack_spinor_split(G, 1, ye, to, cx, nullptr, st);
+      spec_normalise(gh, xe, ye, partials, sums, scale, logs, power_iters + k, st);
+      HIP_LAUNCHED();
+    }
+  }
+  std::vector<double> h(nlog);
+  HIP_TRY(hipMemcpyAsync(h.data(), logs, nlog * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *abs_max = std::exp(mean_tail(h, power_iters / 2, power_iters));
+  *abs_min = inverse_iters > 0 ? std::exp(-mean_tail(h, power_iters + inverse_iters / 2, nlog)) : NAN;
+  if (!std::isfinite(*abs_max) || (inverse_iters > 0 && !std::isfinite(*abs_min)))
+    return fail(QCD_ERR_NONFINITE, "the spectrum estimate is not finite");
+  return QCD_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,64 @@
+"""The even-odd spectrum estimate (qcd_eo_spectrum) against the oracle's
+dense eigenvalues (oracle/spectrum.py) through the C ABI.
+
+Free field: the extremes are real (1 + 16 kappa^2 and 1 - 64 kappa^2, pinned
+in closed form), so power and inverse iteration converge geometrically and the
+estimates agree to 1e-6.  Interacting field: the extremes may be complex
+pairs, where the estimate (a geometric mean of |A x_k| over the second half of
+the steps) converges only as 1 / steps, and the smallest ones can sit close
+together (inverse iteration then converges slowly: 1.5e-2 off after 60 steps
+on 2x4x4x6, 5e-4 on 4^4); 2e-2 relative is allowed there.
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import qcd_inputs as qi  # noqa: E402
+from oracle import spectrum as SP  # noqa: E402
+from gpu_common import to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def q():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_14450_amd as q
+    return q
+
+
+def test_free_field_extremes(q):
+    dims, kappa = (4, 4, 4, 4), 0.124
+    g = q.gauge_upload(to_dev(qi.unit_gauge(dims)), dims)
+    hi, lo = g.eo_spectrum(kappa, power_iters=600, inverse_iters=12, seed=5)
+    assert abs(hi - (1 + 16 * kappa**2)) < 1e-6 * hi, hi
+    assert abs(lo - (1 - 64 * kappa**2)) < 1e-6 * lo, lo
+    g.close()
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (2, 4, 4, 6)])
+def test_interacting_extremes_match_dense_eigenvalues(q, dims):
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 93)
+    want_hi, want_lo = SP.eo_abs_extremes(U, kappa, dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    hi, lo = g.eo_spectrum(kappa, power_iters=4000, inverse_iters=200, seed=7)
+    print(f"dims={dims} max {hi:.6f} vs {want_hi:.6f}, min {lo:.6f} vs {want_lo:.6f}")
+    assert abs(hi - want_hi) < 2e-2 * want_hi
+    assert abs(lo - want_lo) < 2e-2 * want_lo
+    g.close()
+
+
+def test_power_only_and_argument_checks(q):
+    dims = (4, 4, 4, 4)
+    g = q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, 94)), dims)
+    hi, lo = g.eo_spectrum(0.124, power_iters=50, inverse_iters=0)
+    assert hi > 1 and math.isnan(lo)
+    for pi, ii in ((1, 0), (100001, 0), (10, -1), (10, 1001)):
+        with pytest.raises(q.QcdError):
+            g.eo_spectrum(0.124, power_iters=pi, inverse_iters=ii)
+    g.close()
