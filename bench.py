@@ -95,6 +95,26 @@ DSLASH_SOURCES = ("dslash.hip", "half_ops.h", "common.h")
 INNER_TOL = 1e-3
 PAPER_INNER_TOL = 1e-2
 
+# Table 2 of the paper (Sec. 6), quoted as context: another machine, another
+# configuration and kappa, the unit source; "matvec" counts the low-precision
+# solver's products in the mixed rows.
+PAPER_TABLE2 = {
+    "hardware": "Fugaku, A64FX (SVE 512-bit), 16 nodes / 64 MPI ranks, 2.2 GHz",
+    "workload": "32^3x64 even-odd Wilson matrix, kappa=0.13, smeared 4^3x8 configuration tiled, b = e_0, "
+                "|r|^2 < 1e-26",
+    "rows": [
+        {"scheme": "FP64 BiCGStab", "matvec": 775, "seconds": 1.39},
+        {"scheme": "IR + FP32 BiCGStab, s=1, eps_tol^2=1e-12", "matvec": 989, "seconds": 0.96},
+        {"scheme": "IR + FP32 BiCGStab, s=1, eps_tol^2=1e-4", "matvec": 919, "seconds": 0.92},
+        {"scheme": "IR + FP16 BiCGStab, s=128, sigma=64, eps_tol^2=1e-4", "matvec": 858, "seconds": 0.46},
+        {"scheme": "IR + FP16 BiCGStab, s=4096, eps_tol^2=1e-4", "matvec": 920, "seconds": 0.47},
+        {"scheme": "IR + FP16 BiCGStab, s=128, sigma=256, sigma_lambda=256, eps_tol^2=1e-4", "matvec": 834,
+         "seconds": 0.46},
+    ],
+    "fp16_over_fp64_time": 0.46 / 1.39,
+    "fp32_over_fp64_time": 0.92 / 1.39,
+}
+
 
 def dslash_source_sha():
     """sha256 over the Wilson operator's kernel sources, in the order of DSLASH_SOURCES."""
@@ -605,6 +625,9 @@ def main():
         ("solvers_full_matrix" if eo else "solvers_even_odd"): other_form, "dslash": dsl, "batched": batched,
         "learned": learned, "largest_48x48x48x96": largest, "rescaling_study": rescaling,
         "spectrum_even_odd": spectrum,
+        "paper_context": dict(PAPER_TABLE2, this_fp16_over_fp64_time=s_per_solve / others["fp64_bicgstab"]["seconds"],
+                              this_fp32_over_fp64_time=others["fp32_inner_ir"]["seconds"]
+                              / others["fp64_bicgstab"]["seconds"]),
         "tuning": tuned,
         "speedup_vs_fp64": others["fp64_bicgstab"]["seconds"] / s_per_solve,
         "input_generation_s": gen_s,
