@@ -285,8 +285,8 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
  * links, else FP64; tolerance 1e-12); abs_min = 1 / the mean, NaN if
  * inverse_iters = 0.  Needs FP64 links.  Allocates and frees its own buffers
  * (three one-parity FP64 fields and two canonical fields); synchronises.
- * Errors: QCD_ERR_ARG (null handle or output, power_iters outside 2..100000,
- * inverse_iters outside 0..1000), QCD_NOT_CONVERGED if a solve stops short,
+ * Errors: QCD_ERR_ARG (null handle or output, kappa not positive, power_iters
+ * outside 2..100000, inverse_iters outside 0..1000), QCD_NOT_CONVERGED if a solve stops short,
  * QCD_ERR_NONFINITE, QCD_ERR_HIP. */
 qcd_status qcd_eo_spectrum(const qcd_gauge* g, double kappa, int power_iters, int inverse_iters, uint64_t seed,
                            double* abs_max, double* abs_min, void* stream);

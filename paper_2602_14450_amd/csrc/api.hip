@@ -1408,6 +1408,7 @@ qcd_status qcd_eo_spectrum(const qcd_gauge* g, double kappa, int power_iters, in
   qcd_status rc = check_gauge(g, kFP64);
   if (rc) return rc;
   if (!abs_max || !abs_min) return fail(QCD_ERR_ARG, "null output");
+  if (!(kappa > 0) || !std::isfinite(kappa)) return fail(QCD_ERR_ARG, "kappa must be positive and finite");
   if (power_iters < 2 || power_iters > 100000 || inverse_iters < 0 || inverse_iters > 1000)
     return fail(QCD_ERR_ARG, "power_iters must be in 2..100000 and inverse_iters in 0..1000");
   hipStream_t st = S(stream);

@@ -61,4 +61,6 @@ def test_power_only_and_argument_checks(q):
     for pi, ii in ((1, 0), (100001, 0), (10, -1), (10, 1001)):
         with pytest.raises(q.QcdError):
             g.eo_spectrum(0.124, power_iters=pi, inverse_iters=ii)
+    with pytest.raises(q.QcdError):
+        g.eo_spectrum(-0.1, power_iters=10, inverse_iters=0)
     g.close()
