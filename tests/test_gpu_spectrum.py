@@ -7,7 +7,7 @@ estimates agree to 1e-6.  Interacting field: the extremes may be complex
 pairs, where the estimate (a geometric mean of |A x_k| over the second half of
 the steps) converges only as 1 / steps, and the smallest ones can sit close
 together (inverse iteration then converges slowly: 1.5e-2 off after 60 steps
-on 2x4x4x6, 5e-4 on 4^4); 2e-2 relative is allowed there.
+on 2x4x4x6, 4.3e-3 after 200); 2e-2 relative is allowed there.
 """
 import math
 
