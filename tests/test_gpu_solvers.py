@@ -87,6 +87,22 @@ def test_fp64_trajectory_matches_oracle(q, c1, variant):
 def test_mixed_ir(q, c1, cfg):
     x = torch.zeros(c1["b"].shape, dtype=torch.complex128, device="cuda")
     info = q.solve_mixed_ir(c1["g"], c1["k"], x, to_dev(c1["b"]), tol=1e-12, inner_tol=1e-2, **cfg)
+    _check_mixed(c1, cfg, x, info)
+
+
+@pytest.mark.parametrize("inner_tol", [1e-4, 1e-3])
+def test_mixed_ir_other_inner_tolerances(q, c1, inner_tol):
+    # the FP32-inner form with |r| <= 1e-4 |b| per inner solve (the small
+    # configuration's inner tolerance read literally rather than as eps_tol^2),
+    # and the FP16 form at the benchmark's 1e-3
+    for cfg in (dict(inner_prec=1, s=1.0, recalc_shat=False, sigma=0.0),
+                dict(inner_prec=2, s=128.0, recalc_shat=True, sigma=64.0)):
+        x = torch.zeros(c1["b"].shape, dtype=torch.complex128, device="cuda")
+        info = q.solve_mixed_ir(c1["g"], c1["k"], x, to_dev(c1["b"]), tol=1e-12, inner_tol=inner_tol, **cfg)
+        _check_mixed(c1, cfg, x, info)
+
+
+def _check_mixed(c1, cfg, x, info):
     xh = to_host(x)
     assert info.status == "ok", info
     assert info.true_rel_residual <= 1e-12
