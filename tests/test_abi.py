@@ -56,3 +56,16 @@ def test_binding_declares_every_exported_symbol():
     src = open(spec.origin).read()
     for name in declared_functions():
         assert f'"{name}"' in src, name
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is a C ABI: the header compiles as C11 with no C++ or torch types
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use.c"
+    src.write_text('#include "qcd.h"\nint f(void) { qcd_ir_params p = {0}; return (int)p.inner_prec; }\n')
+    r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER),
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
