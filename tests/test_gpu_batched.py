@@ -353,3 +353,30 @@ def test_register_tiles_in_the_even_odd_solver(q):
         res = bs[r] - oracle.dslash(U, xh[r], 0.12, dims)
         assert np.linalg.norm(res) <= 1.01e-12 * np.linalg.norm(bs[r])
     g.close()
+
+
+def test_largest_right_hand_side_count(q):
+    # 64 right-hand sides (the most one call takes) through the operator and
+    # the even-odd FP16-inner refinement; 65 is refused
+    dims, k, n = (4, 4, 4, 4), 0.12, 64
+    U = qi.gauge_field(dims, 0.3, 610)
+    psi = qi.gaussian_source(dims, 611, nrhs=n)
+    g = q.gauge_upload(to_dev(U), dims)
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    q.dslash(g, k, out, x, prec=q.FP16)
+    got = to_host(out)
+    for r in (0, 31, 63):
+        compare(got[r], oracle.dslash(U, psi[r], k, dims, 0), TOL[2], f"64 rhs, rhs={r}")
+    sol = torch.zeros_like(x)
+    infos = q.solve_mixed_ir(g, k, sol, x, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, even_odd=True,
+                             use_graph=True)
+    assert len(infos) == n and all(i.status == "ok" and i.true_rel_residual <= 1e-12 for i in infos)
+    xh = to_host(sol)
+    for r in (0, 63):
+        res = np.linalg.norm(psi[r] - oracle.dslash(U, xh[r], k, dims)) / np.linalg.norm(psi[r])
+        assert res <= 1.01e-12
+    big = to_dev(qi.gaussian_source(dims, 612, nrhs=n + 1))
+    with pytest.raises(q.QcdError):
+        q.dslash(g, k, torch.empty_like(big), big, prec=q.FP16)
+    g.close()
