@@ -69,3 +69,12 @@ def test_header_is_plain_c(tmp_path):
     r = subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.dirname(HEADER),
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libqcd.so not built")
+def test_binding_covers_exactly_the_header():
+    # the Python binding names every entry point the header declares, and no other
+    import sys
+    sys.path.insert(0, ROOT)
+    import paper_2602_14450_amd as q
+    assert sorted(q.EXPORTED) == declared_functions()
