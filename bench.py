@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=20)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
-    ap.add_argument("--no-rescaling-study", action="store_true", help="skip the (s, sigma) grid of Sec. 5")
+    ap.add_argument("--no-rescaling-study", action="store_true", help="skip the (s, sigma) grid of Sec. 6")
     ap.add_argument("--learned-pairs", type=int, default=512, help="training pairs per gauge field (8 fields)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 12-source batched form")
     ap.add_argument("--no-largest", action="store_true", help="skip the 48^3 x 96 form")

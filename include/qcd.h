@@ -54,9 +54,14 @@ typedef enum {
 } qcd_status;
 
 /* Storage precisions of fields and links (Table 1).  FP16 and BF16 store a
- * complex number as two 16-bit halves of one 32-bit word; arithmetic on them
- * is FP32.  BF16 (8 exponent bits, 7 fraction bits) is the alternative inner
- * format the paper's conclusion proposes to compare. */
+ * complex number as two 16-bit halves of one 32-bit word.  Arithmetic on FP16
+ * storage: in the Wilson operator the spin projection is one binary16 add per
+ * component (as the paper's FP16 arithmetic, Sec. 5) and each link product
+ * is a pair of exact binary16 products summed in FP32 (v_dot2_f32_f16); the
+ * reconstruction, the BLAS-1 updates and every reduction are FP32 (scalars
+ * FP64).  BF16 storage: FP32 arithmetic throughout.  BF16 (8 exponent bits,
+ * 7 fraction bits) is the alternative inner format the paper's conclusion
+ * proposes to compare. */
 typedef enum { QCD_FP64 = 0, QCD_FP32 = 1, QCD_FP16 = 2, QCD_BF16 = 3 } qcd_prec;
 /* Flag for qcd_gauge_upload's prec_mask: store all 18 reals of every link
  * even when the field is in SU(3). */
@@ -219,7 +224,9 @@ qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* cano
 /* Wilson operator (eq. (1), Alg. 1 with the projection of Sec. 2):
  * out = op(in) with op one of D, H, D^dag, H^dag.  prec selects the link
  * copy, the storage of in/out (native layout) and the arithmetic (FP64 for
- * FP64, FP32 otherwise).  With QCD_LAYOUT_CANONICAL, in and out are
+ * FP64; FP32 for FP32 and BF16; for FP16 the binary16 projection and exact
+ * binary16 link products summed in FP32 described at qcd_prec, FP32
+ * reconstruction).  With QCD_LAYOUT_CANONICAL, in and out are
  * complex128 canonical fields, converted to/from prec around the
  * application.  With nrhs > 1 the links are read once per site for all
  * right-hand sides (a wave's lanes interleave sites and right-hand sides).
@@ -265,11 +272,19 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
  * captured iteration) and corrects them; the host polls all lattices' device
  * scalars with one synchronisation.  Per right-hand side results match
  * qcd_solve_mixed_ir on that lattice alone.  info may be NULL or hold nlat
- * arrays of nrhs[i] entries.  Workspaces are the handles' own; p->precond
- * must be NULL (QCD_ERR_UNSUPPORTED otherwise).  nlat in 1..64. */
+ * arrays of nrhs[i] entries.  Workspaces: ws may be NULL (every lattice uses
+ * its handle's cached workspace, allocated or grown as in qcd_solve_mixed_ir)
+ * or hold nlat caller-owned device buffers, ws[i] of ws_bytes[i] >=
+ * qcd_workspace_bytes(g[i], 0 (| 8 with inner.even_odd), inner_prec,
+ * inner.max_iter, nrhs[i]) bytes (a NULL entry selects that handle's own);
+ * with every ws[i] given the call allocates no device memory and creates no
+ * HIP objects (the streams and events it forks onto were made at upload).
+ * p->precond must be NULL (QCD_ERR_UNSUPPORTED otherwise).  nlat in 1..64.
+ * QCD_ERR_WORKSPACE if a ws[i] is too small. */
 qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const double* kappa, const int* nrhs,
                                       void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
-                                      qcd_solve_info* const* info, void* stream);
+                                      qcd_solve_info* const* info, void* const* ws, const size_t* ws_bytes,
+                                      void* stream);
 
 /* Estimates of the largest and smallest |eigenvalue| of the even-odd matrix
  * A = 1 - kappa^2 H_eo H_oe of eq. (5), the ratio Sec. 6 quotes for its test

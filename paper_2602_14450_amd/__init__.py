@@ -80,7 +80,8 @@ _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRPara
                                     _sz, _vp]
 _lib.qcd_solve_mixed_ir_batched.argtypes = [_i, ctypes.POINTER(_vp), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(IRParams),
-                                            ctypes.POINTER(ctypes.POINTER(SolveInfo)), _vp]
+                                            ctypes.POINTER(ctypes.POINTER(SolveInfo)), ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_sz), _vp]
 _lib.qcd_solve_mixed_ir_batched.restype = _i
 _lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
 _lib.qcd_autotune_dslash.argtypes = [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_d), _vp]
@@ -325,7 +326,7 @@ def bicgstab(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, prec=FP64, tol=1
     p = _bicg_params(tol, max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every, use_graph, even_odd)
     infos, keep = _make_infos(n, max_iter if history else 0, 1)
     ws = _ptr(workspace) if workspace is not None else None
-    wsb = workspace.numel() if workspace is not None else 0
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     code = _lib.qcd_bicgstab(g.handle, float(kappa), PREC[prec], n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
                              infos, ws, wsb, _stream())
     if raise_on_error:
@@ -348,7 +349,7 @@ def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec
                  precond.handle if precond is not None else None, float(precond_scale))
     infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
     ws = _ptr(workspace) if workspace is not None else None
-    wsb = workspace.numel() if workspace is not None else 0
+    wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     code = _lib.qcd_solve_mixed_ir(g.handle, float(kappa), n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p), infos,
                                    ws, wsb, _stream())
     if raise_on_error:
@@ -449,11 +450,12 @@ class PTC:
 def solve_mixed_ir_batched(gauges, kappas, xs, bs, inner_prec=FP16, tol=1e-12, max_outer=100, s=128.0,
                            recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0, sigma_lambda=0.0,
                            recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, history=False,
-                           raise_on_error=True, use_graph=False, even_odd=False):
+                           raise_on_error=True, use_graph=False, even_odd=False, workspaces=None):
     """Several lattices (distinct Gauge handles, any extents) solved together:
     one refinement whose inner solves run concurrently.  xs[i], bs[i] hold one
-    or several canonical fields of lattice i.  Returns a list (per lattice) of
-    Info or lists of Info."""
+    or several canonical fields of lattice i.  workspaces: None (the handles'
+    own) or one device buffer per lattice (None entries: that handle's own).
+    Returns a list (per lattice) of Info or lists of Info."""
     nl = len(gauges)
     ns = [g.nrhs_of(b) for g, b in zip(gauges, bs)]
     inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
@@ -467,7 +469,12 @@ def solve_mixed_ir_batched(gauges, kappas, xs, bs, inner_prec=FP16, tol=1e-12, m
     xp = (ctypes.c_void_p * nl)(*[_ptr(x).value for x in xs])
     bp = (ctypes.c_void_p * nl)(*[_ptr(b).value for b in bcs])
     ip = (ctypes.POINTER(SolveInfo) * nl)(*[ctypes.cast(m[0], ctypes.POINTER(SolveInfo)) for m in made])
-    code = _lib.qcd_solve_mixed_ir_batched(nl, gh, kp, npp, xp, bp, ctypes.byref(p), ip, _stream())
+    wsp = wsb = None
+    if workspaces is not None:
+        assert len(workspaces) == nl, "one workspace (or None) per lattice"
+        wsp = (ctypes.c_void_p * nl)(*[(_ptr(w).value if w is not None else None) for w in workspaces])
+        wsb = (ctypes.c_size_t * nl)(*[(w.numel() * w.element_size() if w is not None else 0) for w in workspaces])
+    code = _lib.qcd_solve_mixed_ir_batched(nl, gh, kp, npp, xp, bp, ctypes.byref(p), ip, wsp, wsb, _stream())
     if raise_on_error:
         _check(code, allow=(0, 1))
     out = []

@@ -344,13 +344,20 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
   memcpy(&kbits, &kappa, sizeof kbits);
   unsigned sbits;
   memcpy(&sbits, &pc.scale, sizeof sbits);
-  const unsigned long long key[8] = {(unsigned long long)prec, (unsigned long long)w.n, (unsigned long long)w.x,
-                                     kbits, (unsigned long long)ftz,
-                                     ((unsigned long long)(unsigned)g->tune[prec].sched << 16) |
-                                         ((unsigned long long)(unsigned)g->tune[prec].variant << 8) |
-                                         ((unsigned long long)(g->tune[prec].rhs_tile & 0xff)) |
-                                         ((unsigned long long)w.eo << 24),
-                                     (unsigned long long)(uintptr_t)pc.net, pc.net ? sbits : 0ull};
+  // Everything the captured launches bake in: the scalar parameters, the launch
+  // shape, and the address of every workspace region they read or write (the
+  // regions move when max_iter or nrhs changes the carve of one workspace).
+  auto u = [](const void* q) { return (unsigned long long)(uintptr_t)q; };
+  const unsigned long long key[24] = {(unsigned long long)prec, (unsigned long long)w.n, kbits,
+                                      (unsigned long long)ftz,
+                                      ((unsigned long long)(unsigned)g->tune[prec].sched << 16) |
+                                          ((unsigned long long)(unsigned)g->tune[prec].variant << 8) |
+                                          ((unsigned long long)(g->tune[prec].rhs_tile & 0xff)) |
+                                          ((unsigned long long)w.eo << 24),
+                                      u(pc.net), pc.net ? sbits : 0ull, u(w.x), u(w.r), u(w.rstar), u(w.p), u(w.v),
+                                      u(w.t), u(w.z), u(w.t1), u(w.partials), u(w.sc), u(w.history),
+                                      (unsigned long long)w.hist_stride, u(w.sums), u(w.scale),
+                                      (unsigned long long)w.bytes, 0ull, 0ull};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
     return QCD_OK;
@@ -359,7 +366,6 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
     HIP_TRY(hipGraphExecDestroy(g->graph_exec));
     g->graph_exec = nullptr;
   }
-  if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
   bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
@@ -423,28 +429,16 @@ qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_pa
   }
   std::vector<hipGraphExec_t> gexec(nrun, nullptr);
   std::vector<hipStream_t> rs(nrun, st);
-  std::vector<hipEvent_t> done(nrun, nullptr);
-  hipEvent_t fork = nullptr;
-  struct Cleanup {
-    std::vector<hipEvent_t>& d;
-    hipEvent_t& f;
-    ~Cleanup() {
-      for (auto e : d)
-        if (e) (void)hipEventDestroy(e);
-      if (f) (void)hipEventDestroy(f);
-    }
-  } cleanup{done, fork};
+  // several runs: each on its handle's own stream, forked from st by the first
+  // handle's fork event and joined by each handle's done event (all created at
+  // upload, so a solve creates no HIP objects)
+  hipEvent_t fork = runs[0].g->ev_fork;
   for (int r = 0; r < nrun; r++) {
     qcd_gauge* g = const_cast<qcd_gauge*>(runs[r].g);
     if (p.use_graph && any_active(g, runs[r].w->n))
       if ((s = iteration_graph(g, runs[r].prec, runs[r].kappa, *runs[r].w, p.ftz, runs[r].pc, &gexec[r]))) return s;
-    if (nrun > 1) {
-      if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
-      rs[r] = g->cap_stream;
-      HIP_TRY(hipEventCreateWithFlags(&done[r], hipEventDisableTiming));
-    }
+    if (nrun > 1) rs[r] = g->cap_stream;
   }
-  if (nrun > 1) HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
   auto anyrun = [&]() {
     for (int r = 0; r < nrun; r++)
       if (any_active(runs[r].g, runs[r].w->n)) return true;
@@ -467,8 +461,8 @@ qcd_status bicg_loop_multi(const InnerRun* runs, int nrun, const qcd_bicgstab_pa
           bicg_iteration(R.g, R.prec, R.kappa, *R.w, p.ftz, R.pc, rs[r]);
       }
       if (nrun > 1) {
-        HIP_TRY(hipEventRecord(done[r], rs[r]));
-        HIP_TRY(hipStreamWaitEvent(st, done[r], 0));
+        HIP_TRY(hipEventRecord(R.g->ev_done, rs[r]));
+        HIP_TRY(hipStreamWaitEvent(st, R.g->ev_done, 0));
       }
     }
     HIP_LAUNCHED();
@@ -586,6 +580,13 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   }
   if (rc == QCD_OK && hipHostMalloc((void**)&g->host_sc, sizeof(Scalars) * kMaxRhs, 0) != hipSuccess)
     rc = fail(QCD_ERR_HIP, "hipHostMalloc failed");
+  // the handle's stream (graph capture, batched solves) and its two events:
+  // created here so that no solve creates HIP objects
+  if (rc == QCD_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(QCD_ERR_HIP, "hipStreamCreateWithFlags failed");
+  if (rc == QCD_OK && (hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&g->ev_done, hipEventDisableTiming) != hipSuccess))
+    rc = fail(QCD_ERR_HIP, "hipEventCreateWithFlags failed");
   if (rc == QCD_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(QCD_ERR_HIP, "synchronise failed");
   if (rc != QCD_OK) {
     qcd_gauge_free(g);
@@ -603,6 +604,8 @@ qcd_status qcd_gauge_free(qcd_gauge* g) {
   if (g->host_sc) (void)hipHostFree(g->host_sc);
   if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
+  if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
+  if (g->ev_done) (void)hipEventDestroy(g->ev_done);
   delete g;
   return QCD_OK;
 }
@@ -1323,7 +1326,8 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
 
 qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const double* kappa, const int* nrhs,
                                       void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
-                                      qcd_solve_info* const* info, void* stream) {
+                                      qcd_solve_info* const* info, void* const* ws, const size_t* ws_bytes,
+                                      void* stream) {
   const double t0 = now_s();
   qcd_status rc = check_ir_params(p);
   if (rc) return rc;
@@ -1342,7 +1346,9 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
     R.b_dev = b_dev[r];
     R.info = info ? info[r] : nullptr;
     if ((rc = check_ir_run(R, p))) return rc;
-    if ((rc = get_work(g[r], p->inner.even_odd ? kWhatEO : 0, p->inner_prec, p->inner.max_iter, nrhs[r], nullptr, 0,
+    void* wr = ws ? ws[r] : nullptr;
+    const size_t wb = (ws && ws_bytes) ? ws_bytes[r] : 0;
+    if ((rc = get_work(g[r], p->inner.even_odd ? kWhatEO : 0, p->inner_prec, p->inner.max_iter, nrhs[r], wr, wb,
                        &R.w)))
       return rc;
   }

@@ -163,10 +163,12 @@ struct qcd_gauge {
   size_t ws_bytes;
   qcd::Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
   qcd::DslashTune tune[qcd::kNumPrec];
-  // one captured BiCGStab iteration, reused while its key is unchanged
-  hipStream_t cap_stream;
+  // one captured BiCGStab iteration, reused while its key (every value and
+  // device address the captured launches bake in) is unchanged
+  hipStream_t cap_stream;   // created at upload: capture, and this lattice's share of a batched solve
+  hipEvent_t ev_fork, ev_done;  // created at upload: fork / join of a batched solve's streams
   hipGraphExec_t graph_exec;
-  unsigned long long graph_key[8];
+  unsigned long long graph_key[24];
   double su3_dev;  // largest |row2 - conj(row0 x row1)| of the uploaded links (INFINITY if not checked)
 };
 

@@ -1,4 +1,4 @@
-"""The rescaling study of Sec. 5 on synthetic fields.
+"""The rescaling study of Sec. 6 on synthetic fields.
 
 For a grid of the refinement's normalisation s (Alg. 3) and the inner
 residual norm sigma (Alg. 4; Alg. 5 with sigma_lambda = sigma when the

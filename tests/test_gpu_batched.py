@@ -172,6 +172,70 @@ def test_graph_replays_match_eager(q, c1b):
     assert torch.equal(xb, xb2)
 
 
+def test_graph_cache_follows_the_workspace_carve(q, c1b):
+    # one handle, one caller workspace: inner_max_iter 500 and then 2000 move
+    # the partial sums and scalars inside the same buffer (the history before
+    # them grows), so the captured iteration must be rebuilt; each graph solve
+    # is bit-identical to the eager solve with the same parameters
+    g, k = c1b["g"], c1b["k"]
+    b = to_dev(c1b["b"][:2])
+    ws = torch.empty(g.workspace_bytes(0, q.FP16, 2000, 2), dtype=torch.uint8, device="cuda")
+    for mi in (500, 2000, 500):
+        xe = torch.zeros_like(b)
+        ie = q.solve_mixed_ir(g, k, xe, b, inner_max_iter=mi, workspace=ws, use_graph=False)
+        xg = torch.zeros_like(b)
+        ig = q.solve_mixed_ir(g, k, xg, b, inner_max_iter=mi, workspace=ws, use_graph=True)
+        torch.cuda.synchronize()
+        assert all(i.status == "ok" for i in ig), mi
+        assert torch.equal(xg, xe), mi
+        assert [i.inner_iters for i in ig] == [i.inner_iters for i in ie]
+
+
+def test_solves_with_caller_workspaces_allocate_nothing(q):
+    # with caller-owned workspaces, a single solve, a batched solve over two
+    # lattices and an FP64 BiCGStab leave the free device memory unchanged
+    # (after one warm-up call of each, which may instantiate graphs)
+    specs = [((8, 8, 8, 8), 0.12, 2, 611), ((4, 4, 8, 8), 0.124, 1, 612)]
+    gauges, bs, xs = [], [], []
+    for dims, k, n, seed in specs:
+        gauges.append(q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, seed)), dims))
+        bs.append(to_dev(qi.gaussian_source(dims, seed + 1000, nrhs=n)))
+        xs.append(torch.zeros_like(bs[-1]))
+    kappas = [s[1] for s in specs]
+    for eo in (False, True):
+        for use_graph in (False, True):
+            what = 8 if eo else 0
+            ws = [torch.empty(g.workspace_bytes(what, q.FP16, 1000, s[2]), dtype=torch.uint8, device="cuda")
+                  for g, s in zip(gauges, specs)]
+            ws1 = torch.empty(gauges[0].workspace_bytes(what, q.FP16, 1000, specs[0][2]), dtype=torch.uint8,
+                              device="cuda")
+            ws64 = torch.empty(gauges[0].workspace_bytes(1 | what, q.FP64, 1000, specs[0][2]), dtype=torch.uint8,
+                               device="cuda")
+            kw = dict(inner_prec=q.FP16, tol=1e-12, inner_max_iter=1000, even_odd=eo, use_graph=use_graph)
+
+            def run():
+                for x in xs:
+                    x.zero_()
+                q.solve_mixed_ir(gauges[0], kappas[0], xs[0], bs[0], workspace=ws1, **kw)
+                q.solve_mixed_ir_batched(gauges, kappas, xs, bs, workspaces=ws, **kw)
+                q.bicgstab(gauges[0], kappas[0], xs[0], bs[0], prec=q.FP64, tol=1e-12, max_iter=1000,
+                           workspace=ws64, history=False, even_odd=eo, use_graph=use_graph)
+
+            run()
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            for _ in range(2):
+                run()
+            torch.cuda.synchronize()
+            assert torch.cuda.mem_get_info()[0] == free0, (eo, use_graph)
+            del ws, ws1, ws64
+    with pytest.raises(q.QcdError):   # a workspace that is too small is refused
+        small = [torch.empty(256, dtype=torch.uint8, device="cuda") for _ in gauges]
+        q.solve_mixed_ir_batched(gauges, kappas, xs, bs, workspaces=small, inner_prec=q.FP16, tol=1e-12)
+    for g in gauges:
+        g.close()
+
+
 def test_autotune_and_cache(q, tmp_path):
     dims = (8, 8, 8, 8)
     U = qi.gauge_field(dims, 0.3, 61)

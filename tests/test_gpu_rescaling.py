@@ -1,4 +1,4 @@
-"""The (s, sigma) study of Sec. 5 (``rescaling_study``) on a small lattice.
+"""The (s, sigma) study of Sec. 6 (``rescaling_study``) on a small lattice.
 
 Pins: the first inner right-hand side of the even-odd solve with the point
 source b = e_0 has exactly one non-zero element (eta_o = 0, so b' = e_0: the

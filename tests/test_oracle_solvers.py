@@ -228,3 +228,27 @@ def test_point_source_breaks_down_on_full_operator():
     U = qi.gauge_field(dims, 0.3, 97)
     _, info = S.solve_fp64(U, 0.12, dims, qi.point_source(dims), tol=1e-12)
     assert info.breakdown and info.iterations == 1
+
+
+def test_omega_prescription_first_iteration_by_hand():
+    # Alg. 4's omega clause: a 2 x 2 complex system whose first omega^ is
+    # 1/sqrt(5) < 0.7, so the prescription acts with omega0 = 0.7 and not with
+    # omega0 = 0.4 or 0; the first iterate and residual norm against the values
+    # derived by hand in golden/omega0_first_iteration.txt
+    A = np.array([[1, 2], [1, 1j]])
+    b = np.array([1, 0], dtype=complex)
+    rows = []
+    with open(os.path.join(GOLDEN, "omega0_first_iteration.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                w0, *vals = line.split()
+                rows.append((float(w0), [complex(v) for v in vals]))
+    assert [w0 for w0, _ in rows] == [0.7, 0.4, 0.0]
+    for w0, (x0, x1, r0, r1) in rows:
+        x, info = S.bicgstab(lambda v: A @ v, b, S.FP64, tol2=0.0, maxiter=1, omega0=w0)
+        assert info.iterations == 1
+        assert abs(x[0] - x0) < 1e-15 and abs(x[1] - x1) < 1e-15, (w0, x)
+        assert abs(info.history[1] - (abs(r0) ** 2 + abs(r1) ** 2)) < 1e-15, (w0, info.history)
+    # the two forms differ, so a rule that never fires (or always fires) fails one row
+    assert abs(rows[0][1][1] - rows[1][1][1]) > 0.1
