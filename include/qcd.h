@@ -262,6 +262,24 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
 qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
                               const qcd_ir_params* p, qcd_solve_info* info, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * refinement of qcd_solve_mixed_ir (same arguments and results, bit for bit
+ * the same kernels) with its workspace in a fixed 64 MiB device array of the
+ * library instead of a caller or handle buffer.  The array exists once per
+ * GPU from module load to process end; its address is looked up at
+ * qcd_gauge_upload.  This call allocates nothing and creates no HIP object.
+ * Limits: the workspace qcd_workspace_bytes() reports for the call (what = 0,
+ * | 8 with inner.even_odd) must fit in 64 MiB, else QCD_ERR_WORKSPACE before
+ * any launch (16^4 with one right-hand side fits); p->precond must be NULL and
+ * p->inner.use_graph 0 (QCD_ERR_UNSUPPORTED).  Every call on a GPU shares that
+ * GPU's array, which keeps the last call's contents (nothing in it needs to
+ * start at zero): calls that overlap on one GPU (several host threads, or
+ * streams that run concurrently) race and corrupt each other.
+ * Synchronises. */
+qcd_status qcd_solve_mixed_ir_static(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
+                                     const qcd_ir_params* p, qcd_solve_info* info, void* stream);
+
 /* Several lattices in one call (the batched form of Alg. 3): nlat gauge
  * handles (distinct, possibly of different extents), each with its own kappa,
  * nrhs right-hand sides b_dev[i] and solutions x_dev[i] (canonical complex128,

@@ -78,6 +78,9 @@ _lib.qcd_bicgstab.argtypes = [_vp, _d, _i, _i, _vp, _vp, ctypes.POINTER(Bicgstab
                               _vp, _sz, _vp]
 _lib.qcd_solve_mixed_ir.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRParams), ctypes.POINTER(SolveInfo), _vp,
                                     _sz, _vp]
+_lib.qcd_solve_mixed_ir_static.argtypes = [_vp, _d, _i, _vp, _vp, ctypes.POINTER(IRParams),
+                                           ctypes.POINTER(SolveInfo), _vp]
+_lib.qcd_solve_mixed_ir_static.restype = _i
 _lib.qcd_solve_mixed_ir_batched.argtypes = [_i, ctypes.POINTER(_vp), ctypes.POINTER(_d), ctypes.POINTER(_i),
                                             ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(IRParams),
                                             ctypes.POINTER(ctypes.POINTER(SolveInfo)), ctypes.POINTER(_vp),
@@ -107,7 +110,7 @@ for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get
     getattr(_lib, _f).restype = _i
 
 EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free",
-            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_batched",
+            "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_static", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_apply_prec", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
             "qcd_gaussian_spinors", "qcd_eo_spectrum"]
@@ -352,6 +355,24 @@ def solve_mixed_ir(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec
     wsb = workspace.numel() * workspace.element_size() if workspace is not None else 0
     code = _lib.qcd_solve_mixed_ir(g.handle, float(kappa), n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p), infos,
                                    ws, wsb, _stream())
+    if raise_on_error:
+        _check(code, allow=(0, 1))
+    return _infos_out(code, infos, keep)
+
+
+def solve_mixed_ir_static(g: Gauge, kappa, x: torch.Tensor, b: torch.Tensor, inner_prec=FP16, tol=1e-12,
+                          max_outer=100, s=128.0, recalc_shat=True, inner_tol=1e-2, inner_max_iter=10000, sigma=64.0,
+                          sigma_lambda=0.0, recalc_gamma=True, omega0=0.7, ftz=False, check_every=0, history=False,
+                          raise_on_error=True, even_odd=False):
+    """solve_mixed_ir with the library's static device workspace (no device
+    allocation; workspace of at most 64 MiB, no graph, no network)."""
+    n = g.nrhs_of(b)
+    inner = _bicg_params(inner_tol, inner_max_iter, sigma, sigma_lambda, recalc_gamma, omega0, ftz, check_every,
+                         False, even_odd)
+    p = IRParams(float(tol), int(max_outer), PREC[inner_prec], float(s), int(bool(recalc_shat)), inner, None, 0.0)
+    infos, keep = _make_infos(n, inner_max_iter * 4 if history else 0, max_outer)
+    code = _lib.qcd_solve_mixed_ir_static(g.handle, float(kappa), n, _ptr(x), _ptr(_as_c128(b)), ctypes.byref(p),
+                                          infos, _stream())
     if raise_on_error:
         _check(code, allow=(0, 1))
     return _infos_out(code, infos, keep)

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -50,6 +51,9 @@ template <typename... A> qcd_status fail(qcd_status code, const char* fmt, A... 
   } while (0)
 
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// address of the static workspace on the current device (defined with it below)
+qcd_status scratch_address(void** out);
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -534,6 +538,14 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   qcd_gauge* g = new qcd_gauge();
   memset(g, 0, sizeof(*g));
   g->g = make_geom(dims);
+  {  // the static workspace's address on this device, once per device
+    void* sp = nullptr;
+    const qcd_status src = scratch_address(&sp);
+    if (src != QCD_OK) {
+      delete g;
+      return src;
+    }
+  }
   // defaults measured on MI355X at 32^3 x 64 with rotating buffers (the tuner
   // may override them): z slabs per XCD; prefetch 2 hops at 2 waves per SIMD
   // (FP16, FP32), 1 hop at 2 (FP64)
@@ -1295,6 +1307,40 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
   return res;
 }
 
+// Workspace of qcd_solve_mixed_ir_static: a fixed device array of the library,
+// one instance per GPU (each device holds it at its own address from module
+// load to process end).  Host code uses the address hipGetSymbolAddress
+// returns for the current device, never the array's name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// The current device's address of `scratch`, looked up once per device.
+qcd_status scratch_address(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(QCD_ERR_UNSUPPORTED, "device %d is beyond the %d devices the static workspace serves", dev,
+                kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(QCD_ERR_HIP, "hipGetSymbolAddress of the static workspace: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return QCD_OK;
+}
+
 qcd_status check_ir_params(const qcd_ir_params* p) {
   if (!p) return fail(QCD_ERR_ARG, "null parameters");
   if (!(p->tol > 0) || p->max_outer <= 0 || !(p->s > 0)) return fail(QCD_ERR_ARG, "tol > 0, max_outer > 0, s > 0 required");
@@ -1321,6 +1367,33 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
   if ((rc = check_ir_run(R, p))) return rc;
   const int what = R.net ? 3 : (p->inner.even_odd ? kWhatEO : 0);
   if ((rc = get_work(g, what, p->inner_prec, p->inner.max_iter, nrhs, ws, ws_bytes, &R.w))) return rc;
+  return solve_ir_runs(&R, 1, p, S(stream), t0);
+}
+
+qcd_status qcd_solve_mixed_ir_static(const qcd_gauge* g, double kappa, int nrhs, void* x_dev, const void* b_dev,
+                                     const qcd_ir_params* p, qcd_solve_info* info, void* stream) {
+  const double t0 = now_s();
+  qcd_status rc = check_ir_params(p);
+  if (rc) return rc;
+  if (p->precond) return fail(QCD_ERR_UNSUPPORTED, "the static-workspace solve takes no network preconditioner");
+  if (p->inner.use_graph)
+    return fail(QCD_ERR_UNSUPPORTED, "the static-workspace solve does not capture graphs (instantiation allocates)");
+  IrRun R;
+  R.g = g;
+  R.kappa = kappa;
+  R.n = nrhs;
+  R.x_dev = x_dev;
+  R.b_dev = b_dev;
+  R.info = info;
+  if ((rc = check_ir_run(R, p))) return rc;
+  const int what = p->inner.even_odd ? kWhatEO : 0;
+  const size_t need = carve(g, what, p->inner_prec, p->inner.max_iter, nrhs, nullptr).bytes;
+  if (need > kScratchBytes)
+    return fail(QCD_ERR_WORKSPACE, "the solve needs %zu bytes of workspace; the static workspace holds %zu", need,
+                kScratchBytes);
+  void* base = nullptr;
+  if ((rc = scratch_address(&base))) return rc;
+  if ((rc = get_work(g, what, p->inner_prec, p->inner.max_iter, nrhs, base, kScratchBytes, &R.w))) return rc;
   return solve_ir_runs(&R, 1, p, S(stream), t0);
 }
 
