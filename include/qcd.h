@@ -348,6 +348,15 @@ qcd_status qcd_ptc_free(qcd_ptc* net);
 /* Point the network at another gauge field with the same extents (training
  * over several fields with one set of weights and optimiser state). */
 qcd_status qcd_ptc_set_gauge(qcd_ptc* net, const qcd_gauge* g);
+/* Precision of the channel mixing in the two-pass form (training, the loss
+ * and gradient calls, and qcd_ptc_apply): QCD_BF16 (the default; inputs,
+ * weights and output gradients rounded to BF16 on the BF16 matrix cores) or
+ * QCD_FP32 (all of them FP32 on the FP32 matrix cores, for gradients that
+ * agree with an FP64 reference to FP32 rounding).  The FP16 form that the
+ * inner solver applies keeps BF16 mixing.  Reallocates the handle's GEMM
+ * operands (FP32 doubles them); synchronises.  QCD_ERR_ARG for another
+ * precision. */
+qcd_status qcd_ptc_set_mixing(qcd_ptc* net, qcd_prec prec, void* stream);
 /* Set the weights of a (1, 2, 2, 1) network to the third-order Neumann
  * series of the Wilson matrix, M = sum_{k=0..3} (kappa H)^k, so that
  * D M = 1 - (kappa H)^4 (with D = 1 - kappa H, eq. (1)).  Layers: (psi,
@@ -375,6 +384,18 @@ qcd_status qcd_ptc_apply_prec(qcd_ptc* net, qcd_prec prec, int nbatch, void* out
  * weights).  r_dev, e_dev: nbatch canonical complex128 fields.  Synchronises. */
 qcd_status qcd_ptc_loss_grad(qcd_ptc* net, int nbatch, const void* r_dev, const void* e_dev, double* loss,
                              double* grad_host, void* stream);
+/* The residual loss (1/B) sum_b |D M(r_b) - r_b|^2 / |r_b|^2, with D the
+ * Wilson matrix of eq. (1) at kappa (FP32 operator on the handle's FP32
+ * links), and if grad_host is not NULL its gradient in the layout of the
+ * weights.  It measures how far D M is from the identity on the sources, the
+ * quantity a right preconditioner is judged by, and needs no solves
+ * (r_dev: nbatch canonical complex128 fields).  Synchronises.  QCD_ERR_ARG
+ * for kappa not positive and finite. */
+qcd_status qcd_ptc_loss_grad_residual(qcd_ptc* net, double kappa, int nbatch, const void* r_dev, double* loss,
+                                      double* grad_host, void* stream);
+/* One Adam step (as qcd_ptc_train_step) on the residual loss above. */
+qcd_status qcd_ptc_train_step_residual(qcd_ptc* net, double kappa, int nbatch, const void* r_dev, double lr,
+                                       double* loss, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights with
  * learning rate lr; loss (may be NULL) receives the loss before the step. */
 qcd_status qcd_ptc_train_step(qcd_ptc* net, int nbatch, const void* r_dev, const void* e_dev, double lr, double* loss,

@@ -22,6 +22,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import OP_DDAG, dslash
+
 PATHS = [(None, 0)] + [(mu, d) for mu in range(4) for d in (+1, -1)]   # p = 0, +x, -x, +y, ...
 
 
@@ -81,6 +83,57 @@ def forward(U, psi, Ws, nb, keep=False):
     return (x[0], inputs) if keep else x[0]
 
 
+def site_neighbour(dims, sites, mu, d):
+    """Lexicographic index of site + d * mu-hat (periodic) for an array of sites."""
+    lx, ly, lz, lt = dims
+    c = [sites % lx, (sites // lx) % ly, (sites // (lx * ly)) % lz, sites // (lx * ly * lz)]
+    c[mu] = (c[mu] + d) % dims[mu]
+    return c[0] + lx * (c[1] + ly * (c[2] + lz * c[3]))
+
+
+def forward_sites(U, psi, Ws, dims, sites):
+    """The network's output M(psi) at the listed sites only, shape (len(sites), 4, 3).
+
+    Layer l's output at a site needs layer l's input at that site and its
+    eight neighbours, so going backwards from the last layer the sites that
+    each layer must be evaluated on grow by one hop per layer; each layer is
+    then the same sum over paths and input channels as :func:`layer`,
+    evaluated on that set only (for lattices too large to run the full
+    network in numpy).
+    """
+    sites = np.asarray(sites, dtype=np.int64)
+    L = len(Ws)
+    need = [None] * (L + 1)
+    need[L] = np.unique(sites)
+    for l in range(L, 0, -1):
+        grown = [need[l]] + [site_neighbour(dims, need[l], mu, d) for mu in range(4) for d in (+1, -1)]
+        need[l - 1] = np.unique(np.concatenate(grown))
+    x = psi[need[0]][None]                       # (C_in = 1, sites of need[0], 4, 3)
+    for l, W in enumerate(Ws):
+        have, want = need[l], need[l + 1]
+        out = np.zeros((W.shape[1], len(want), 4, 3), dtype=np.complex128)
+        for p in range(9):
+            mu, d = PATHS[p]
+            if mu is None:
+                src = want
+            else:
+                src = site_neighbour(dims, want, mu, d)
+            pos = np.searchsorted(have, src)
+            assert np.all(have[pos] == src)
+            for i in range(x.shape[0]):
+                f = x[i, pos]
+                if mu is None:
+                    t = f
+                elif d > 0:                      # U_mu(x) psi(x + mu)
+                    t = np.einsum("sab,sjb->sja", U[want, mu], f)
+                else:                            # U_mu(x - mu)^dagger psi(x - mu)
+                    t = np.einsum("sba,sjb->sja", np.conj(U[src, mu]), f)
+                out += np.einsum("jab,sbc->jsac", W[p, :, i], t)
+        x = out
+    pos = np.searchsorted(need[L], sites)
+    return x[0, pos]
+
+
 def loss(U, rs, es, Ws, nb):
     """mean over the batch of |M(r_b) - e_b|^2 / |e_b|^2."""
     tot = 0.0
@@ -88,6 +141,49 @@ def loss(U, rs, es, Ws, nb):
         m = forward(U, r, Ws, nb)
         tot += np.vdot(m - e, m - e).real / np.vdot(e, e).real
     return tot / len(rs)
+
+
+def backprop(U, Ws, inputs, dout, nb, dWs):
+    """Add the weight gradients of one sample to dWs, given the layer inputs
+    of its forward pass and the gradient dout (1, V, 4, 3) of its output."""
+    for l in range(len(Ws) - 1, -1, -1):
+        W, fields = Ws[l], inputs[l]
+        cin = fields.shape[0]
+        din = np.zeros_like(fields)
+        for i in range(cin):
+            for p in range(9):
+                t = transport(U, fields[i], nb, p)
+                # dW[p, j, i] = sum_x dout_j(x) t(x)^H over spin (colour summed)
+                dWs[l][p, :, i] += np.einsum("jsac,sbc->jab", dout, np.conj(t))
+                # dX = W^H dout, then the adjoint transport
+                dx = np.einsum("jba,jsbc->sac", np.conj(W[p, :, i]), dout)
+                din[i] += transport_adj(U, dx, nb, p)
+        dout = din
+
+
+def loss_residual(U, kappa, rs, Ws, nb, dims):
+    """mean over the batch of |D M(r_b) - r_b|^2 / |r_b|^2, D the Wilson matrix of eq. (1)."""
+    tot = 0.0
+    for r in rs:
+        y = dslash(U, forward(U, r, Ws, nb), kappa, dims)
+        tot += np.vdot(y - r, y - r).real / np.vdot(r, r).real
+    return tot / len(rs)
+
+
+def grad_residual(U, kappa, rs, Ws, nb, dims):
+    """(residual loss, [dW per layer]): the output gradient of sample b is
+    2 / (B |r_b|^2) D^dagger (D M r_b - r_b), then back-propagation."""
+    dWs = [np.zeros_like(W) for W in Ws]
+    tot = 0.0
+    B = len(rs)
+    for r in rs:
+        m, inputs = forward(U, r, Ws, nb, keep=True)
+        y = dslash(U, m, kappa, dims)
+        rn = np.vdot(r, r).real
+        tot += np.vdot(y - r, y - r).real / rn
+        dout = (2.0 / (B * rn)) * dslash(U, y - r, kappa, dims, OP_DDAG)[None]
+        backprop(U, Ws, inputs, dout, nb, dWs)
+    return tot / B, dWs
 
 
 def grad(U, rs, es, Ws, nb):
@@ -100,17 +196,6 @@ def grad(U, rs, es, Ws, nb):
         en = np.vdot(e, e).real
         tot += np.vdot(m - e, m - e).real / en
         dout = (2.0 / (B * en)) * (m - e)[None]          # dL/dRe + i dL/dIm of the output
-        for l in range(len(Ws) - 1, -1, -1):
-            W, fields = Ws[l], inputs[l]
-            cin = fields.shape[0]
-            din = np.zeros_like(fields)
-            for i in range(cin):
-                for p in range(9):
-                    t = transport(U, fields[i], nb, p)
-                    # dW[p, j, i] = sum_x dout_j(x) t(x)^H over spin (colour summed)
-                    dWs[l][p, :, i] += np.einsum("jsac,sbc->jab", dout, np.conj(t))
-                    # dX = W^H dout, then the adjoint transport
-                    dx = np.einsum("jba,jsbc->sac", np.conj(W[p, :, i]), dout)
-                    din[i] += transport_adj(U, dx, nb, p)
-            dout = din
+        backprop(U, Ws, inputs, dout, nb, dWs)
     return tot / B, dWs
+

@@ -101,10 +101,14 @@ _lib.qcd_eo_spectrum.argtypes = [_vp, _d, _i, _i, ctypes.c_uint64, ctypes.POINTE
 _lib.qcd_ptc_loss_grad.argtypes = [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp, _vp]
 _lib.qcd_ptc_train_step.argtypes = [_vp, _i, _vp, _vp, _d, ctypes.POINTER(_d), _vp]
 _lib.qcd_ptc_set_gauge.argtypes = [_vp, _vp]
+_lib.qcd_ptc_set_mixing.argtypes = [_vp, _i, _vp]
+_lib.qcd_ptc_loss_grad_residual.argtypes = [_vp, _d, _i, _vp, ctypes.POINTER(_d), _vp, _vp]
+_lib.qcd_ptc_train_step_residual.argtypes = [_vp, _d, _i, _vp, _d, ctypes.POINTER(_d), _vp]
 _lib.qcd_ptc_init_neumann.argtypes = [_vp, _d, _vp]
 for _f in ("qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_set_weights", "qcd_ptc_get_weights", "qcd_ptc_apply",
            "qcd_ptc_apply_prec", "qcd_eo_spectrum",
            "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
+           "qcd_ptc_set_mixing", "qcd_ptc_loss_grad_residual", "qcd_ptc_train_step_residual",
            "qcd_autotune_dslash", "qcd_set_dslash_tuning", "qcd_get_dslash_tuning", "qcd_gauge_upload", "qcd_gauge_free", "qcd_convert",
            "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir"):
     getattr(_lib, _f).restype = _i
@@ -113,6 +117,7 @@ EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qc
             "qcd_spinor_bytes", "qcd_workspace_bytes", "qcd_convert", "qcd_unconvert", "qcd_dslash", "qcd_residual", "qcd_bicgstab", "qcd_solve_mixed_ir", "qcd_solve_mixed_ir_static", "qcd_solve_mixed_ir_batched",
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_apply_prec", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
+            "qcd_ptc_set_mixing", "qcd_ptc_loss_grad_residual", "qcd_ptc_train_step_residual",
             "qcd_gaussian_spinors", "qcd_eo_spectrum"]
 
 
@@ -459,6 +464,28 @@ class PTC:
         _check(_lib.qcd_ptc_loss_grad(self.handle, nb, _ptr(_as_c128(r)), _ptr(_as_c128(e)), ctypes.byref(loss),
                                       flat.ctypes.data if want_grad else None, _stream()))
         return (loss.value, self._unflatten(flat)) if want_grad else loss.value
+
+    def set_mixing(self, prec):
+        """Channel mixing of the two-pass form in BF16 (default) or FP32."""
+        _check(_lib.qcd_ptc_set_mixing(self.handle, PREC[prec], _stream()))
+
+    def loss_grad_residual(self, kappa, r: torch.Tensor, want_grad=True):
+        """Residual loss mean |D M r - r|^2 / |r|^2 and (optionally) its weight gradient."""
+        import numpy as np
+        nb = 1 if r.dim() == 3 else r.shape[0]
+        loss = ctypes.c_double()
+        flat = np.empty(self.nweights, dtype=np.complex128) if want_grad else None
+        _check(_lib.qcd_ptc_loss_grad_residual(self.handle, float(kappa), nb, _ptr(_as_c128(r)), ctypes.byref(loss),
+                                               flat.ctypes.data if want_grad else None, _stream()))
+        return (loss.value, self._unflatten(flat)) if want_grad else loss.value
+
+    def train_step_residual(self, kappa, r: torch.Tensor, lr=1e-3):
+        """One Adam step on the residual loss; returns the loss before the step."""
+        nb = 1 if r.dim() == 3 else r.shape[0]
+        loss = ctypes.c_double()
+        _check(_lib.qcd_ptc_train_step_residual(self.handle, float(kappa), nb, _ptr(_as_c128(r)), float(lr),
+                                                ctypes.byref(loss), _stream()))
+        return loss.value
 
     def train_step(self, r: torch.Tensor, e: torch.Tensor, lr=1e-3):
         nb = 1 if r.dim() == 3 else r.shape[0]

@@ -39,6 +39,29 @@ __device__ __forceinline__ short to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
 
+// Element type E of the two-pass GEMM operands (X, A, DO): BF16 (as short
+// bits) on the 16x16x16 BF16 matrix-core instruction, or FP32 on the 16x16x4
+// FP32 one (the network's FP32 mixing mode).  In both a lane supplies four
+// consecutive k of its row or column: one BF16 instruction takes all four,
+// or four FP32 instructions take one each (the sum over k is the same).
+template <typename E> struct Mix;
+template <> struct Mix<short> {
+  using V4 = bf16x4;
+  static __device__ __forceinline__ short cvt(float f) { return to_bf16(f); }
+  static __device__ __forceinline__ f32x4 mma(V4 a, V4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mix<float> {
+  using V4 = f32x4;
+  static __device__ __forceinline__ float cvt(float f) { return f; }
+  static __device__ __forceinline__ f32x4 mma(V4 a, V4 b, f32x4 c) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q], c, 0, 0, 0);
+    return c;
+  }
+};
+
 struct PtcLayerDev {
   int cin, cout, K, M, Kp;  // K = 9*cin*4 complex inputs, M = cout*4 complex outputs, Kp = 2K rounded to 16
 };
@@ -82,10 +105,11 @@ __device__ __forceinline__ size_t xidx(size_t nc, int nk, size_t n, int k) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward transport: X (BF16) at (n, k), n = b * ncols + column (site, colour),
+// Forward transport: X (BF16 or FP32) at (n, k), n = b * ncols + column (site, colour),
 // k = reim*K + (p*cin + i)*4 + spin; k in [2K, Kp) and padding sites are zero.
+template <typename E>
 __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, const float2* __restrict__ act,
-                                                       const float2* __restrict__ U, int recon, short* __restrict__ X) {
+                                                       const float2* __restrict__ U, int recon, E* __restrict__ X) {
   const int b = blockIdx.y;
   const int i_site = blockIdx.x * 256 + threadIdx.x;  // over 2 * nb * 64 (padding included)
   const int per = g.nb * 64;
@@ -121,22 +145,23 @@ __global__ __launch_bounds__(256) void k_ptc_transport(Geom g, PtcLayerDev L, co
       }
       const int k0 = (p * L.cin + i) * 4;
       for (int cc = 0; cc < 3; cc++) {
-        bf16x4 re, im;
+        typename Mix<E>::V4 re, im;
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-          re[s] = to_bf16(t[3 * s + cc].re);
-          im[s] = to_bf16(t[3 * s + cc].im);
+          re[s] = Mix<E>::cvt(t[3 * s + cc].re);
+          im[s] = Mix<E>::cvt(t[3 * s + cc].im);
         }
         // k0 and K are multiples of 4, so each group of 4 stays in one k-tile
-        *reinterpret_cast<bf16x4*>(X + xidx(nc, nk, n0 + cc, k0)) = re;
-        *reinterpret_cast<bf16x4*>(X + xidx(nc, nk, n0 + cc, L.K + k0)) = im;
+        *reinterpret_cast<typename Mix<E>::V4*>(X + xidx(nc, nk, n0 + cc, k0)) = re;
+        *reinterpret_cast<typename Mix<E>::V4*>(X + xidx(nc, nk, n0 + cc, L.K + k0)) = im;
       }
     }
   }
 }
 
-// A[16][Kp] (BF16) from the complex weights W[p][j][i][s'][s] of one layer.
-__global__ void k_ptc_prep_A(PtcLayerDev L, const float2* __restrict__ W, short* __restrict__ A) {
+// A[16][Kp] (BF16 or FP32) from the complex weights W[p][j][i][s'][s] of one layer.
+template <typename E>
+__global__ void k_ptc_prep_A(PtcLayerDev L, const float2* __restrict__ W, E* __restrict__ A) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 16 * L.Kp) return;
   const int r = idx / L.Kp, k = idx % L.Kp;
@@ -154,19 +179,20 @@ __global__ void k_ptc_prep_A(PtcLayerDev L, const float2* __restrict__ W, short*
     else if (rim && kre) v = w.y;
     else v = w.x;
   }
-  A[idx] = to_bf16(v);
+  A[idx] = Mix<E>::cvt(v);
 }
 
 // Channel mixing: out[b][j] (native FP32 fields) = layer(X).  One wave per
 // tile of 16 columns; A fragments stay in registers.
-__global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const short* __restrict__ X,
-                                                 const short* __restrict__ A, float2* __restrict__ out, int nbatch) {
+template <typename E>
+__global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const E* __restrict__ X,
+                                                 const E* __restrict__ A, float2* __restrict__ out, int nbatch) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
   const size_t N = ncols(g);
   const size_t ntiles = (N * nbatch) / 16;  // N is a multiple of 192
   const int nk = L.Kp / 16;
-  bf16x4 af[9];
+  typename Mix<E>::V4 af[9];
 #pragma unroll
   for (int kt = 0; kt < 9; kt++)
 #pragma unroll
@@ -178,8 +204,9 @@ __global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const sh
 #pragma unroll
     for (int kt = 0; kt < 9; kt++) {
       if (kt >= nk) break;
-      const bf16x4 bf = *reinterpret_cast<const bf16x4*>(X + xidx(N, nk, n, kt * 16 + 4 * (lane / 16)));
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kt], bf, acc, 0, 0, 0);
+      const typename Mix<E>::V4 bf =
+          *reinterpret_cast<const typename Mix<E>::V4*>(X + xidx(N, nk, n, kt * 16 + 4 * (lane / 16)));
+      acc = Mix<E>::mma(af[kt], bf, acc);
     }
     // lane holds rows 4*(lane/16) + q of column n
     const int b = (int)(n / N);
@@ -424,18 +451,19 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
 // ---------------------------------------------------------------------------
 // Backward.
 
-// dOut (native FP32 fields) -> DO[b][n][16] BF16 real form (re rows, im rows, zeros).
-__global__ __launch_bounds__(256) void k_ptc_dout_bf16(Geom g, PtcLayerDev L, const float2* __restrict__ dout,
-                                                       short* __restrict__ DO) {
+// dOut (native FP32 fields) -> DO[b][n][16] in E, real form (re rows, im rows, zeros).
+template <typename E>
+__global__ __launch_bounds__(256) void k_ptc_dout_mix(Geom g, PtcLayerDev L, const float2* __restrict__ dout,
+                                                      E* __restrict__ DO) {
   const int b = blockIdx.y;
   const int i_site = blockIdx.x * 256 + threadIdx.x;
   const int per = g.nb * 64;
   if (i_site >= 2 * per) return;
   const int par = i_site >= per, h = i_site - par * per;
-  short* d = DO + ((size_t)b * ncols(g) + col_of(g, par, h)) * 16;
+  E* d = DO + ((size_t)b * ncols(g) + col_of(g, par, h)) * 16;
   const size_t fstride = spinor_elems(g);
   for (int cc = 0; cc < 3; cc++) {
-    short row[16];
+    E row[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) row[r] = 0;
     if (h < g.Vh) {
@@ -443,21 +471,22 @@ __global__ __launch_bounds__(256) void k_ptc_dout_bf16(Geom g, PtcLayerDev L, co
         cx<float> f[12];
         load_site(dout + ((size_t)b * L.cout + j) * fstride, g, par, h, f);
         for (int sp = 0; sp < 4; sp++) {
-          row[4 * j + sp] = to_bf16(f[3 * sp + cc].re);
-          row[L.M + 4 * j + sp] = to_bf16(f[3 * sp + cc].im);
+          row[4 * j + sp] = Mix<E>::cvt(f[3 * sp + cc].re);
+          row[L.M + 4 * j + sp] = Mix<E>::cvt(f[3 * sp + cc].im);
         }
       }
     }
     for (int r = 0; r < 16; r += 4) {
-      bf16x4 v = {row[r], row[r + 1], row[r + 2], row[r + 3]};
-      *reinterpret_cast<bf16x4*>(d + (size_t)cc * 16 + r) = v;
+      typename Mix<E>::V4 v = {row[r], row[r + 1], row[r + 2], row[r + 3]};
+      *reinterpret_cast<typename Mix<E>::V4*>(d + (size_t)cc * 16 + r) = v;
     }
   }
 }
 
 // DX[b][n][k] (FP32) = sum_r A[r][k] DO[b][n][r]: one MFMA per (k tile, column tile).
-__global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const short* __restrict__ DO,
-                                                    const short* __restrict__ A, float* __restrict__ DX, int nbatch) {
+template <typename E>
+__global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const E* __restrict__ DO,
+                                                    const E* __restrict__ A, float* __restrict__ DX, int nbatch) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
   const size_t N = ncols(g) * nbatch;
@@ -466,13 +495,13 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dx(Geom g, PtcLayerDev L, const
   for (size_t tile = wave; tile < ntiles; tile += nwaves) {
     const size_t n = tile * 16 + (lane % 16);
     const size_t nc = ncols(g);
-    const bf16x4 bf = *reinterpret_cast<const bf16x4*>(DO + n * 16 + 4 * (lane / 16));
+    const typename Mix<E>::V4 bf = *reinterpret_cast<const typename Mix<E>::V4*>(DO + n * 16 + 4 * (lane / 16));
     for (int kt = 0; kt < nk; kt++) {
-      bf16x4 at;  // A^T tile: row = k, column = r
+      typename Mix<E>::V4 at;  // A^T tile: row = k, column = r
 #pragma unroll
       for (int q = 0; q < 4; q++) at[q] = A[(4 * (lane / 16) + q) * L.Kp + kt * 16 + (lane % 16)];
       f32x4 acc = {0, 0, 0, 0};
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(at, bf, acc, 0, 0, 0);
+      acc = Mix<E>::mma(at, bf, acc);
       // lane holds rows k = kt*16 + 4*(lane/16) + q of column n
       *reinterpret_cast<f32x4*>(DX + xidx(nc, nk, n, kt * 16 + 4 * (lane / 16))) = acc;
     }
@@ -536,8 +565,9 @@ __global__ __launch_bounds__(256) void k_ptc_transport_adj(Geom g, PtcLayerDev L
 }
 
 // G partials: Gp[wave][16][Kp] = sum over the wave's columns of DO[n][r] X[n][k].
-__global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const short* __restrict__ DO,
-                                                    const short* __restrict__ X, float* __restrict__ Gp, int nbatch) {
+template <typename E>
+__global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const E* __restrict__ DO,
+                                                    const E* __restrict__ X, float* __restrict__ Gp, int nbatch) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * 256 + threadIdx.x) >> 6, nwaves = gridDim.x * 4;
   const size_t N = ncols(g) * nbatch;
@@ -549,16 +579,16 @@ __global__ __launch_bounds__(256) void k_ptc_mix_dw(Geom g, PtcLayerDev L, const
   for (int kt = 0; kt < 9; kt++) acc[kt] = (f32x4){0, 0, 0, 0};
   for (size_t tile = wave; tile < ntiles; tile += nwaves) {
     const size_t n0 = tile * 16;
-    bf16x4 a;  // A[r][nn] = DO[n0 + nn][r]: row r = lane % 16, nn = 4*(lane/16) + q
+    typename Mix<E>::V4 a;  // A[r][nn] = DO[n0 + nn][r]: row r = lane % 16, nn = 4*(lane/16) + q
 #pragma unroll
     for (int q = 0; q < 4; q++) a[q] = DO[(n0 + 4 * (lane / 16) + q) * 16 + (lane % 16)];
 #pragma unroll
     for (int kt = 0; kt < 9; kt++) {
       if (kt >= nk) break;
-      bf16x4 bb;  // B[nn][k] = X(n0 + nn, kt*16 + lane % 16)
+      typename Mix<E>::V4 bb;  // B[nn][k] = X(n0 + nn, kt*16 + lane % 16)
 #pragma unroll
       for (int q = 0; q < 4; q++) bb[q] = X[xidx(nc, nk, n0 + 4 * (lane / 16) + q, kt * 16 + (lane % 16))];
-      acc[kt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[kt], 0, 0, 0);
+      acc[kt] = Mix<E>::mma(a, bb, acc[kt]);
     }
   }
   // lane holds G[4*(lane/16) + q][kt*16 + lane % 16]
@@ -745,14 +775,15 @@ struct qcd_ptc {
   float2* adam_m;
   float2* adam_v;
   int adam_step;
-  short* A[kPtcMaxLayers];          // BF16 GEMM operands (training ordering)
+  int mix_fp32;                     // 1: the two-pass GEMMs (A, X, DO) in FP32, else BF16
+  void* A[kPtcMaxLayers];           // GEMM operands (training ordering), BF16 or FP32
   short* Af[kPtcMaxLayers];         // BF16 GEMM operands (fused inference ordering)
   __half2* act16[kPtcMaxLayers + 1];  // FP16 hidden activations of the solver's applications
   float2* act[kPtcMaxLayers + 1];   // activations (batch x channels native FP32 fields)
   float2* target;                   // training targets (batch fields)
   float2* dact[2];                  // gradient ping-pong buffers
-  short* X[kPtcMaxLayers];          // transported inputs per layer (kept for the backward pass)
-  short* DO;
+  void* X[kPtcMaxLayers];           // transported inputs per layer (kept for the backward pass), BF16 or FP32
+  void* DO;                         // output gradient in the real form, BF16 or FP32
   float* DX;
   float* Gp;
   double* dwp;                      // weight-gradient slices [kDwSlices][M*K][4]
@@ -793,8 +824,12 @@ qcd_status alloc(qcd_ptc* n, void** p, size_t bytes) {
 void prep_weights(qcd_ptc* n, hipStream_t st) {
   for (int l = 0; l < n->nlayers; l++) {
     const int cnt = 16 * n->L[l].Kp;
-    hipLaunchKernelGGL(k_ptc_prep_A, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
-                       (const float2*)(n->w + n->woff[l]), n->A[l]);
+    if (n->mix_fp32)
+      hipLaunchKernelGGL(k_ptc_prep_A<float>, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
+                         (const float2*)(n->w + n->woff[l]), (float*)n->A[l]);
+    else
+      hipLaunchKernelGGL(k_ptc_prep_A<short>, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
+                         (const float2*)(n->w + n->woff[l]), (short*)n->A[l]);
     hipLaunchKernelGGL(k_ptc_prep_Af, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
                        (const float2*)(n->w + n->woff[l]), n->Af[l]);
   }
@@ -820,19 +855,67 @@ void fused_layer(const qcd_ptc* n, int l, int nb, const SA* in, SA* out, const S
 // Forward through all layers from act[0].  With train, the two-pass form
 // keeps the transported inputs of every layer for the backward pass; else
 // each layer is one fused kernel.
-void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
+template <typename E> void two_pass_layer(qcd_ptc* n, int l, int nb, hipStream_t st) {
   const Geom& g = n->g;
+  hipLaunchKernelGGL(k_ptc_transport<E>, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, n->L[l],
+                     (const float2*)n->act[l], links32(n), recon_of(n, kFP32), (E*)n->X[l]);
+  hipLaunchKernelGGL(k_ptc_mix<E>, dim3(n->mix_blocks), dim3(256), 0, st, g, n->L[l], (const E*)n->X[l],
+                     (const E*)n->A[l], n->act[l + 1], nb);
+}
+
+// (the FP32 mixing mode runs every FP32-activation forward in the two-pass form)
+void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
   for (int l = 0; l < n->nlayers; l++) {
-    if (!train) {
+    if (n->mix_fp32) {
+      two_pass_layer<float>(n, l, nb, st);
+    } else if (!train) {
       fused_layer<float2, float2>(n, l, nb, n->act[l], n->act[l + 1], links32(n), 1.0f, nullptr, 0, st);
-      continue;
+    } else {
+      two_pass_layer<short>(n, l, nb, st);
     }
-    short* X = n->X[l];
-    hipLaunchKernelGGL(k_ptc_transport, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, n->L[l],
-                       (const float2*)n->act[l], links32(n), recon_of(n, kFP32), X);
-    hipLaunchKernelGGL(k_ptc_mix, dim3(n->mix_blocks), dim3(256), 0, st, g, n->L[l], (const short*)X,
-                       (const short*)n->A[l], n->act[l + 1], nb);
   }
+}
+
+// One layer's backward from dact[cur]: weight gradient into n->grad, and
+// (l > 0) the input gradient into dact[cur ^ 1].
+template <typename E> void backward_layer(qcd_ptc* n, int l, int nb, int cur, hipStream_t st) {
+  const Geom& g = n->g;
+  const PtcLayerDev& L = n->L[l];
+  hipLaunchKernelGGL(k_ptc_dout_mix<E>, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, L,
+                     (const float2*)n->dact[cur], (E*)n->DO);
+  hipLaunchKernelGGL(k_ptc_mix_dw<E>, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const E*)n->DO,
+                     (const E*)n->X[l], n->Gp, nb);
+  hipLaunchKernelGGL(k_ptc_dw_slices, dim3((L.M * L.K + 63) / 64, kDwSlices), dim3(64), 0, st, L,
+                     (const float*)n->Gp, n->mix_blocks * 4, n->dwp);
+  hipLaunchKernelGGL(k_ptc_dw_finish, dim3((L.M * L.K + 255) / 256), dim3(256), 0, st, L, (const double*)n->dwp,
+                     n->grad + n->woff[l]);
+  if (l > 0) {
+    hipLaunchKernelGGL(k_ptc_mix_dx<E>, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const E*)n->DO,
+                       (const E*)n->A[l], n->DX, nb);
+    hipLaunchKernelGGL(k_ptc_transport_adj, dim3(site_blocks(g), nb), dim3(256), 0, st, g, L, (const float*)n->DX,
+                       links32(n), recon_of(n, kFP32), n->dact[cur ^ 1]);
+  }
+}
+
+// Weight gradient (into n->grad) from the output gradient in dact[0].
+void backward(qcd_ptc* n, int nb, hipStream_t st) {
+  int cur = 0;
+  for (int l = n->nlayers - 1; l >= 0; l--) {
+    if (n->mix_fp32) backward_layer<float>(n, l, nb, cur, st);
+    else backward_layer<short>(n, l, nb, cur, st);
+    if (l > 0) cur ^= 1;
+  }
+}
+
+// mean over the batch of sums[2b] / sums[2b + 1] (synchronises)
+qcd_status read_loss(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
+  std::vector<double> h(2 * nb);
+  PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+  PTC_TRY(hipStreamSynchronize(st));
+  double tot = 0;
+  for (int b = 0; b < nb; b++) tot += h[2 * b] / h[2 * b + 1];
+  *loss = tot / nb;
+  return QCD_OK;
 }
 
 // Loss and gradient of the weights (into n->grad) for the batch in act[0] / target.
@@ -847,34 +930,63 @@ qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
   hipLaunchKernelGGL(k_ptc_dout, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[last],
                      (const float2*)n->target, (const double*)n->sums, nb, n->dact[0]);
   PTC_TRY(hipMemsetAsync(n->grad, 0, n->nweights * sizeof(float2), st));
-  int cur = 0;
-  for (int l = n->nlayers - 1; l >= 0; l--) {
-    const PtcLayerDev& L = n->L[l];
-    hipLaunchKernelGGL(k_ptc_dout_bf16, dim3(site_blocks_pad(g), nb), dim3(256), 0, st, g, L,
-                       (const float2*)n->dact[cur], n->DO);
-    hipLaunchKernelGGL(k_ptc_mix_dw, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
-                       (const short*)n->X[l], n->Gp, nb);
-    hipLaunchKernelGGL(k_ptc_dw_slices, dim3((L.M * L.K + 63) / 64, kDwSlices), dim3(64), 0, st, L,
-                       (const float*)n->Gp, n->mix_blocks * 4, n->dwp);
-    hipLaunchKernelGGL(k_ptc_dw_finish, dim3((L.M * L.K + 255) / 256), dim3(256), 0, st, L, (const double*)n->dwp,
-                       n->grad + n->woff[l]);
-    if (l > 0) {
-      hipLaunchKernelGGL(k_ptc_mix_dx, dim3(n->mix_blocks), dim3(256), 0, st, g, L, (const short*)n->DO,
-                         (const short*)n->A[l], n->DX, nb);
-      hipLaunchKernelGGL(k_ptc_transport_adj, dim3(site_blocks(g), nb), dim3(256), 0, st, g, L, (const float*)n->DX,
-                         links32(n), recon_of(n, kFP32), n->dact[cur ^ 1]);
-      cur ^= 1;
-    }
-  }
+  backward(n, nb, st);
   PTC_LAUNCHED();
-  if (loss) {
-    std::vector<double> h(2 * nb);
-    PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
-    PTC_TRY(hipStreamSynchronize(st));
-    double tot = 0;
-    for (int b = 0; b < nb; b++) tot += h[2 * b] / h[2 * b + 1];
-    *loss = tot / nb;
-  }
+  if (loss) return read_loss(n, nb, loss, st);
+  return QCD_OK;
+}
+
+// The residual loss (1/B) sum_b |D M r_b - r_b|^2 / |r_b|^2 for the batch in
+// act[0], D the Wilson matrix of eq. (1) (FP32 operator on the handle's FP32
+// links), and its weight gradient: the output gradient is
+// 2 / (B |r_b|^2) D^dag (D M r_b - r_b).  target holds D M r, dact[1] the
+// scaled residual before D^dag.
+qcd_status loss_grad_residual(qcd_ptc* n, double kappa, int nb, double* loss, hipStream_t st) {
+  const Geom& g = n->g;
+  const qcd_gauge* G = n->gauge;
+  forward(n, nb, true, st);
+  const int last = n->nlayers;
+  launch_dslash(kFP32, g, G->tune[kFP32], kOpD, kEpiNone, nb, n->target, n->act[last], G->U[kFP32], kappa, nullptr,
+                nullptr, nullptr, 0, st);
+  hipLaunchKernelGGL(k_ptc_loss_parts, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->target,
+                     (const float2*)n->act[0], n->partials);
+  hipLaunchKernelGGL(k_ptc_loss_finish, dim3(nb), dim3(1024), 0, st, (const double*)n->partials, site_blocks(g), nb,
+                     n->sums);
+  hipLaunchKernelGGL(k_ptc_dout, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->target,
+                     (const float2*)n->act[0], (const double*)n->sums, nb, n->dact[1]);
+  launch_dslash(kFP32, g, G->tune[kFP32], kOpDdag, kEpiNone, nb, n->dact[0], n->dact[1], G->U[kFP32], kappa, nullptr,
+                nullptr, nullptr, 0, st);
+  PTC_TRY(hipMemsetAsync(n->grad, 0, n->nweights * sizeof(float2), st));
+  backward(n, nb, st);
+  PTC_LAUNCHED();
+  if (loss) return read_loss(n, nb, loss, st);
+  return QCD_OK;
+}
+
+// Adam on the FP32 master weights from n->grad, then the GEMM operands.
+void adam_step(qcd_ptc* n, double lr, hipStream_t st) {
+  n->adam_step++;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)n->adam_step), c2 = 1.0f - powf(b2, (float)n->adam_step);
+  const int cnt = (int)(2 * n->nweights);
+  hipLaunchKernelGGL(k_adam, dim3((cnt + 255) / 256), dim3(256), 0, st, (float*)n->w, (const float*)n->grad,
+                     (float*)n->adam_m, (float*)n->adam_v, cnt, (float)lr, b1, b2, 1e-8f, c1, c2);
+  prep_weights(n, st);
+}
+
+// Replace one of the handle's buffers by a new one of `bytes`.
+qcd_status realloc_buf(qcd_ptc* n, void** p, size_t bytes) {
+  void* q = nullptr;
+  PTC_TRY(hipMalloc(&q, bytes ? bytes : 256));
+  for (auto& a : n->allocs)
+    if (a == *p) {
+      (void)hipFree(a);
+      a = q;
+      *p = q;
+      return QCD_OK;
+    }
+  n->allocs.push_back(q);
+  *p = q;
   return QCD_OK;
 }
 
@@ -1104,15 +1216,64 @@ qcd_status qcd_ptc_train_step(qcd_ptc* n, int nbatch, const void* r_dev, const v
                               void* stream) {
   qcd_status rc = qcd_ptc_loss_grad(n, nbatch, r_dev, e_dev, loss, nullptr, stream);
   if (rc) return rc;
+  adam_step(n, lr, (hipStream_t)stream);
+  PTC_LAUNCHED();
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_loss_grad_residual(qcd_ptc* n, double kappa, int nbatch, const void* r_dev, double* loss,
+                                      double* grad_host, void* stream) {
+  qcd_status rc = check_batch(n, nbatch);
+  if (rc) return rc;
+  if (!r_dev) return pfail(QCD_ERR_ARG, "null vector");
+  if (!(kappa > 0) || !std::isfinite(kappa)) return pfail(QCD_ERR_ARG, "kappa must be positive and finite");
   hipStream_t st = (hipStream_t)stream;
-  n->adam_step++;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.0f - powf(b1, (float)n->adam_step), c2 = 1.0f - powf(b2, (float)n->adam_step);
-  const int cnt = (int)(2 * n->nweights);
-  hipLaunchKernelGGL(k_adam, dim3((cnt + 255) / 256), dim3(256), 0, st, (float*)n->w, (const float*)n->grad,
-                     (float*)n->adam_m, (float*)n->adam_v, cnt, (float)lr, b1, b2, 1e-8f, c1, c2);
+  launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)r_dev, 1.0, 0, nullptr, st);
+  if ((rc = loss_grad_residual(n, kappa, nbatch, loss, st))) return rc;
+  if (grad_host) {
+    std::vector<float2> h(n->nweights);
+    PTC_TRY(hipMemcpyAsync(h.data(), n->grad, n->nweights * sizeof(float2), hipMemcpyDeviceToHost, st));
+    PTC_TRY(hipStreamSynchronize(st));
+    for (size_t i = 0; i < n->nweights; i++) {
+      grad_host[2 * i] = h[i].x;
+      grad_host[2 * i + 1] = h[i].y;
+    }
+  }
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_train_step_residual(qcd_ptc* n, double kappa, int nbatch, const void* r_dev, double lr,
+                                       double* loss, void* stream) {
+  qcd_status rc = qcd_ptc_loss_grad_residual(n, kappa, nbatch, r_dev, loss, nullptr, stream);
+  if (rc) return rc;
+  adam_step(n, lr, (hipStream_t)stream);
+  PTC_LAUNCHED();
+  return QCD_OK;
+}
+
+qcd_status qcd_ptc_set_mixing(qcd_ptc* n, qcd_prec prec, void* stream) {
+  if (!n) return pfail(QCD_ERR_ARG, "null network handle");
+  if (prec != QCD_BF16 && prec != QCD_FP32) return pfail(QCD_ERR_ARG, "the mixing runs in BF16 or FP32");
+  const int want = prec == QCD_FP32;
+  if (want == n->mix_fp32) return QCD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  PTC_TRY(hipStreamSynchronize(st));  // no launch may still read the old buffers
+  const size_t es = want ? sizeof(float) : sizeof(short);
+  const Geom& g = n->g;
+  const size_t N = (size_t)2 * g.nb * 64 * 3;
+  int maxKp = 16;
+  for (int l = 0; l < n->nlayers; l++) maxKp = std::max(maxKp, n->L[l].Kp);
+  qcd_status rc = QCD_OK;
+  for (int l = 0; l < n->nlayers && rc == QCD_OK; l++) {
+    rc = realloc_buf(n, &n->A[l], 16 * (size_t)n->L[l].Kp * es);
+    if (rc == QCD_OK) rc = realloc_buf(n, &n->X[l], (size_t)n->max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * es);
+  }
+  if (rc == QCD_OK) rc = realloc_buf(n, &n->DO, (size_t)n->max_batch * N * 16 * es);
+  if (rc) return rc;
+  n->mix_fp32 = want;
   prep_weights(n, st);
   PTC_LAUNCHED();
+  PTC_TRY(hipStreamSynchronize(st));
   return QCD_OK;
 }
 

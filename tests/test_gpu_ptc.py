@@ -297,22 +297,103 @@ def test_device_sources_match_the_input_generator(q):
     assert abs(np.mean(np.abs(big) ** 2) - 1.0) < 1e-2 and abs(np.mean(big)) < 5e-3
 
 
-def test_fp16_apply_at_full_size_matches_fp32_apply(q):
-    # 32^3 x 64, the headline lattice: the oracle's whole-lattice forward is
-    # too slow here, so the FP16 form (checked against the oracle above on
-    # small lattices) is compared with the FP32 form of the same weights.
-    # They differ by binary16 roundings (u = 2^-11) of input, links and hidden
-    # activations, and by BF16 roundings of slightly different mixing inputs:
-    # the oracle tolerances hold between them too.
-    dims = (32, 32, 32, 64)
+@pytest.mark.parametrize("dims", [(32, 32, 32, 64)])
+def test_apply_at_full_size_matches_oracle_on_sampled_sites(q, dims):
+    # 32^3 x 64, the headline lattice: the oracle's network evaluated on 66
+    # sampled sites (its three-hop neighbourhoods only) against the FP32 apply
+    # (fused BF16 mixing) and the FP16 form the inner solver applies, whose
+    # launches here have the full lattice's block count and schedule
     V = qi.volume(dims)
-    g = q.gauge_upload(to_dev(qi.gauge_field(dims, 0.3, 70)), dims, precs=(q.FP32, q.FP16))
+    U = qi.gauge_field(dims, 0.3, 70)
+    psi = qi.gaussian_source(dims, 72)
+    Ws = qi.ptc_weights(CH, seed=71, scale=0.5)
+    rng = np.random.default_rng(73)
+    sites = np.concatenate([[0, V - 1], rng.integers(0, V, 64)])
+    want = P.forward_sites(U, psi, Ws, dims, sites)
+    g = q.gauge_upload(to_dev(U), dims, precs=(q.FP32, q.FP16))
     net = q.PTC(g, CH, max_batch=1)
-    net.set_weights(qi.ptc_weights(CH, seed=71, scale=0.5))
-    psi = q.gaussian_spinors((V, 4, 3), 72)
-    o16, o32 = torch.empty_like(psi), torch.empty_like(psi)
-    net.apply_prec(o16, psi, q.FP16)
-    net.apply_prec(o32, psi, q.FP32)
-    check(to_host(o16), to_host(o32), 1e-2, 5e-2, "fp16 vs fp32 at 32^3 x 64")
+    net.set_weights(Ws)
+    x = to_dev(psi)
+    o16, o32 = torch.empty_like(x), torch.empty_like(x)
+    net.apply_prec(o16, x, q.FP16)
+    net.apply_prec(o32, x, q.FP32)
+    check(to_host(o32)[sites], want, 1e-2, 5e-2, "fp32 apply at 32^3 x 64, sampled sites")
+    check(to_host(o16)[sites], want, 1e-2, 5e-2, "fp16 apply at 32^3 x 64, sampled sites")
+    net.close()
+    g.close()
+    del x, o16, o32
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_fp32_mixing_matches_oracle_tightly(q, dims):
+    # With FP32 mixing (FP32 transported inputs, weights and output gradients on
+    # the FP32 matrix cores) every rounding is FP32 (u = 2^-24) over sums of a
+    # few hundred terms: forward, loss and gradients agree with the FP64 oracle
+    # to 1e-5, for the regression loss and for the residual loss.
+    U = qi.gauge_field(dims, 0.3, 75)
+    B = 2
+    k = 0.124
+    rs = qi.gaussian_source(dims, 76, nrhs=B)
+    es = qi.gaussian_source(dims, 77, nrhs=B)
+    Ws = qi.ptc_weights(CH, seed=78, scale=0.5)
+    nb = P.neighbours(dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, CH, max_batch=B)
+    net.set_weights(Ws)
+    net.set_mixing(q.FP32)
+    out = torch.empty_like(to_dev(rs))
+    net.apply(out, to_dev(rs))
+    got = to_host(out)
+    for b in range(B):
+        check(got[b], P.forward(U, rs[b], Ws, nb), 1e-5, 1e-4, f"fp32-mixing forward dims={dims} b={b}")
+    want_loss, want_grad = P.grad(U, list(rs), list(es), Ws, nb)
+    loss, grad = net.loss_grad(to_dev(rs), to_dev(es))
+    assert abs(loss - want_loss) <= 1e-5 * want_loss, (loss, want_loss)
+    for l, (a, b_) in enumerate(zip(grad, want_grad)):
+        r = rel(a, b_)
+        assert r <= 1e-5, f"layer {l}: gradient norm-relative error {r:.3e}"
+    want_loss, want_grad = P.grad_residual(U, k, list(rs), Ws, nb, dims)
+    loss, grad = net.loss_grad_residual(k, to_dev(rs))
+    assert abs(loss - want_loss) <= 1e-5 * want_loss, (loss, want_loss)
+    for l, (a, b_) in enumerate(zip(grad, want_grad)):
+        r = rel(a, b_)
+        assert r <= 1e-5, f"layer {l}: residual-loss gradient norm-relative error {r:.3e}"
+    # back to BF16 mixing: the BF16 results of a fresh network, bit for bit
+    net.set_mixing(q.BF16)
+    fresh = q.PTC(g, CH, max_batch=B)
+    fresh.set_weights(Ws)
+    o1, o2 = torch.empty_like(out), torch.empty_like(out)
+    net.apply(o1, to_dev(rs))
+    fresh.apply(o2, to_dev(rs))
+    assert torch.equal(o1, o2)
+    fresh.close()
+    net.close()
+    g.close()
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_residual_loss_and_gradient_bf16_match_oracle(q, dims):
+    # the residual loss with BF16 mixing: the tolerances of the regression loss
+    U = qi.gauge_field(dims, 0.3, 85)
+    B = 2
+    k = 0.124
+    rs = qi.gaussian_source(dims, 86, nrhs=B)
+    Ws = qi.ptc_weights(CH, seed=87, scale=0.5)
+    nb = P.neighbours(dims)
+    want_loss, want_grad = P.grad_residual(U, k, list(rs), Ws, nb, dims)
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, CH, max_batch=B)
+    net.set_weights(Ws)
+    loss, grad = net.loss_grad_residual(k, to_dev(rs))
+    assert abs(loss - want_loss) <= 1e-2 * want_loss
+    for l, (a, b_) in enumerate(zip(grad, want_grad)):
+        r = rel(a, b_)
+        assert r <= 3e-2, f"layer {l}: gradient norm-relative error {r:.3e}"
+    # a training step on the residual loss lowers it
+    l0 = net.train_step_residual(k, to_dev(rs), lr=1e-3)
+    for _ in range(20):
+        l1 = net.train_step_residual(k, to_dev(rs), lr=1e-3)
+    assert l1 < l0, (l0, l1)
     net.close()
     g.close()
