@@ -539,6 +539,9 @@ def main():
             g.autotune(prec, nrhs=1, reps=10)
         tuned[name] = list(g.get_tuning(prec)) + [g.link_reals(prec)]
     calib_bytes = calibration_copy(torch)
+    ceiling = q.stream_probe()   # hand-written 16-byte streaming sweeps: what HBM delivers on this GPU
+    print(f"[bench] stream probe: read {ceiling['read_GBps']:.0f} copy {ceiling['copy_GBps']:.0f} "
+          f"write {ceiling['write_GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     # Wilson operator roofline (dominant kernel of the inner solve), timed
     # before the solver workspaces are allocated
     dsl = {}
@@ -722,7 +725,14 @@ def main():
                 frac=dsl["fp16"]["frac"], traffic=traffic, kernel="k_dslash<__half2, D>",
                 bytes_per_site=DSLASH_BYTES[2], sites_per_launch=V,
                 algorithmic_bytes_per_launch=DSLASH_BYTES[2] * V, copy_GBps=copy_bandwidth(torch),
-                valu_issue_frac=valu_frac, link_reals=tuned["fp16"][3])
+                valu_issue_frac=valu_frac, link_reals=tuned["fp16"][3],
+                us_median=dsl["fp16"]["us_median"], stream_probe=ceiling)
+    # the bytes the kernel must move with its two-row links (12 of 18 reals)
+    two_row = 96 + 2 * 48 if tuned["fp16"][3] == 12 else DSLASH_BYTES[2]
+    roof["stored_bytes_per_site"] = two_row
+    roof["stored_GBps"] = two_row * V / (dsl["fp16"]["us"] * 1e-6) / 1e9
+    roof["stored_frac"] = roof["stored_GBps"] / PEAK_HBM_GBS
+    roof["frac_of_stream_read"] = dsl["fp16"]["GBps"] / ceiling["read_GBps"]
     rescaling = None
     if not args.no_rescaling_study and dims == (32, 32, 32, 64):
         from paper_2602_14450_amd import rescaling_study as RS

@@ -169,8 +169,13 @@ int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
  * rhs_tile (0 = automatic, 1, 2, 4) is the number of right-hand sides whose
  * lanes share one wave's link loads in a multi-RHS application, -2, -3, -4 the
  * number a thread applies one loaded link to (it must divide nrhs, else 1 is
- * used; automatic takes 3 or 2 per thread for FP16 and 1 otherwise).  Results
- * do not depend on these choices beyond FP16 rounding of the register tiles. */
+ * used; automatic takes 3 or 2 per thread for FP16 and 1 otherwise); 8 selects
+ * the matrix-core form for FP16 storage: the SU(3) products of a hop for a
+ * tile of 16, 12, 8, 6 or 4 right-hand sides (the largest dividing nrhs) run
+ * as binary16 16 x 16 x 16 matrix-core products, two sites per instruction;
+ * it applies to the plain operator (launches with a reduction epilogue and
+ * other precisions use one right-hand side per thread).  Results do not
+ * depend on these choices beyond FP16 rounding of the tiles' summation order. */
 qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int variant, int rhs_tile);
 qcd_status qcd_get_dslash_tuning(const qcd_gauge* g, qcd_prec prec, int* sched, int* variant, int* rhs_tile);
 
@@ -323,6 +328,18 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
  * QCD_ERR_NONFINITE, QCD_ERR_HIP. */
 qcd_status qcd_eo_spectrum(const qcd_gauge* g, double kappa, int power_iters, int inverse_iters, uint64_t seed,
                            double* abs_max, double* abs_min, void* stream);
+
+/* Memory-system probe (a diagnostic; not part of the method): the average
+ * time in microseconds of one sweep over bytes (a positive multiple of 16)
+ * that reads src_dev (mode 0), copies src_dev to dst_dev (mode 1) or writes
+ * dst_dev (mode 2), every lane moving 16-byte granules with non-temporal
+ * loads and stores, timed with HIP events over reps (1..10000) sweeps after
+ * one untimed sweep.  dst_dev holds bytes (mode 0 may store there only if
+ * the data read happens to hash to a fixed pattern).  The bandwidth the
+ * Wilson operator is compared with is measured this way on the same GPU.
+ * Synchronises.  QCD_ERR_ARG for invalid arguments. */
+qcd_status qcd_stream_probe(void* dst_dev, const void* src_dev, size_t bytes, int mode, int reps, double* us,
+                            void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner: a gauge-covariant parallel-transport network.

@@ -87,6 +87,8 @@ _lib.qcd_solve_mixed_ir_batched.argtypes = [_i, ctypes.POINTER(_vp), ctypes.POIN
                                             ctypes.POINTER(_sz), _vp]
 _lib.qcd_solve_mixed_ir_batched.restype = _i
 _lib.qcd_set_dslash_tuning.argtypes = [_vp, _i, _i, _i, _i]
+_lib.qcd_stream_probe.argtypes = [_vp, _vp, _sz, _i, _i, ctypes.POINTER(_d), _vp]
+_lib.qcd_stream_probe.restype = _i
 _lib.qcd_autotune_dslash.argtypes = [_vp, _i, _i, _i, ctypes.c_char_p, ctypes.POINTER(_d), _vp]
 _lib.qcd_get_dslash_tuning.argtypes = [_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
 _lib.qcd_ptc_create.argtypes = [ctypes.POINTER(_vp), _vp, _i, ctypes.POINTER(_i), _i, _vp]
@@ -118,7 +120,7 @@ EXPORTED = ["qcd_last_error", "qcd_gauge_link_reals", "qcd_autotune_dslash", "qc
             "qcd_ptc_create", "qcd_ptc_free", "qcd_ptc_num_weights", "qcd_ptc_set_weights", "qcd_ptc_get_weights",
             "qcd_ptc_apply", "qcd_ptc_apply_prec", "qcd_ptc_loss_grad", "qcd_ptc_train_step", "qcd_ptc_set_gauge", "qcd_ptc_init_neumann",
             "qcd_ptc_set_mixing", "qcd_ptc_loss_grad_residual", "qcd_ptc_train_step_residual",
-            "qcd_gaussian_spinors", "qcd_eo_spectrum"]
+            "qcd_gaussian_spinors", "qcd_eo_spectrum", "qcd_stream_probe"]
 
 
 class QcdError(RuntimeError):
@@ -229,6 +231,21 @@ def gauge_upload(U, dims, precs=(FP64, FP32, FP16, BF16), full_links=False) -> G
 
 def _one_or_list(vals, n):
     return vals[0] if n == 1 else list(vals)
+
+
+def stream_probe(nbytes=1 << 30, reps=20):
+    """GB/s of plain 16-byte streaming sweeps (qcd_stream_probe): read-only,
+    copy (bytes read + written) and write-only, on fresh device buffers."""
+    nbytes -= nbytes % 16
+    src = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = {}
+    for mode, name, moved in ((0, "read", 1), (1, "copy", 2), (2, "write", 1)):
+        us = ctypes.c_double()
+        _check(_lib.qcd_stream_probe(_ptr(dst), _ptr(src), nbytes, mode, int(reps), ctypes.byref(us), _stream()))
+        out[name + "_GBps"] = moved * nbytes / (us.value * 1e-6) / 1e9
+    del src, dst
+    return out
 
 
 def gaussian_spinors(shape, seed: int) -> torch.Tensor:

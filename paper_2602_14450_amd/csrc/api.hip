@@ -626,8 +626,9 @@ qcd_status qcd_set_dslash_tuning(qcd_gauge* g, qcd_prec prec, int sched, int var
   if (!g || !valid_prec(prec)) return fail(QCD_ERR_ARG, "invalid handle or precision");
   if (sched < 0 || sched >= kDslashScheds || variant < 0 || variant >= kDslashVariants)
     return fail(QCD_ERR_ARG, "sched must be 0..%d and variant 0..%d", kDslashScheds - 1, kDslashVariants - 1);
-  if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4 && !(rhs_tile >= -4 && rhs_tile <= -2))
-    return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2, 4 (lanes) or -2, -3, -4 (per thread)");
+  if (rhs_tile != 0 && rhs_tile != 1 && rhs_tile != 2 && rhs_tile != 4 && !(rhs_tile >= -4 && rhs_tile <= -2) &&
+      rhs_tile != kRhsTileMfma)
+    return fail(QCD_ERR_ARG, "rhs_tile must be 0 (automatic), 1, 2, 4 (lanes), -2, -3, -4 (per thread) or 8 (matrix cores)");
   g->tune[prec] = DslashTune{sched, variant, rhs_tile, g->tune[prec].recon};
   return QCD_OK;
 }
@@ -706,12 +707,16 @@ qcd_status qcd_autotune_dslash(qcd_gauge* g, qcd_prec prec, int nrhs, int reps, 
   (void)hipEventCreate(&e1);
   DslashTune best = g->tune[prec];
   float best_ms = 1e30f;
-  const int tiles[6] = {1, 2, 4, -2, -3, -4};
-  for (int ti = 0; ti < 6; ti++) {
+  const int tiles[7] = {1, 2, 4, -2, -3, -4, kRhsTileMfma};
+  for (int ti = 0; ti < 7; ti++) {
     const int T = tiles[ti];
     const int A = T < 0 ? -T : T;
-    if (nrhs % A || (A > 1 && nrhs == 1)) continue;
-    for (int sched = 0; sched < kDslashScheds; sched++)
+    if (T == kRhsTileMfma) {
+      if (prec != QCD_FP16 || mfma_rhs_tile(nrhs) == 0) continue;
+    } else if (nrhs % A || (A > 1 && nrhs == 1)) {
+      continue;
+    }
+    for (int sched = 0; sched < (T == kRhsTileMfma ? 1 : kDslashScheds); sched++)
       for (int var = 0; var < (T == 1 ? kDslashVariants : 1); var++) {
         if (sched > 1 && make_sched(g->g, sched, T > 0 ? T : 1, T > 0 ? nrhs : nrhs / A).mode != sched)
           continue;  // not applicable
@@ -1428,6 +1433,33 @@ qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const
   return solve_ir_runs(runs.data(), nlat, p, S(stream), t0);
 }
 
+
+qcd_status qcd_stream_probe(void* dst_dev, const void* src_dev, size_t bytes, int mode, int reps, double* us,
+                            void* stream) {
+  if (!us || mode < 0 || mode > 2 || reps < 1 || reps > 10000 || bytes == 0 || bytes % 16)
+    return fail(QCD_ERR_ARG, "mode 0..2, reps 1..10000, bytes a positive multiple of 16 and an output are required");
+  if (!dst_dev || (mode < 2 && !src_dev)) return fail(QCD_ERR_ARG, "null buffer");
+  hipStream_t st = S(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(QCD_ERR_HIP, "hipEventCreate failed");
+  }
+  launch_stream_probe(mode, dst_dev, src_dev, bytes, st);  // warm-up
+  (void)hipEventRecord(e0, st);
+  for (int i = 0; i < reps; i++) launch_stream_probe(mode, dst_dev, src_dev, bytes, st);
+  (void)hipEventRecord(e1, st);
+  hipError_t e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(QCD_ERR_HIP, "probe timing: %s", hipGetErrorString(e));
+  HIP_LAUNCHED();
+  *us = (double)ms * 1e3 / reps;
+  return QCD_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Extreme |eigenvalues| of the even-odd matrix (a diagnostic).

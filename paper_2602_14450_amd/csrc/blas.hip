@@ -785,3 +785,70 @@ void launch_widen(const Geom& g, int prec, int n, double* dst, const void* src, 
   QCD_DISPATCH(prec, widen_t, g, n, dst, src, scale_dev, st);
 }
 }  // namespace qcd
+
+// ---------------------------------------------------------------------------
+// Streaming probes of the memory system: the bandwidth a plain sweep reaches
+// on this GPU, the ceiling the Wilson operator's bandwidth is read against.
+// Every lane moves 16-byte granules, four independent ones per loop trip, in
+// a grid-stride sweep; loads and stores are non-temporal (each byte is
+// touched once).
+namespace qcd {
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Reads n granules; the XOR of what a lane read is stored only if it equals a
+// fixed pattern (so the loads stay live without adding traffic); the store
+// index stays below the grid's thread count, which launch_stream_probe keeps
+// at most n.
+__global__ __launch_bounds__(256) void k_stream_read(const u32x4* __restrict__ src, size_t n,
+                                                     u32x4* __restrict__ sink) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  u32x4 acc = {0u, 0u, 0u, 0u};
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const u32x4 a = __builtin_nontemporal_load(src + i);
+    const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+    const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+    const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+    acc ^= (a ^ b) ^ (c ^ d);
+  }
+  for (; i < n; i += stride) acc ^= __builtin_nontemporal_load(src + i);
+  if (acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u && acc.z == 0xf39cc060u && acc.w == 0x5cedc834u)
+    sink[(size_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src, size_t n,
+                                                     u32x4* __restrict__ dst) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const u32x4 a = __builtin_nontemporal_load(src + i);
+    const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+    const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+    const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+    __builtin_nontemporal_store(a, dst + i);
+    __builtin_nontemporal_store(b, dst + i + stride);
+    __builtin_nontemporal_store(c, dst + i + 2 * stride);
+    __builtin_nontemporal_store(d, dst + i + 3 * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+__global__ __launch_bounds__(256) void k_stream_write(size_t n, u32x4* __restrict__ dst) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  const u32x4 v = {(unsigned)blockIdx.x, (unsigned)threadIdx.x, 0u, 0u};
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) __builtin_nontemporal_store(v, dst + i);
+}
+
+// mode 0: read src; 1: copy src -> dst; 2: write dst.  bytes a multiple of 16.
+void launch_stream_probe(int mode, void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  // 8 blocks of 256 threads per compute unit (256 CUs), never more threads than granules
+  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(2048, n / 256));
+  if (mode == 0)
+    hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, st, (const u32x4*)src, n, (u32x4*)dst);
+  else if (mode == 1)
+    hipLaunchKernelGGL(k_stream_copy, dim3(grid), dim3(256), 0, st, (const u32x4*)src, n, (u32x4*)dst);
+  else
+    hipLaunchKernelGGL(k_stream_write, dim3(grid), dim3(256), 0, st, n, (u32x4*)dst);
+}
+}  // namespace qcd

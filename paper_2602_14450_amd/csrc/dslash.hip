@@ -770,6 +770,246 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
   if constexpr (EPI != kEpiNone) block_reduce_store_R<NV, R>(red, partials, r0, sched.nsb, bp.sb);
 }
 
+// ---------------------------------------------------------------------------
+// Several right-hand sides on the matrix cores (FP16 storage).  A hop's SU(3)
+// products for T right-hand sides at a site are one complex matrix product,
+// U (3 x 3) times the 2T projected half-spinors (3 x 2T); in real form
+// [[Re U, -Im U], [Im U, Re U]] times [Re h; Im h].  One 16 x 16 x 16 binary16
+// matrix-core instruction takes two sites at once, block-diagonally: rows
+// 8 s + 2 a + (re/im) of the output and columns 8 s + 2 b + (re/im) of K
+// belong to site s of a wave's pair (colour 3 is padding), and its 16 columns
+// are 8 right-hand sides times the two half-spinors (T = 12 or 16 takes two
+// instructions per hop, sharing the link operand).  Lane l = 16 G + n feeds
+// column n with K rows 4G .. 4G + 3 (site G / 2, colours 2 (G % 2) and
+// 2 (G % 2) + 1) and receives the output rows of the same site and colours,
+// so every lane projects, and later accumulates, only its own colour pair;
+// the two half-spinors of a right-hand side sit in adjacent lanes and are
+// exchanged after each product, so both lanes reconstruct the full
+// four-spinor and each stores half of it.  Products are exact binary16
+// products summed in FP32, as in the scalar FP16 path; the reconstruction
+// is FP32.  Only the plain operator (no reduction epilogue) takes this form.
+typedef _Float16 h4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// neighbour half index one hop along +mu (bwd false) or -mu (bwd true)
+__device__ __forceinline__ int hop_neighbour_rt(const Geom& g, int h, const Coord& c, int mu, bool bwd) {
+  if (mu == 0) {
+    const int base = h - (c.x >> 1);
+    const int xn = bwd ? ((c.x == 0) ? g.L[0] - 1 : c.x - 1) : ((c.x + 1 == g.L[0]) ? 0 : c.x + 1);
+    return base + (xn >> 1);
+  }
+  const int cm = mu == 1 ? c.y : (mu == 2 ? c.z : c.t);
+  const int st = mu == 1 ? g.sy : (mu == 2 ? g.sz : g.st);
+  if (bwd) return (cm == 0) ? h + (g.L[mu] - 1) * st : h - st;
+  return (cm + 1 == g.L[mu]) ? h - (g.L[mu] - 1) * st : h + st;
+}
+
+
+// binary16 value of a complex (re, im) pair scaled by a unit: 0 -> 1, 1 -> -1, 2 -> i, 3 -> -i
+__device__ __forceinline__ h2v h_unit(h2v x, int code) {
+  const h2v r = (code & 2) ? h2v{-x.y, x.x} : x;
+  return (code == 1 || code == 3) ? -r : r;
+}
+
+template <typename S, int OP, int NC, int NE, bool EO>
+__global__ __launch_bounds__(256) void k_dslash_mfma(Geom g, S* __restrict__ out, const S* __restrict__ in,
+                                                     const S* __restrict__ U, double kappa,
+                                                     const Scalars* __restrict__ scal, int ftz,
+                                                     const S* __restrict__ cin, int tpar, int T) {
+  static_assert(std::is_same<S, __half2>::value, "the matrix-core form is built for FP16 storage");
+  constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
+  constexpr bool HOP_ONLY = (OP == kOpH || OP == kOpHdag);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int n = lane & 15, G = lane >> 4;
+  const int cg = G & 1;        // colour pair: (0, 1) or (2, padding)
+  const int hh = n & 1;        // half-spinor of this lane's column
+  const int r0 = blockIdx.y * T;
+  const int nsite = EO ? g.Vh : 2 * g.Vh;
+  const int pair = blockIdx.x * 4 + wid;
+  const int my_site = 2 * pair + (G >> 1);              // the site of this lane's B / D rows
+  const int a_site = 2 * pair + ((lane & 15) >> 3);     // the site of this lane's A rows
+  const bool my_valid = my_site < nsite;
+  // (par, h) of a site index; an index past the end maps to the parity's first site
+  auto locate = [&](int sidx, int& par, int& h) {
+    if (sidx >= nsite) sidx = sidx & 1;
+    if (EO) {
+      par = tpar;
+      h = sidx;
+    } else {
+      par = sidx >= g.Vh;
+      h = sidx - par * g.Vh;
+    }
+  };
+  int mpar, mh, apar, ah;
+  locate(my_site, mpar, mh);
+  locate(a_site, apar, ah);
+  const Coord mc = decode(g, mpar, mh), ac = decode(g, apar, ah);
+  const size_t vs = EO ? (size_t)g.nb * 768 : spinor_elems(g);
+  // A operand: row m = lane % 16 -> (site m / 8, colour row a, re/im ri); K group G -> (site G / 2, colours b0, b0 + 1)
+  const int arow = lane & 15;
+  const int a = (arow & 7) >> 1, ri = arow & 1, b0 = 2 * cg;
+  const bool a_live = (arow >> 3) == (G >> 1) && a < 3;
+  cx<float> acc[NC][4][2];  // [column group][spin][colour of the pair]
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+      for (int k = 0; k < 2; k++) acc[c][sp][k] = cx<float>(0.f, 0.f);
+  bool col_ok[NC];
+#pragma unroll
+  for (int c = 0; c < NC; c++) col_ok[c] = (c * 8 + (n >> 1)) < T && my_valid;
+  // skip right-hand sides whose solver stopped (uniform over a wave only per column, so no early exit)
+#pragma unroll
+  for (int c = 0; c < NC; c++)
+    if (scal && col_ok[c] && !scal[r0 + c * 8 + (n >> 1)].active) col_ok[c] = false;
+
+#pragma unroll
+  for (int hop = 0; hop < 8; hop++) {
+    const int MU = hop >> 1;
+    const bool BWD = hop & 1;
+    const bool MINUS = BWD ? DAG : !DAG;
+    // --- link of the A rows' site: U_mu(x) forward, U_mu(x - mu) backward (applied as U^dag)
+    const int an = hop_neighbour_rt(g, ah, ac, MU, BWD);
+    const int lp = BWD ? (apar ^ 1) : apar, lh = BWD ? an : ah;
+    h2v u[9];
+    {
+      const S* lb = U + lk_block<NE>(g, MU, lp, lh);
+      const int ll = lh & 63;
+      if constexpr (NE == 6) {
+        const typename Lay<S>::Gran q = *reinterpret_cast<const typename Lay<S>::Gran*>(lb + ll * 4);
+#pragma unroll
+        for (int k = 0; k < 4; k++) u[k] = h2_of(q.s[k]);
+        const Pair<S> t = *reinterpret_cast<const Pair<S>*>(lb + 4 * 64 + ll * 2);
+        u[4] = h2_of(t.s[0]);
+        u[5] = h2_of(t.s[1]);
+        h_third_row(u);
+      } else {
+        const typename Lay<S>::Gran q0 = *reinterpret_cast<const typename Lay<S>::Gran*>(lb + ll * 4);
+        const typename Lay<S>::Gran q1 = *reinterpret_cast<const typename Lay<S>::Gran*>(lb + 64 * 4 + ll * 4);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          u[k] = h2_of(q0.s[k]);
+          u[4 + k] = h2_of(q1.s[k]);
+        }
+        u[8] = h2_of(lb[8 * 64 + ll]);
+      }
+    }
+    // entries e_b = U[a][b] (forward) or conj(U[b][a]) (backward) for b = b0, b0 + 1
+    h4v af = h4v{0, 0, 0, 0};
+    if (a_live) {
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        const int b = b0 + j;
+        h2v e = h2v{0, 0};
+        if (b < 3) {
+          const int idx = BWD ? 3 * b + a : 3 * a + b;
+          h2v v = u[0];
+#pragma unroll
+          for (int k = 1; k < 9; k++) v = idx == k ? u[k] : v;
+          e = BWD ? h2v{v.x, -v.y} : v;
+        }
+        // real form row ri: (Re e, -Im e) for ri = 0, (Im e, Re e) for ri = 1
+        af[2 * j] = ri ? e.y : e.x;
+        af[2 * j + 1] = ri ? e.x : -e.y;
+      }
+    }
+    // --- B operand: this lane's half-spinor, colours of its pair, for each column group
+    const int nn = hop_neighbour_rt(g, mh, mc, MU, BWD);
+    const int npar = EO ? 0 : (mpar ^ 1);
+    const S* sbase = in + sp_block(g, npar, nn) + (nn & 63) * 4;
+    // spins and unit factor of this half (the projection of project_h)
+    int sa, sb, code;
+    if (MU == 0) { sa = hh; sb = 3 - hh; code = MINUS ? 2 : 3; }
+    else if (MU == 1) { sa = hh; sb = 3 - hh; code = (MINUS != (hh == 1)) ? 0 : 1; }
+    else if (MU == 2) { sa = hh; sb = 2 + hh; code = (MINUS != (hh == 1)) ? 2 : 3; }
+    else { sa = sb = MINUS ? 2 + hh : hh; code = 0; }
+    f4v d[NC];  // products: colours (a0, a1) of this lane's pair as (re, im, re, im)
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      h4v bf = h4v{0, 0, 0, 0};
+      if (col_ok[c]) {
+        const S* fb = sbase + (size_t)(c * 8 + (n >> 1)) * vs + (size_t)r0 * vs;
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+          const int col = b0 + j;
+          if (col < 3) {
+            const int ka = 3 * sa + col, kb = 3 * sb + col;
+            const h2v fa = h2_of(fb[(ka >> 2) * 256 + (ka & 3)]);
+            const h2v fv = h2_of(fb[(kb >> 2) * 256 + (kb & 3)]);
+            const h2v hv = fa + h_unit(fv, code);
+            bf[2 * j] = hv.x;
+            bf[2 * j + 1] = hv.y;
+          }
+        }
+      }
+      d[c] = __builtin_amdgcn_mfma_f32_16x16x16f16(af, bf, f4v{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    }
+    // --- exchange halves with the neighbouring lane and reconstruct (accumulate<MU, MINUS>)
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      f4v o;
+#pragma unroll
+      for (int q = 0; q < 4; q++) o[q] = __shfl_xor(d[c][q], 1, 64);
+      const f4v u1 = hh ? o : d[c], u2 = hh ? d[c] : o;  // half 1 and half 2, colours (a0, a1) as (re, im, re, im)
+#pragma unroll
+      for (int k = 0; k < 2; k++) {
+        const float x1 = u1[2 * k], y1 = u1[2 * k + 1], x2 = u2[2 * k], y2 = u2[2 * k + 1];
+        auto add = [&](int sp, float xr, float xi) {
+          acc[c][sp][k].re += xr;
+          acc[c][sp][k].im += xi;
+        };
+        if (MU == 3) {
+          if (MINUS) { add(2, x1, y1); add(3, x2, y2); }
+          else { add(0, x1, y1); add(1, x2, y2); }
+        } else {
+          add(0, x1, y1);
+          add(1, x2, y2);
+          if (MU == 0) {
+            if (MINUS) { add(2, y2, -x2); add(3, y1, -x1); }   // -i u2, -i u1
+            else { add(2, -y2, x2); add(3, -y1, x1); }         //  i u2,  i u1
+          } else if (MU == 1) {
+            if (MINUS) { add(2, -x2, -y2); add(3, x1, y1); }
+            else { add(2, x2, y2); add(3, -x1, -y1); }
+          } else {
+            if (MINUS) { add(2, y1, -x1); add(3, -y2, x2); }   // -i u1,  i u2
+            else { add(2, -y1, x1); add(3, y2, -x2); }         //  i u1, -i u2
+          }
+        }
+      }
+    }
+  }
+  // --- output: this lane's colours, spins (0, 1) for half 0 and (2, 3) for half 1
+  const float k = (float)kappa;
+#pragma unroll
+  for (int c = 0; c < NC; c++) {
+    if (!col_ok[c]) continue;
+    const size_t fo = (size_t)(r0 + c * 8 + (n >> 1)) * vs + sp_block(g, EO ? 0 : mpar, mh) + (mh & 63) * 4;
+    const S* cb = (EO ? cin : in) + fo;
+    S* ob = out + fo;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      const int sp = 2 * hh + q;
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        const int col = b0 + j;
+        if (col >= 3) continue;
+        const int kk = 3 * sp + col;
+        const int off = (kk >> 2) * 256 + (kk & 3);
+        // acc holds spins by index; select this lane's spin without indexing registers at run time
+        const float xr = hh ? acc[c][2 + q][j].re : acc[c][q][j].re;
+        const float xi = hh ? acc[c][2 + q][j].im : acc[c][q][j].im;
+        cx<float> o(xr, xi);
+        if constexpr (!HOP_ONLY) {
+          const cx<float> ctr = Traits<S>::load(cb + off);
+          o = cx<float>(ctr.re - k * xr, ctr.im - k * xi);
+        }
+        ob[off] = Traits<S>::pack(o, ftz);
+      }
+    }
+  }
+}
+
 // One translation unit per storage precision (QCD_DSLASH_PREC = 0, 1, 2, 3 for
 // FP64, FP32, FP16, BF16) keeps the kernel instantiations of a build parallel; the
 // FP16 unit also holds the precision-independent helpers and the dispatcher.
@@ -893,10 +1133,55 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
 #undef QCD_LAUNCH
 }
 
+// The matrix-core form: grid.x covers the site pairs (four per block), grid.y the tiles of T right-hand sides.
+template <int NE>
+static void launch_dslash_mfma(const Geom& g, int op, int n, void* out, const void* in, const void* U,
+                               double kappa, const Scalars* scal, int ftz, const void* cin, int eo_par,
+                               hipStream_t st) {
+  const int T = mfma_rhs_tile(n);
+  const bool eo = eo_par >= 0;
+  const int nsite = eo ? g.Vh : 2 * g.Vh;
+  const int npair = (nsite + 1) / 2;
+  const dim3 grid((npair + 3) / 4, n / T), block(256);
+  __half2* o = (__half2*)out;
+  const __half2* i = (const __half2*)in;
+  const __half2* u = (const __half2*)U;
+  const __half2* ci = (const __half2*)cin;
+  const int tp = eo ? eo_par : 0;
+#define QCD_MFMA(OPV, EOV)                                                                                        \
+  do {                                                                                                            \
+    if (T > 8)                                                                                                    \
+      hipLaunchKernelGGL((k_dslash_mfma<__half2, OPV, 2, NE, EOV>), grid, block, 0, st, g, o, i, u, kappa, scal, ftz, \
+                         ci, tp, T);                                                                              \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_dslash_mfma<__half2, OPV, 1, NE, EOV>), grid, block, 0, st, g, o, i, u, kappa, scal, ftz, \
+                         ci, tp, T);                                                                              \
+  } while (0)
+  if (eo) {
+    if (op == kOpH) QCD_MFMA(kOpH, true);
+    else QCD_MFMA(kOpD, true);
+  } else {
+    switch (op) {
+      case kOpD: QCD_MFMA(kOpD, false); break;
+      case kOpH: QCD_MFMA(kOpH, false); break;
+      case kOpDdag: QCD_MFMA(kOpDdag, false); break;
+      default: QCD_MFMA(kOpHdag, false); break;
+    }
+  }
+#undef QCD_MFMA
+}
+
 template <typename S, int NE>
 static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                             int ftz, const void* cin, int eo_par, hipStream_t st) {
+  if constexpr (std::is_same<S, __half2>::value) {
+    // the matrix-core form, when chosen, for the plain operator of a tileable number of right-hand sides
+    if (tune.rhs_tile == kRhsTileMfma && epi == kEpiNone && mfma_rhs_tile(n) > 0) {
+      launch_dslash_mfma<NE>(g, op, n, out, in, U, kappa, scal, ftz, cin, eo_par, st);
+      return;
+    }
+  }
   const int R = reg_tile_for(tune, n);
   if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
   if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);

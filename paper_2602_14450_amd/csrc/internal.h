@@ -71,10 +71,20 @@ struct DslashTune {
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
                 // (prefetching 2 hops at 5 waves spills registers and measured slower in every precision)
   int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
-                // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers)
+                // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers);
+                // 8 = the matrix-core form (kRhsTileMfma)
   int recon;    // links stored as 6 entries (rows 0, 1; row 2 rebuilt) instead of 9: a property of the data
 };
 constexpr int kDslashVariants = 6;
+// rhs_tile code of the matrix-core form (FP16 storage, plain operator; 4, 6, 8, 12 or 16 right-hand sides per tile)
+constexpr int kRhsTileMfma = 8;
+// right-hand sides per matrix-core tile for n right-hand sides (0: the form does not apply)
+inline int mfma_rhs_tile(int n) {
+  const int cand[5] = {16, 12, 8, 6, 4};
+  for (int i = 0; i < 5; i++)
+    if (n % cand[i] == 0) return cand[i];
+  return 0;
+}
 struct DslashSched {
   int mode, nsb, ntiles, Lz, Lt, bp, zc, sub, H;  // H: half-sites per parity per block
 };
@@ -138,6 +148,8 @@ void launch_convert_finish(int n, Scalars* sc, const double* partials, int nrows
                            hipStream_t st);
 void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, const void* xlo, hipStream_t st);
 void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st);
+// memory-system probe: mode 0 reads src, 1 copies src to dst, 2 writes dst (bytes a multiple of 16)
+void launch_stream_probe(int mode, void* dst, const void* src, size_t bytes, hipStream_t st);
 
 }  // namespace qcd
 

@@ -45,6 +45,71 @@ def test_multi_rhs_dslash(q, dims, nrhs, prec):
     g.close()
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (2, 4, 6, 10), (4, 6, 8, 10), (2, 2, 2, 2)])
+@pytest.mark.parametrize("nrhs", [4, 6, 8, 12, 16])
+def test_matrix_core_multi_rhs_dslash(q, dims, nrhs):
+    # the matrix-core form of the FP16 operator (rhs_tile 8: tiles of 4, 6, 8,
+    # 12 or 16 right-hand sides, one or two instructions per hop) against the
+    # oracle, all four operators; ragged volumes (an odd number of site pairs
+    # per block of four) and the 2^4 lattice where x + mu and x - mu coincide
+    U = qi.gauge_field(dims, 0.3, 131 + nrhs)
+    psi = qi.gaussian_source(dims, 132, nrhs=nrhs)
+    g = q.gauge_upload(to_dev(U), dims)
+    g.set_tuning(q.FP16, 0, 0, 8)
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    for op in (0, 1, 2, 3):
+        q.dslash(g, 0.124, out, x, op=op, prec=q.FP16, layout=q.CANONICAL)
+        torch.cuda.synchronize()
+        got = to_host(out)
+        for r in range(nrhs):
+            compare(got[r], oracle.dslash(U, psi[r], 0.124, dims, op), TOL[2], f"mfma {dims} n={nrhs} rhs={r} op={op}")
+    g.close()
+
+
+def test_matrix_core_form_at_full_size_on_sampled_sites(q):
+    # 12 right-hand sides at 32^3 x 64, the benchmark's batched operator, with
+    # the matrix-core form: sampled output sites against the oracle's operator
+    dims = (32, 32, 32, 64)
+    V = qi.volume(dims)
+    U = qi.gauge_field(dims, 0.3, 201)
+    psi = qi.gaussian_source(dims, 141, nrhs=12)
+    g = q.gauge_upload(to_dev(U), dims, precs=(q.FP64, q.FP16))
+    g.set_tuning(q.FP16, 0, 0, 8)
+    x = to_dev(psi)
+    out = torch.empty_like(x)
+    q.dslash(g, 0.124, out, x, op=0, prec=q.FP16, layout=q.CANONICAL)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(142)
+    sites = np.concatenate([[0, 1, V - 1], rng.integers(0, V, 200)])
+    got = to_host(out)
+    for r in (0, 5, 11):
+        want = oracle.dslash_sites(U, psi[r], 0.124, dims, sites)
+        compare(got[r][sites], want, TOL[2], f"mfma 32^3x64 rhs={r}")
+    del x, out
+    g.close()
+    torch.cuda.empty_cache()
+
+
+def test_matrix_core_form_in_the_even_odd_batched_solve(q):
+    # with rhs_tile 8 the hop-only one-parity launches of a batched even-odd
+    # solve take the matrix-core form: every true residual still meets 1e-12
+    dims, k = (8, 8, 8, 8), 0.12
+    U = qi.gauge_field(dims, 0.3, 151)
+    b = qi.gaussian_source(dims, 152, nrhs=8)
+    g = q.gauge_upload(to_dev(U), dims)
+    g.set_tuning(q.FP16, 0, 0, 8)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    infos = q.solve_mixed_ir(g, k, x, to_dev(b), inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, even_odd=True,
+                             use_graph=True)
+    xh = to_host(x)
+    for r in range(8):
+        assert infos[r].status == "ok" and infos[r].true_rel_residual <= 1e-12
+        res = np.linalg.norm(b[r] - oracle.dslash(U, xh[r], k, dims)) / np.linalg.norm(b[r])
+        assert res <= 1.01e-12, (r, res)
+    g.close()
+
+
 @pytest.mark.parametrize("dims", [(8, 16, 32, 4), (8, 32, 8, 16)])
 @pytest.mark.parametrize("rhs_tile", [1, 2, 4, -2, -4])
 def test_rhs_tile_choices_agree_bitwise(q, rhs_tile, dims):
