@@ -102,6 +102,7 @@ struct Work {
   int hist_stride = 1;
   double* sums = nullptr;
   double* scale = nullptr;
+  double* outer_log = nullptr;  // device-driven refinement: (|r|, zeros) per step, kOuterLog steps per right-hand side
   size_t bytes = 0;
 };
 
@@ -158,6 +159,7 @@ Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char*
   w.sc = (Scalars*)c.take(sizeof(Scalars) * n);
   w.sums = (double*)c.take(8 * sizeof(double) * n);
   w.scale = (double*)c.take(sizeof(double) * n);
+  if (what == 0 || what == 3) w.outer_log = (double*)c.take(sizeof(double) * 2 * kOuterLog * n);
   w.bytes = c.off;
   return w;
 }
@@ -287,16 +289,19 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
 
 // FP64 residual r = b - D x with |r|^2 partials for all right-hand sides
 // (only those still refining are computed).
-void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* outer_mask, hipStream_t st) {
+// With outer_mask, only the right-hand sides it selects are computed (mask 1:
+// those whose device-driven refinement step is due).
+void residual64(const qcd_gauge* g, double kappa, const Work& w, const Scalars* outer_mask, hipStream_t st,
+                int mask = 0) {
   if (w.eo) {  // r = b' - (x_e - kappa^2 H_eo H_oe x_e)
     launch_dslash(kFP64, g->g, g->tune[kFP64], kOpH, kEpiNone, w.n, w.t64, w.x64, g->U[kFP64], 1.0, nullptr, nullptr,
-                  outer_mask, 0, st, nullptr, 1);
+                  outer_mask, 0, st, nullptr, 1, mask);
     launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.r64, w.t64, g->U[kFP64], kappa * kappa,
-                  w.bp64, w.partials, outer_mask, 0, st, w.x64, 0);
+                  w.bp64, w.partials, outer_mask, 0, st, w.x64, 0, mask);
     return;
   }
   launch_dslash(kFP64, g->g, g->tune[kFP64], kOpD, kEpiResid, w.n, w.r64, w.x64, g->U[kFP64], kappa, w.b64,
-                w.partials, outer_mask, 0, st);
+                w.partials, outer_mask, 0, st, nullptr, -1, mask);
 }
 int residual_rows(const qcd_gauge* g, const Work& w) {
   return dslash_partial_rows(g->g, g->tune[kFP64], w.n, w.eo);
@@ -337,31 +342,60 @@ qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_de
   return QCD_OK;
 }
 
-// Capture one iteration (8 kernels) into a hip graph.  Capture runs on the
-// handle's own stream (the null stream cannot be captured); the graph is
+// The refinement step of Alg. 3 run from the device, for the right-hand sides
+// whose inner solve has stopped (every kernel checks outer_step): x += (|r| /
+// s^) double(t~), the FP64 residual r = b - D x and its norm (step count,
+// stop tests, log), y~ = low(r s / |r|) and s^, and the next inner start.
+void device_step(const qcd_gauge* g, double kappa, const Work& w, const qcd_ir_params* p, hipStream_t st) {
+  const Geom G = w.eo ? half_geom(g->g) : g->g;  // geometry of the refined vectors
+  const int prec = p->inner_prec;
+  launch_correct(G, prec, w.n, w.sc, (double*)w.x64, w.x, st);
+  residual64(g, kappa, w, w.sc, st, 1);
+  launch_outer_residual_norm(w.n, w.sc, w.partials, dslash_partial_rows(g->g, g->tune[kFP64], w.n, w.eo), p->s, st,
+                             w.outer_log);
+  launch_convert(G, prec, w.n, w.sc, (const double*)w.r64, w.r, w.rstar, w.partials, p->inner.ftz, st);
+  launch_convert_finish(w.n, w.sc, w.partials, site_grid(G), p->recalc_shat, p->s, st);
+}
+
+// Iterations of the device-driven refinement captured with one device step.
+constexpr int kStepGraphIters = 4;
+
+// Capture one iteration (8 kernels), or (dev_p given) kStepGraphIters
+// iterations followed by the device step, into a hip graph.  Capture runs on
+// the handle's own stream (the null stream cannot be captured); the graph is
 // launched on the caller's stream.  The kernels take every changing value
-// from device memory, so one capture serves every iteration.
+// from device memory, so one capture serves every iteration (and step).
 qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Work& w, int ftz, const Precond& pc,
-                           hipGraphExec_t* out) {
+                           hipGraphExec_t* out, const qcd_ir_params* dev_p = nullptr) {
   qcd_gauge* g = const_cast<qcd_gauge*>(gc);
-  unsigned long long kbits;
+  unsigned long long kbits, sbits64 = 0;
   memcpy(&kbits, &kappa, sizeof kbits);
   unsigned sbits;
   memcpy(&sbits, &pc.scale, sizeof sbits);
+  if (dev_p) memcpy(&sbits64, &dev_p->s, sizeof sbits64);
   // Everything the captured launches bake in: the scalar parameters, the launch
   // shape, and the address of every workspace region they read or write (the
   // regions move when max_iter or nrhs changes the carve of one workspace).
   auto u = [](const void* q) { return (unsigned long long)(uintptr_t)q; };
-  const unsigned long long key[24] = {(unsigned long long)prec, (unsigned long long)w.n, kbits,
+  const unsigned long long key[32] = {(unsigned long long)prec, (unsigned long long)w.n, kbits,
                                       (unsigned long long)ftz,
                                       ((unsigned long long)(unsigned)g->tune[prec].sched << 16) |
                                           ((unsigned long long)(unsigned)g->tune[prec].variant << 8) |
                                           ((unsigned long long)(g->tune[prec].rhs_tile & 0xff)) |
-                                          ((unsigned long long)w.eo << 24),
+                                          ((unsigned long long)w.eo << 24) |
+                                          ((unsigned long long)(g->tune[kFP64].rhs_tile & 0xff) << 32) |
+                                          ((unsigned long long)(unsigned)g->tune[kFP64].sched << 40) |
+                                          ((unsigned long long)(unsigned)g->tune[kFP64].variant << 48),
                                       u(pc.net), pc.net ? sbits : 0ull, u(w.x), u(w.r), u(w.rstar), u(w.p), u(w.v),
                                       u(w.t), u(w.z), u(w.t1), u(w.partials), u(w.sc), u(w.history),
                                       (unsigned long long)w.hist_stride, u(w.sums), u(w.scale),
-                                      (unsigned long long)w.bytes, 0ull, 0ull};
+                                      (unsigned long long)w.bytes,
+                                      dev_p ? (1ull | ((unsigned long long)dev_p->recalc_shat << 1) |
+                                               ((unsigned long long)dev_p->inner_prec << 2) |
+                                               ((unsigned long long)dev_p->inner.ftz << 8))
+                                            : 0ull,
+                                      sbits64, u(w.x64), u(w.r64), u(w.b64), u(w.bp64), u(w.t64), u(w.outer_log),
+                                      0ull};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
     return QCD_OK;
@@ -372,7 +406,12 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
   }
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
+  if (dev_p) {
+    for (int k = 0; k < kStepGraphIters; k++) bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
+    device_step(g, kappa, w, dev_p, g->cap_stream);
+  } else {
+    bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
+  }
   hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
   if (e != hipSuccess) return fail(QCD_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
@@ -1253,6 +1292,113 @@ qcd_status ir_finish(IrRun& R, double t0) {
   return res;
 }
 
+// The refinement with its steps run from the device (graph replay): after the
+// first step's conversion, each lattice replays a graph of kStepGraphIters
+// inner iterations and one device step; a right-hand side whose inner solve
+// stopped gets its correction, FP64 residual, stop test and next start in
+// that step, so one host poll serves several refinement steps.  The host
+// reads the device's step counts, stop reasons and log at the end.
+qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream_t st) {
+  qcd_status rc;
+  std::vector<IrRun*> act;
+  for (int r = 0; r < nrun; r++) {
+    IrRun& R = runs[r];
+    if (!R.any) continue;
+    qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
+    for (int i = 0; i < R.n; i++) {
+      Scalars& h = g->host_sc[i];
+      h.dev_outer = 1;
+      h.outer_step = h.outer_active ? 1 : 0;
+      h.max_outer = p->max_outer;
+      h.outer_count = h.inner_total = h.fail = 0;
+      h.last_status = kConverged;
+      h.first_shat = 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(R.w.sc, g->host_sc, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
+    if ((rc = ir_begin_step(R, p, st))) return rc;  // the first conversion and inner start
+    act.push_back(&R);
+  }
+  const int nact = (int)act.size();
+  std::vector<hipGraphExec_t> gexec(nact, nullptr);
+  std::vector<hipStream_t> rs(nact, st);
+  std::vector<InnerRun> ir;
+  for (int a = 0; a < nact; a++) {
+    IrRun& R = *act[a];
+    if ((rc = iteration_graph(R.g, p->inner_prec, R.kappa, R.w, p->inner.ftz, Precond{}, &gexec[a], p))) return rc;
+    if (nact > 1) rs[a] = R.g->cap_stream;
+    ir.push_back(InnerRun{R.g, p->inner_prec, R.kappa, &R.w, Precond{}});
+  }
+  auto refining = [](const IrRun& R) {
+    for (int i = 0; i < R.n; i++)
+      if (R.g->host_sc[i].outer_active) return true;
+    return false;
+  };
+  // graph launches between polls: two at first, then about two refinement
+  // steps' worth of iterations as observed so far
+  int per_poll = 2;
+  long launched = 0;
+  const long cap = (long)p->max_outer * (p->inner.max_iter / kStepGraphIters + 2) + 4;
+  while (nact > 0) {
+    bool any = false;
+    if (nact > 1) HIP_TRY(hipEventRecord(act[0]->g->ev_fork, st));
+    for (int a = 0; a < nact; a++) {
+      IrRun& R = *act[a];
+      if (!refining(R)) continue;
+      any = true;
+      if (nact > 1) HIP_TRY(hipStreamWaitEvent(rs[a], act[0]->g->ev_fork, 0));
+      for (int j = 0; j < per_poll; j++) HIP_TRY(hipGraphLaunch(gexec[a], rs[a]));
+      if (nact > 1) {
+        HIP_TRY(hipEventRecord(R.g->ev_done, rs[a]));
+        HIP_TRY(hipStreamWaitEvent(st, R.g->ev_done, 0));
+      }
+    }
+    if (!any) break;
+    launched += per_poll;
+    if ((rc = read_scalars_all(ir.data(), nact, st))) return rc;
+    if (launched > cap) break;
+    long it = 0, steps = 0;
+    for (int a = 0; a < nact; a++)
+      for (int i = 0; i < act[a]->n; i++) {
+        const Scalars& h = act[a]->g->host_sc[i];
+        it += h.inner_total + h.iter;
+        steps += h.outer_count + 1;
+      }
+    const double per_step = steps > 0 ? (double)it / steps : 8.0;
+    per_poll = (int)std::min(64.0, std::max(1.0, std::ceil(2.0 * (per_step + 1.0) / kStepGraphIters)));
+  }
+  // the device's bookkeeping
+  std::vector<double> log;
+  for (int a = 0; a < nact; a++) {
+    IrRun& R = *act[a];
+    log.assign((size_t)2 * kOuterLog * R.n, 0.0);
+    HIP_TRY(hipMemcpyAsync(log.data(), R.w.outer_log, log.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < R.n; i++) {
+      const Scalars& h = R.g->host_sc[i];
+      R.outer[i] = h.outer_count;
+      R.inner_total[i] = h.inner_total;
+      R.last_status[i] = h.last_status;
+      if (h.outer_count > 0) R.rn[i] = h.out_rnorm;
+      if (h.fail)
+        R.result[i] = fail(h.fail == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
+                           "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
+                           h.last_status, h.outer_count - 1);
+      else if (h.outer_active || (h.outer_count > 0 && h.out_rnorm > h.out_tol * h.out_bnorm))
+        R.result[i] = worse(R.result[i], QCD_NOT_CONVERGED);
+      if (R.info) {
+        qcd_solve_info& in = R.info[i];
+        in.first_shat_over_s = h.outer_count > 0 ? h.first_shat / p->s : 0.0;
+        for (int k = 0; k < h.outer_count && k < kOuterLog; k++) {
+          if (in.outer_history && k < in.outer_history_cap)
+            in.outer_history[k] = log[((size_t)i * kOuterLog + k) * 2] / R.bn[i];
+          if (in.zeros && k < in.outer_history_cap) in.zeros[k] = log[((size_t)i * kOuterLog + k) * 2 + 1];
+        }
+      }
+    }
+  }
+  return QCD_OK;
+}
+
 // The refinement of Alg. 3 for several lattices at once: every refinement
 // step converts all of them, runs their inner solves together
 // (bicg_loop_multi) and corrects them.  runs[r].w must be set.
@@ -1271,7 +1417,18 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
     ir_after_start(runs[r]);
     if (runs[r].w.eo && (rc = ir_eo_scale_tol(runs[r], p, st))) return rc;
   }
-  for (int step = 0;; step++) {
+  // with graph replay the steps run from the device, unless a network (whose
+  // step may be undone from the host), per-step inner histories or more steps
+  // than the device log holds are asked for
+  bool dev = p->inner.use_graph && p->max_outer <= kOuterLog;
+  for (int r = 0; r < nrun; r++) {
+    if (runs[r].net) dev = false;
+    if (runs[r].info)
+      for (int i = 0; i < runs[r].n; i++)
+        if (runs[r].info[i].history && runs[r].info[i].history_cap > 0) dev = false;
+  }
+  if (dev && (rc = solve_ir_dev(runs, nrun, p, st))) return rc;
+  for (int step = 0; !dev; step++) {
     std::vector<IrRun*> act;
     for (int r = 0; r < nrun; r++)
       if (runs[r].any) act.push_back(&runs[r]);

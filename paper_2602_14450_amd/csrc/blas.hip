@@ -296,7 +296,7 @@ __global__ __launch_bounds__(256) void k_convert(Geom g, const Scalars* __restri
   using Gr = GrOf<S>;
   constexpr int C = Lay<S>::C;
   const Scalars* sc = scal + blockIdx.y;
-  if (!sc->outer_active) return;
+  if (!sc->outer_active || (sc->dev_outer && !sc->outer_step)) return;
   SiteId id = site_id(g);
   r64 += (size_t)blockIdx.y * spinor_elems(g);
   QCD_RHS_OFFSET(S, y); QCD_RHS_OFFSET(S, rstar);
@@ -336,6 +336,7 @@ __global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restri
                                                  const S* __restrict__ xlo) {
   const Scalars* sc = scal + blockIdx.y;
   if (!sc->outer_active || sc->iter == 0 || sc->status == kNonFinite) return;
+  if (sc->dev_outer && !sc->outer_step) return;
   SiteId id = site_id(g);
   if (!id.valid) return;
   x64 += (size_t)blockIdx.y * spinor_elems(g);
@@ -364,9 +365,11 @@ __device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
 }
 __device__ __forceinline__ bool finite_c(cx<double> a) { return isfinite(a.re) && isfinite(a.im); }
 
+// End of an inner solve; with device-driven refinement its refinement step becomes due.
 __device__ void stop(Scalars* sc, int status) {
   sc->status = status;
   sc->active = 0;
+  if (sc->dev_outer && sc->outer_active) sc->outer_step = 1;
 }
 
 // Start of a BiCGStab run: x0 = 0, r = r* = b, p = v = 0, rho' = |r|^2,
@@ -498,24 +501,62 @@ __global__ void k_iter_end(Scalars* scal, const double* partials, int nrows, dou
 // Outer step: |r| of the FP64 residual, the rescaling factor s / |r| and the
 // outer stopping test (|r| <= tol |b|); the first call (from the packing of
 // b) also records |b|.
-__global__ void k_outer_norm(Scalars* scal, const double* partials, int nrows, double s_target) {
+//
+// Device-driven refinement (dev_outer): only right-hand sides whose step is
+// due take part; the step is counted, the inner solve's iterations and stop
+// reason are recorded, (|r|, zeros of the y~ this step solved with) is
+// logged, and refining ends on a failed inner solve (non-finite, or no
+// iteration: breakdown), a non-finite |r|, the tolerance or max_outer steps.
+__global__ void k_outer_norm(Scalars* scal, const double* partials, int nrows, double s_target, double* log) {
   if (!scal[blockIdx.x].outer_active) return;
+  if (scal[blockIdx.x].dev_outer && !scal[blockIdx.x].outer_step) return;
   QCD_FINISH_BEGIN(1)
   sc->out_rnorm = sqrt(s[0]);
   if (sc->out_bnorm < 0.0) sc->out_bnorm = sc->out_rnorm;
   sc->out_scale = (s[0] > 0.0) ? s_target / sc->out_rnorm : 0.0;
+  if (sc->dev_outer) {
+    const int k = sc->outer_count;
+    if (log && k < kOuterLog) {
+      log[((size_t)blockIdx.x * kOuterLog + k) * 2] = sc->out_rnorm;
+      log[((size_t)blockIdx.x * kOuterLog + k) * 2 + 1] = sc->zeros;
+    }
+    sc->outer_count = k + 1;
+    sc->inner_total += sc->iter;
+    sc->last_status = sc->status;
+    if (sc->status == kNonFinite || sc->iter == 0) {
+      sc->fail = sc->status == kNonFinite ? kNonFinite : kBreakdown;
+      sc->outer_active = 0;
+      return;
+    }
+    if (!isfinite(sc->out_rnorm)) {
+      sc->fail = kNonFinite;
+      sc->outer_active = 0;
+      return;
+    }
+  }
   if (!(sc->out_rnorm > sc->out_tol * sc->out_bnorm)) sc->outer_active = 0;
+  if (sc->dev_outer && sc->outer_count >= sc->max_outer) sc->outer_active = 0;
 }
 
 // After the conversion: s^ (Alg. 3) and the start of the inner BiCGStab.
+// Device-driven refinement: only a right-hand side whose step is due
+// continues (the flag is cleared before the inner start, which raises it
+// again if that start stops at once, so the next step sees it).
 __global__ void k_convert_finish(Scalars* scal, const double* partials, int nrows, int recalc_shat, double s_target) {
+  if (scal[blockIdx.x].dev_outer && !scal[blockIdx.x].outer_step) return;
   if (!scal[blockIdx.x].outer_active) {
-    if (threadIdx.x == 0) { scal[blockIdx.x].active = 0; scal[blockIdx.x].iter = 0; }
+    if (threadIdx.x == 0) {
+      scal[blockIdx.x].active = 0;
+      scal[blockIdx.x].iter = 0;
+      scal[blockIdx.x].outer_step = 0;
+    }
     return;
   }
   QCD_FINISH_BEGIN(2)
   sc->shat = recalc_shat ? sqrt(s[0]) : s_target;
   sc->zeros = s[1];
+  if (sc->outer_count == 0) sc->first_shat = sc->shat;
+  sc->outer_step = 0;
   bicg_init_dev(sc, s[0]);
 }
 
@@ -731,8 +772,8 @@ void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, doub
 }
 
 void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
-                                hipStream_t st) {
-  hipLaunchKernelGGL(k_outer_norm, dim3(n), dim3(1024), 0, st, sc, partials, nrows, s_target);
+                                hipStream_t st, double* log) {
+  hipLaunchKernelGGL(k_outer_norm, dim3(n), dim3(1024), 0, st, sc, partials, nrows, s_target, log);
 }
 
 template <typename S>

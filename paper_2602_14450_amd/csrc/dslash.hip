@@ -335,6 +335,12 @@ __device__ __forceinline__ void hop_all(const Geom& g, const S* __restrict__ in,
   hop_pipe<0, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, buf, a);
 }
 
+// Whether a launch computes a right-hand side: mask 0 takes those whose inner
+// solve is active, mask 1 those whose device-driven refinement step is due.
+__device__ __forceinline__ bool scal_live(const Scalars& s, int mask) {
+  return (mask ? s.outer_step : s.active) != 0;
+}
+
 // Thread -> (site, right-hand side).  A block of 256 threads is four waves:
 // waves 0 and 1 take parity 0 and 1 of the first H/2 half indices of the
 // block, waves 2 and 3 the next H/2, so the link a site reads as its forward
@@ -395,7 +401,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
                                                      const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                      const S* __restrict__ aux, double* __restrict__ partials,
                                                      const Scalars* __restrict__ scal, int ftz,
-                                                     const S* __restrict__ cin, int tpar) {
+                                                     const S* __restrict__ cin, int tpar, int mask) {
   using T_ = typename Traits<S>::T;
   const BlockPos bp = block_pos(sched);
   const int tid = threadIdx.x;
@@ -405,10 +411,10 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
   if (scal) {  // skip blocks whose right-hand sides have all stopped
     bool any = false;
 #pragma unroll
-    for (int i = 0; i < T; i++) any |= scal[bp.tile * T + i].active != 0;
+    for (int i = 0; i < T; i++) any |= scal_live(scal[bp.tile * T + i], mask);
     if (!any) return;
   }
-  const bool live = !scal || scal[rhs].active != 0;
+  const bool live = !scal || scal_live(scal[rhs], mask);
   const int par = EO ? tpar : (wid & 1);
   const int h = EO ? bp.h0 + wid * (64 / T) + lane / T : bp.h0 + (wid >> 1) * (64 / T) + lane / T;
   const int fpar = EO ? 0 : par;  // parity index of this site in its own fields
@@ -676,7 +682,7 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
                                                       const S* __restrict__ in, const S* __restrict__ U, double kappa,
                                                       const S* __restrict__ aux, double* __restrict__ partials,
                                                       const Scalars* __restrict__ scal, int ftz,
-                                                      const S* __restrict__ cin, int tpar) {
+                                                      const S* __restrict__ cin, int tpar, int mask) {
   using T_ = typename Traits<S>::T;
   const BlockPos bp = block_pos(sched);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -685,7 +691,7 @@ __global__ __launch_bounds__(256, 2) void k_dslash_mr(Geom g, DslashSched sched,
   bool any = false;
 #pragma unroll
   for (int r = 0; r < R; r++) {
-    live[r] = !scal || scal[r0 + r].active != 0;
+    live[r] = !scal || scal_live(scal[r0 + r], mask);
     any |= live[r];
   }
   if (!any) return;  // uniform over the block
@@ -815,7 +821,7 @@ template <typename S, int OP, int NC, int NE, bool EO>
 __global__ __launch_bounds__(256) void k_dslash_mfma(Geom g, S* __restrict__ out, const S* __restrict__ in,
                                                      const S* __restrict__ U, double kappa,
                                                      const Scalars* __restrict__ scal, int ftz,
-                                                     const S* __restrict__ cin, int tpar, int T) {
+                                                     const S* __restrict__ cin, int tpar, int T, int mask) {
   static_assert(std::is_same<S, __half2>::value, "the matrix-core form is built for FP16 storage");
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr bool HOP_ONLY = (OP == kOpH || OP == kOpHdag);
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(256) void k_dslash_mfma(Geom g, S* __restrict__ out
   // skip right-hand sides whose solver stopped (uniform over a wave only per column, so no early exit)
 #pragma unroll
   for (int c = 0; c < NC; c++)
-    if (scal && col_ok[c] && !scal[r0 + c * 8 + (n >> 1)].active) col_ok[c] = false;
+    if (scal && col_ok[c] && !scal_live(scal[r0 + c * 8 + (n >> 1)], mask)) col_ok[c] = false;
 
 #pragma unroll
   for (int hop = 0; hop < 8; hop++) {
@@ -1020,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_dslash_mfma(Geom g, S* __restrict__ out
 template <typename S, int DEPTH, int OCC, int T, int NE>
 static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, const void* cin, int eo_par, hipStream_t st) {
+                            int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
   const S* i = (const S*)in;
@@ -1032,10 +1038,10 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
   do {                                                                                                               \
     if (T == 1 && sc.ntiles == 1)                                                                                    \
       hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true, T == 1>), grid, block, 0, st, g, sc, o, i, \
-                         u, kappa, x, partials, scal, ftz, ci, eo_par);                                              \
+                         u, kappa, x, partials, scal, ftz, ci, eo_par, mask);                                        \
     else                                                                                                             \
       hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, true, false>), grid, block, 0, st, g, sc, o, i,  \
-                         u, kappa, x, partials, scal, ftz, ci, eo_par);                                              \
+                         u, kappa, x, partials, scal, ftz, ci, eo_par, mask);                                        \
   } while (0)
     if (op == kOpH) QCD_LAUNCH_EO(kOpH, kEpiNone);
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
@@ -1049,7 +1055,7 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
   }
 #define QCD_LAUNCH(OPV, EPIV)                                                                                          \
   hipLaunchKernelGGL((k_dslash<S, OPV, EPIV, DEPTH, OCC, T, NE, false, false>), grid, block, 0, st, g, sc, o, i, u, kappa, \
-                     x, partials, scal, ftz, nullptr, 0)
+                     x, partials, scal, ftz, nullptr, 0, mask)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -1072,26 +1078,26 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 template <typename S, int T, int NE>
 static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
                                const void* in, const void* U, double kappa, const void* aux, double* partials,
-                               const Scalars* scal, int ftz, const void* cin, int eo_par, hipStream_t st) {
+                               const Scalars* scal, int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   const DslashSched sc = make_sched(g, tune.sched, T, n, eo_par >= 0);
   if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
-    launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
     return;
   }
   switch (tune.variant) {
-    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
-    case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
-    case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
-    case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
-    case 5: launch_dslash_v<S, 1, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
-    default: launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st); break;
+    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    case 5: launch_dslash_v<S, 1, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    default: launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
   }
 }
 
 template <typename S, int R, int NE>
 static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                              const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                             int ftz, const void* cin, int eo_par, hipStream_t st) {
+                             int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   const DslashSched sc = make_sched(g, tune.sched, 1, n / R, eo_par >= 0);
   dim3 grid(sc.nsb * sc.ntiles), block(256);
   S* o = (S*)out;
@@ -1102,7 +1108,7 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
   if (eo_par >= 0) {
 #define QCD_LAUNCH_EO(OPV, EPIV)                                                                                 \
   hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE, true>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
-                     scal, ftz, ci, eo_par)
+                     scal, ftz, ci, eo_par, mask)
     if (op == kOpH) QCD_LAUNCH_EO(kOpH, kEpiNone);
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
     else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
@@ -1113,7 +1119,7 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
   }
 #define QCD_LAUNCH(OPV, EPIV)                                                                                     \
   hipLaunchKernelGGL((k_dslash_mr<S, OPV, EPIV, R, NE, false>), grid, block, 0, st, g, sc, o, i, u, kappa, x, partials, \
-                     scal, ftz, nullptr, 0)
+                     scal, ftz, nullptr, 0, mask)
   if (epi == kEpiNone) {
     switch (op) {
       case kOpD: QCD_LAUNCH(kOpD, kEpiNone); break;
@@ -1137,7 +1143,7 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
 template <int NE>
 static void launch_dslash_mfma(const Geom& g, int op, int n, void* out, const void* in, const void* U,
                                double kappa, const Scalars* scal, int ftz, const void* cin, int eo_par,
-                               hipStream_t st) {
+                               hipStream_t st, int mask) {
   const int T = mfma_rhs_tile(n);
   const bool eo = eo_par >= 0;
   const int nsite = eo ? g.Vh : 2 * g.Vh;
@@ -1152,10 +1158,10 @@ static void launch_dslash_mfma(const Geom& g, int op, int n, void* out, const vo
   do {                                                                                                            \
     if (T > 8)                                                                                                    \
       hipLaunchKernelGGL((k_dslash_mfma<__half2, OPV, 2, NE, EOV>), grid, block, 0, st, g, o, i, u, kappa, scal, ftz, \
-                         ci, tp, T);                                                                              \
+                         ci, tp, T, mask);                                                                        \
     else                                                                                                          \
       hipLaunchKernelGGL((k_dslash_mfma<__half2, OPV, 1, NE, EOV>), grid, block, 0, st, g, o, i, u, kappa, scal, ftz, \
-                         ci, tp, T);                                                                              \
+                         ci, tp, T, mask);                                                                        \
   } while (0)
   if (eo) {
     if (op == kOpH) QCD_MFMA(kOpH, true);
@@ -1174,41 +1180,41 @@ static void launch_dslash_mfma(const Geom& g, int op, int n, void* out, const vo
 template <typename S, int NE>
 static void launch_dslash_r(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, const void* cin, int eo_par, hipStream_t st) {
+                            int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   if constexpr (std::is_same<S, __half2>::value) {
     // the matrix-core form, when chosen, for the plain operator of a tileable number of right-hand sides
     if (tune.rhs_tile == kRhsTileMfma && epi == kEpiNone && mfma_rhs_tile(n) > 0) {
-      launch_dslash_mfma<NE>(g, op, n, out, in, U, kappa, scal, ftz, cin, eo_par, st);
+      launch_dslash_mfma<NE>(g, op, n, out, in, U, kappa, scal, ftz, cin, eo_par, st, mask);
       return;
     }
   }
   const int R = reg_tile_for(tune, n);
-  if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
-  if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
-  if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  if (R == 4) return launch_dslash_mr<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
+  if (R == 3) return launch_dslash_mr<S, 3, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
+  if (R == 2) return launch_dslash_mr<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   const int T = rhs_tile_for(tune, n);
   if (T == 4)
-    launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_tile<S, 4, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else if (T == 2)
-    launch_dslash_tile<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_tile<S, 2, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else
-    launch_dslash_tile<S, 1, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_tile<S, 1, NE>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 
 template <typename S>
 static void launch_dslash_t(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                             const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                            int ftz, const void* cin, int eo_par, hipStream_t st) {
+                            int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   if (tune.recon)
-    launch_dslash_r<S, 6>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_r<S, 6>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else
-    launch_dslash_r<S, 9>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_r<S, 9>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 
 #define QCD_DSLASH_ARGS                                                                                          \
   const Geom &g, const DslashTune &tune, int op, int epi, int n, void *out, const void *in, const void *U, \
       double kappa, const void *aux, double *partials, const Scalars *scal, int ftz, const void *cin, int eo_par, \
-      hipStream_t st
+      hipStream_t st, int mask
 void launch_dslash_f64(QCD_DSLASH_ARGS);
 void launch_dslash_f32(QCD_DSLASH_ARGS);
 void launch_dslash_f16(QCD_DSLASH_ARGS);
@@ -1216,19 +1222,19 @@ void launch_dslash_bf16(QCD_DSLASH_ARGS);
 
 #if QCD_DSLASH_PREC == 0
 void launch_dslash_f64(QCD_DSLASH_ARGS) {
-  launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  launch_dslash_t<double2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 #elif QCD_DSLASH_PREC == 1
 void launch_dslash_f32(QCD_DSLASH_ARGS) {
-  launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  launch_dslash_t<float2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 #elif QCD_DSLASH_PREC == 3
 void launch_dslash_bf16(QCD_DSLASH_ARGS) {
-  launch_dslash_t<bf2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  launch_dslash_t<bf2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 #else
 void launch_dslash_f16(QCD_DSLASH_ARGS) {
-  launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+  launch_dslash_t<__half2>(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 
 int rhs_tile_for(const DslashTune& tune, int n) {
@@ -1294,17 +1300,17 @@ int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo) {
 
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune_in, int op, int epi, int n, void* out,
                    const void* in, const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
-                   int ftz, hipStream_t st, const void* cin, int eo_par) {
+                   int ftz, hipStream_t st, const void* cin, int eo_par, int mask) {
   DslashTune tune = resolve_rhs_tile(tune_in, prec, n);
   if (epi == kEpiRecon) tune.rhs_tile = 1;  // built for one right-hand side per thread only
   if (prec == kFP64)
-    launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_f64(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else if (prec == kFP32)
-    launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_f32(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else if (prec == kBF16)
-    launch_dslash_bf16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_bf16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
   else
-    launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st);
+    launch_dslash_f16(g, tune, op, epi, n, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
 }
 #endif
 #undef QCD_DSLASH_ARGS

@@ -61,8 +61,24 @@ struct Scalars {
   double zeros;                  // zero reals in y~
   double out_bnorm;              // |b|, for the outer stopping test
   double out_tol;
-  double pad[2];
+  // device-driven refinement: the stop of an inner solve raises outer_step, and
+  // the refinement step's kernels (correction, FP64 residual, its norm, the
+  // conversion and the next inner start) act only on right-hand sides that
+  // have it, so a captured graph of iterations and one step runs several
+  // refinement steps between host polls
+  int dev_outer;                 // 1: device-driven refinement for this right-hand side
+  int outer_step;                // 1 from the stop of an inner solve until its refinement step is done
+  int outer_count;               // refinement steps done (device-driven)
+  int inner_total;               // inner iterations over all steps (device-driven)
+  int max_outer;                 // refinement step cap (device-driven)
+  int fail;                      // status of the inner solve that ended refining (kNonFinite, kBreakdown), else 0
+  int last_status;               // stop reason of the last inner solve (device-driven)
+  int pad_i;
+  double first_shat;             // s^ of the first refinement step (device-driven)
+  double pad[1];
 };
+// refinement steps whose |r| and zero count the device-driven refinement logs per right-hand side
+constexpr int kOuterLog = 64;
 
 // Launch choices of the Wilson operator (picked by the tuner).
 struct DslashTune {
@@ -99,9 +115,11 @@ int reg_tile_for(const DslashTune& tune, int n);
 // Scalars[n], and partial sums are laid out [rhs][row][value].
 
 // launchers (dslash.hip)
+// mask (with scal): 0 computes the right-hand sides whose inner solve is active, 1 those whose
+// device-driven refinement step is due (outer_step)
 void launch_dslash(int prec, const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out, const void* in,
                    const void* U, double kappa, const void* aux, double* partials, const Scalars* scal, int ftz,
-                   hipStream_t st, const void* cin = nullptr, int eo_par = -1);
+                   hipStream_t st, const void* cin = nullptr, int eo_par = -1, int mask = 0);
 int dslash_partial_rows(const Geom& g, const DslashTune& tune, int n, bool eo = false);  // rows per right-hand side
 
 // launchers (blas.hip)
@@ -140,8 +158,9 @@ void launch_xr_update(const Geom& g, int prec, int n, Scalars* sc, void* x, void
 void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, double* history, int hist_stride,
                      hipStream_t st);
 
+// with log (device-driven refinement): log[rhs][k] = (|r|, zeros of y~) of step k
 void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
-                                hipStream_t st);
+                                hipStream_t st, double* log = nullptr);
 void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r64, void* y, void* rstar,
                     double* partials, int ftz, hipStream_t st);
 void launch_convert_finish(int n, Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
@@ -180,7 +199,7 @@ struct qcd_gauge {
   hipStream_t cap_stream;   // created at upload: capture, and this lattice's share of a batched solve
   hipEvent_t ev_fork, ev_done;  // created at upload: fork / join of a batched solve's streams
   hipGraphExec_t graph_exec;
-  unsigned long long graph_key[24];
+  unsigned long long graph_key[32];
   double su3_dev;  // largest |row2 - conj(row0 x row1)| of the uploaded links (INFINITY if not checked)
 };
 

@@ -237,6 +237,34 @@ def test_graph_replays_match_eager(q, c1b):
     assert torch.equal(xb, xb2)
 
 
+@pytest.mark.parametrize("eo", [False, True])
+def test_device_driven_steps_match_host_driven(q, c1b, eo):
+    # with graph replay the refinement steps run from the device (a graph of
+    # inner iterations and one step, replayed between host polls); solutions,
+    # counts, the per-step residual and zero-count logs and s^/s are the
+    # host-driven refinement's, bit for bit (sources: normal, small, zero)
+    g, k = c1b["g"], c1b["k"]
+    b = to_dev(c1b["b"])
+    xh, xd = torch.zeros_like(b), torch.zeros_like(b)
+    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo)
+    idv = q.solve_mixed_ir(g, k, xd, b, use_graph=True, even_odd=eo)
+    torch.cuda.synchronize()
+    assert torch.equal(xh, xd)
+    for a, d in zip(ih, idv):
+        assert (a.status, a.outer_iters, a.inner_iters, a.matvec_low, a.matvec_fp64) == \
+               (d.status, d.outer_iters, d.inner_iters, d.matvec_low, d.matvec_fp64)
+        assert a.outer_history == d.outer_history and a.zeros == d.zeros
+        assert a.first_shat_over_s == d.first_shat_over_s and a.true_rel_residual == d.true_rel_residual
+    # a step cap ends both forms at the same x, reported as not converged
+    xh, xd = torch.zeros_like(b), torch.zeros_like(b)
+    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo, max_outer=2, raise_on_error=False)
+    idv = q.solve_mixed_ir(g, k, xd, b, use_graph=True, even_odd=eo, max_outer=2, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert torch.equal(xh, xd)
+    assert [i.status for i in idv] == [i.status for i in ih]
+    assert idv[0].status == "not_converged" and idv[0].outer_iters == 2
+
+
 def test_graph_cache_follows_the_workspace_carve(q, c1b):
     # one handle, one caller workspace: inner_max_iter 500 and then 2000 move
     # the partial sums and scalars inside the same buffer (the history before
