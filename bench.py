@@ -56,6 +56,10 @@ def parse():
                     help="run the launch-shape tuner first (default: the library's measured defaults)")
     ap.add_argument("--only-dslash", action="store_true",
                     help="time only the Wilson operator and the calibration copy (for counter runs)")
+    ap.add_argument("--profile-form", choices=("headline", "headline-graph", "twelve", "twelve-seq", "mixed",
+                                               "mixed-seq"),
+                    help="run one solve form twice, 0.3 s apart, and nothing else (for kernel traces: the "
+                         "second run follows the largest gap in the trace)")
     return ap.parse_args()
 
 
@@ -508,6 +512,54 @@ def oracle_baseline(U, b, k, dims, eo, x_head):
     return res
 
 
+def profile_form(args, q, torch, np, qi):
+    """One solve form twice (the second is the one to read in a kernel trace)."""
+    dims, k = tuple(int(v) for v in args.dims.split(",")), args.kappa
+    kw = dict(inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, inner_tol=INNER_TOL, inner_max_iter=20000,
+              even_odd=True)
+    form = args.profile_form
+    if form.startswith("mixed"):
+        specs = [((16, 16, 16, 16), 301), ((24, 24, 24, 48), 302), ((32, 32, 32, 64), 303)]
+        gs, bs, xs = [], [], []
+        for d, seed in specs:
+            gs.append(q.gauge_upload(torch.from_numpy(qi.gauge_field(d, 0.3, seed)).cuda(), d))
+            bs.append(torch.from_numpy(qi.gaussian_source(d, seed + 1000, nrhs=4)).cuda())
+            xs.append(torch.zeros_like(bs[-1]))
+
+        def run():
+            for x in xs:
+                x.zero_()
+            if form == "mixed":
+                q.solve_mixed_ir_batched(gs, [k] * 3, xs, bs, use_graph=True, **kw)
+            else:
+                for g, x, b in zip(gs, xs, bs):
+                    q.solve_mixed_ir(g, k, x, b, use_graph=True, **kw)
+    else:
+        g = q.gauge_upload(torch.from_numpy(qi.gauge_field(dims, args.eps, 201)).cuda(), dims)
+        if form.startswith("twelve"):
+            b = torch.from_numpy(np.stack([qi.point_source(dims, sp, c) for sp in range(4) for c in range(3)])).cuda()
+        else:
+            b = torch.from_numpy(qi.gaussian_source(dims, 202)).cuda()
+        x = torch.zeros_like(b)
+
+        def run():
+            x.zero_()
+            if form == "twelve-seq":
+                for r in range(12):
+                    q.solve_mixed_ir(g, k, x[r], b[r].contiguous(), use_graph=True, **kw)
+            else:
+                q.solve_mixed_ir(g, k, x, b, use_graph=(form != "headline"), **kw)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        if rep:
+            time.sleep(0.3)
+        ts = time.perf_counter()
+        run()
+        torch.cuda.synchronize()
+        print(f"[bench] profile form {form}: run {rep} {1e3 * (time.perf_counter() - ts):.2f} ms", file=sys.stderr,
+              flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -521,6 +573,9 @@ def main():
     import qcd_inputs as qi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.profile_form:
+        profile_form(args, q, torch, np, qi)
+        return
     dims = tuple(int(v) for v in args.dims.split(","))
     V = int(np.prod(dims))
     k = args.kappa
