@@ -495,6 +495,182 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
 }
 
 // ---------------------------------------------------------------------------
+// The operator with the x and y neighbours staged in LDS (full lattice, one
+// right-hand side per thread, no reduction epilogue; launch variant 6).  A
+// block covers R = H / (Lx/2) whole x rows of both parities at one (z, t)
+// (H = 128 half sites per parity); it stages its own sites and the rows
+// y0 - 1 and y0 + R of both parities once, as 16-byte granules laid out
+// [parity][granule][row][x/2] so that a wave reading one granule reads
+// consecutive LDS words, and the x and y hops and the centre term take their
+// spinors from there.  Links and the z and t neighbours come from global memory.
+template <int MU, bool BWD> __device__ __forceinline__ int hop_neighbour(const Geom& g, int h, const Coord& c);
+
+constexpr int kLdsMaxLxh = 64;                       // Lx <= 128
+constexpr int kLdsEntries = 128 + 2 * kLdsMaxLxh;    // (R + 2) * (Lx/2) half sites at most per parity
+
+template <typename S> struct LdsTile {
+  const typename Lay<S>::Gran* t;  // LDS granules [parity][granule][row][x/2]
+  int rows, lxh;
+  __device__ __forceinline__ const typename Lay<S>::Gran& at(int par, int j, int row, int xh) const {
+    return t[((par * Lay<S>::G + j) * rows + row) * lxh + xh];
+  }
+};
+
+// The hop's link granules (as hop_load): U_mu(x) at (par, h) forward, U_mu(x - mu) at (par ^ 1, hn) backward.
+template <int HOP, int NE, typename S>
+__device__ __forceinline__ void hop_load_link(const Geom& g, const S* __restrict__ U, int par, int h, int hn,
+                                              HopRaw<S, NE>& d) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr int C = Lay<S>::C, F = LkLay<S, NE>::F, TAIL = LkLay<S, NE>::TAIL;
+  using Gr = typename Lay<S>::Gran;
+  const int lp = BWD ? (par ^ 1) : par, lh = BWD ? hn : h;
+  const S* lb = U + lk_block<NE>(g, MU, lp, lh);
+  const int lane = lh & 63;
+#pragma unroll
+  for (int j = 0; j < F / C; j++) d.lk[j] = *reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C);
+  if constexpr (NE == 9) {
+#pragma unroll
+    for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
+  } else if constexpr (TAIL == 2) {
+    const Pair<S> v = *reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2);
+    d.tail[0] = v.s[0];
+    d.tail[1] = v.s[1];
+  }
+}
+
+// hop_load with the x and y neighbours' spinors from the LDS tile (row and xh
+// locate this site in it; rows are offset by the halo row).
+template <int HOP, bool DAG, int NE, typename S>
+__device__ __forceinline__ void hop_load_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
+                                             int par, int h, const Coord& c, int row, int xh, const LdsTile<S>& L,
+                                             HopRaw<S, NE>& d, int dep = 0) {
+  constexpr int MU = HOP >> 1;
+  constexpr bool BWD = HOP & 1;
+  constexpr bool MINUS = BWD ? DAG : !DAG;
+  if constexpr (MU >= 2) {
+    hop_load<HOP, DAG, NE, false, false>(g, in, U, par, h, c, d, dep);
+  } else {
+    const int hn = hop_neighbour<MU, BWD>(g, h, c) + dep;
+    int rn = row + dep, xn = xh;
+    if constexpr (MU == 0) {
+      const int xx = BWD ? ((c.x == 0) ? g.L[0] - 1 : c.x - 1) : ((c.x + 1 == g.L[0]) ? 0 : c.x + 1);
+      xn = xx >> 1;
+    } else {
+      rn += BWD ? -1 : 1;
+    }
+#pragma unroll
+    for (int j = 0; j < Lay<S>::G; j++)
+      if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = L.at(par ^ 1, j, rn, xn);
+    hop_load_link<HOP, NE>(g, U, par, h + dep, hn, d);
+  }
+}
+
+template <int I, int DEPTH, bool DAG, int NE, typename S, typename T>
+__device__ __forceinline__ void hop_pipe_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
+                                             const PipeArgs& pa, int row, int xh, const LdsTile<S>& L,
+                                             HopRaw<S, NE> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
+  if constexpr (I < 8) {
+    hop_compute<I, DAG, NE>(buf[I % (DEPTH + 1)], a);
+    reg_barrier(a);
+    if constexpr (I + DEPTH + 1 < 8) {
+      int dep = 0;
+      asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
+      hop_load_lds<I + DEPTH + 1, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, row, xh, L,
+                                           buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
+    }
+    QCD_FENCE();
+    hop_pipe_lds<I + 1, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf, a);
+  }
+}
+
+template <int I, int DEPTH, bool DAG, int NE, typename S>
+__device__ __forceinline__ void hop_prologue_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
+                                                 const PipeArgs& pa, int row, int xh, const LdsTile<S>& L,
+                                                 HopRaw<S, NE> (&buf)[DEPTH + 1]) {
+  if constexpr (I <= DEPTH) {
+    hop_load_lds<I, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, row, xh, L, buf[I]);
+    hop_prologue_lds<I + 1, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf);
+  }
+}
+
+// Whether the LDS form applies: blocks of H = 128 half sites cover whole x rows of one (z, t) plane.
+inline bool lds_form_applies(const Geom& g) {
+  const int R = 128 / g.Lxh;
+  return g.Lxh <= kLdsMaxLxh && 128 % g.Lxh == 0 && g.L[1] % R == 0;
+}
+
+template <typename S, int OP, int DEPTH, int NE>
+__global__ __launch_bounds__(256, 2) void k_dslash_lds(Geom g, DslashSched sched, S* __restrict__ out,
+                                                       const S* __restrict__ in, const S* __restrict__ U,
+                                                       double kappa, int ftz) {
+  using T_ = typename Traits<S>::T;
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C, G = Lay<S>::G;
+  constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
+  __shared__ Gr tile[2 * G * kLdsEntries];
+  const BlockPos bp = block_pos(sched);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int lxh = g.Lxh, R = 128 / lxh, rows = R + 2;
+  const LdsTile<S> L{tile, rows, lxh};
+  const int par = wid & 1;
+  const int j = (wid >> 1) * 64 + lane;  // half site within the block
+  const int h = bp.h0 + j;
+  const int row = j / lxh + 1, xh = j - (j / lxh) * lxh;
+  // the block's rows: plane base and the y of its first row
+  const int y0 = (bp.h0 / lxh) % g.L[1];
+  const int pbase = bp.h0 - y0 * lxh;
+  // stage the block's own sites
+  if (h < g.Vh) {
+    const S* b = in + sp_block(g, par, h) + (h & 63) * C;
+#pragma unroll
+    for (int k = 0; k < G; k++) tile[((par * G + k) * rows + row) * lxh + xh] = *reinterpret_cast<const Gr*>(b + k * 64 * C);
+  }
+  // and the rows above and below, both parities
+  for (int k = tid; k < 2 * 2 * lxh * G; k += 256) {
+    const int jg = k % G, r1 = k / G;
+    const int xs = r1 % lxh, r2 = r1 / lxh;
+    const int which = r2 & 1, hp = r2 >> 1;
+    const int yy = which ? (y0 + R) % g.L[1] : (y0 + g.L[1] - 1) % g.L[1];
+    const int hh = pbase + yy * lxh + xs;
+    tile[((hp * G + jg) * rows + (which ? R + 1 : 0)) * lxh + xs] =
+        *reinterpret_cast<const Gr*>(in + sp_block(g, hp, hh) + (hh & 63) * C + jg * 64 * C);
+  }
+  __syncthreads();
+  if (h >= g.Vh) return;
+  const Coord c = decode(g, par, h);
+  cx<T_> a[4][3];
+#pragma unroll
+  for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+    for (int cc = 0; cc < 3; cc++) a[sp][cc] = cx<T_>(0, 0);
+  {
+    HopRaw<S, NE> buf[DEPTH + 1];
+    const PipeArgs pa{par, h, c};
+    hop_prologue_lds<0, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf);
+    hop_pipe_lds<0, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf, a);
+  }
+  const T_ k = (T_)kappa;
+  S* ob = out + sp_block(g, par, h) + (h & 63) * C;
+#pragma unroll
+  for (int jj = 0; jj < G; jj++) {
+    const Gr cv = L.at(par, jj, row, xh);
+    Gr v;
+#pragma unroll
+    for (int cc = 0; cc < C; cc++) {
+      const int i = jj * C + cc;
+      cx<T_> o = a[i / 3][i % 3];
+      if constexpr (!(OP == kOpH || OP == kOpHdag)) {
+        const cx<T_> ctr = Traits<S>::load(&cv.s[cc]);
+        o = ctr - k * o;
+      }
+      v.s[cc] = Traits<S>::pack(o, ftz);
+    }
+    store_stream(reinterpret_cast<Gr*>(ob + jj * 64 * C), v);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Several right-hand sides per thread: the thread of a site applies the link
 // it loaded (and rebuilt) once to R right-hand sides, so the link conversion,
 // the row-2 rebuild and the neighbour addressing are paid once per site
@@ -1075,11 +1251,35 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 #undef QCD_LAUNCH
 }
 
+template <typename S, int NE>
+static void launch_dslash_lds(const Geom& g, const DslashSched& sc, int op, void* out, const void* in, const void* U,
+                              double kappa, int ftz, hipStream_t st) {
+  const dim3 grid(sc.nsb), block(256);
+#define QCD_LDS(OPV)                                                                                           \
+  hipLaunchKernelGGL((k_dslash_lds<S, OPV, 1, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, (const S*)U, \
+                     kappa, ftz)
+  switch (op) {
+    case kOpD: QCD_LDS(kOpD); break;
+    case kOpH: QCD_LDS(kOpH); break;
+    case kOpDdag: QCD_LDS(kOpDdag); break;
+    default: QCD_LDS(kOpHdag); break;
+  }
+#undef QCD_LDS
+}
+
 template <typename S, int T, int NE>
 static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, int epi, int n, void* out,
                                const void* in, const void* U, double kappa, const void* aux, double* partials,
                                const Scalars* scal, int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   const DslashSched sc = make_sched(g, tune.sched, T, n, eo_par >= 0);
+  if constexpr (T == 1 && sizeof(S) == 4) {
+    // variant 6: x and y neighbours staged in LDS (16-bit storage: 24 KB per block; plain
+    // full-lattice operator, one right-hand side)
+    if (tune.variant == 6 && n == 1 && eo_par < 0 && epi == kEpiNone && !scal && lds_form_applies(g)) {
+      launch_dslash_lds<S, NE>(g, sc, op, out, in, U, kappa, ftz, st);
+      return;
+    }
+  }
   if constexpr (T > 1) {  // multi-RHS tiles are built in the default variant only
     launch_dslash_v<S, 1, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
     return;

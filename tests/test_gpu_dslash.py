@@ -193,3 +193,46 @@ def test_bf16_operator_is_the_rounded_exact_operator(q):
             assert np.all(d <= ulp + 1e-6 * rms), f"op={op}: {np.max(d / ulp):.2f} ulp"
             assert np.count_nonzero(d) <= max(4, a.size // 200), f"op={op}: {np.count_nonzero(d)} of {a.size} differ"
     g.close()
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 4, 4), (32, 8, 4, 6), (64, 4, 2, 2), (2, 4, 6, 10), (32, 32, 32, 64)])
+@pytest.mark.parametrize("prec", [2, 3])
+def test_lds_staged_variant_matches_oracle(q, dims, prec):
+    # launch variant 6 (x and y neighbours staged in LDS; blocks of whole x
+    # rows, so the halo rows wrap in y on the small lattices) against the
+    # oracle for every operator and schedule, and against variant 0 element
+    # by element: the same products in the same order, so the two differ at
+    # most where the compiler fuses the final FP32 sums differently (one unit
+    # of the storage format in rare elements); on (2, 4, 6, 10) a block does
+    # not cover whole rows and variant 6 is variant 0 itself
+    U, psi = fields(dims, gseed=21 + sum(dims), sseed=22)
+    g = q.gauge_upload(to_dev(U), dims, precs=(q.FP64, prec))
+    a = g.native_spinor(prec)
+    q.convert(g, prec, a, to_dev(psi), want_norm=False)
+    ref, got = g.native_spinor(prec), g.native_spinor(prec)
+    big = dims == (32, 32, 32, 64)
+    unit = 2.0 ** -10 if prec == 2 else 2.0 ** -7     # one unit in the last place, relative, of FP16 / BF16
+    o_ref = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    o_got = torch.empty_like(o_ref)
+    for op in ([0] if big else OPS):
+        for sched in ([1] if big else [0, 1, 4]):
+            g.set_tuning(prec, sched, 0, 1)
+            q.dslash(g, 0.124, ref, a, op=op, prec=prec, layout=q.NATIVE)
+            g.set_tuning(prec, sched, 6, 1)
+            q.dslash(g, 0.124, got, a, op=op, prec=prec, layout=q.NATIVE)
+            q.unconvert(g, prec, o_ref, ref)
+            q.unconvert(g, prec, o_got, got)
+            torch.cuda.synchronize()
+            r, v = to_host(o_ref).reshape(-1), to_host(o_got).reshape(-1)
+            for part in (np.real, np.imag):
+                d = np.abs(part(v) - part(r))
+                assert np.all(d <= unit * np.abs(part(r)) + 1e-30), (dims, prec, op, sched, d.max())
+            frac = np.mean(r != v)
+            assert frac <= 1e-3, (dims, prec, op, sched, frac)
+            if not big:
+                compare(to_host(o_got), oracle.dslash(U, psi, 0.124, dims, op), TOL[prec], f"lds {dims} op={op}")
+            else:
+                V = qi.volume(dims)
+                sites = np.random.default_rng(23).integers(0, V, 300)
+                compare(to_host(o_got)[sites], oracle.dslash_sites(U, psi, 0.124, dims, sites), TOL[prec], "lds 32^3x64")
+    g.close()
