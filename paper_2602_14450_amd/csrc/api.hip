@@ -587,10 +587,11 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   }
   // defaults measured on MI355X at 32^3 x 64 with rotating buffers (the tuner
   // may override them): z slabs per XCD; prefetch 2 hops at 2 waves per SIMD
-  // (FP16, FP32), 1 hop at 2 (FP64)
+  // (FP32; FP16 with its x and y neighbours staged in LDS where the plain
+  // full-lattice operator allows it, else the same), 1 hop at 2 (FP64)
   g->tune[kFP64] = DslashTune{1, 0, 0, 0};
   g->tune[kFP32] = DslashTune{1, 1, 0, 0};
-  g->tune[kFP16] = DslashTune{1, 1, 0, 0};
+  g->tune[kFP16] = DslashTune{1, 6, 0, 0};
   g->tune[kBF16] = DslashTune{1, 1, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);
   hipStream_t st = S(stream);

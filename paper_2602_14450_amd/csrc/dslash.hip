@@ -1285,7 +1285,8 @@ static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, in
     return;
   }
   switch (tune.variant) {
-    case 1: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
+    case 1:
+    case 6: launch_dslash_v<S, 2, 2, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
     case 2: launch_dslash_v<S, 0, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
     case 3: launch_dslash_v<S, 1, 3, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;
     case 4: launch_dslash_v<S, 0, 4, T, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask); break;

@@ -86,7 +86,7 @@ struct DslashTune {
                 // 4: XCD t slabs swept in z order
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
                 // (prefetching 2 hops at 5 waves spills registers and measured slower in every precision);
-                // 6: x and y neighbours staged in LDS (FP16 / BF16 plain full-lattice operator; else as 0)
+                // 6: x and y neighbours staged in LDS (FP16 / BF16 plain full-lattice operator; else as 1)
   int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
                 // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers);
                 // 8 = the matrix-core form (kRhsTileMfma)
