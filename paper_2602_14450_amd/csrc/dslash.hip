@@ -389,6 +389,67 @@ __device__ __forceinline__ BlockPos block_pos(const DslashSched& sc) {
   return p;
 }
 
+// The centre term, the epilogue's sums and the store of one site's result
+// (a: the site's hop sum; the reductions see the stored, rounded values).
+template <typename S, int OP, int EPI, bool EO, int NV, typename T_>
+__device__ __forceinline__ void site_finish(const Geom& g, S* __restrict__ out, const S* __restrict__ in,
+                                            const S* __restrict__ cin, const S* __restrict__ aux, int fpar, int h,
+                                            double kappa, int ftz, const cx<T_> (&a)[4][3], double (&red)[NV]) {
+  constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
+  const T_ k = (T_)kappa;
+  cx<T_> o[12], ctr[12], ax[12];
+  if constexpr (!(OP == kOpH || OP == kOpHdag)) {
+    if constexpr (EO) load_site_stream(cin, g, fpar, h, ctr);  // read once
+    else load_site(EO ? cin : in, g, fpar, h, ctr);  // the full form's centre is also neighbour data
+  }
+  if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site_stream(aux, g, fpar, h, ax);
+#pragma unroll
+  for (int i = 0; i < 12; i++) {
+    if constexpr (OP == kOpH || OP == kOpHdag) {
+      o[i] = a[i / 3][i % 3];
+    } else {
+      o[i] = ctr[i] - k * a[i / 3][i % 3];
+      if constexpr (EPI == kEpiResid) o[i] = ax[i] - o[i];
+    }
+  }
+  // round to storage; the reductions see the stored values
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C;
+  S* ob = out + sp_block(g, fpar, h) + (h & 63) * C;
+  T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+#pragma unroll
+  for (int j = 0; j < Lay<S>::G; j++) {
+    Gr v;
+#pragma unroll
+    for (int cc = 0; cc < C; cc++) {
+      const int i = j * C + cc;
+      v.s[cc] = Traits<S>::pack(o[i], ftz);
+      if constexpr (EPI != kEpiNone) {
+        const cx<T_> os = Traits<S>::load(&v.s[cc]);
+        if constexpr (EPI == kEpiDotAux) {  // (aux, out) = sum conj(aux) out
+          acc0 += ax[i].re * os.re + ax[i].im * os.im;
+          acc1 += ax[i].re * os.im - ax[i].im * os.re;
+        } else if constexpr (TS) {  // (t, s) with t = out, s = in (TS) or aux (TSAux); |t|^2, |s|^2
+          const cx<T_> sv = (EPI == kEpiTSAux) ? ax[i] : ctr[i];
+          acc0 += os.re * sv.re + os.im * sv.im;
+          acc1 += os.re * sv.im - os.im * sv.re;
+          acc2 += norm2(os);
+          acc3 += norm2(sv);
+        } else if constexpr (EPI == kEpiRecon) {  // cin - (out - |kappa| H in), as a separate residual launch forms it
+          const cx<T_> dv = os - (-k) * a[i / 3][i % 3];
+          acc0 += norm2(ctr[i] - dv);
+        } else {
+          acc0 += norm2(os);
+        }
+      }
+    }
+    store_stream(reinterpret_cast<Gr*>(ob + j * 64 * C), v);
+  }
+  if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
+  if constexpr (TS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
+  if constexpr (EPI == kEpiResid || EPI == kEpiRecon) { red[0] = acc0; }
+}
+
 // out = D in, H in, D^dag in, or b - D in, with optional reduction epilogues,
 // for T right-hand sides per wave (vectors of right-hand side r start at
 // r * vstride elements).  With EO the output covers parity tpar only and every
@@ -438,58 +499,7 @@ __global__ __launch_bounds__(256, OCC) void k_dslash(Geom g, DslashSched sched, 
 #pragma unroll
       for (int cc = 0; cc < 3; cc++) a[s][cc] = cx<T_>(0, 0);
     hop_all<DEPTH, DAG, NE, EO, LNT>(g, in, U, par, h, c, a);
-    const T_ k = (T_)kappa;
-    cx<T_> o[12], ctr[12], ax[12];
-    if constexpr (!(OP == kOpH || OP == kOpHdag)) {
-      if constexpr (EO) load_site_stream(cin, g, fpar, h, ctr);  // read once
-      else load_site(EO ? cin : in, g, fpar, h, ctr);  // the full form's centre is also neighbour data
-    }
-    if constexpr (EPI == kEpiResid || EPI == kEpiDotAux || EPI == kEpiTSAux) load_site_stream(aux, g, fpar, h, ax);
-#pragma unroll
-    for (int i = 0; i < 12; i++) {
-      if constexpr (OP == kOpH || OP == kOpHdag) {
-        o[i] = a[i / 3][i % 3];
-      } else {
-        o[i] = ctr[i] - k * a[i / 3][i % 3];
-        if constexpr (EPI == kEpiResid) o[i] = ax[i] - o[i];
-      }
-    }
-    // round to storage; the reductions see the stored values
-    using Gr = typename Lay<S>::Gran;
-    constexpr int C = Lay<S>::C;
-    S* ob = out + sp_block(g, fpar, h) + (h & 63) * C;
-    T_ acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-#pragma unroll
-    for (int j = 0; j < Lay<S>::G; j++) {
-      Gr v;
-#pragma unroll
-      for (int cc = 0; cc < C; cc++) {
-        const int i = j * C + cc;
-        v.s[cc] = Traits<S>::pack(o[i], ftz);
-        if constexpr (EPI != kEpiNone) {
-          const cx<T_> os = Traits<S>::load(&v.s[cc]);
-          if constexpr (EPI == kEpiDotAux) {  // (aux, out) = sum conj(aux) out
-            acc0 += ax[i].re * os.re + ax[i].im * os.im;
-            acc1 += ax[i].re * os.im - ax[i].im * os.re;
-          } else if constexpr (TS) {  // (t, s) with t = out, s = in (TS) or aux (TSAux); |t|^2, |s|^2
-            const cx<T_> sv = (EPI == kEpiTSAux) ? ax[i] : ctr[i];
-            acc0 += os.re * sv.re + os.im * sv.im;
-            acc1 += os.re * sv.im - os.im * sv.re;
-            acc2 += norm2(os);
-            acc3 += norm2(sv);
-          } else if constexpr (EPI == kEpiRecon) {  // cin - (out - |kappa| H in), as a separate residual launch forms it
-            const cx<T_> dv = os - (-k) * a[i / 3][i % 3];
-            acc0 += norm2(ctr[i] - dv);
-          } else {
-            acc0 += norm2(os);
-          }
-        }
-      }
-      store_stream(reinterpret_cast<Gr*>(ob + j * 64 * C), v);
-    }
-    if constexpr (EPI == kEpiDotAux) { red[0] = acc0; red[1] = acc1; }
-    if constexpr (TS) { red[0] = acc0; red[1] = acc1; red[2] = acc2; red[3] = acc3; }
-    if constexpr (EPI == kEpiResid || EPI == kEpiRecon) { red[0] = acc0; }
+    site_finish<S, OP, EPI, EO, NV>(g, out, in, cin, aux, fpar, h, kappa, ftz, a, red);
   }
   if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, T>(red, partials, bp.tile * T, sched.nsb, bp.sb);
 }
@@ -517,7 +527,7 @@ template <typename S> struct LdsTile {
 };
 
 // The hop's link granules (as hop_load): U_mu(x) at (par, h) forward, U_mu(x - mu) at (par ^ 1, hn) backward.
-template <int HOP, int NE, typename S>
+template <int HOP, int NE, bool LNT, typename S>
 __device__ __forceinline__ void hop_load_link(const Geom& g, const S* __restrict__ U, int par, int h, int hn,
                                               HopRaw<S, NE>& d) {
   constexpr int MU = HOP >> 1;
@@ -528,20 +538,21 @@ __device__ __forceinline__ void hop_load_link(const Geom& g, const S* __restrict
   const S* lb = U + lk_block<NE>(g, MU, lp, lh);
   const int lane = lh & 63;
 #pragma unroll
-  for (int j = 0; j < F / C; j++) d.lk[j] = *reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C);
+  for (int j = 0; j < F / C; j++) d.lk[j] = load_link_gran<LNT>(reinterpret_cast<const Gr*>(lb + j * 64 * C + lane * C));
   if constexpr (NE == 9) {
 #pragma unroll
     for (int k = F; k < 9; k++) d.tail[k - F] = lb[F * 64 + (k - F) * 64 + lane];
   } else if constexpr (TAIL == 2) {
-    const Pair<S> v = *reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2);
+    const Pair<S> v = load_link_pair<LNT>(reinterpret_cast<const Pair<S>*>(lb + F * 64 + lane * 2));
     d.tail[0] = v.s[0];
     d.tail[1] = v.s[1];
   }
 }
 
 // hop_load with the x and y neighbours' spinors from the LDS tile (row and xh
-// locate this site in it; rows are offset by the halo row).
-template <int HOP, bool DAG, int NE, typename S>
+// locate this site in it; rows are offset by the halo row).  The one-parity
+// form's tile holds the input field's single parity.
+template <int HOP, bool DAG, int NE, bool EO, bool LNT, typename S>
 __device__ __forceinline__ void hop_load_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                              int par, int h, const Coord& c, int row, int xh, const LdsTile<S>& L,
                                              HopRaw<S, NE>& d, int dep = 0) {
@@ -549,7 +560,7 @@ __device__ __forceinline__ void hop_load_lds(const Geom& g, const S* __restrict_
   constexpr bool BWD = HOP & 1;
   constexpr bool MINUS = BWD ? DAG : !DAG;
   if constexpr (MU >= 2) {
-    hop_load<HOP, DAG, NE, false, false>(g, in, U, par, h, c, d, dep);
+    hop_load<HOP, DAG, NE, EO, LNT>(g, in, U, par, h, c, d, dep);
   } else {
     const int hn = hop_neighbour<MU, BWD>(g, h, c) + dep;
     int rn = row + dep, xn = xh;
@@ -561,12 +572,12 @@ __device__ __forceinline__ void hop_load_lds(const Geom& g, const S* __restrict_
     }
 #pragma unroll
     for (int j = 0; j < Lay<S>::G; j++)
-      if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = L.at(par ^ 1, j, rn, xn);
-    hop_load_link<HOP, NE>(g, U, par, h + dep, hn, d);
+      if (gran_needed<MU, MINUS, S>(j)) d.sp[j] = L.at(EO ? 0 : par ^ 1, j, rn, xn);
+    hop_load_link<HOP, NE, LNT>(g, U, par, h + dep, hn, d);
   }
 }
 
-template <int I, int DEPTH, bool DAG, int NE, typename S, typename T>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, bool LNT, typename S, typename T>
 __device__ __forceinline__ void hop_pipe_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                              const PipeArgs& pa, int row, int xh, const LdsTile<S>& L,
                                              HopRaw<S, NE> (&buf)[DEPTH + 1], cx<T> (&a)[4][3]) {
@@ -576,21 +587,21 @@ __device__ __forceinline__ void hop_pipe_lds(const Geom& g, const S* __restrict_
     if constexpr (I + DEPTH + 1 < 8) {
       int dep = 0;
       asm volatile("" : "+v"(dep) : "v"(a[0][0].re));
-      hop_load_lds<I + DEPTH + 1, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, row, xh, L,
+      hop_load_lds<I + DEPTH + 1, DAG, NE, EO, LNT>(g, in, U, pa.par, pa.h, pa.c, row, xh, L,
                                            buf[(I + DEPTH + 1) % (DEPTH + 1)], dep);
     }
     QCD_FENCE();
-    hop_pipe_lds<I + 1, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf, a);
+    hop_pipe_lds<I + 1, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, row, xh, L, buf, a);
   }
 }
 
-template <int I, int DEPTH, bool DAG, int NE, typename S>
+template <int I, int DEPTH, bool DAG, int NE, bool EO, bool LNT, typename S>
 __device__ __forceinline__ void hop_prologue_lds(const Geom& g, const S* __restrict__ in, const S* __restrict__ U,
                                                  const PipeArgs& pa, int row, int xh, const LdsTile<S>& L,
                                                  HopRaw<S, NE> (&buf)[DEPTH + 1]) {
   if constexpr (I <= DEPTH) {
-    hop_load_lds<I, DAG, NE>(g, in, U, pa.par, pa.h, pa.c, row, xh, L, buf[I]);
-    hop_prologue_lds<I + 1, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf);
+    hop_load_lds<I, DAG, NE, EO, LNT>(g, in, U, pa.par, pa.h, pa.c, row, xh, L, buf[I]);
+    hop_prologue_lds<I + 1, DEPTH, DAG, NE, EO, LNT>(g, in, U, pa, row, xh, L, buf);
   }
 }
 
@@ -647,8 +658,8 @@ __global__ __launch_bounds__(256, 2) void k_dslash_lds(Geom g, DslashSched sched
   {
     HopRaw<S, NE> buf[DEPTH + 1];
     const PipeArgs pa{par, h, c};
-    hop_prologue_lds<0, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf);
-    hop_pipe_lds<0, DEPTH, DAG, NE>(g, in, U, pa, row, xh, L, buf, a);
+    hop_prologue_lds<0, DEPTH, DAG, NE, false, false>(g, in, U, pa, row, xh, L, buf);
+    hop_pipe_lds<0, DEPTH, DAG, NE, false, false>(g, in, U, pa, row, xh, L, buf, a);
   }
   const T_ k = (T_)kappa;
   S* ob = out + sp_block(g, par, h) + (h & 63) * C;
@@ -668,6 +679,85 @@ __global__ __launch_bounds__(256, 2) void k_dslash_lds(Geom g, DslashSched sched
     }
     store_stream(reinterpret_cast<Gr*>(ob + jj * 64 * C), v);
   }
+}
+
+// The one-parity operator of the even-odd form with the x and y neighbours in
+// LDS (one right-hand side per launch tile, every epilogue; variant 6).  A
+// block covers H = 256 half sites of the output parity, R = H / (Lx/2) whole
+// x rows at one (z, t); the input field (the other parity) is staged for
+// those rows and the rows y0 - 1 and y0 + R.  The centre term, the auxiliary
+// vectors, the links and the z and t neighbours come from global memory, as
+// in k_dslash.
+constexpr int kLdsEoEntries = 256 + 2 * kLdsMaxLxh;
+
+inline bool lds_eo_form_applies(const Geom& g) {
+  const int R = 256 / g.Lxh;
+  return g.Lxh <= kLdsMaxLxh && 256 % g.Lxh == 0 && g.L[1] % R == 0;
+}
+
+template <typename S, int OP, int EPI, int DEPTH, int NE>
+__global__ __launch_bounds__(256, 2) void k_dslash_lds_eo(Geom g, DslashSched sched, S* __restrict__ out,
+                                                          const S* __restrict__ in, const S* __restrict__ U,
+                                                          double kappa, const S* __restrict__ aux,
+                                                          double* __restrict__ partials,
+                                                          const Scalars* __restrict__ scal, int ftz,
+                                                          const S* __restrict__ cin, int tpar, int mask) {
+  using T_ = typename Traits<S>::T;
+  using Gr = typename Lay<S>::Gran;
+  constexpr int C = Lay<S>::C, G = Lay<S>::G;
+  constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
+  constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
+  constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
+  __shared__ Gr tile[G * kLdsEoEntries];
+  const BlockPos bp = block_pos(sched);
+  const int rhs = bp.tile;
+  if (scal && !scal_live(scal[rhs], mask)) return;  // the whole block belongs to one right-hand side
+  const int tid = threadIdx.x;
+  const int h = bp.h0 + tid;
+  const size_t vo = (size_t)rhs * (size_t)g.nb * 768;
+  in += vo;
+  out += vo;
+  if (aux) aux += vo;
+  if (cin) cin += vo;
+  const int lxh = g.Lxh, R = 256 / lxh, rows = R + 2;
+  const LdsTile<S> L{tile, rows, lxh};
+  const int row = tid / lxh + 1, xh = tid - (tid / lxh) * lxh;
+  const int y0 = (bp.h0 / lxh) % g.L[1];
+  const int pbase = bp.h0 - y0 * lxh;
+  {  // the input field on the block's rows (same half index, the other parity) ...
+    const S* b = in + sp_block(g, 0, h) + (h & 63) * C;
+#pragma unroll
+    for (int k = 0; k < G; k++) tile[(k * rows + row) * lxh + xh] = *reinterpret_cast<const Gr*>(b + k * 64 * C);
+  }
+  // ... and on the rows above and below
+  for (int k = tid; k < 2 * lxh * G; k += 256) {
+    const int jg = k % G, r1 = k / G;
+    const int xs = r1 % lxh, which = r1 / lxh;
+    const int yy = which ? (y0 + R) % g.L[1] : (y0 + g.L[1] - 1) % g.L[1];
+    const int hh = pbase + yy * lxh + xs;
+    tile[(jg * rows + (which ? R + 1 : 0)) * lxh + xs] =
+        *reinterpret_cast<const Gr*>(in + sp_block(g, 0, hh) + (hh & 63) * C + jg * 64 * C);
+  }
+  __syncthreads();
+  double red[NV];
+#pragma unroll
+  for (int i = 0; i < NV; i++) red[i] = 0.0;
+  {
+    const Coord c = decode(g, tpar, h);
+    cx<T_> a[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+      for (int cc = 0; cc < 3; cc++) a[sp][cc] = cx<T_>(0, 0);
+    {
+      HopRaw<S, NE> buf[DEPTH + 1];
+      const PipeArgs pa{tpar, h, c};
+      hop_prologue_lds<0, DEPTH, DAG, NE, true, true>(g, in, U, pa, row, xh, L, buf);
+      hop_pipe_lds<0, DEPTH, DAG, NE, true, true>(g, in, U, pa, row, xh, L, buf, a);
+    }
+    site_finish<S, OP, EPI, true, NV>(g, out, in, cin, aux, 0, h, kappa, ftz, a, red);
+  }
+  if constexpr (EPI != kEpiNone) block_reduce_store_T<NV, 1>(red, partials, rhs, sched.nsb, bp.sb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1252,6 +1342,22 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 }
 
 template <typename S, int NE>
+static void launch_dslash_lds_eo(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
+                                 const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
+                                 int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
+  const dim3 grid(sc.nsb * sc.ntiles), block(256);
+#define QCD_LDS_EO(OPV, EPIV)                                                                                    \
+  hipLaunchKernelGGL((k_dslash_lds_eo<S, OPV, EPIV, 1, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, \
+                     (const S*)U, kappa, (const S*)aux, partials, scal, ftz, (const S*)cin, eo_par, mask)
+  if (op == kOpH) QCD_LDS_EO(kOpH, kEpiNone);
+  else if (epi == kEpiNone) QCD_LDS_EO(kOpD, kEpiNone);
+  else if (epi == kEpiDotAux) QCD_LDS_EO(kOpD, kEpiDotAux);
+  else if (epi == kEpiTS) QCD_LDS_EO(kOpD, kEpiTS);
+  else QCD_LDS_EO(kOpD, kEpiResid);
+#undef QCD_LDS_EO
+}
+
+template <typename S, int NE>
 static void launch_dslash_lds(const Geom& g, const DslashSched& sc, int op, void* out, const void* in, const void* U,
                               double kappa, int ftz, hipStream_t st) {
   const dim3 grid(sc.nsb), block(256);
@@ -1277,6 +1383,12 @@ static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, in
     // full-lattice operator, one right-hand side)
     if (tune.variant == 6 && n == 1 && eo_par < 0 && epi == kEpiNone && !scal && lds_form_applies(g)) {
       launch_dslash_lds<S, NE>(g, sc, op, out, in, U, kappa, ftz, st);
+      return;
+    }
+    // and its one-parity form for the even-odd solvers (the epilogues they use)
+    if (tune.variant == 6 && eo_par >= 0 && epi != kEpiRecon && (op == kOpH || op == kOpD) &&
+        n == 1 && lds_eo_form_applies(g) && sc.H == 256) {
+      launch_dslash_lds_eo<S, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
       return;
     }
   }

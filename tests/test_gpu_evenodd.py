@@ -168,3 +168,73 @@ def test_even_odd_bicgstab_low_precision_several_sources(q, prec):
         assert res <= 20 * tol
     assert not np.any(xh[1])
     g.close()
+
+
+# Lattices where blocks of 256 half sites of one parity cover whole x rows, so
+# that the one-parity launches take the LDS-staged form (launch variant 6):
+# the y halo rows wrap onto the block's own rows when R = Ly and come from the
+# neighbouring block's rows otherwise; the XCD-slab schedules apply on the
+# second and third; (4, 6, 8, 10) takes the plain form under variant 6.
+LDS_EO_SHAPES = [(16, 64, 2, 4), (32, 32, 8, 2), (64, 16, 2, 8), (128, 4, 2, 2), (4, 6, 8, 10)]
+
+
+@pytest.mark.parametrize("dims", LDS_EO_SHAPES)
+@pytest.mark.parametrize("prec", [2, 3])
+def test_lds_staged_schur_operator(q, dims, prec):
+    # the Schur operator (two one-parity launches, the intermediate rounded to
+    # storage) with variant 6 against variant 1, element by element, and
+    # against the oracle: the hops are the same products in the same order,
+    # so the two differ only where the compiler fuses an FP32 sum differently
+    # (a unit of the storage format, which the second hop can carry into a
+    # second unit)
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 760 + sum(dims))
+    psi = qi.gaussian_source(dims, 761)
+    e = EO.even_mask(dims)
+    want = EO.schur(U, psi, kappa, dims)
+    g = q.gauge_upload(to_dev(U), dims, precs=(q.FP64, prec))
+    unit = 2.0 ** -10 if prec == 2 else 2.0 ** -7
+    ref = torch.empty(psi.shape, dtype=torch.complex128, device="cuda")
+    got = torch.empty_like(ref)
+    for sched in (0, 1, 4):
+        g.set_tuning(prec, sched, 1, 1)
+        q.dslash(g, kappa, ref, to_dev(psi), op=q.OP_SCHUR, prec=prec)
+        g.set_tuning(prec, sched, 6, 1)
+        q.dslash(g, kappa, got, to_dev(psi), op=q.OP_SCHUR, prec=prec)
+        torch.cuda.synchronize()
+        r, v = to_host(ref).reshape(-1), to_host(got).reshape(-1)
+        for part in (np.real, np.imag):
+            d = np.abs(part(v) - part(r))
+            assert np.all(d <= 2 * unit * np.abs(part(r)) + 1e-30), (dims, prec, sched, d.max())
+        assert np.mean(r != v) <= 1e-2, (dims, prec, sched, np.mean(r != v))
+        gv = to_host(got)
+        assert not np.any(gv[~e])
+        compare(gv[e], want[e], TOL[prec], f"lds schur dims={dims} prec={prec} sched={sched}")
+    g.close()
+
+
+def test_lds_staged_even_odd_refinement(q):
+    # the FP16-inner even-odd refinement on a lattice where its one-parity
+    # launches take the LDS form, against the oracle's x* and against the
+    # plain launches (iteration counts within one of each other)
+    dims = (32, 32, 8, 2)
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 770)
+    bs = qi.gaussian_source(dims, 771)
+    x_ref, _ = EO.solve_fp64(U, kappa, dims, bs, tol=1e-13)
+    g = q.gauge_upload(to_dev(U), dims)
+    b = to_dev(bs)
+    iters = {}
+    for var in (1, 6):
+        g.set_tuning(q.FP16, 1, var, 1)
+        for graph in (False, True):
+            x = torch.zeros_like(b)
+            info = q.solve_mixed_ir(g, kappa, x, b, inner_prec=q.FP16, tol=1e-12, inner_tol=1e-3, even_odd=True,
+                                    use_graph=graph)
+            assert info.status == "ok" and info.true_rel_residual <= 1e-12, (var, graph, info)
+            xh = to_host(x)
+            assert np.linalg.norm(xh - x_ref) <= 1e-10 * np.linalg.norm(x_ref), (var, graph)
+            iters[(var, graph)] = info.inner_iters
+    assert abs(iters[(6, False)] - iters[(1, False)]) <= 1, iters
+    assert iters[(6, True)] == iters[(6, False)], iters
+    g.close()
