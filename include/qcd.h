@@ -166,9 +166,12 @@ int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
  * variant 0..5 selects how many hops' loads are prefetched while one hop is
  * computed and the minimum waves per SIMD the kernel is compiled for:
  * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4), and 6:
- * the x and y neighbour spinors staged once per block in LDS (FP16 and BF16,
- * the plain operator on full fields with one right-hand side when blocks of
- * 128 half sites cover whole x rows; otherwise as 1).
+ * the x and y neighbour spinors staged once per block in LDS, in the plain
+ * operator on full fields (FP16 and BF16, when blocks of 128 half sites per
+ * parity cover whole x rows) and in the one-parity launches of the even-odd
+ * solvers (every precision, when blocks of 256 half sites cover whole x rows;
+ * x extent at most 128, 64 for FP64), one right-hand side per launch tile;
+ * otherwise as 1; 7: the same LDS forms, otherwise as 0.
  * rhs_tile (0 = automatic, 1, 2, 4) is the number of right-hand sides whose
  * lanes share one wave's link loads in a multi-RHS application, -2, -3, -4 the
  * number a thread applies one loaded link to (it must divide nrhs, else 1 is

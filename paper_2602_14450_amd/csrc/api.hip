@@ -585,12 +585,14 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
       return src;
     }
   }
-  // defaults measured on MI355X at 32^3 x 64 with rotating buffers (the tuner
-  // may override them): z slabs per XCD; prefetch 2 hops at 2 waves per SIMD
-  // (FP32; FP16 with its x and y neighbours staged in LDS where the plain
-  // full-lattice operator allows it, else the same), 1 hop at 2 (FP64)
+  // defaults measured on MI355X at 32^3 x 64 with rotating buffers and in the
+  // even-odd solves (the tuner may override them): z slabs per XCD; prefetch 2
+  // hops at 2 waves per SIMD (FP16 and FP32 with their x and y neighbours
+  // staged in LDS where the form applies: FP16 in the full-lattice and the
+  // one-parity launches, FP32 in the one-parity ones), 1 hop at 2 (FP64, whose
+  // LDS form measured no faster)
   g->tune[kFP64] = DslashTune{1, 0, 0, 0};
-  g->tune[kFP32] = DslashTune{1, 1, 0, 0};
+  g->tune[kFP32] = DslashTune{1, 6, 0, 0};
   g->tune[kFP16] = DslashTune{1, 6, 0, 0};
   g->tune[kBF16] = DslashTune{1, 1, 0, 0};
   memcpy(g->dims, dims, sizeof g->dims);

@@ -688,11 +688,16 @@ __global__ __launch_bounds__(256, 2) void k_dslash_lds(Geom g, DslashSched sched
 // those rows and the rows y0 - 1 and y0 + R.  The centre term, the auxiliary
 // vectors, the links and the z and t neighbours come from global memory, as
 // in k_dslash.
-constexpr int kLdsEoEntries = 256 + 2 * kLdsMaxLxh;
+// Rows of at most 64 half sites (32 for FP64 spinors, which keeps the tile
+// within 64 KB: 320 x 192 B).
+template <typename S> struct LdsEo {
+  static constexpr int kMaxLxh = Lay<S>::G > 6 ? 32 : 64;
+  static constexpr int kEntries = 256 + 2 * kMaxLxh;
+};
 
-inline bool lds_eo_form_applies(const Geom& g) {
+template <typename S> inline bool lds_eo_form_applies(const Geom& g) {
   const int R = 256 / g.Lxh;
-  return g.Lxh <= kLdsMaxLxh && 256 % g.Lxh == 0 && g.L[1] % R == 0;
+  return g.Lxh <= LdsEo<S>::kMaxLxh && 256 % g.Lxh == 0 && g.L[1] % R == 0;
 }
 
 template <typename S, int OP, int EPI, int DEPTH, int NE>
@@ -708,7 +713,7 @@ __global__ __launch_bounds__(256, 2) void k_dslash_lds_eo(Geom g, DslashSched sc
   constexpr bool DAG = (OP == kOpDdag || OP == kOpHdag);
   constexpr bool TS = (EPI == kEpiTS || EPI == kEpiTSAux);
   constexpr int NV = (EPI == kEpiNone) ? 1 : (EPI == kEpiDotAux ? 2 : (TS ? 4 : 1));
-  __shared__ Gr tile[G * kLdsEoEntries];
+  __shared__ Gr tile[G * LdsEo<S>::kEntries];
   const BlockPos bp = block_pos(sched);
   const int rhs = bp.tile;
   if (scal && !scal_live(scal[rhs], mask)) return;  // the whole block belongs to one right-hand side
@@ -1378,16 +1383,19 @@ static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, in
                                const void* in, const void* U, double kappa, const void* aux, double* partials,
                                const Scalars* scal, int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   const DslashSched sc = make_sched(g, tune.sched, T, n, eo_par >= 0);
-  if constexpr (T == 1 && sizeof(S) == 4) {
-    // variant 6: x and y neighbours staged in LDS (16-bit storage: 24 KB per block; plain
-    // full-lattice operator, one right-hand side)
-    if (tune.variant == 6 && n == 1 && eo_par < 0 && epi == kEpiNone && !scal && lds_form_applies(g)) {
-      launch_dslash_lds<S, NE>(g, sc, op, out, in, U, kappa, ftz, st);
-      return;
+  if constexpr (T == 1) {
+    const bool lds = tune.variant == 6 || tune.variant == 7;
+    // variants 6 and 7: x and y neighbours staged in LDS; the full-lattice form
+    // (16-bit storage: 24 KB per block; plain operator, one right-hand side) ...
+    if constexpr (sizeof(S) == 4) {
+      if (lds && n == 1 && eo_par < 0 && epi == kEpiNone && !scal && lds_form_applies(g)) {
+        launch_dslash_lds<S, NE>(g, sc, op, out, in, U, kappa, ftz, st);
+        return;
+      }
     }
-    // and its one-parity form for the even-odd solvers (the epilogues they use)
-    if (tune.variant == 6 && eo_par >= 0 && epi != kEpiRecon && (op == kOpH || op == kOpD) &&
-        n == 1 && lds_eo_form_applies(g) && sc.H == 256) {
+    // ... and the one-parity form for the even-odd solvers (the epilogues they use)
+    if (lds && eo_par >= 0 && epi != kEpiRecon && (op == kOpH || op == kOpD) && n == 1 &&
+        lds_eo_form_applies<S>(g) && sc.H == 256) {
       launch_dslash_lds_eo<S, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
       return;
     }

@@ -86,13 +86,14 @@ struct DslashTune {
                 // 4: XCD t slabs swept in z order
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
                 // (prefetching 2 hops at 5 waves spills registers and measured slower in every precision);
-                // 6: x and y neighbours staged in LDS (FP16 / BF16 plain full-lattice operator; else as 1)
+                // 6: x and y neighbours staged in LDS (the FP16 / BF16 plain full-lattice operator and the
+                // one-parity launches of every precision, one right-hand side; else as 1); 7: as 6, else as 0
   int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
                 // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers);
                 // 8 = the matrix-core form (kRhsTileMfma)
   int recon;    // links stored as 6 entries (rows 0, 1; row 2 rebuilt) instead of 9: a property of the data
 };
-constexpr int kDslashVariants = 7;
+constexpr int kDslashVariants = 8;
 // rhs_tile code of the matrix-core form (FP16 storage, plain operator; 4, 6, 8, 12 or 16 right-hand sides per tile)
 constexpr int kRhsTileMfma = 8;
 // right-hand sides per matrix-core tile for n right-hand sides (0: the form does not apply)
