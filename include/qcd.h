@@ -84,8 +84,10 @@ typedef struct {
   int recalc_gamma;    /* 1: gamma is the measured ratio |r stored| / |r before rescaling| */
   double omega0;       /* omega prescription threshold; the paper uses 0.7; 0 disables */
   int ftz;             /* 1: a binary16 store below 2^-14 (BF16: 2^-126) in magnitude is flushed to zero */
-  int check_every;     /* > 0: host polls the convergence flag every this many iterations; 0: adaptive
-                          (first poll after 4, then after the number the convergence rate predicts) */
+  int check_every;     /* > 0: host polls the convergence flag every this many iterations (and, in
+                          qcd_solve_mixed_ir, drives each refinement step itself); 0: adaptive (qcd_bicgstab:
+                          first poll after 4, then after the number the convergence rate predicts;
+                          qcd_solve_mixed_ir: the steps run from the device, see there) */
   int use_graph;       /* 1: one iteration is captured in a hip graph (on a stream the handle owns) and
                           replayed; results are identical to plain launches */
   int even_odd;        /* 1: solve the even-odd preconditioned system of eq. (4)-(6) (the paper's form):
@@ -266,7 +268,14 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
  * b_dev, x_dev canonical complex128.  nrhs right-hand sides are solved
  * together: every kernel handles all of them, each with its own scalars,
  * and a right-hand side that has met the tolerance is skipped by the kernels
- * (per-right-hand-side masks).  Returns (the worst over right-hand sides)
+ * (per-right-hand-side masks).  With p->inner.check_every = 0 and no network
+ * or inner history, the refinement steps run from the device: the host
+ * queues blocks of inner iterations, each followed by the kernels of one
+ * refinement step that act only for right-hand sides whose inner solve has
+ * stopped, and polls after as many blocks as the convergence so far predicts
+ * (the first poll's block sizes come from the handle's previous such call
+ * with the same tolerances); results are bit for bit those of host-driven
+ * steps (check_every > 0).  Returns (the worst over right-hand sides)
  * QCD_OK when the FP64 true residual reaches tol, QCD_NOT_CONVERGED after
  * max_outer steps (x valid), QCD_ERR_NONFINITE / QCD_ERR_BREAKDOWN if an
  * inner solve failed before any progress.  Synchronises. */

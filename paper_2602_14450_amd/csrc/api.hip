@@ -357,22 +357,18 @@ void device_step(const qcd_gauge* g, double kappa, const Work& w, const qcd_ir_p
   launch_convert_finish(w.n, w.sc, w.partials, site_grid(G), p->recalc_shat, p->s, st);
 }
 
-// Iterations of the device-driven refinement captured with one device step.
-constexpr int kStepGraphIters = 4;
-
-// Capture one iteration (8 kernels), or (dev_p given) kStepGraphIters
-// iterations followed by the device step, into a hip graph.  Capture runs on
-// the handle's own stream (the null stream cannot be captured); the graph is
-// launched on the caller's stream.  The kernels take every changing value
-// from device memory, so one capture serves every iteration (and step).
+// Capture one iteration (8 kernels, 14 with the network) into a hip graph.
+// Capture runs on the handle's own stream (the null stream cannot be
+// captured); the graph is launched on the caller's stream.  The kernels take
+// every changing value from device memory, so one capture serves every
+// iteration.
 qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Work& w, int ftz, const Precond& pc,
-                           hipGraphExec_t* out, const qcd_ir_params* dev_p = nullptr) {
+                           hipGraphExec_t* out) {
   qcd_gauge* g = const_cast<qcd_gauge*>(gc);
-  unsigned long long kbits, sbits64 = 0;
+  unsigned long long kbits;
   memcpy(&kbits, &kappa, sizeof kbits);
   unsigned sbits;
   memcpy(&sbits, &pc.scale, sizeof sbits);
-  if (dev_p) memcpy(&sbits64, &dev_p->s, sizeof sbits64);
   // Everything the captured launches bake in: the scalar parameters, the launch
   // shape, and the address of every workspace region they read or write (the
   // regions move when max_iter or nrhs changes the carve of one workspace).
@@ -389,13 +385,7 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
                                       u(pc.net), pc.net ? sbits : 0ull, u(w.x), u(w.r), u(w.rstar), u(w.p), u(w.v),
                                       u(w.t), u(w.z), u(w.t1), u(w.partials), u(w.sc), u(w.history),
                                       (unsigned long long)w.hist_stride, u(w.sums), u(w.scale),
-                                      (unsigned long long)w.bytes,
-                                      dev_p ? (1ull | ((unsigned long long)dev_p->recalc_shat << 1) |
-                                               ((unsigned long long)dev_p->inner_prec << 2) |
-                                               ((unsigned long long)dev_p->inner.ftz << 8))
-                                            : 0ull,
-                                      sbits64, u(w.x64), u(w.r64), u(w.b64), u(w.bp64), u(w.t64), u(w.outer_log),
-                                      0ull};
+                                      (unsigned long long)w.bytes};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
     return QCD_OK;
@@ -406,12 +396,7 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
   }
   hipGraph_t graph;
   HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
-  if (dev_p) {
-    for (int k = 0; k < kStepGraphIters; k++) bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
-    device_step(g, kappa, w, dev_p, g->cap_stream);
-  } else {
-    bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
-  }
+  bicg_iteration(g, prec, kappa, w, ftz, pc, g->cap_stream);
   hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
   if (e != hipSuccess) return fail(QCD_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&g->graph_exec, graph, nullptr, nullptr, 0);
@@ -1295,12 +1280,20 @@ qcd_status ir_finish(IrRun& R, double t0) {
   return res;
 }
 
-// The refinement with its steps run from the device (graph replay): after the
-// first step's conversion, each lattice replays a graph of kStepGraphIters
-// inner iterations and one device step; a right-hand side whose inner solve
-// stopped gets its correction, FP64 residual, stop test and next start in
-// that step, so one host poll serves several refinement steps.  The host
-// reads the device's step counts, stop reasons and log at the end.
+// The refinement with its steps run from the device: after the first step's
+// conversion, each lattice is queued blocks of K inner iterations (replayed
+// one-iteration graphs with use_graph, else direct launches) followed by one
+// device step; a right-hand side whose inner solve stopped gets its
+// correction, FP64 residual, stop test and next start in the first device
+// step after it, and the kernels of everything else return at once.  The
+// host polls after a number of blocks: K follows the inner iterations per
+// refinement step seen so far (an iteration queued past an inner stop, or a
+// device step queued before one, costs a few microseconds per launch), and
+// the blocks per poll the steps that the residual reduction so far predicts
+// to remain (a poll costs a host round trip with the GPU idle).  The first
+// poll's K and blocks come from the handle's previous device-driven solve
+// with the same tolerances and inner precision, else 4 and 2.  The host reads
+// the device's step counts, stop reasons and log at the end.
 qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream_t st) {
   qcd_status rc;
   std::vector<IrRun*> act;
@@ -1325,22 +1318,31 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
   std::vector<hipGraphExec_t> gexec(nact, nullptr);
   std::vector<hipStream_t> rs(nact, st);
   std::vector<InnerRun> ir;
+  const double hkey[4] = {p->tol, p->inner.tol, (double)p->inner_prec, (double)p->inner.even_odd};
+  int K = 0, blocks = 0;
   for (int a = 0; a < nact; a++) {
     IrRun& R = *act[a];
-    if ((rc = iteration_graph(R.g, p->inner_prec, R.kappa, R.w, p->inner.ftz, Precond{}, &gexec[a], p))) return rc;
+    if (p->inner.use_graph &&
+        (rc = iteration_graph(R.g, p->inner_prec, R.kappa, R.w, p->inner.ftz, Precond{}, &gexec[a])))
+      return rc;
     if (nact > 1) rs[a] = R.g->cap_stream;
     ir.push_back(InnerRun{R.g, p->inner_prec, R.kappa, &R.w, Precond{}});
+    if (!memcmp(R.g->hint_key, hkey, sizeof hkey)) {
+      K = std::max(K, R.g->hint_iters);
+      blocks = std::max(blocks, R.g->hint_steps);
+    }
+  }
+  if (K <= 0 || blocks <= 0) {
+    K = 4;
+    blocks = 2;
   }
   auto refining = [](const IrRun& R) {
     for (int i = 0; i < R.n; i++)
       if (R.g->host_sc[i].outer_active) return true;
     return false;
   };
-  // graph launches between polls: two at first, then about two refinement
-  // steps' worth of iterations as observed so far
-  int per_poll = 2;
   long launched = 0;
-  const long cap = (long)p->max_outer * (p->inner.max_iter / kStepGraphIters + 2) + 4;
+  const long cap = (long)p->max_outer * ((long)p->inner.max_iter + 2) + 8;
   while (nact > 0) {
     bool any = false;
     if (nact > 1) HIP_TRY(hipEventRecord(act[0]->g->ev_fork, st));
@@ -1349,25 +1351,61 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
       if (!refining(R)) continue;
       any = true;
       if (nact > 1) HIP_TRY(hipStreamWaitEvent(rs[a], act[0]->g->ev_fork, 0));
-      for (int j = 0; j < per_poll; j++) HIP_TRY(hipGraphLaunch(gexec[a], rs[a]));
+      for (int b = 0; b < blocks; b++) {
+        for (int j = 0; j < K; j++) {
+          if (gexec[a])
+            HIP_TRY(hipGraphLaunch(gexec[a], rs[a]));
+          else
+            bicg_iteration(R.g, p->inner_prec, R.kappa, R.w, p->inner.ftz, Precond{}, rs[a]);
+        }
+        device_step(R.g, R.kappa, R.w, p, rs[a]);
+      }
       if (nact > 1) {
         HIP_TRY(hipEventRecord(R.g->ev_done, rs[a]));
         HIP_TRY(hipStreamWaitEvent(st, R.g->ev_done, 0));
       }
     }
     if (!any) break;
-    launched += per_poll;
+    HIP_LAUNCHED();
+    launched += (long)blocks * K;
     if ((rc = read_scalars_all(ir.data(), nact, st))) return rc;
     if (launched > cap) break;
-    long it = 0, steps = 0;
+    int kn = 1, rem = 1;
     for (int a = 0; a < nact; a++)
       for (int i = 0; i < act[a]->n; i++) {
         const Scalars& h = act[a]->g->host_sc[i];
-        it += h.inner_total + h.iter;
-        steps += h.outer_count + 1;
+        if (!h.outer_active) continue;
+        if (h.outer_count > 0) {
+          kn = std::max(kn, (h.inner_total + h.outer_count - 1) / h.outer_count);
+          // steps still needed at the mean reduction per step so far
+          const double rel = h.out_rnorm / h.out_bnorm, goal = h.out_tol;
+          const double rate = std::pow(rel, 1.0 / h.outer_count);
+          int need = 2;
+          if (rel > goal && rate > 0.0 && rate < 0.999)
+            need = (int)std::min(64.0, std::max(1.0, std::ceil(std::log(goal / rel) / std::log(rate))));
+          rem = std::max(rem, need);
+        } else {
+          kn = std::max(kn, h.iter + 1);  // the first inner solve runs on
+          rem = std::max(rem, 2);
+        }
       }
-    const double per_step = steps > 0 ? (double)it / steps : 8.0;
-    per_poll = (int)std::min(64.0, std::max(1.0, std::ceil(2.0 * (per_step + 1.0) / kStepGraphIters)));
+    K = std::min(64, kn);
+    blocks = rem;
+  }
+  // the hint for the next device-driven solve on each handle
+  for (int a = 0; a < nact; a++) {
+    IrRun& R = *act[a];
+    qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
+    int it = 0, st_max = 0;
+    for (int i = 0; i < R.n; i++) {
+      const Scalars& h = g->host_sc[i];
+      if (h.outer_count <= 0) continue;
+      st_max = std::max(st_max, h.outer_count);
+      it = std::max(it, (h.inner_total + h.outer_count - 1) / h.outer_count);
+    }
+    g->hint_iters = std::min(64, it);
+    g->hint_steps = std::min(64, st_max);
+    memcpy(g->hint_key, hkey, sizeof hkey);
   }
   // the device's bookkeeping
   std::vector<double> log;
@@ -1420,10 +1458,11 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
     ir_after_start(runs[r]);
     if (runs[r].w.eo && (rc = ir_eo_scale_tol(runs[r], p, st))) return rc;
   }
-  // with graph replay the steps run from the device, unless a network (whose
-  // step may be undone from the host), per-step inner histories or more steps
-  // than the device log holds are asked for
-  bool dev = p->inner.use_graph && p->max_outer <= kOuterLog;
+  // the steps run from the device unless the host is asked to poll every
+  // check_every iterations, or a network (whose step may be undone from the
+  // host), per-step inner histories or more steps than the device log holds
+  // are asked for
+  bool dev = p->inner.check_every <= 0 && p->max_outer <= kOuterLog;
   for (int r = 0; r < nrun; r++) {
     if (runs[r].net) dev = false;
     if (runs[r].info)

@@ -203,5 +203,9 @@ struct qcd_gauge {
   hipGraphExec_t graph_exec;
   unsigned long long graph_key[32];
   double su3_dev;  // largest |row2 - conj(row0 x row1)| of the uploaded links (INFINITY if not checked)
+  // what the last device-driven refinement on this handle took (inner iterations
+  // per step, steps), with the parameters it ran with; a scheduling hint only
+  int hint_iters, hint_steps;
+  double hint_key[4];
 };
 

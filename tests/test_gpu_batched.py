@@ -239,25 +239,31 @@ def test_graph_replays_match_eager(q, c1b):
 
 @pytest.mark.parametrize("eo", [False, True])
 def test_device_driven_steps_match_host_driven(q, c1b, eo):
-    # with graph replay the refinement steps run from the device (a graph of
-    # inner iterations and one step, replayed between host polls); solutions,
-    # counts, the per-step residual and zero-count logs and s^/s are the
-    # host-driven refinement's, bit for bit (sources: normal, small, zero)
+    # by default the refinement steps run from the device (blocks of inner
+    # iterations, each followed by one step's kernels, polled as the
+    # convergence predicts; with graph replay or plain launches); with
+    # check_every the host drives every step.  Solutions, counts, the
+    # per-step residual and zero-count logs and s^/s are the same bit for bit
+    # (sources: normal, small, zero), also on a repeated call, whose first
+    # poll comes after the blocks the previous call saw
     g, k = c1b["g"], c1b["k"]
     b = to_dev(c1b["b"])
-    xh, xd = torch.zeros_like(b), torch.zeros_like(b)
-    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo)
-    idv = q.solve_mixed_ir(g, k, xd, b, use_graph=True, even_odd=eo)
-    torch.cuda.synchronize()
-    assert torch.equal(xh, xd)
-    for a, d in zip(ih, idv):
-        assert (a.status, a.outer_iters, a.inner_iters, a.matvec_low, a.matvec_fp64) == \
-               (d.status, d.outer_iters, d.inner_iters, d.matvec_low, d.matvec_fp64)
-        assert a.outer_history == d.outer_history and a.zeros == d.zeros
-        assert a.first_shat_over_s == d.first_shat_over_s and a.true_rel_residual == d.true_rel_residual
+    xh = torch.zeros_like(b)
+    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo, check_every=4)
+    for graph in (True, False, False):
+        xd = torch.zeros_like(b)
+        idv = q.solve_mixed_ir(g, k, xd, b, use_graph=graph, even_odd=eo)
+        torch.cuda.synchronize()
+        assert torch.equal(xh, xd), graph
+        for a, d in zip(ih, idv):
+            assert (a.status, a.outer_iters, a.inner_iters, a.matvec_low, a.matvec_fp64) == \
+                   (d.status, d.outer_iters, d.inner_iters, d.matvec_low, d.matvec_fp64)
+            assert a.outer_history == d.outer_history and a.zeros == d.zeros
+            assert a.first_shat_over_s == d.first_shat_over_s and a.true_rel_residual == d.true_rel_residual
     # a step cap ends both forms at the same x, reported as not converged
     xh, xd = torch.zeros_like(b), torch.zeros_like(b)
-    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo, max_outer=2, raise_on_error=False)
+    ih = q.solve_mixed_ir(g, k, xh, b, use_graph=False, even_odd=eo, max_outer=2, raise_on_error=False,
+                          check_every=4)
     idv = q.solve_mixed_ir(g, k, xd, b, use_graph=True, even_odd=eo, max_outer=2, raise_on_error=False)
     torch.cuda.synchronize()
     assert torch.equal(xh, xd)
