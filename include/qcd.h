@@ -268,8 +268,9 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
  * b_dev, x_dev canonical complex128.  nrhs right-hand sides are solved
  * together: every kernel handles all of them, each with its own scalars,
  * and a right-hand side that has met the tolerance is skipped by the kernels
- * (per-right-hand-side masks).  With p->inner.check_every = 0 and no network
- * or inner history, the refinement steps run from the device: the host
+ * (per-right-hand-side masks).  With p->inner.check_every = 0, no network or
+ * inner history and max_outer <= 128, the refinement steps run from the
+ * device: the host
  * queues blocks of inner iterations, each followed by the kernels of one
  * refinement step that act only for right-hand sides whose inner solve has
  * stopped, and polls after as many blocks as the convergence so far predicts

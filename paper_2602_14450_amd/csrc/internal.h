@@ -78,7 +78,7 @@ struct Scalars {
   double pad[1];
 };
 // refinement steps whose |r| and zero count the device-driven refinement logs per right-hand side
-constexpr int kOuterLog = 64;
+constexpr int kOuterLog = 128;
 
 // Launch choices of the Wilson operator (picked by the tuner).
 struct DslashTune {
