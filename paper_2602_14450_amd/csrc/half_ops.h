@@ -15,13 +15,16 @@ __device__ __forceinline__ h2v h_swap(h2v x) { return h2v{x.y, x.x}; }     // (i
 __device__ __forceinline__ h2v h_muli(h2v x) { return h2v{-x.y, x.x}; }    // i x
 __device__ __forceinline__ float hdot(h2v a, h2v b, float c) { return __builtin_amdgcn_fdot2(a, b, c, false); }
 
-// conj(x y - z w) from binary16 entries: exact products, FP32 sums, one
-// round-to-nearest-even conversion back to binary16
+// conj(x y - z w) = conj(x) conj(y) - conj(z) conj(w) in packed binary16
+// arithmetic (one multiply and three fused multiply-adds on (re, im) pairs,
+// each rounded to binary16, as the paper's FP16 arithmetic): the lane halves
+// of x and z are broadcast and the swaps and signs of y and w fold into the
+// instructions' operand selects and negations
 __device__ __forceinline__ h2v h_rebuild(h2v x, h2v y, h2v z, h2v w) {
-  const h2v zn = -z;
-  const float re = hdot(zn, h_conjv(w), hdot(x, h_conjv(y), 0.0f));
-  const float im = hdot(zn, h_swap(w), hdot(x, h_swap(y), 0.0f));
-  return h2v{(_Float16)re, (_Float16)(-im)};
+  h2v c = h2v{x.x, x.x} * h_conjv(y);                                  // (xr yr, -xr yi)
+  c = __builtin_elementwise_fma(h2v{x.y, x.y}, -h_swap(y), c);          // conj(x y)
+  c = __builtin_elementwise_fma(-h2v{z.x, z.x}, h_conjv(w), c);
+  return __builtin_elementwise_fma(h2v{z.y, z.y}, h_swap(w), c);       // - conj(z w)
 }
 // row 2 = conj(row0 x row1), as su3_third_row
 __device__ __forceinline__ void h_third_row(h2v (&u)[9]) {
