@@ -23,7 +23,8 @@
  * Gamma matrices: the Dirac basis whose gamma_1 is the one printed in Sec. 2
  *   (gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = diag(1,1,-1,-1)).
  * Pointers named *_dev are device pointers; the caller owns all device
- *   memory passed in.  `stream` is a hipStream_t (NULL = default stream).
+ *   memory passed in.  Canonical complex128 fields must be 16-byte aligned
+ *   (QCD_ERR_ARG otherwise).  `stream` is a hipStream_t (NULL = default stream).
  * Several right-hand sides: calls taking nrhs (1..64) expect nrhs fields
  *   back to back (canonical: [rhs][site][spin][colour]; native: nrhs native
  *   fields of qcd_spinor_bytes() each); per-right-hand-side outputs (norms,

@@ -201,6 +201,13 @@ qcd_status check_nrhs(int n) {
   return QCD_OK;
 }
 
+// Canonical complex128 fields are read and written one complex (16 bytes) per access.
+qcd_status check_canonical(const void* p, const char* what) {
+  if (!p) return fail(QCD_ERR_ARG, "null %s", what);
+  if ((uintptr_t)p & 15) return fail(QCD_ERR_ARG, "%s is not 16-byte aligned (complex128)", what);
+  return QCD_OK;
+}
+
 qcd_status read_scalars(const qcd_gauge* g, const Work& w, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(g->host_sc, w.sc, sizeof(Scalars) * w.n, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -317,9 +324,11 @@ void eo_setup(const qcd_gauge* g, double kappa, const Work& w, const void* b_dev
 }
 // x_o = eta_o + kappa H_oe x_e, the canonical solution, and |b - D x|^2 of the
 // full system per right-hand side in r2 (synchronises): the odd rows come from
-// the reconstruction launch itself, the even rows eta_e - (x_e - kappa H_eo x_o)
-// from one more one-parity launch (residual vector left in r64).
-qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_dev, double* r2, hipStream_t st) {
+// the reconstruction launch itself; with even_rows the even rows eta_e - (x_e -
+// kappa H_eo x_o) from one more one-parity launch (residual vector left in
+// r64), else r2 holds the odd rows only (the caller adds the even rows it has).
+qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_dev, double* r2, hipStream_t st,
+                     bool even_rows = true) {
   const Geom& G = g->g;
   const int n = w.n;
   DslashTune one = g->tune[kFP64];
@@ -329,16 +338,17 @@ qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_de
   double* pe = w.partials + (size_t)n * rows_o;
   launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiRecon, n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr, po,
                 nullptr, 0, st, w.eta_o, 1);
-  launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
-                nullptr, 0, st, w.x64, 0);
+  if (even_rows)
+    launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
+                  nullptr, 0, st, w.x64, 0);
   launch_unpack_spinor_split(G, n, (double*)x_dev, w.x64, w.x64o, st);
   launch_finish_sum(n, po, rows_o, 1, w.sums, st);
-  launch_finish_sum(n, pe, rows_e, 1, w.sums + n, st);
+  if (even_rows) launch_finish_sum(n, pe, rows_e, 1, w.sums + n, st);
   HIP_LAUNCHED();
   double h[2 * kMaxRhs];
-  HIP_TRY(hipMemcpyAsync(h, w.sums, 2 * n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h, w.sums, (even_rows ? 2 : 1) * n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  for (int i = 0; i < n; i++) r2[i] = h[i] + h[n + i];
+  for (int i = 0; i < n; i++) r2[i] = h[i] + (even_rows ? h[n + i] : 0.0);
   return QCD_OK;
 }
 
@@ -619,6 +629,9 @@ qcd_status qcd_gauge_upload(qcd_gauge** out, const int dims[4], const void* U_de
   }
   if (rc == QCD_OK && hipHostMalloc((void**)&g->host_sc, sizeof(Scalars) * kMaxRhs, 0) != hipSuccess)
     rc = fail(QCD_ERR_HIP, "hipHostMalloc failed");
+  if (rc == QCD_OK &&
+      hipHostMalloc((void**)&g->host_log, sizeof(double) * 2 * kOuterLog * kMaxRhs, 0) != hipSuccess)
+    rc = fail(QCD_ERR_HIP, "hipHostMalloc failed");
   // the handle's stream (graph capture, batched solves) and its two events:
   // created here so that no solve creates HIP objects
   if (rc == QCD_OK && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -641,6 +654,7 @@ qcd_status qcd_gauge_free(qcd_gauge* g) {
     if (g->U[p]) (void)hipFree(g->U[p]);
   if (g->ws) (void)hipFree(g->ws);
   if (g->host_sc) (void)hipHostFree(g->host_sc);
+  if (g->host_log) (void)hipHostFree(g->host_log);
   if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
   if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   if (g->ev_fork) (void)hipEventDestroy(g->ev_fork);
@@ -800,6 +814,7 @@ qcd_status qcd_convert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* native
   if (rc) return rc;
   if ((rc = check_nrhs(nrhs))) return rc;
   if (!valid_prec(prec) || !native_dev || !canonical_dev) return fail(QCD_ERR_ARG, "invalid argument");
+  if ((rc = check_canonical(canonical_dev, "canonical field"))) return rc;
   hipStream_t st = S(stream);
   Work w;
   if (norm2) {
@@ -819,6 +834,7 @@ qcd_status qcd_unconvert(const qcd_gauge* g, qcd_prec prec, int nrhs, void* cano
   if (rc) return rc;
   if ((rc = check_nrhs(nrhs))) return rc;
   if (!valid_prec(prec) || !native_dev || !canonical_dev) return fail(QCD_ERR_ARG, "invalid argument");
+  if ((rc = check_canonical(canonical_dev, "canonical field"))) return rc;
   launch_unpack_spinor(g->g, prec, nrhs, (double*)canonical_dev, native_dev, nullptr, scale, S(stream));
   HIP_LAUNCHED();
   return QCD_OK;
@@ -840,6 +856,9 @@ qcd_status qcd_dslash(const qcd_gauge* g, double kappa, qcd_op op, qcd_prec prec
   if (!out_dev || !in_dev || out_dev == in_dev) return fail(QCD_ERR_ARG, "out and in must be distinct non-null buffers");
   if (op < QCD_OP_D || op > QCD_OP_SCHUR) return fail(QCD_ERR_ARG, "invalid op %d", (int)op);
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
+  if (layout == QCD_LAYOUT_CANONICAL &&
+      ((rc = check_canonical(out_dev, "out")) || (rc = check_canonical(in_dev, "in"))))
+    return rc;
   hipStream_t st = S(stream);
   if (op == QCD_OP_SCHUR) {
     // out_e = in_e - kappa^2 H_eo H_oe in_e, out_o = 0; the odd half of out holds H_oe in_e meanwhile
@@ -893,6 +912,8 @@ qcd_status qcd_residual(const qcd_gauge* g, double kappa, int nrhs, void* r_dev,
   if (rc) return rc;
   if ((rc = check_nrhs(nrhs))) return rc;
   if (!r_dev || !x_dev || !b_dev) return fail(QCD_ERR_ARG, "null argument");
+  if ((rc = check_canonical(r_dev, "r")) || (rc = check_canonical(x_dev, "x")) || (rc = check_canonical(b_dev, "b")))
+    return rc;
   hipStream_t st = S(stream);
   Work w;
   rc = get_work(g, 1, kFP64, 1, nrhs, nullptr, 0, &w);
@@ -986,6 +1007,7 @@ qcd_status qcd_bicgstab(const qcd_gauge* g, double kappa, qcd_prec prec, int nrh
   if (rc) return rc;
   if ((rc = check_nrhs(nrhs))) return rc;
   if (!x_dev || !b_dev) return fail(QCD_ERR_ARG, "null vector");
+  if ((rc = check_canonical(x_dev, "x")) || (rc = check_canonical(b_dev, "b"))) return rc;
   if (!(kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   if ((rc = check_bicg_params(p))) return rc;
   hipStream_t st = S(stream);
@@ -1067,6 +1089,7 @@ struct IrRun {
   bool any = false;
   int pc_steps = 0, pc_fallback = -1;
   double bfull[kMaxRhs];  // |b| of the full system (even-odd: the stop test is scaled to it)
+  bool log_pending = false;  // the device step log is on its way to the handle's pinned copy
 };
 
 qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
@@ -1074,6 +1097,7 @@ qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
   if (rc) return rc;
   if ((rc = check_nrhs(R.n))) return rc;
   if (!R.x_dev || !R.b_dev) return fail(QCD_ERR_ARG, "null vector");
+  if ((rc = check_canonical(R.x_dev, "x")) || (rc = check_canonical(R.b_dev, "b"))) return rc;
   if (!(R.kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
   if (R.net && p->inner.even_odd) return fail(QCD_ERR_UNSUPPORTED, "the network preconditions the full operator only");
   if (R.net) {
@@ -1088,7 +1112,9 @@ qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
 }
 
 // b in the native FP64 layout; r = b, x = 0; |b| and the first rescaling on the device.
-qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
+// dev: the device-driven refinement follows, whose start (|b|, the even-odd
+// tolerance, the step bookkeeping) stays on the device with no host read.
+qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st, bool dev) {
   const Geom& G = R.g->g;
   Scalars hs[kMaxRhs];
   for (int i = 0; i < R.n; i++) {
@@ -1099,32 +1125,35 @@ qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
   if (R.w.eo) {
     // eta_e, eta_o and b' (eq. (4)-(6)), |b| of the full system, r = b', x_e = 0
     eo_setup(R.g, R.kappa, R.w, R.b_dev, st);
-    double b2[kMaxRhs];
-    qcd_status rc = read_sum(R.w, site_grid(G), 1, b2, st);
-    if (rc) return rc;
-    for (int i = 0; i < R.n; i++) R.bfull[i] = sqrt(b2[i]);
+    if (dev) {
+      launch_finish_sum(R.n, R.w.partials, site_grid(G), 1, R.w.sums, st);  // |b|^2, kept on the device
+    } else {
+      double b2[kMaxRhs];
+      qcd_status rc = read_sum(R.w, site_grid(G), 1, b2, st);
+      if (rc) return rc;
+      for (int i = 0; i < R.n; i++) R.bfull[i] = sqrt(b2[i]);
+    }
     const Geom gh = half_geom(G);
     launch_narrow(gh, kFP64, R.n, R.w.r64, (const double*)R.w.bp64, R.w.partials, 0, st);
     launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(gh), p->s, st);
     launch_zero(gh, kFP64, R.n, R.w.x64, st);
+    if (dev) launch_ir_dev_start(R.n, R.w.sc, R.w.sums, p->tol, p->max_outer, st);
     return QCD_OK;
   }
   launch_pack_spinor(G, kFP64, R.n, R.w.b64, (const double*)R.b_dev, 1.0, 0, R.w.partials, st);
   launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(G), p->s, st);
   HIP_TRY(hipMemcpyAsync(R.w.r64, R.w.b64, R.n * spinor_bytes(G, kFP64), hipMemcpyDeviceToDevice, st));
   launch_zero(G, kFP64, R.n, R.w.x64, st);
+  if (dev) launch_ir_dev_start(R.n, R.w.sc, nullptr, p->tol, p->max_outer, st);
   return QCD_OK;
 }
 
-void ir_after_start(IrRun& R) {
-  R.any = false;
+// The host's bookkeeping of a refinement before any scalar is read back.
+void ir_init_host(IrRun& R) {
   for (int i = 0; i < R.n; i++) {
-    const Scalars& h = R.g->host_sc[i];
-    R.bn[i] = R.rn[i] = h.out_rnorm;
     R.outer[i] = R.inner_total[i] = 0;
     R.last_status[i] = kConverged;
     R.result[i] = QCD_OK;
-    if (!std::isfinite(R.bn[i])) R.result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
     if (R.info) {
       R.info[i].history_len = 0;
       R.info[i].first_shat_over_s = 0;
@@ -1132,10 +1161,20 @@ void ir_after_start(IrRun& R) {
       R.info[i].precond_fallback = -1;
       R.info[i].precond_scale = 0;
     }
+  }
+  R.pc.net = R.net;
+}
+
+void ir_after_start(IrRun& R) {
+  ir_init_host(R);
+  R.any = false;
+  for (int i = 0; i < R.n; i++) {
+    const Scalars& h = R.g->host_sc[i];
+    R.bn[i] = R.rn[i] = h.out_rnorm;
+    if (!std::isfinite(R.bn[i])) R.result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
     R.any |= h.outer_active && std::isfinite(R.bn[i]);
   }
   if (R.n == 1 && !std::isfinite(R.bn[0])) R.any = false;
-  R.pc.net = R.net;
 }
 
 // Even-odd: the refinement stops on the residual of the even system, whose
@@ -1299,18 +1338,9 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
   std::vector<IrRun*> act;
   for (int r = 0; r < nrun; r++) {
     IrRun& R = runs[r];
-    if (!R.any) continue;
-    qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
-    for (int i = 0; i < R.n; i++) {
-      Scalars& h = g->host_sc[i];
-      h.dev_outer = 1;
-      h.outer_step = h.outer_active ? 1 : 0;
-      h.max_outer = p->max_outer;
-      h.outer_count = h.inner_total = h.fail = 0;
-      h.last_status = kConverged;
-      h.first_shat = 0.0;
-    }
-    HIP_TRY(hipMemcpyAsync(R.w.sc, g->host_sc, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
+    // the start (ir_start with dev) set the device's step bookkeeping; the host
+    // mirror is refreshed at the first poll, until then every right-hand side counts as refining
+    for (int i = 0; i < R.n; i++) R.g->host_sc[i].outer_active = 1;
     if ((rc = ir_begin_step(R, p, st))) return rc;  // the first conversion and inner start
     act.push_back(&R);
   }
@@ -1407,37 +1437,49 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
     g->hint_steps = std::min(64, st_max);
     memcpy(g->hint_key, hkey, sizeof hkey);
   }
-  // the device's bookkeeping
-  std::vector<double> log;
+  // the device's bookkeeping: counts, stop reasons and the last |r| from the
+  // scalars of the last poll; the step log is copied into the handle's pinned
+  // buffer behind the work still to come and read after the final synchronisation
   for (int a = 0; a < nact; a++) {
     IrRun& R = *act[a];
-    log.assign((size_t)2 * kOuterLog * R.n, 0.0);
-    HIP_TRY(hipMemcpyAsync(log.data(), R.w.outer_log, log.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpyAsync(R.g->host_log, R.w.outer_log, sizeof(double) * 2 * kOuterLog * R.n,
+                           hipMemcpyDeviceToHost, st));
+    R.log_pending = true;
     for (int i = 0; i < R.n; i++) {
       const Scalars& h = R.g->host_sc[i];
+      R.bn[i] = h.bfull;
+      R.rn[i] = h.out_rnorm;
+      if (!std::isfinite(R.bn[i])) R.result[i] = fail(QCD_ERR_ARG, "non-finite right-hand side %d", i);
       R.outer[i] = h.outer_count;
       R.inner_total[i] = h.inner_total;
       R.last_status[i] = h.last_status;
-      if (h.outer_count > 0) R.rn[i] = h.out_rnorm;
       if (h.fail)
         R.result[i] = fail(h.fail == kNonFinite ? QCD_ERR_NONFINITE : QCD_ERR_BREAKDOWN,
                            "inner solve of right-hand side %d failed (status %d) in refinement step %d", i,
                            h.last_status, h.outer_count - 1);
       else if (h.outer_active || (h.outer_count > 0 && h.out_rnorm > h.out_tol * h.out_bnorm))
         R.result[i] = worse(R.result[i], QCD_NOT_CONVERGED);
-      if (R.info) {
-        qcd_solve_info& in = R.info[i];
-        in.first_shat_over_s = h.outer_count > 0 ? h.first_shat / p->s : 0.0;
-        for (int k = 0; k < h.outer_count && k < kOuterLog; k++) {
-          if (in.outer_history && k < in.outer_history_cap)
-            in.outer_history[k] = log[((size_t)i * kOuterLog + k) * 2] / R.bn[i];
-          if (in.zeros && k < in.outer_history_cap) in.zeros[k] = log[((size_t)i * kOuterLog + k) * 2 + 1];
-        }
-      }
+      if (R.info) R.info[i].first_shat_over_s = h.outer_count > 0 ? h.first_shat / p->s : 0.0;
     }
   }
   return QCD_OK;
+}
+
+// The per-step residuals and zero counts of a device-driven refinement, from
+// the handle's pinned copy of the step log (after the stream has synchronised).
+void dev_log_to_info(IrRun& R) {
+  if (!R.log_pending) return;
+  R.log_pending = false;
+  if (!R.info) return;
+  const double* log = R.g->host_log;
+  for (int i = 0; i < R.n; i++) {
+    qcd_solve_info& in = R.info[i];
+    for (int k = 0; k < R.outer[i] && k < kOuterLog; k++) {
+      if (in.outer_history && k < in.outer_history_cap)
+        in.outer_history[k] = log[((size_t)i * kOuterLog + k) * 2] / R.bn[i];
+      if (in.zeros && k < in.outer_history_cap) in.zeros[k] = log[((size_t)i * kOuterLog + k) * 2 + 1];
+    }
+  }
 }
 
 // The refinement of Alg. 3 for several lattices at once: every refinement
@@ -1445,19 +1487,6 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
 // (bicg_loop_multi) and corrects them.  runs[r].w must be set.
 qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream_t st, double t0) {
   qcd_status rc;
-  for (int r = 0; r < nrun; r++)
-    if ((rc = ir_start(runs[r], p, st))) return rc;
-  HIP_LAUNCHED();
-  {
-    std::vector<InnerRun> ir(nrun);
-    for (int r = 0; r < nrun; r++) ir[r] = InnerRun{runs[r].g, p->inner_prec, runs[r].kappa, &runs[r].w, Precond{}};
-    if ((rc = read_scalars_all(ir.data(), nrun, st))) return rc;
-  }
-  for (int r = 0; r < nrun; r++) {
-    runs[r].pc.scale = (float)p->precond_scale;
-    ir_after_start(runs[r]);
-    if (runs[r].w.eo && (rc = ir_eo_scale_tol(runs[r], p, st))) return rc;
-  }
   // the steps run from the device unless the host is asked to poll every
   // check_every iterations, or a network (whose step may be undone from the
   // host), per-step inner histories or more steps than the device log holds
@@ -1469,7 +1498,22 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
       for (int i = 0; i < runs[r].n; i++)
         if (runs[r].info[i].history && runs[r].info[i].history_cap > 0) dev = false;
   }
-  if (dev && (rc = solve_ir_dev(runs, nrun, p, st))) return rc;
+  for (int r = 0; r < nrun; r++)
+    if ((rc = ir_start(runs[r], p, st, dev))) return rc;
+  HIP_LAUNCHED();
+  if (dev) {
+    for (int r = 0; r < nrun; r++) ir_init_host(runs[r]);
+    if ((rc = solve_ir_dev(runs, nrun, p, st))) return rc;
+  } else {
+    std::vector<InnerRun> ir(nrun);
+    for (int r = 0; r < nrun; r++) ir[r] = InnerRun{runs[r].g, p->inner_prec, runs[r].kappa, &runs[r].w, Precond{}};
+    if ((rc = read_scalars_all(ir.data(), nrun, st))) return rc;
+    for (int r = 0; r < nrun; r++) {
+      runs[r].pc.scale = (float)p->precond_scale;
+      ir_after_start(runs[r]);
+      if (runs[r].w.eo && (rc = ir_eo_scale_tol(runs[r], p, st))) return rc;
+    }
+  }
   for (int step = 0; !dev; step++) {
     std::vector<IrRun*> act;
     for (int r = 0; r < nrun; r++)
@@ -1496,10 +1540,17 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
     IrRun& R = runs[r];
     if (R.w.eo) {
       // x_o from x_e, the canonical solution, and |b - D x| of the full system for the report
+      // The even rows of b - D x are those of the last refinement step's FP64
+      // residual eta_e + kappa H_eo eta_o - (x_e - kappa^2 H_eo H_oe x_e), taken
+      // at the x_e returned (the two forms agree in exact arithmetic; here they
+      // differ by the rounding of the stored x_o), so only the odd rows are
+      // computed again, in the reconstruction launch.  A network run may have
+      // undone its last step, so there the even rows are recomputed.
       double r2[kMaxRhs];
-      if ((rc = eo_finish(R.g, R.kappa, R.w, R.x_dev, r2, st))) return rc;
+      const bool even_rows = R.net != nullptr;
+      if ((rc = eo_finish(R.g, R.kappa, R.w, R.x_dev, r2, st, even_rows))) return rc;
       for (int i = 0; i < R.n; i++)
-        if (R.outer[i] > 0) R.rn[i] = sqrt(r2[i]);
+        if (R.outer[i] > 0) R.rn[i] = sqrt(r2[i] + (even_rows ? 0.0 : R.rn[i] * R.rn[i]));
     } else {
       launch_unpack_spinor(R.g->g, kFP64, R.n, (double*)R.x_dev, R.w.x64, nullptr, 1.0, st);
     }
@@ -1507,7 +1558,10 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
   HIP_LAUNCHED();
   HIP_TRY(hipStreamSynchronize(st));
   qcd_status res = QCD_OK;
-  for (int r = 0; r < nrun; r++) res = worse(res, ir_finish(runs[r], t0));
+  for (int r = 0; r < nrun; r++) {
+    dev_log_to_info(runs[r]);
+    res = worse(res, ir_finish(runs[r], t0));
+  }
   return res;
 }
 

@@ -122,8 +122,10 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst
     S* b = odd ? (id.par ? odd : dst) + (size_t)rhs * g.nb * 768 + sp_block(g, 0, id.h)
                : dst + (size_t)rhs * spinor_elems(g) + sp_block(g, id.par, id.h);
     T acc = 0;
+    const double2* s2 = reinterpret_cast<const double2*>(src) + s * 12;  // one 16-byte load per complex
     for (int k = 0; k < 12; k++) {
-      const S v = pack_from_double<S>(scale * src[(s * 12 + k) * 2], scale * src[(s * 12 + k) * 2 + 1], ftz);
+      const double2 c = s2[k];
+      const S v = pack_from_double<S>(scale * c.x, scale * c.y, ftz);
       b[sp_off<S>(k, lane)] = v;
       acc += norm2(Traits<S>::load(&v));
     }
@@ -149,10 +151,8 @@ __global__ __launch_bounds__(256) void k_unpack_spinor(Geom g, double* __restric
     load_site((id.par ? odd : src) + (size_t)rhs * g.nb * 768, g, 0, id.h, f);
   else
     load_site(src + (size_t)rhs * spinor_elems(g), g, id.par, id.h, f);
-  for (int k = 0; k < 12; k++) {
-    dst[(s * 12 + k) * 2] = scale * (double)f[k].re;
-    dst[(s * 12 + k) * 2 + 1] = scale * (double)f[k].im;
-  }
+  double2* d2 = reinterpret_cast<double2*>(dst) + s * 12;  // one 16-byte store per complex
+  for (int k = 0; k < 12; k++) d2[k] = make_double2(scale * (double)f[k].re, scale * (double)f[k].im);
 }
 
 template <typename S>
@@ -538,6 +538,27 @@ __global__ void k_outer_norm(Scalars* scal, const double* partials, int nrows, d
   if (sc->dev_outer && sc->outer_count >= sc->max_outer) sc->outer_active = 0;
 }
 
+// Start of the device-driven refinement, after the start norm |b'| (k_outer_norm):
+// |b| of the full system (b2: |b|^2 of the even-odd form's b, else |b'| = |b|),
+// the even-odd stop test taken relative to it, and the step bookkeeping.
+__global__ void k_ir_dev_start(Scalars* scal, const double* b2, double tol, int max_outer) {
+  if (threadIdx.x != 0) return;
+  Scalars* sc = scal + blockIdx.x;
+  if (b2) {
+    const double bf = sqrt(b2[blockIdx.x]), bp = sc->out_rnorm;
+    sc->bfull = bf;
+    if (bp > 0 && isfinite(bp)) sc->out_tol = tol * bf / bp;
+  } else {
+    sc->bfull = sc->out_rnorm;
+  }
+  sc->dev_outer = 1;
+  sc->outer_step = sc->outer_active ? 1 : 0;
+  sc->max_outer = max_outer;
+  sc->outer_count = sc->inner_total = sc->fail = 0;
+  sc->last_status = kConverged;
+  sc->first_shat = 0.0;
+}
+
 // After the conversion: s^ (Alg. 3) and the start of the inner BiCGStab.
 // Device-driven refinement: only a right-hand side whose step is due
 // continues (the flag is cleared before the inner start, which raises it
@@ -787,6 +808,9 @@ void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r
   QCD_DISPATCH(prec, convert_t, g, n, sc, r64, y, rstar, partials, ftz, st);
 }
 
+void launch_ir_dev_start(int n, Scalars* sc, const double* b2_dev, double tol, int max_outer, hipStream_t st) {
+  hipLaunchKernelGGL(k_ir_dev_start, dim3(n), dim3(64), 0, st, sc, b2_dev, tol, max_outer);
+}
 void launch_convert_finish(int n, Scalars* sc, const double* partials, int nrows, int recalc_shat, double s_target,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_convert_finish, dim3(n), dim3(1024), 0, st, sc, partials, nrows, recalc_shat, s_target);

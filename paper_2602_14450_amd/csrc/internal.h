@@ -75,7 +75,7 @@ struct Scalars {
   int last_status;               // stop reason of the last inner solve (device-driven)
   int pad_i;
   double first_shat;             // s^ of the first refinement step (device-driven)
-  double pad[1];
+  double bfull;                  // |b| of the full system (device-driven start)
 };
 // refinement steps whose |r| and zero count the device-driven refinement logs per right-hand side
 constexpr int kOuterLog = 128;
@@ -161,6 +161,9 @@ void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, doub
                      hipStream_t st);
 
 // with log (device-driven refinement): log[rhs][k] = (|r|, zeros of y~) of step k
+// start of the device-driven refinement: |b| (from b2_dev, or the start norm),
+// the even-odd tolerance relative to it, and the step bookkeeping
+void launch_ir_dev_start(int n, Scalars* sc, const double* b2_dev, double tol, int max_outer, hipStream_t st);
 void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
                                 hipStream_t st, double* log = nullptr);
 void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r64, void* y, void* rstar,
@@ -195,6 +198,7 @@ struct qcd_gauge {
   void* ws;          // cached workspace used when the caller passes none
   size_t ws_bytes;
   qcd::Scalars* host_sc;  // pinned mirror of the device scalars (kMaxRhs entries)
+  double* host_log;       // pinned copy of the device-driven refinement's step log (kMaxRhs x kOuterLog x 2)
   qcd::DslashTune tune[qcd::kNumPrec];
   // one captured BiCGStab iteration, reused while its key (every value and
   // device address the captured launches bake in) is unchanged
