@@ -174,7 +174,8 @@ int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
  * parity cover whole x rows) and in the one-parity launches of the even-odd
  * solvers (every precision, when blocks of 256 half sites cover whole x rows;
  * x extent at most 128, 64 for FP64), one right-hand side per launch tile;
- * otherwise as 1; 7: the same LDS forms, otherwise as 0.
+ * otherwise as 1; 7: the same LDS forms with two hops prefetched in 16-bit
+ * storage (one in FP32 and FP64), otherwise as 0.
  * rhs_tile (0 = automatic, 1, 2, 4) is the number of right-hand sides whose
  * lanes share one wave's link loads in a multi-RHS application, -2, -3, -4 the
  * number a thread applies one loaded link to (it must divide nrhs, else 1 is

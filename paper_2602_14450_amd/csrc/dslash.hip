@@ -1346,13 +1346,13 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
 #undef QCD_LAUNCH
 }
 
-template <typename S, int NE>
+template <typename S, int NE, int DEPTH>
 static void launch_dslash_lds_eo(const Geom& g, const DslashSched& sc, int op, int epi, void* out, const void* in,
                                  const void* U, double kappa, const void* aux, double* partials, const Scalars* scal,
                                  int ftz, const void* cin, int eo_par, hipStream_t st, int mask) {
   const dim3 grid(sc.nsb * sc.ntiles), block(256);
 #define QCD_LDS_EO(OPV, EPIV)                                                                                    \
-  hipLaunchKernelGGL((k_dslash_lds_eo<S, OPV, EPIV, 1, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, \
+  hipLaunchKernelGGL((k_dslash_lds_eo<S, OPV, EPIV, DEPTH, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, \
                      (const S*)U, kappa, (const S*)aux, partials, scal, ftz, (const S*)cin, eo_par, mask)
   if (op == kOpH) QCD_LDS_EO(kOpH, kEpiNone);
   else if (epi == kEpiNone) QCD_LDS_EO(kOpD, kEpiNone);
@@ -1362,12 +1362,12 @@ static void launch_dslash_lds_eo(const Geom& g, const DslashSched& sc, int op, i
 #undef QCD_LDS_EO
 }
 
-template <typename S, int NE>
+template <typename S, int NE, int DEPTH>
 static void launch_dslash_lds(const Geom& g, const DslashSched& sc, int op, void* out, const void* in, const void* U,
                               double kappa, int ftz, hipStream_t st) {
   const dim3 grid(sc.nsb), block(256);
 #define QCD_LDS(OPV)                                                                                           \
-  hipLaunchKernelGGL((k_dslash_lds<S, OPV, 1, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, (const S*)U, \
+  hipLaunchKernelGGL((k_dslash_lds<S, OPV, DEPTH, NE>), grid, block, 0, st, g, sc, (S*)out, (const S*)in, (const S*)U, \
                      kappa, ftz)
   switch (op) {
     case kOpD: QCD_LDS(kOpD); break;
@@ -1389,14 +1389,22 @@ static void launch_dslash_tile(const Geom& g, const DslashTune& tune, int op, in
     // (16-bit storage: 24 KB per block; plain operator, one right-hand side) ...
     if constexpr (sizeof(S) == 4) {
       if (lds && n == 1 && eo_par < 0 && epi == kEpiNone && !scal && lds_form_applies(g)) {
-        launch_dslash_lds<S, NE>(g, sc, op, out, in, U, kappa, ftz, st);
+        if (tune.variant == 7)
+          launch_dslash_lds<S, NE, 2>(g, sc, op, out, in, U, kappa, ftz, st);
+        else
+          launch_dslash_lds<S, NE, 1>(g, sc, op, out, in, U, kappa, ftz, st);
         return;
       }
     }
     // ... and the one-parity form for the even-odd solvers (the epilogues they use)
     if (lds && eo_par >= 0 && epi != kEpiRecon && (op == kOpH || op == kOpD) && n == 1 &&
         lds_eo_form_applies<S>(g) && sc.H == 256) {
-      launch_dslash_lds_eo<S, NE>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st, mask);
+      if (sizeof(S) == 4 && tune.variant == 7)
+        launch_dslash_lds_eo<S, NE, 2>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st,
+                                       mask);
+      else
+        launch_dslash_lds_eo<S, NE, 1>(g, sc, op, epi, out, in, U, kappa, aux, partials, scal, ftz, cin, eo_par, st,
+                                       mask);
       return;
     }
   }

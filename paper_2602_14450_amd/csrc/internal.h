@@ -87,7 +87,8 @@ struct DslashTune {
   int variant;  // (hops prefetched, min waves per SIMD): 0 (1,2), 1 (2,2), 2 (0,3), 3 (1,3), 4 (0,4), 5 (1,4)
                 // (prefetching 2 hops at 5 waves spills registers and measured slower in every precision);
                 // 6: x and y neighbours staged in LDS (the FP16 / BF16 plain full-lattice operator and the
-                // one-parity launches of every precision, one right-hand side; else as 1); 7: as 6, else as 0
+                // one-parity launches of every precision, one right-hand side; else as 1); 7: as 6 with two
+                // hops prefetched in 16-bit storage, else as 0
   int rhs_tile; // right-hand sides sharing a link: 0 = automatic; 1, 2, 4 = that many in adjacent lanes;
                 // -2, -3, -4 = that many per thread (link loaded and rebuilt once in registers);
                 // 8 = the matrix-core form (kRhsTileMfma)
