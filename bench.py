@@ -842,7 +842,8 @@ def main():
         "metric": METRIC, "value": s_per_solve, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": s_per_solve * 1e3, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp16 storage (binary16 projection, binary16 products summed in fp32, fp32 updates); fp64 refinement",
+        "dtype": "fp16 storage (binary16 projection and row-2 rebuild, binary16 products summed in fp32, "
+                 "fp32 updates); fp64 refinement",
         "data": "synthetic",
         "config": {"workload": f"Wilson D x = b, {'x'.join(map(str, dims))} lattice, eps={args.eps} SU(3) links, "
                                f"kappa={k}, 1 Gaussian source, FP64 IR + FP16 BiCGStab (s=128, sigma=64, "

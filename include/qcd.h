@@ -57,8 +57,10 @@ typedef enum {
 /* Storage precisions of fields and links (Table 1).  FP16 and BF16 store a
  * complex number as two 16-bit halves of one 32-bit word.  Arithmetic on FP16
  * storage: in the Wilson operator the spin projection is one binary16 add per
- * component (as the paper's FP16 arithmetic, Sec. 5) and each link product
- * is a pair of exact binary16 products summed in FP32 (v_dot2_f32_f16); the
+ * component (as the paper's FP16 arithmetic, Sec. 5), row 2 of a two-row
+ * link is rebuilt with binary16 multiplies and fused multiply-adds, and each
+ * link product is a pair of exact binary16 products summed in FP32
+ * (v_dot2_f32_f16); the
  * reconstruction, the BLAS-1 updates and every reduction are FP32 (scalars
  * FP64).  BF16 storage: FP32 arithmetic throughout.  BF16 (8 exponent bits,
  * 7 fraction bits) is the alternative inner format the paper's conclusion
