@@ -1366,6 +1366,10 @@ qcd_status solve_ir_dev(IrRun* runs, int nrun, const qcd_ir_params* p, hipStream
     K = 4;
     blocks = 2;
   }
+  // at most 256 iterations before the first poll: a call much easier than the
+  // last one (a zero source after a hard solve) would otherwise queue many
+  // blocks whose launches all return at once
+  blocks = std::max(1, std::min(blocks, 256 / K));
   auto refining = [](const IrRun& R) {
     for (int i = 0; i < R.n; i++)
       if (R.g->host_sc[i].outer_active) return true;

@@ -271,6 +271,29 @@ def test_device_driven_steps_match_host_driven(q, c1b, eo):
     assert idv[0].status == "not_converged" and idv[0].outer_iters == 2
 
 
+def test_device_driven_steps_after_a_harder_call(q, c1b):
+    # the first poll of a device-driven refinement takes its block sizes from
+    # the handle's previous call: after a normal source, a zero source returns
+    # x = 0 with no step, and a small source solves as with host-driven steps
+    g, k = c1b["g"], c1b["k"]
+    b = to_dev(c1b["b"][:1])
+    x = torch.zeros_like(b)
+    info = q.solve_mixed_ir(g, k, x, b, even_odd=True)
+    assert info.status == "ok" and info.outer_iters > 1
+    z = torch.zeros_like(b)
+    xz = torch.ones_like(b)
+    iz = q.solve_mixed_ir(g, k, xz, z, even_odd=True)
+    torch.cuda.synchronize()
+    assert iz.status == "ok" and iz.outer_iters == 0 and iz.inner_iters == 0
+    assert not bool(xz.abs().max() > 0)
+    small = to_dev(c1b["b"][2:3])
+    xd, xh = torch.zeros_like(small), torch.zeros_like(small)
+    idv = q.solve_mixed_ir(g, k, xd, small, even_odd=True)
+    ih = q.solve_mixed_ir(g, k, xh, small, even_odd=True, check_every=4)
+    torch.cuda.synchronize()
+    assert torch.equal(xd, xh) and idv.inner_iters == ih.inner_iters and idv.status == "ok"
+
+
 def test_graph_cache_follows_the_workspace_carve(q, c1b):
     # one handle, one caller workspace: inner_max_iter 500 and then 2000 move
     # the partial sums and scalars inside the same buffer (the history before
