@@ -327,17 +327,24 @@ void eo_setup(const qcd_gauge* g, double kappa, const Work& w, const void* b_dev
 // the reconstruction launch itself; with even_rows the even rows eta_e - (x_e -
 // kappa H_eo x_o) from one more one-parity launch (residual vector left in
 // r64), else r2 holds the odd rows only (the caller adds the even rows it has).
+// With hop_kept, t64 holds H_oe x_e of the x_e returned (the last refinement
+// step's residual computed it) and the reconstruction streams instead of hopping.
 qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_dev, double* r2, hipStream_t st,
-                     bool even_rows = true) {
+                     bool even_rows = true, bool hop_kept = false) {
   const Geom& G = g->g;
   const int n = w.n;
   DslashTune one = g->tune[kFP64];
   one.rhs_tile = 1;
-  const int rows_o = dslash_partial_rows(G, one, n, true), rows_e = dslash_partial_rows(G, g->tune[kFP64], n, true);
+  const Geom gh = half_geom(G);
+  const int rows_o = hop_kept ? site_grid(gh) : dslash_partial_rows(G, one, n, true);
+  const int rows_e = dslash_partial_rows(G, g->tune[kFP64], n, true);
   double* po = w.partials;
   double* pe = w.partials + (size_t)n * rows_o;
-  launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiRecon, n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr, po,
-                nullptr, 0, st, w.eta_o, 1);
+  if (hop_kept)
+    launch_eo_recon(gh, n, (double*)w.x64o, (const double*)w.eta_o, (const double*)w.t64, kappa, po, st);
+  else
+    launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiRecon, n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr, po,
+                  nullptr, 0, st, w.eta_o, 1);
   if (even_rows)
     launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
                   nullptr, 0, st, w.x64, 0);
@@ -1550,9 +1557,14 @@ qcd_status solve_ir_runs(IrRun* runs, int nrun, const qcd_ir_params* p, hipStrea
       // differ by the rounding of the stored x_o), so only the odd rows are
       // computed again, in the reconstruction launch.  A network run may have
       // undone its last step, so there the even rows are recomputed.
+      // Without a network the last step's residual also left H_oe x_e of the
+      // returned x_e in t64 (every right-hand side took a step; else x_e = 0
+      // never met that launch), so x_o = eta_o + kappa t64 needs no hop.
       double r2[kMaxRhs];
       const bool even_rows = R.net != nullptr;
-      if ((rc = eo_finish(R.g, R.kappa, R.w, R.x_dev, r2, st, even_rows))) return rc;
+      bool hop_kept = !even_rows;
+      for (int i = 0; i < R.n; i++) hop_kept = hop_kept && R.outer[i] > 0;
+      if ((rc = eo_finish(R.g, R.kappa, R.w, R.x_dev, r2, st, even_rows, hop_kept))) return rc;
       for (int i = 0; i < R.n; i++)
         if (R.outer[i] > 0) R.rn[i] = sqrt(r2[i] + (even_rows ? 0.0 : R.rn[i] * R.rn[i]));
     } else {

@@ -353,6 +353,34 @@ __global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restri
   store_site(x64, g, id.par, id.h, xo, 0);
 }
 
+// Even-odd reconstruction from the last refinement step's hop: x_o = eta_o +
+// kappa t with t = H_oe x_e (eq. (6)), and the odd rows eta_o - (x_o - kappa t)
+// of b - D x from the stored x_o as |.|^2 partials per block.  One-parity
+// FP64 fields in the half geometry; right-hand side blockIdx.y.
+__global__ __launch_bounds__(256) void k_eo_recon(Geom g, double2* __restrict__ xo, const double2* __restrict__ eta,
+                                                  const double2* __restrict__ t, double kappa,
+                                                  double* __restrict__ partials) {
+  SiteId id = site_id(g);
+  double red[1] = {0.0};
+  if (id.valid) {
+    const size_t o = (size_t)blockIdx.y * spinor_elems(g);
+    cx<double> e[12], tt[12], x[12];
+    load_site(eta + o, g, id.par, id.h, e);
+    load_site(t + o, g, id.par, id.h, tt);
+#pragma unroll
+    for (int k = 0; k < 12; k++) x[k] = cx<double>(e[k].re + kappa * tt[k].re, e[k].im + kappa * tt[k].im);
+    store_site(xo + o, g, id.par, id.h, x, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+      const double rr = e[k].re - (x[k].re - kappa * tt[k].re), ri = e[k].im - (x[k].im - kappa * tt[k].im);
+      acc += rr * rr + ri * ri;
+    }
+    red[0] = acc;
+  }
+  block_reduce_store<1>(red, partials + (size_t)blockIdx.y * gridDim.x, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Finish kernels: block b sums the partial rows of right-hand side b, thread
 // 0 updates that right-hand side's scalars.
@@ -822,6 +850,12 @@ static void correct_t(const Geom& g, int n, Scalars* sc, double* x64, const void
 }
 void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, const void* xlo, hipStream_t st) {
   QCD_DISPATCH(prec, correct_t, g, n, sc, x64, xlo, st);
+}
+
+void launch_eo_recon(const Geom& gh, int n, double* xo, const double* eta_o, const double* t, double kappa,
+                     double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_eo_recon, dim3(site_grid(gh), n), dim3(256), 0, st, gh, (double2*)xo, (const double2*)eta_o,
+                     (const double2*)t, kappa, partials);
 }
 
 void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st) {

@@ -162,6 +162,10 @@ void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, doub
                      hipStream_t st);
 
 // with log (device-driven refinement): log[rhs][k] = (|r|, zeros of y~) of step k
+// x_o = eta_o + kappa t (t = H_oe x_e, one-parity FP64 fields in the half geometry gh) and
+// |eta_o - (x_o - kappa t)|^2 partials, site_grid(gh) rows per right-hand side
+void launch_eo_recon(const Geom& gh, int n, double* xo, const double* eta_o, const double* t, double kappa,
+                     double* partials, hipStream_t st);
 // start of the device-driven refinement: |b| (from b2_dev, or the start norm),
 // the even-odd tolerance relative to it, and the step bookkeeping
 void launch_ir_dev_start(int n, Scalars* sc, const double* b2_dev, double tol, int max_outer, hipStream_t st);
