@@ -110,12 +110,16 @@ typedef struct {
   double s;                 /* the residual is rescaled to norm s before conversion */
   int recalc_shat;          /* 1: correct with s^ = |single(y~)| (Alg. 3); 0: with s */
   qcd_bicgstab_params inner;/* inner.tol is eps_tol (the paper's eps_tol^2 = 1e-4 is tol = 1e-2) */
-  const qcd_ptc* precond;   /* NULL, or a network (built on the same gauge handle, max_batch >= nrhs) used
-                               as right preconditioner M of the FP16 inner solve: the inner BiCGStab solves
+  const qcd_ptc* precond;   /* NULL, or a network (built on the same gauge handle; it takes the right-hand
+                               sides max_batch at a time) used as right preconditioner M of the FP16 inner
+                               solve: the inner BiCGStab solves
                                (D c M) u = y~ and the refinement step corrects with t = c M u.  A step whose
                                FP64 residual does not drop, or that goes non-finite, is undone and the call
                                continues without the network (flexible refinement: the outer FP64 residual
-                               is recomputed every step, so M may differ from D^-1 by any amount) */
+                               is recomputed every step, so M may differ from D^-1 by any amount).  With
+                               inner.even_odd the even system is preconditioned by the even-even block of M:
+                               z = even rows of c M (v, 0), since the even-even block of D^-1 is the inverse
+                               of the matrix of eq. (5) */
   double precond_scale;     /* c above; 0 = 1 / (largest |M v| / |v| over the first inner right-hand sides),
                                which keeps the FP16 vectors in the range of the plain solver */
 } qcd_ir_params;
@@ -137,7 +141,8 @@ typedef struct {
   int outer_history_cap;
   double* zeros;            /* optional: zero reals in y~ per refinement step (Fig. 9 diagnostic),
                                capacity outer_history_cap */
-  int precond_steps;        /* refinement steps whose inner solve used the network */
+  int precond_steps;        /* refinement steps of the call whose inner solve used the network (the same
+                               for every right-hand side of the call) */
   int precond_fallback;     /* refinement step at which the network was dropped, or -1 */
   double precond_scale;     /* the scale c used (0 without a network) */
 } qcd_solve_info;
@@ -205,7 +210,7 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec);
 
 /* Workspace bytes that qcd_solve_mixed_ir (what = 0; what = 3 with a network
  * preconditioner), qcd_bicgstab (what = 1) or qcd_dslash with canonical
- * layout (what = 2) need, what = 0 or 1 plus 8 for the even-odd form, for inner precision
+ * layout (what = 2) need, what = 0, 1 or 3 plus 8 for the even-odd form, for inner precision
  * prec, max_iter history entries and nrhs right-hand sides.  The size depends
  * on the handle's current launch tuning (the operator's partial-sum rows per
  * right-hand side): query it again after qcd_set_dslash_tuning or
@@ -378,7 +383,10 @@ qcd_status qcd_stream_probe(void* dst_dev, const void* src_dev, size_t bytes, in
  * per layer boundary (channels[0] = channels[nlayers] = 1, others 1 or 2) on
  * the lattice of g (which must hold FP32 links; the handle keeps a pointer
  * to g, which must outlive it), for batches of up to max_batch fields.
- * Weights start at zero.  Device buffers are owned by the handle. */
+ * Weights start at zero.  Device buffers are owned by the handle; those of
+ * the two-pass form (training, the loss and gradient calls, FP32 mixing) are
+ * allocated by the first call that uses it, so a handle that only
+ * preconditions holds the activations of max_batch fields and no more. */
 qcd_status qcd_ptc_create(qcd_ptc** net, const qcd_gauge* g, int nlayers, const int* channels, int max_batch,
                           void* stream);
 qcd_status qcd_ptc_free(qcd_ptc* net);

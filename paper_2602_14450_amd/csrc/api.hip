@@ -96,6 +96,9 @@ struct Work {
   bool eo = false;
   void* t1 = nullptr;
   double2 *eta_e = nullptr, *eta_o = nullptr, *bp64 = nullptr, *t64 = nullptr, *x64o = nullptr;
+  // even-odd with a network: full FP16 fields around M (the odd halves of zin stay zero)
+  void* zin = nullptr;
+  void* zout = nullptr;
   double* partials = nullptr;
   Scalars* sc = nullptr;
   double* history = nullptr;
@@ -107,7 +110,7 @@ struct Work {
 };
 
 // what: 0 refinement, 1 BiCGStab, 2 operator with canonical layout, 3 preconditioned refinement;
-// | kWhatEO: the even-odd form of 0 or 1
+// | kWhatEO: the even-odd form of 0, 1 or 3
 constexpr int kWhatEO = 8;
 Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char* base) {
   const Geom& g = G->g;
@@ -116,7 +119,7 @@ Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char*
   Carve c{base};
   Work w;
   w.n = n;
-  if (eo && (what == 0 || what == 1)) {
+  if (eo && (what == 0 || what == 1 || what == 3)) {
     const Geom gh = half_geom(g);
     w.eo = true;
     w.eta_e = (double2*)c.take(n * spinor_bytes(gh, kFP64));
@@ -135,6 +138,12 @@ Work carve(const qcd_gauge* G, int what_in, int prec, int max_iter, int n, char*
     w.t1 = c.take(n * spinor_bytes(gh, prec));
     w.hist_stride = max_iter > 0 ? max_iter : 1;
     w.history = (double*)c.take(sizeof(double) * (size_t)w.hist_stride * n);
+    if (what == 3) {
+      w.z = c.take(n * spinor_bytes(gh, prec));
+      w.x64b = (double2*)c.take(n * spinor_bytes(gh, kFP64));
+      w.zin = c.take(n * spinor_bytes(g, prec));
+      w.zout = c.take(n * spinor_bytes(g, prec));
+    }
   } else if (what == 0 || what == 1 || what == 3) {
     w.x64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
     w.b64 = (double2*)c.take(n * spinor_bytes(g, kFP64));
@@ -248,9 +257,28 @@ struct Precond {
   float scale = 1.0f;
 };
 
+// z = c M v for n inner (FP16) vectors.  Even-odd: z = the even rows of c M (v, 0).
+// The even-even block of D^-1 is the inverse of the Schur complement of
+// eq. (5), so the even-even block of a network that approximates D^-1 is a
+// right preconditioner of the even system (the third-order Neumann weights
+// give 1 + kappa^2 H_eo H_oe there, the first-order series of its inverse).
+void precond_apply(const qcd_gauge* g, const Precond& pc, const Work& w, int n, const void* v, void* z, int ftz,
+                   const Scalars* sc, hipStream_t st) {
+  if (!w.eo) {
+    ptc_apply_half(pc.net, n, v, z, pc.scale, ftz, sc, st);
+    return;
+  }
+  const Geom gh = half_geom(g->g);
+  const size_t half = spinor_elems(gh), full = spinor_elems(g->g);
+  launch_copy_fields(gh, kFP16, n, w.zin, full, v, half, st);
+  ptc_apply_half(pc.net, n, w.zin, w.zout, pc.scale, ftz, sc, st);
+  launch_copy_fields(gh, kFP16, n, z, half, w.zout, full, st);
+}
+
 // One BiCGStab iteration of Alg. 4 / Alg. 5 for all right-hand sides, entirely on the device.
 // With a preconditioner the operator is D c M: v = D (c M p), t = D (c M s), and (t, s) is
-// taken against s itself (the TSAux epilogue), so x accumulates the iterate u of D c M u = y.
+// taken against s itself (the TSAux epilogue), so x accumulates the iterate u of D c M u = y
+// (even-odd: the Schur matrix times the even-even block of c M).
 void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, int ftz, const Precond& pc,
                     hipStream_t st) {
   const Geom& G = g->g;
@@ -263,12 +291,23 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
     const int erows = dslash_partial_rows(G, tu, n, true);
     const double k2 = kappa * kappa;
     launch_p_update(gh, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
-    launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.p, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
-    launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.t1, U, k2, w.rstar, w.partials, w.sc, ftz, st, w.p, 0);
+    const void* pv = w.p;  // the vector the Schur operator acts on: p, or c M p
+    if (pc.net) {
+      precond_apply(g, pc, w, n, w.p, w.z, ftz, w.sc, st);
+      pv = w.z;
+    }
+    launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, pv, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
+    launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.t1, U, k2, w.rstar, w.partials, w.sc, ftz, st, pv, 0);
     launch_alpha(n, w.sc, w.partials, erows, st);
     launch_s_update(gh, prec, n, w.sc, w.r, w.v, ftz, st);
-    launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.r, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
-    launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.t1, U, k2, nullptr, w.partials, w.sc, ftz, st, w.r, 0);
+    if (pc.net) {  // t = A (c M s), with (t, s) taken against s itself
+      precond_apply(g, pc, w, n, w.r, w.z, ftz, w.sc, st);
+      launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.z, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
+      launch_dslash(prec, G, tu, kOpD, kEpiTSAux, n, w.t, w.t1, U, k2, w.r, w.partials, w.sc, ftz, st, w.z, 0);
+    } else {
+      launch_dslash(prec, G, tu, kOpH, kEpiNone, n, w.t1, w.r, U, 1.0, nullptr, nullptr, w.sc, ftz, st, nullptr, 1);
+      launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.t1, U, k2, nullptr, w.partials, w.sc, ftz, st, w.r, 0);
+    }
     launch_omega(n, w.sc, w.partials, erows, st);
     launch_xr_update(gh, prec, n, w.sc, w.x, w.r, w.t, w.p, w.rstar, w.partials, ftz, st);
     launch_iter_end(n, w.sc, w.partials, flat_rows(gh, prec), w.history, w.hist_stride, st);
@@ -276,7 +315,7 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
   }
   launch_p_update(G, prec, n, w.sc, w.p, w.v, w.r, ftz, st);
   if (pc.net) {
-    ptc_apply_half(pc.net, n, w.p, w.z, pc.scale, ftz, w.sc, st);
+    precond_apply(g, pc, w, n, w.p, w.z, ftz, w.sc, st);
     launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.z, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
   } else {
     launch_dslash(prec, G, tu, kOpD, kEpiDotAux, n, w.v, w.p, U, kappa, w.rstar, w.partials, w.sc, ftz, st);
@@ -284,7 +323,7 @@ void bicg_iteration(const qcd_gauge* g, int prec, double kappa, const Work& w, i
   launch_alpha(n, w.sc, w.partials, drows, st);
   launch_s_update(G, prec, n, w.sc, w.r, w.v, ftz, st);
   if (pc.net) {
-    ptc_apply_half(pc.net, n, w.r, w.z, pc.scale, ftz, w.sc, st);
+    precond_apply(g, pc, w, n, w.r, w.z, ftz, w.sc, st);
     launch_dslash(prec, G, tu, kOpD, kEpiTSAux, n, w.t, w.z, U, kappa, w.r, w.partials, w.sc, ftz, st);
   } else {
     launch_dslash(prec, G, tu, kOpD, kEpiTS, n, w.t, w.r, U, kappa, nullptr, w.partials, w.sc, ftz, st);
@@ -374,7 +413,7 @@ void device_step(const qcd_gauge* g, double kappa, const Work& w, const qcd_ir_p
   launch_convert_finish(w.n, w.sc, w.partials, site_grid(G), p->recalc_shat, p->s, st);
 }
 
-// Capture one iteration (8 kernels, 14 with the network) into a hip graph.
+// Capture one iteration (8 kernels, 14 with the network; even-odd 10 and 20) into a hip graph.
 // Capture runs on the handle's own stream (the null stream cannot be
 // captured); the graph is launched on the caller's stream.  The kernels take
 // every changing value from device memory, so one capture serves every
@@ -402,7 +441,7 @@ qcd_status iteration_graph(const qcd_gauge* gc, int prec, double kappa, const Wo
                                       u(pc.net), pc.net ? sbits : 0ull, u(w.x), u(w.r), u(w.rstar), u(w.p), u(w.v),
                                       u(w.t), u(w.z), u(w.t1), u(w.partials), u(w.sc), u(w.history),
                                       (unsigned long long)w.hist_stride, u(w.sums), u(w.scale),
-                                      (unsigned long long)w.bytes};
+                                      (unsigned long long)w.bytes, u(w.zin), u(w.zout)};
   if (g->graph_exec && memcmp(key, g->graph_key, sizeof key) == 0) {
     *out = g->graph_exec;
     return QCD_OK;
@@ -811,7 +850,7 @@ size_t qcd_spinor_bytes(const qcd_gauge* g, qcd_prec prec) {
 
 size_t qcd_workspace_bytes(const qcd_gauge* g, int what, qcd_prec prec, int max_iter, int nrhs) {
   if (!g || !valid_prec(prec) || (what & ~(7 | kWhatEO)) || (what & 7) > 3 || nrhs < 1 || nrhs > kMaxRhs) return 0;
-  if ((what & kWhatEO) && (what & 7) > 1) return 0;
+  if ((what & kWhatEO) && (what & 7) == 2) return 0;
   return carve(g, what, prec, max_iter, nrhs, nullptr).bytes;
 }
 
@@ -1106,12 +1145,9 @@ qcd_status check_ir_run(const IrRun& R, const qcd_ir_params* p) {
   if (!R.x_dev || !R.b_dev) return fail(QCD_ERR_ARG, "null vector");
   if ((rc = check_canonical(R.x_dev, "x")) || (rc = check_canonical(R.b_dev, "b"))) return rc;
   if (!(R.kappa > 0)) return fail(QCD_ERR_ARG, "kappa must be > 0");
-  if (R.net && p->inner.even_odd) return fail(QCD_ERR_UNSUPPORTED, "the network preconditions the full operator only");
   if (R.net) {
     if (p->inner_prec != kFP16) return fail(QCD_ERR_UNSUPPORTED, "the network preconditioner runs with the FP16 inner solve");
     if (ptc_gauge(R.net) != R.g) return fail(QCD_ERR_ARG, "the network is bound to another gauge handle");
-    if (R.n > ptc_max_batch(R.net))
-      return fail(QCD_ERR_ARG, "nrhs %d exceeds the network's max_batch %d", R.n, ptc_max_batch(R.net));
     if (!(p->precond_scale >= 0) || !std::isfinite(p->precond_scale))
       return fail(QCD_ERR_ARG, "precond_scale must be finite and >= 0");
   }
@@ -1144,6 +1180,7 @@ qcd_status ir_start(IrRun& R, const qcd_ir_params* p, hipStream_t st, bool dev) 
     launch_narrow(gh, kFP64, R.n, R.w.r64, (const double*)R.w.bp64, R.w.partials, 0, st);
     launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, site_grid(gh), p->s, st);
     launch_zero(gh, kFP64, R.n, R.w.x64, st);
+    if (R.net) launch_zero(G, kFP16, R.n, R.w.zin, st);  // the odd halves the network reads stay zero
     if (dev) launch_ir_dev_start(R.n, R.w.sc, R.w.sums, p->tol, p->max_outer, st);
     return QCD_OK;
   }
@@ -1210,7 +1247,12 @@ qcd_status ir_begin_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
   HIP_LAUNCHED();
   if (R.pc.net && R.pc.scale == 0.0f) {  // c = 1 / gain of M, measured on the first y~
     double gain = 0;
-    qcd_status rc = ptc_gain(R.pc.net, R.n, R.w.r, &gain, st);
+    const void* y = R.w.r;
+    if (R.w.eo) {  // the gain of M on (y~, 0)
+      launch_copy_fields(G, kFP16, R.n, R.w.zin, spinor_elems(R.g->g), R.w.r, spinor_elems(G), st);
+      y = R.w.zin;
+    }
+    qcd_status rc = ptc_gain(R.pc.net, R.n, y, &gain, st);
     if (rc) return rc;
     R.pc.scale = gain > 0 ? (float)(1.0 / gain) : 1.0f;
   }
@@ -1239,7 +1281,7 @@ qcd_status ir_end_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
                          R.sc[i].status, R.outer[i]);
   }
   if (R.pc.net) {
-    ptc_apply_half(R.pc.net, R.n, R.w.x, R.w.z, R.pc.scale, p->inner.ftz, nullptr, st);
+    precond_apply(R.g, R.pc, R.w, R.n, R.w.x, R.w.z, p->inner.ftz, nullptr, st);
     launch_correct(G, prec, R.n, R.w.sc, (double*)R.w.x64, R.w.z, st);
   } else {
     launch_correct(G, prec, R.n, R.w.sc, (double*)R.w.x64, R.w.x, st);
@@ -1255,7 +1297,7 @@ qcd_status ir_end_step(IrRun& R, const qcd_ir_params* p, hipStream_t st) {
 // restored for the right-hand sides that failed and the run continues
 // without the network); then the outer counters and stop flags.
 qcd_status ir_after_step(IrRun& R, const qcd_ir_params* p, int step, hipStream_t st) {
-  const Geom& G = R.g->g;
+  const Geom G = R.w.eo ? half_geom(R.g->g) : R.g->g;  // geometry of the refined vectors
   qcd_gauge* g = const_cast<qcd_gauge*>(R.g);
   if (R.pc.net) {
     bool undo = false;
@@ -1276,8 +1318,7 @@ qcd_status ir_after_step(IrRun& R, const qcd_ir_params* p, int step, hipStream_t
       for (int i = 0; i < R.n; i++) g->host_sc[i].outer_active = R.sc[i].outer_active;
       HIP_TRY(hipMemcpyAsync(R.w.sc, g->host_sc, sizeof(Scalars) * R.n, hipMemcpyHostToDevice, st));
       residual64(R.g, R.kappa, R.w, nullptr, st);
-      launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, dslash_partial_rows(G, R.g->tune[kFP64], R.n), p->s,
-                                 st);
+      launch_outer_residual_norm(R.n, R.w.sc, R.w.partials, residual_rows(R.g, R.w), p->s, st);
       HIP_LAUNCHED();
       qcd_status rc = read_scalars(R.g, R.w, st);
       if (rc) return rc;
@@ -1639,7 +1680,7 @@ qcd_status qcd_solve_mixed_ir(const qcd_gauge* g, double kappa, int nrhs, void* 
   R.info = info;
   R.net = const_cast<qcd_ptc*>(p->precond);
   if ((rc = check_ir_run(R, p))) return rc;
-  const int what = R.net ? 3 : (p->inner.even_odd ? kWhatEO : 0);
+  const int what = (R.net ? 3 : 0) | (p->inner.even_odd ? kWhatEO : 0);
   if ((rc = get_work(g, what, p->inner_prec, p->inner.max_iter, nrhs, ws, ws_bytes, &R.w))) return rc;
   return solve_ir_runs(&R, 1, p, S(stream), t0);
 }

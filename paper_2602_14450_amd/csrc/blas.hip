@@ -166,6 +166,20 @@ __global__ __launch_bounds__(256) void k_zero(Geom g, S* __restrict__ dst) {
     reinterpret_cast<Gr*>(dst)[e] = z;
 }
 
+// dst = src for the one-parity fields of blockIdx.y right-hand sides, whose
+// vectors start dst_stride / src_stride elements apart: the even half of a full
+// field has the one-parity layout at the field's start, so this moves even-odd
+// vectors into and out of full fields.
+template <typename S>
+__global__ __launch_bounds__(256) void k_copy_fields(Geom gh, S* __restrict__ dst, size_t dst_stride,
+                                                     const S* __restrict__ src, size_t src_stride) {
+  using Gr = typename Lay<S>::Gran;
+  const size_t n = spinor_granules<S>(gh);
+  Gr* d = reinterpret_cast<Gr*>(dst + (size_t)blockIdx.y * dst_stride);
+  const Gr* a = reinterpret_cast<const Gr*>(src + (size_t)blockIdx.y * src_stride);
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) d[e] = a[e];
+}
+
 // ---------------------------------------------------------------------------
 // BiCGStab body (Alg. 4 / Alg. 5).  Vectors: x, r (holds s between the two
 // matrix applications), r*, p, v, t.  All are walked granule by granule.
@@ -771,6 +785,16 @@ template <typename S> static void zero_t(const Geom& g, int n, void* dst, hipStr
 }
 void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st) {
   QCD_DISPATCH(prec, zero_t, g, n, dst, st);
+}
+template <typename S>
+static void copy_fields_t(const Geom& gh, int n, void* dst, size_t dst_stride, const void* src, size_t src_stride,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_fields<S>, dim3(flat_grid<S>(gh), n), dim3(256), 0, st, gh, (S*)dst, dst_stride,
+                     (const S*)src, src_stride);
+}
+void launch_copy_fields(const Geom& gh, int prec, int n, void* dst, size_t dst_stride, const void* src,
+                        size_t src_stride, hipStream_t st) {
+  QCD_DISPATCH(prec, copy_fields_t, gh, n, dst, dst_stride, src, src_stride, st);
 }
 
 void launch_bicg_init(int n, Scalars* sc, const double* partials, int nrows, hipStream_t st) {

@@ -1318,7 +1318,9 @@ static void launch_dslash_v(const Geom& g, const DslashSched& sc, int op, int ep
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
     else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
     else if (epi == kEpiTS) QCD_LAUNCH_EO(kOpD, kEpiTS);
-    else if (epi == kEpiRecon) {
+    else if (epi == kEpiTSAux) {  // the network-preconditioned Schur operator: FP16 only
+      if constexpr (std::is_same<S, __half2>::value) QCD_LAUNCH_EO(kOpD, kEpiTSAux);
+    } else if (epi == kEpiRecon) {
       if constexpr (std::is_same<S, double2>::value && T == 1) QCD_LAUNCH_EO(kOpD, kEpiRecon);
     } else QCD_LAUNCH_EO(kOpD, kEpiResid);
 #undef QCD_LAUNCH_EO
@@ -1358,7 +1360,9 @@ static void launch_dslash_lds_eo(const Geom& g, const DslashSched& sc, int op, i
   else if (epi == kEpiNone) QCD_LDS_EO(kOpD, kEpiNone);
   else if (epi == kEpiDotAux) QCD_LDS_EO(kOpD, kEpiDotAux);
   else if (epi == kEpiTS) QCD_LDS_EO(kOpD, kEpiTS);
-  else QCD_LDS_EO(kOpD, kEpiResid);
+  else if (epi == kEpiTSAux) {
+    if constexpr (std::is_same<S, __half2>::value) QCD_LDS_EO(kOpD, kEpiTSAux);
+  } else QCD_LDS_EO(kOpD, kEpiResid);
 #undef QCD_LDS_EO
 }
 
@@ -1442,7 +1446,9 @@ static void launch_dslash_mr(const Geom& g, const DslashTune& tune, int op, int 
     else if (epi == kEpiNone) QCD_LAUNCH_EO(kOpD, kEpiNone);
     else if (epi == kEpiDotAux) QCD_LAUNCH_EO(kOpD, kEpiDotAux);
     else if (epi == kEpiTS) QCD_LAUNCH_EO(kOpD, kEpiTS);
-    else QCD_LAUNCH_EO(kOpD, kEpiResid);
+    else if (epi == kEpiTSAux) {
+      if constexpr (std::is_same<S, __half2>::value) QCD_LAUNCH_EO(kOpD, kEpiTSAux);
+    } else QCD_LAUNCH_EO(kOpD, kEpiResid);
 #undef QCD_LAUNCH_EO
     return;
   }

@@ -142,6 +142,10 @@ void launch_pack_spinor_split(const Geom& g, int n, void* even, void* odd, const
 void launch_unpack_spinor_split(const Geom& g, int n, double* canon, const void* even, const void* odd,
                                 hipStream_t st);
 void launch_zero(const Geom& g, int prec, int n, void* dst, hipStream_t st);
+// n one-parity fields (geometry gh) copied; right-hand side b of dst / src starts
+// b * dst_stride / b * src_stride stored complex numbers in
+void launch_copy_fields(const Geom& gh, int prec, int n, void* dst, size_t dst_stride, const void* src,
+                        size_t src_stride, hipStream_t st);
 // ncomplex complex normal values (canonical complex128) from a counter-based stream keyed by seed
 void launch_gaussian(double* out, int64_t ncomplex, uint64_t seed, hipStream_t st);
 // native FP64 -> native prec (RNE, |stored|^2 partials if not null); native prec -> FP64 times scale_dev[rhs]

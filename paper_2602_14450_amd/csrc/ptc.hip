@@ -780,6 +780,9 @@ struct qcd_ptc {
   short* Af[kPtcMaxLayers];         // BF16 GEMM operands (fused inference ordering)
   __half2* act16[kPtcMaxLayers + 1];  // FP16 hidden activations of the solver's applications
   float2* act[kPtcMaxLayers + 1];   // activations (batch x channels native FP32 fields)
+  // Buffers of the two-pass form (training, and the FP32 mixing mode), allocated
+  // on its first use: a handle that only preconditions never holds them.
+  bool two_pass_ready;
   float2* target;                   // training targets (batch fields)
   float2* dact[2];                  // gradient ping-pong buffers
   void* X[kPtcMaxLayers];           // transported inputs per layer (kept for the backward pass), BF16 or FP32
@@ -835,6 +838,36 @@ void prep_weights(qcd_ptc* n, hipStream_t st) {
   }
 }
 
+// Widest GEMM operand row of the network, and the rows of a batch element.
+int max_kp(const qcd_ptc* n) {
+  int m = 16;
+  for (int l = 0; l < n->nlayers; l++) m = std::max(m, n->L[l].Kp);
+  return m;
+}
+size_t gemm_rows(const Geom& g) { return (size_t)2 * g.nb * 64 * 3; }
+
+// The two-pass form's buffers (max_batch elements each), on first use.
+qcd_status ensure_two_pass(qcd_ptc* n) {
+  if (n->two_pass_ready) return QCD_OK;
+  const Geom& g = n->g;
+  const size_t N = gemm_rows(g), es = n->mix_fp32 ? sizeof(float) : sizeof(short);
+  const int maxKp = max_kp(n);
+  int maxc = 1;
+  for (int l = 0; l <= n->nlayers; l++) maxc = std::max(maxc, n->channels[l]);
+  qcd_status rc = QCD_OK;
+  // the FP32-mixing inference reuses X[0] for every layer: it takes the widest layer's size
+  for (int l = 0; l < n->nlayers && rc == QCD_OK; l++)
+    rc = alloc(n, &n->X[l], (size_t)n->max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * es);
+  if (rc == QCD_OK) rc = alloc(n, &n->DO, (size_t)n->max_batch * N * 16 * es);
+  if (rc == QCD_OK) rc = alloc(n, (void**)&n->DX, (size_t)n->max_batch * N * maxKp * sizeof(float));
+  if (rc == QCD_OK) rc = alloc(n, (void**)&n->target, fields_bytes(g, n->max_batch));
+  if (rc == QCD_OK) rc = alloc(n, (void**)&n->dact[0], fields_bytes(g, (size_t)n->max_batch * maxc));
+  if (rc == QCD_OK) rc = alloc(n, (void**)&n->dact[1], fields_bytes(g, (size_t)n->max_batch * maxc));
+  if (rc) return rc;
+  n->two_pass_ready = true;
+  return QCD_OK;
+}
+
 template <typename SA, typename SL>
 void fused_layer(const qcd_ptc* n, int l, int nb, const SA* in, SA* out, const SL* U, float oscale,
                  const Scalars* scal, int ftz, hipStream_t st) {
@@ -864,7 +897,11 @@ template <typename E> void two_pass_layer(qcd_ptc* n, int l, int nb, hipStream_t
 }
 
 // (the FP32 mixing mode runs every FP32-activation forward in the two-pass form)
-void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
+qcd_status forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
+  if (train || n->mix_fp32) {
+    qcd_status rc = ensure_two_pass(n);
+    if (rc) return rc;
+  }
   for (int l = 0; l < n->nlayers; l++) {
     if (n->mix_fp32) {
       two_pass_layer<float>(n, l, nb, st);
@@ -874,6 +911,7 @@ void forward(qcd_ptc* n, int nb, bool train, hipStream_t st) {
       two_pass_layer<short>(n, l, nb, st);
     }
   }
+  return QCD_OK;
 }
 
 // One layer's backward from dact[cur]: weight gradient into n->grad, and
@@ -921,7 +959,8 @@ qcd_status read_loss(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
 // Loss and gradient of the weights (into n->grad) for the batch in act[0] / target.
 qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
   const Geom& g = n->g;
-  forward(n, nb, true, st);
+  qcd_status rc = forward(n, nb, true, st);
+  if (rc) return rc;
   const int last = n->nlayers;
   hipLaunchKernelGGL(k_ptc_loss_parts, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[last],
                      (const float2*)n->target, n->partials);
@@ -944,7 +983,8 @@ qcd_status loss_grad(qcd_ptc* n, int nb, double* loss, hipStream_t st) {
 qcd_status loss_grad_residual(qcd_ptc* n, double kappa, int nb, double* loss, hipStream_t st) {
   const Geom& g = n->g;
   const qcd_gauge* G = n->gauge;
-  forward(n, nb, true, st);
+  qcd_status rc = forward(n, nb, true, st);
+  if (rc) return rc;
   const int last = n->nlayers;
   launch_dslash(kFP32, g, G->tune[kFP32], kOpD, kEpiNone, nb, n->target, n->act[last], G->U[kFP32], kappa, nullptr,
                 nullptr, nullptr, 0, st);
@@ -1004,15 +1044,21 @@ namespace qcd {
 // layer.  Used by the preconditioned inner solver (all launches are
 // stream-ordered and capturable); batches whose solver has stopped are
 // skipped when scal is given.
+// More than max_batch fields are taken max_batch at a time (the hidden
+// activations hold max_batch elements).
 void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float scale, int ftz, const Scalars* scal,
                     hipStream_t st) {
   const __half2* U = (const __half2*)n->gauge->U[kFP16];
-  const __half2* src = (const __half2*)in;
-  for (int l = 0; l < n->nlayers; l++) {
-    const bool last = l == n->nlayers - 1;
-    __half2* dst = last ? (__half2*)out : n->act16[l + 1];
-    fused_layer<__half2, __half2>(n, l, nb, src, dst, U, last ? scale : 1.0f, scal, ftz, st);
-    src = dst;
+  const size_t fe = spinor_elems(n->g);
+  for (int b0 = 0; b0 < nb; b0 += n->max_batch) {
+    const int c = std::min(n->max_batch, nb - b0);
+    const __half2* src = (const __half2*)in + b0 * fe;
+    for (int l = 0; l < n->nlayers; l++) {
+      const bool last = l == n->nlayers - 1;
+      __half2* dst = last ? (__half2*)out + b0 * fe : n->act16[l + 1];
+      fused_layer<__half2, __half2>(n, l, c, src, dst, U, last ? scale : 1.0f, scal ? scal + b0 : nullptr, ftz, st);
+      src = dst;
+    }
   }
 }
 // Largest |M(v_b)| / |v_b| over the nb native FP16 fields v_b (zero fields
@@ -1020,20 +1066,25 @@ void ptc_apply_half(qcd_ptc* n, int nb, const void* in, void* out, float scale, 
 qcd_status ptc_gain(qcd_ptc* n, int nb, const void* in, double* gain, hipStream_t st) {
   const Geom& g = n->g;
   if (!n->gauge->U[kFP16]) return pfail(QCD_ERR_ARG, "the gauge handle holds no FP16 links");
-  hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const __half2*)in, n->act[0], 1.0f);
-  forward(n, nb, false, st);
-  hipLaunchKernelGGL(k_ptc_norms, dim3(site_blocks(g), nb), dim3(256), 0, st, g, (const float2*)n->act[0],
-                     (const float2*)n->act[n->nlayers], n->partials);
-  hipLaunchKernelGGL(k_ptc_loss_finish, dim3(nb), dim3(1024), 0, st, (const double*)n->partials, site_blocks(g), nb,
-                     n->sums);
-  PTC_LAUNCHED();
-  std::vector<double> h(2 * nb);
-  PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
-  PTC_TRY(hipStreamSynchronize(st));
   double best = 0;
-  for (int b = 0; b < nb; b++)
-    if (h[2 * b] > 0 && std::isfinite(h[2 * b + 1])) best = std::max(best, std::sqrt(h[2 * b + 1] / h[2 * b]));
-    else if (h[2 * b] > 0) return pfail(QCD_ERR_NONFINITE, "network output is not finite");
+  std::vector<double> h(2 * n->max_batch);
+  for (int b0 = 0; b0 < nb; b0 += n->max_batch) {  // max_batch fields at a time
+    const int c = std::min(n->max_batch, nb - b0);
+    hipLaunchKernelGGL(k_h2f, dim3(site_blocks(g), c), dim3(256), 0, st, g,
+                       (const __half2*)in + (size_t)b0 * spinor_elems(g), n->act[0], 1.0f);
+    qcd_status rc = forward(n, c, false, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_ptc_norms, dim3(site_blocks(g), c), dim3(256), 0, st, g, (const float2*)n->act[0],
+                       (const float2*)n->act[n->nlayers], n->partials);
+    hipLaunchKernelGGL(k_ptc_loss_finish, dim3(c), dim3(1024), 0, st, (const double*)n->partials, site_blocks(g), c,
+                       n->sums);
+    PTC_LAUNCHED();
+    PTC_TRY(hipMemcpyAsync(h.data(), n->sums, 2 * c * sizeof(double), hipMemcpyDeviceToHost, st));
+    PTC_TRY(hipStreamSynchronize(st));
+    for (int b = 0; b < c; b++)
+      if (h[2 * b] > 0 && std::isfinite(h[2 * b + 1])) best = std::max(best, std::sqrt(h[2 * b + 1] / h[2 * b]));
+      else if (h[2 * b] > 0) return pfail(QCD_ERR_NONFINITE, "network output is not finite");
+  }
   *gain = best;
   return QCD_OK;
 }
@@ -1066,7 +1117,7 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
   n->nlayers = nlayers;
   n->max_batch = max_batch;
   n->nweights = 0;
-  int maxKp = 16, maxc = 1;
+  int maxKp = 16;
   for (int l = 0; l <= nlayers; l++) n->channels[l] = channels[l];
   for (int l = 0; l < nlayers; l++) {
     PtcLayerDev& L = n->L[l];
@@ -1078,10 +1129,8 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
     n->woff[l] = n->nweights;
     n->nweights += (size_t)9 * L.cout * L.cin * 16;
     maxKp = std::max(maxKp, L.Kp);
-    maxc = std::max(maxc, std::max(L.cin, L.cout));
   }
   const Geom& g = n->g;
-  const size_t N = (size_t)2 * g.nb * 64 * 3;
   n->mix_blocks = 1024;
   qcd_status rc = QCD_OK;
 #define PTC_ALLOC(ptr, bytes) \
@@ -1093,18 +1142,11 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
   for (int l = 0; l < nlayers; l++) {
     PTC_ALLOC(n->A[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
     PTC_ALLOC(n->Af[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
-    // inference reuses X[0] for every layer, so it takes the widest layer's size
-    PTC_ALLOC(n->X[l], (size_t)max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * sizeof(short));
   }
   for (int l = 0; l <= nlayers; l++) PTC_ALLOC(n->act[l], fields_bytes(g, (size_t)max_batch * channels[l]));
   // act16[0] and act16[nlayers] hold the input and output of qcd_ptc_apply_prec in FP16
   for (int l = 0; l <= nlayers; l++)
     PTC_ALLOC(n->act16[l], (size_t)max_batch * channels[l] * spinor_elems(g) * sizeof(__half2));
-  PTC_ALLOC(n->target, fields_bytes(g, max_batch));
-  PTC_ALLOC(n->dact[0], fields_bytes(g, (size_t)max_batch * maxc));
-  PTC_ALLOC(n->dact[1], fields_bytes(g, (size_t)max_batch * maxc));
-  PTC_ALLOC(n->DO, (size_t)max_batch * N * 16 * sizeof(short));
-  PTC_ALLOC(n->DX, (size_t)max_batch * N * maxKp * sizeof(float));
   PTC_ALLOC(n->Gp, (size_t)n->mix_blocks * 4 * 16 * maxKp * sizeof(float));
   size_t max_mk = 0;
   for (int l = 0; l < nlayers; l++) max_mk = std::max(max_mk, (size_t)n->L[l].M * n->L[l].K);
@@ -1169,7 +1211,7 @@ qcd_status qcd_ptc_apply(qcd_ptc* n, int nbatch, void* out_dev, const void* in_d
   if (!out_dev || !in_dev) return pfail(QCD_ERR_ARG, "null vector");
   hipStream_t st = (hipStream_t)stream;
   launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)in_dev, 1.0, 0, nullptr, st);
-  forward(n, nbatch, false, st);
+  if ((rc = forward(n, nbatch, false, st))) return rc;
   launch_unpack_spinor(n->g, kFP32, nbatch, (double*)out_dev, n->act[n->nlayers], nullptr, 1.0, st);
   PTC_LAUNCHED();
   return QCD_OK;
@@ -1196,6 +1238,7 @@ qcd_status qcd_ptc_loss_grad(qcd_ptc* n, int nbatch, const void* r_dev, const vo
   qcd_status rc = check_batch(n, nbatch);
   if (rc) return rc;
   if (!r_dev || !e_dev) return pfail(QCD_ERR_ARG, "null vector");
+  if ((rc = ensure_two_pass(n))) return rc;
   hipStream_t st = (hipStream_t)stream;
   launch_pack_spinor(n->g, kFP32, nbatch, n->act[0], (const double*)r_dev, 1.0, 0, nullptr, st);
   launch_pack_spinor(n->g, kFP32, nbatch, n->target, (const double*)e_dev, 1.0, 0, nullptr, st);
@@ -1259,16 +1302,15 @@ qcd_status qcd_ptc_set_mixing(qcd_ptc* n, qcd_prec prec, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   PTC_TRY(hipStreamSynchronize(st));  // no launch may still read the old buffers
   const size_t es = want ? sizeof(float) : sizeof(short);
-  const Geom& g = n->g;
-  const size_t N = (size_t)2 * g.nb * 64 * 3;
-  int maxKp = 16;
-  for (int l = 0; l < n->nlayers; l++) maxKp = std::max(maxKp, n->L[l].Kp);
+  const size_t N = gemm_rows(n->g);
+  const int maxKp = max_kp(n);
   qcd_status rc = QCD_OK;
   for (int l = 0; l < n->nlayers && rc == QCD_OK; l++) {
     rc = realloc_buf(n, &n->A[l], 16 * (size_t)n->L[l].Kp * es);
-    if (rc == QCD_OK) rc = realloc_buf(n, &n->X[l], (size_t)n->max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * es);
+    if (rc == QCD_OK && n->two_pass_ready)  // else they are made at the new width on first use
+      rc = realloc_buf(n, &n->X[l], (size_t)n->max_batch * N * (l == 0 ? maxKp : n->L[l].Kp) * es);
   }
-  if (rc == QCD_OK) rc = realloc_buf(n, &n->DO, (size_t)n->max_batch * N * 16 * es);
+  if (rc == QCD_OK && n->two_pass_ready) rc = realloc_buf(n, &n->DO, (size_t)n->max_batch * N * 16 * es);
   if (rc) return rc;
   n->mix_fp32 = want;
   prep_weights(n, st);

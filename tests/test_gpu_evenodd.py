@@ -108,15 +108,73 @@ def test_even_odd_graph_replay_and_batched_lattices(q):
         g.close()
 
 
-def test_even_odd_rejects_network(q):
-    dims = (4, 4, 4, 8)
+# The network preconditions eq. (5) through its even-even block (the even rows
+# of M (v, 0)); with the third-order Neumann weights that block is
+# 1 + kappa^2 H_eo H_oe, so the inner solve needs fewer iterations, and every
+# solve must still reach the oracle's x*.
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (4, 6, 8, 10)])
+def test_even_odd_refinement_with_network(q, dims):
+    kappa = 0.124
     U = qi.gauge_field(dims, 0.3, 740)
+    bs = qi.gaussian_source(dims, 741, nrhs=3)
+    bs[1] *= 1e-3          # different norms in one batch
     g = q.gauge_upload(to_dev(U), dims)
-    net = q.PTC(g, (1, 2, 2, 1))
-    net.init_neumann(0.12)
-    b = to_dev(qi.gaussian_source(dims, 741))
+    net = q.PTC(g, (1, 2, 2, 1), max_batch=3)
+    net.init_neumann(kappa)
+    b = to_dev(bs)
+    runs = []
+    for use_graph in (False, True):
+        x = torch.zeros_like(b)
+        infos = q.solve_mixed_ir(g, kappa, x, b, inner_prec=q.FP16, tol=1e-12, precond=net, even_odd=True,
+                                 use_graph=use_graph)
+        runs.append((x, infos))
+    plain = q.solve_mixed_ir(g, kappa, torch.zeros_like(b), b, inner_prec=q.FP16, tol=1e-12, even_odd=True)
+    assert torch.equal(runs[0][0], runs[1][0])
+    xh = to_host(runs[0][0])
+    steps = max(info.outer_iters for info in runs[0][1])   # the network's step count is the call's
+    for r in range(3):
+        info = runs[0][1][r]
+        assert info.status == "ok" and info.true_rel_residual <= 1e-12
+        assert runs[1][1][r].inner_iters == info.inner_iters
+        assert info.precond_fallback == -1 and info.precond_steps == steps and info.precond_scale > 0
+        res = bs[r] - oracle.dslash(U, xh[r], kappa, dims)
+        assert np.linalg.norm(res) <= 1.01e-12 * np.linalg.norm(bs[r])
+        x_ref, _ = EO.solve_fp64(U, kappa, dims, bs[r], tol=1e-13)
+        assert np.linalg.norm(xh[r] - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+        assert info.inner_iters < plain[r].inner_iters, (r, info.inner_iters, plain[r].inner_iters)
+    net.close()
+    g.close()
+
+
+def test_even_odd_zero_network_falls_back(q):
+    # M = 0 breaks the first inner solve down; the step is undone (x_e restored,
+    # the even residual recomputed) and the call finishes with the plain solver
+    dims = (4, 6, 8, 10)
+    kappa = 0.124
+    U = qi.gauge_field(dims, 0.3, 742)
+    b = qi.gaussian_source(dims, 743)
+    g = q.gauge_upload(to_dev(U), dims)
+    net = q.PTC(g, (1, 2, 2, 1), max_batch=1)
+    x = torch.zeros(b.shape, dtype=torch.complex128, device="cuda")
+    info = q.solve_mixed_ir(g, kappa, x, to_dev(b), inner_prec=q.FP16, tol=1e-12, precond=net, even_odd=True)
+    assert info.status == "ok" and info.true_rel_residual <= 1e-12
+    assert info.precond_fallback == 0 and info.precond_steps == 0
+    x_ref, _ = EO.solve_fp64(U, kappa, dims, b, tol=1e-13)
+    assert np.linalg.norm(to_host(x) - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    res = b - oracle.dslash(U, to_host(x), kappa, dims)
+    assert np.linalg.norm(res) <= 1.01e-12 * np.linalg.norm(b)
+    # a caller workspace of the size the library reports for it (what = 3 + 8)
+    # gives the same solve; one byte less is refused before any launch
+    need = g.workspace_bytes(3 | 8, q.FP16, 1000, 1)
+    assert need > g.workspace_bytes(8, q.FP16, 1000, 1)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    x2 = torch.zeros_like(x)
+    info2 = q.solve_mixed_ir(g, kappa, x2, to_dev(b), inner_prec=q.FP16, tol=1e-12, precond=net, even_odd=True,
+                             inner_max_iter=1000, workspace=ws)
+    assert torch.equal(x, x2) and info2.inner_iters == info.inner_iters
     with pytest.raises(q.QcdError):
-        q.solve_mixed_ir(g, 0.12, torch.zeros_like(b), b, inner_prec=q.FP16, precond=net, even_odd=True)
+        q.solve_mixed_ir(g, kappa, torch.zeros_like(x), to_dev(b), inner_prec=q.FP16, tol=1e-12, precond=net,
+                         even_odd=True, inner_max_iter=1000, workspace=ws[:need - 1])
     net.close()
     g.close()
 

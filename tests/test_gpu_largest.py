@@ -13,7 +13,8 @@ elsewhere) must be within 3x of it; the solver's own FP64 residual must meet
 * the 12 spin-colour point sources at the origin in one batched even-odd
   refinement with the FP16 inner solver (s = 128, sigma = 64, graph replay);
 * a network trained on 16^4 pairs, applied unchanged as right preconditioner
-  of the full-matrix refinement at 48^3 x 96.
+  of the full-matrix refinement at 48^3 x 96 (2 Gaussian sources), and of
+  the even-odd refinement of the 12 point sources in one call.
 """
 import numpy as np
 import pytest
@@ -106,7 +107,8 @@ def test_twelve_point_sources_even_odd(q, big):
     torch.cuda.empty_cache()
 
 
-def test_network_trained_on_16_4_applied_unchanged(q, big):
+@pytest.fixture(scope="module")
+def weights16(q):
     from paper_2602_14450_amd import ptc_train as T
     net16, sets, _ = T.train_preconditioner((16, 16, 16, 16), 0.124, nfields=2, pairs_per_field=64, batch=16)
     weights = net16.get_weights()
@@ -114,6 +116,12 @@ def test_network_trained_on_16_4_applied_unchanged(q, big):
     for s in sets:
         s.gauge.close()
     del sets
+    torch.cuda.empty_cache()
+    return weights
+
+
+def test_network_trained_on_16_4_applied_unchanged(q, big, weights16):
+    weights = weights16
     g = big["g"]
     net = q.PTC(g, (1, 2, 2, 1), max_batch=2)
     net.set_weights(weights)
@@ -126,6 +134,30 @@ def test_network_trained_on_16_4_applied_unchanged(q, big):
         assert i.status == "ok" and i.true_rel_residual <= 1e-12, i
         assert i.precond_fallback == -1 and i.precond_steps == i.outer_iters
     for r in range(2):
+        rel = residual_checks(big["U"], to_host(x[r]), bs[r], big["near"], big["far"])
+        assert rel <= 3e-12, (r, rel)
+    net.close()
+    del b, x
+    torch.cuda.empty_cache()
+
+
+def test_network_trained_on_16_4_even_odd_twelve_sources(q, big, weights16):
+    # the paper's operator (eq. (5)) with the 12 point sources in one call and
+    # the 16^4-trained network as right preconditioner through its even-even
+    # block, two right-hand sides at a time
+    g = big["g"]
+    net = q.PTC(g, (1, 2, 2, 1), max_batch=2)
+    net.set_weights(weights16)
+    bs = np.stack([qi.point_source(DIMS, sp, c) for sp in range(4) for c in range(3)])
+    b = to_dev(bs)
+    x = torch.zeros_like(b)
+    infos = q.solve_mixed_ir(g, KAPPA, x, b, inner_prec=q.FP16, s=128.0, sigma=64.0, tol=1e-12, even_odd=True,
+                             use_graph=True, precond=net)
+    torch.cuda.synchronize()
+    for i in infos:
+        assert i.status == "ok" and i.true_rel_residual <= 1e-12, i
+        assert i.precond_fallback == -1 and i.precond_steps >= 1, i
+    for r in (0, 7, 11):
         rel = residual_checks(big["U"], to_host(x[r]), bs[r], big["near"], big["far"])
         assert rel <= 3e-12, (r, rel)
     net.close()
