@@ -103,31 +103,46 @@ __global__ void k_max_finish(const double* __restrict__ partials, int nrows, dou
   }
 }
 
-// dst = round(scale * canon) for right-hand side blockIdx.y; partial
-// |dst|^2 per block from the stored values.
-// With `odd` set the destination is split by parity: even sites go to the
-// one-parity fields at dst, odd sites to those at odd.
+// Canonical <-> native spinors, one thread per half index h: the sites
+// (2j, y, z, t) and (2j + 1, y, z, t), 24 consecutive canonical complex numbers,
+// are site h of parities p0 = (y + z + t) & 1 and p0 ^ 1, so a wave reads or
+// writes one contiguous canonical segment and the field is streamed once.
+// Geometry: the full lattice.  With `odd` set the native side is split by
+// parity: even sites in dst, odd sites in odd, each a one-parity field.
+__device__ __forceinline__ int64_t pair_site(const Geom& g, int h, int* p0) {
+  const Coord c = decode(g, 0, h);
+  *p0 = (c.y + c.z + c.t) & 1;
+  return (c.x & ~1) + (int64_t)g.L[0] * (c.y + (int64_t)g.L[1] * (c.z + (int64_t)g.L[2] * c.t));
+}
+
+// dst = scale * src rounded to S (FP16 flushing to zero with ftz); |dst|^2
+// partials per block (blocks past the half sites add zero rows, so a launch
+// keeps site_grid(g) rows).
 template <typename S>
 __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst, const double* __restrict__ src,
                                                      double scale, int ftz, double* __restrict__ partials,
                                                      S* __restrict__ odd) {
   using T = typename Traits<S>::T;
-  SiteId id = site_id(g);
+  const int h = blockIdx.x * 256 + threadIdx.x;
   const int rhs = blockIdx.y;
   src += (size_t)rhs * volume(g) * 24;
   double red[1] = {0.0};
-  if (id.valid) {
-    const int64_t s = lex_site(g, id.par, id.h);
-    const int lane = id.h & 63;
-    S* b = odd ? (id.par ? odd : dst) + (size_t)rhs * g.nb * 768 + sp_block(g, 0, id.h)
-               : dst + (size_t)rhs * spinor_elems(g) + sp_block(g, id.par, id.h);
+  if (h < g.Vh) {
+    int p0;
+    const int64_t s0 = pair_site(g, h, &p0);
+    const double2* s2 = reinterpret_cast<const double2*>(src) + s0 * 12;  // one 16-byte load per complex
+    const int lane = h & 63;
     T acc = 0;
-    const double2* s2 = reinterpret_cast<const double2*>(src) + s * 12;  // one 16-byte load per complex
-    for (int k = 0; k < 12; k++) {
-      const double2 c = s2[k];
-      const S v = pack_from_double<S>(scale * c.x, scale * c.y, ftz);
-      b[sp_off<S>(k, lane)] = v;
-      acc += norm2(Traits<S>::load(&v));
+    for (int q = 0; q < 2; q++) {
+      const int par = p0 ^ q;
+      S* b = odd ? (par ? odd : dst) + (size_t)rhs * g.nb * 768 + sp_block(g, 0, h)
+                 : dst + (size_t)rhs * spinor_elems(g) + sp_block(g, par, h);
+      for (int k = 0; k < 12; k++) {
+        const double2 c = s2[q * 12 + k];
+        const S v = pack_from_double<S>(scale * c.x, scale * c.y, ftz);
+        b[sp_off<S>(k, lane)] = v;
+        acc += norm2(Traits<S>::load(&v));
+      }
     }
     red[0] = acc;
   }
@@ -135,24 +150,27 @@ __global__ __launch_bounds__(256) void k_pack_spinor(Geom g, S* __restrict__ dst
 }
 
 // canon = scale * double(src) with scale = scale_dev[rhs] (if given) or scale.
-// With `odd` set the source is split by parity as in k_pack_spinor.
 template <typename S>
 __global__ __launch_bounds__(256) void k_unpack_spinor(Geom g, double* __restrict__ dst, const S* __restrict__ src,
                                                        const double* __restrict__ scale_dev, double scale,
                                                        const S* __restrict__ odd) {
-  SiteId id = site_id(g);
-  if (!id.valid) return;
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  if (h >= g.Vh) return;
   const int rhs = blockIdx.y;
   dst += (size_t)rhs * volume(g) * 24;
   if (scale_dev) scale = scale_dev[rhs];
-  const int64_t s = lex_site(g, id.par, id.h);
-  cx<typename Traits<S>::T> f[12];
-  if (odd)
-    load_site((id.par ? odd : src) + (size_t)rhs * g.nb * 768, g, 0, id.h, f);
-  else
-    load_site(src + (size_t)rhs * spinor_elems(g), g, id.par, id.h, f);
-  double2* d2 = reinterpret_cast<double2*>(dst) + s * 12;  // one 16-byte store per complex
-  for (int k = 0; k < 12; k++) d2[k] = make_double2(scale * (double)f[k].re, scale * (double)f[k].im);
+  int p0;
+  const int64_t s0 = pair_site(g, h, &p0);
+  double2* d2 = reinterpret_cast<double2*>(dst) + s0 * 12;  // one 16-byte store per complex
+  for (int q = 0; q < 2; q++) {
+    const int par = p0 ^ q;
+    cx<typename Traits<S>::T> f[12];
+    if (odd)
+      load_site((par ? odd : src) + (size_t)rhs * g.nb * 768, g, 0, h, f);
+    else
+      load_site(src + (size_t)rhs * spinor_elems(g), g, par, h, f);
+    for (int k = 0; k < 12; k++) d2[q * 12 + k] = make_double2(scale * (double)f[k].re, scale * (double)f[k].im);
+  }
 }
 
 template <typename S>
@@ -729,8 +747,8 @@ void launch_pack_spinor(const Geom& g, int prec, int n, void* dst, const double*
 template <typename S>
 static void unpack_spinor_t(const Geom& g, int n, double* c, const void* src, const double* sd, double scale,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3(site_grid(g), n), dim3(256), 0, st, g, c, (const S*)src, sd, scale,
-                     nullptr);
+  hipLaunchKernelGGL(k_unpack_spinor<S>, dim3((g.Vh + 255) / 256, n), dim3(256), 0, st, g, c, (const S*)src, sd,
+                     scale, nullptr);
 }
 void launch_unpack_spinor(const Geom& g, int prec, int n, double* canon, const void* src, const double* scale_dev,
                           double scale, hipStream_t st) {
@@ -744,7 +762,7 @@ void launch_pack_spinor_split(const Geom& g, int n, void* even, void* odd, const
 }
 void launch_unpack_spinor_split(const Geom& g, int n, double* canon, const void* even, const void* odd,
                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_unpack_spinor<double2>, dim3(site_grid(g), n), dim3(256), 0, st, g, canon,
+  hipLaunchKernelGGL(k_unpack_spinor<double2>, dim3((g.Vh + 255) / 256, n), dim3(256), 0, st, g, canon,
                      (const double2*)even, nullptr, 1.0, (const double2*)odd);
 }
 
