@@ -237,11 +237,20 @@ __device__ __forceinline__ T hop_compute(const HopRaw<S, NE>& d, cx<T> (&a)[4][3
     project_h<MU, MINUS>(f, h1, h2);
     HLink<BWD> L;
     h_link_prep<BWD>(u, L);
-    cx<float> w1[3], w2[3];
-    h_mult<BWD>(L, h1, w1);
-    h_mult<BWD>(L, h2, w2);
-    accumulate<MU, MINUS>(a, w1, w2);
-    return w1[0].re + w2[2].im;
+    if constexpr (MU == 3) {
+      // t hops: the projection keeps one spin half and the product adds to
+      // that half alone, so its dot-product chains start from the accumulators
+      constexpr int s0 = MINUS ? 2 : 0;
+      h_mult_acc<BWD>(L, h1, a[s0]);
+      h_mult_acc<BWD>(L, h2, a[s0 + 1]);
+      return a[s0][0].re + a[s0 + 1][2].im;
+    } else {
+      cx<float> w1[3], w2[3];
+      h_mult<BWD>(L, h1, w1);
+      h_mult<BWD>(L, h2, w2);
+      accumulate<MU, MINUS>(a, w1, w2);
+      return w1[0].re + w2[2].im;
+    }
   }
   cx<T> f[4][3], h1[3], h2[3], u[9], w1[3], w2[3];
 #pragma unroll
@@ -855,10 +864,16 @@ __device__ __forceinline__ void hop_compute_r(const HopRawR<S, NE, R>& d, cx<T> 
           }
         }
       project_h<MU, MINUS>(f, h1, h2);
-      cx<float> w1[3], w2[3];
-      h_mult<BWD>(L, h1, w1);
-      h_mult<BWD>(L, h2, w2);
-      accumulate<MU, MINUS>(a[r], w1, w2);
+      if constexpr (MU == 3) {  // as in hop_compute: chains start from the accumulators
+        constexpr int s0 = MINUS ? 2 : 0;
+        h_mult_acc<BWD>(L, h1, a[r][s0]);
+        h_mult_acc<BWD>(L, h2, a[r][s0 + 1]);
+      } else {
+        cx<float> w1[3], w2[3];
+        h_mult<BWD>(L, h1, w1);
+        h_mult<BWD>(L, h2, w2);
+        accumulate<MU, MINUS>(a[r], w1, w2);
+      }
     }
     return;
   }

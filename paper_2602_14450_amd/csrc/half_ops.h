@@ -60,4 +60,16 @@ __device__ __forceinline__ void h_mult(const HLink<BWD>& L, const h2v (&h)[3], c
   }
 }
 
+// w += U h (forward) or U^dag h (backward): the same products as h_mult with
+// each chain starting from the accumulator instead of zero
+template <bool BWD>
+__device__ __forceinline__ void h_mult_acc(const HLink<BWD>& L, const h2v (&h)[3], cx<float> (&w)[3]) {
+#pragma unroll
+  for (int r = 0; r < 3; r++) {
+    const int k0 = BWD ? r : 3 * r, dk = BWD ? 3 : 1;
+    w[r].re = hdot(L.p[k0 + 2 * dk], h[2], hdot(L.p[k0 + dk], h[1], hdot(L.p[k0], h[0], w[r].re)));
+    w[r].im = hdot(L.q[k0 + 2 * dk], h[2], hdot(L.q[k0 + dk], h[1], hdot(L.q[k0], h[0], w[r].im)));
+  }
+}
+
 }  // namespace qcd
