@@ -197,3 +197,31 @@ def test_preconditioner_argument_checks(q, system):
     net.close()
     g.close()
     other.close()
+
+
+@pytest.mark.parametrize("mixing", [3, 1])  # BF16, FP32
+def test_training_buffers_made_on_first_use(q, mixing):
+    # a handle that has only applied the network in FP16 (no training buffers
+    # yet) makes them at its first loss call, in the mixing precision set
+    # before: loss and gradient equal those of a handle whose first call is
+    # the loss itself
+    dims = (4, 4, 4, 8)
+    U = qi.gauge_field(dims, 0.3, 350)
+    g = q.gauge_upload(to_dev(U), dims)
+    r = to_dev(qi.gaussian_source(dims, 351, nrhs=2))
+    res = []
+    for first_apply in (True, False):
+        net = q.PTC(g, CH, max_batch=2)
+        net.init_neumann(KAPPA)
+        if mixing == 1:
+            net.set_mixing(q.FP32)
+        if first_apply:
+            out = torch.empty_like(r)
+            net.apply_prec(out, r, q.FP16)
+        res.append(net.loss_grad_residual(KAPPA, r))
+        net.close()
+    (l0, g0), (l1, g1) = res
+    assert l0 == l1 and np.isfinite(l0)
+    for a, b in zip(g0, g1):
+        assert np.array_equal(a, b)
+    g.close()
