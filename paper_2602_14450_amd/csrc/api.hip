@@ -379,15 +379,17 @@ qcd_status eo_finish(const qcd_gauge* g, double kappa, const Work& w, void* x_de
   const int rows_e = dslash_partial_rows(G, g->tune[kFP64], n, true);
   double* po = w.partials;
   double* pe = w.partials + (size_t)n * rows_o;
-  if (hop_kept)
-    launch_eo_recon(gh, n, (double*)w.x64o, (const double*)w.eta_o, (const double*)w.t64, kappa, po, st);
-  else
+  if (hop_kept) {  // x_o goes straight to the canonical output
+    launch_eo_recon_unpack(G, n, (double*)x_dev, (const double*)w.x64, (const double*)w.eta_o,
+                           (const double*)w.t64, kappa, po, st);
+  } else {
     launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiRecon, n, w.x64o, w.x64, g->U[kFP64], -kappa, nullptr, po,
                   nullptr, 0, st, w.eta_o, 1);
-  if (even_rows)
-    launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
-                  nullptr, 0, st, w.x64, 0);
-  launch_unpack_spinor_split(G, n, (double*)x_dev, w.x64, w.x64o, st);
+    if (even_rows)
+      launch_dslash(kFP64, G, g->tune[kFP64], kOpD, kEpiResid, n, w.r64, w.x64o, g->U[kFP64], kappa, w.eta_e, pe,
+                    nullptr, 0, st, w.x64, 0);
+    launch_unpack_spinor_split(G, n, (double*)x_dev, w.x64, w.x64o, st);
+  }
   launch_finish_sum(n, po, rows_o, 1, w.sums, st);
   if (even_rows) launch_finish_sum(n, pe, rows_e, 1, w.sums + n, st);
   HIP_LAUNCHED();

@@ -385,32 +385,45 @@ __global__ __launch_bounds__(256) void k_correct(Geom g, const Scalars* __restri
   store_site(x64, g, id.par, id.h, xo, 0);
 }
 
-// Even-odd reconstruction from the last refinement step's hop: x_o = eta_o +
-// kappa t with t = H_oe x_e (eq. (6)), and the odd rows eta_o - (x_o - kappa t)
-// of b - D x from the stored x_o as |.|^2 partials per block.  One-parity
-// FP64 fields in the half geometry; right-hand side blockIdx.y.
-__global__ __launch_bounds__(256) void k_eo_recon(Geom g, double2* __restrict__ xo, const double2* __restrict__ eta,
-                                                  const double2* __restrict__ t, double kappa,
-                                                  double* __restrict__ partials) {
-  SiteId id = site_id(g);
+// The end of an even-odd solve in one pass: x_o = eta_o + kappa t with t =
+// H_oe x_e from the last refinement step's hop (eq. (6)), and the canonical
+// solution (x_e from its one-parity field, x_o as formed) written pair by pair
+// as in k_unpack_spinor, so x_o never goes through memory; the odd rows
+// eta_o - (x_o - kappa t) of b - D x as |.|^2 partials per block of half sites
+// (site_grid of the one-parity geometry).  g: the full lattice; one-parity FP64
+// fields; right-hand side blockIdx.y.
+__global__ __launch_bounds__(256) void k_eo_recon_unpack(Geom g, double* __restrict__ canon,
+                                                         const double2* __restrict__ xe,
+                                                         const double2* __restrict__ eta,
+                                                         const double2* __restrict__ t, double kappa,
+                                                         double* __restrict__ partials) {
+  const int h = blockIdx.x * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
   double red[1] = {0.0};
-  if (id.valid) {
-    const size_t o = (size_t)blockIdx.y * spinor_elems(g);
-    cx<double> e[12], tt[12], x[12];
-    load_site(eta + o, g, id.par, id.h, e);
-    load_site(t + o, g, id.par, id.h, tt);
-#pragma unroll
-    for (int k = 0; k < 12; k++) x[k] = cx<double>(e[k].re + kappa * tt[k].re, e[k].im + kappa * tt[k].im);
-    store_site(xo + o, g, id.par, id.h, x, 0);
+  if (h < g.Vh) {
+    const size_t o = (size_t)rhs * g.nb * 768;  // one-parity field of this right-hand side
+    int p0;
+    const int64_t s0 = pair_site(g, h, &p0);
+    double2* d2 = reinterpret_cast<double2*>(canon + (size_t)rhs * volume(g) * 24) + s0 * 12;
+    // the pair's even site goes to slot p0, its odd site to slot 1 - p0: the
+    // same instructions for every lane, only the store addresses differ
+    cx<double> x[12];
+    load_site(xe + o, g, 0, h, x);
+    for (int k = 0; k < 12; k++) d2[p0 * 12 + k] = make_double2(x[k].re, x[k].im);
+    cx<double> e[12], tt[12];
+    load_site(eta + o, g, 0, h, e);
+    load_site(t + o, g, 0, h, tt);
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < 12; k++) {
+      x[k] = cx<double>(e[k].re + kappa * tt[k].re, e[k].im + kappa * tt[k].im);
       const double rr = e[k].re - (x[k].re - kappa * tt[k].re), ri = e[k].im - (x[k].im - kappa * tt[k].im);
       acc += rr * rr + ri * ri;
     }
+    for (int k = 0; k < 12; k++) d2[(1 - p0) * 12 + k] = make_double2(x[k].re, x[k].im);
     red[0] = acc;
   }
-  block_reduce_store<1>(red, partials + (size_t)blockIdx.y * gridDim.x, blockIdx.x);
+  block_reduce_store<1>(red, partials + (size_t)rhs * gridDim.x, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -894,12 +907,11 @@ void launch_correct(const Geom& g, int prec, int n, Scalars* sc, double* x64, co
   QCD_DISPATCH(prec, correct_t, g, n, sc, x64, xlo, st);
 }
 
-void launch_eo_recon(const Geom& gh, int n, double* xo, const double* eta_o, const double* t, double kappa,
-                     double* partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_eo_recon, dim3(site_grid(gh), n), dim3(256), 0, st, gh, (double2*)xo, (const double2*)eta_o,
-                     (const double2*)t, kappa, partials);
+void launch_eo_recon_unpack(const Geom& g, int n, double* canon, const double* xe, const double* eta_o,
+                            const double* t, double kappa, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_eo_recon_unpack, dim3((g.Vh + 255) / 256, n), dim3(256), 0, st, g, canon, (const double2*)xe,
+                     (const double2*)eta_o, (const double2*)t, kappa, partials);
 }
-
 void launch_finish_sum(int n, const double* partials, int nrows, int nv, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_finish_sum_any, dim3(n), dim3(1024), 0, st, partials, nrows, nv, out);
 }

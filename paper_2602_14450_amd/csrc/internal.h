@@ -165,14 +165,15 @@ void launch_xr_update(const Geom& g, int prec, int n, Scalars* sc, void* x, void
 void launch_iter_end(int n, Scalars* sc, const double* partials, int nrows, double* history, int hist_stride,
                      hipStream_t st);
 
-// with log (device-driven refinement): log[rhs][k] = (|r|, zeros of y~) of step k
-// x_o = eta_o + kappa t (t = H_oe x_e, one-parity FP64 fields in the half geometry gh) and
-// |eta_o - (x_o - kappa t)|^2 partials, site_grid(gh) rows per right-hand side
-void launch_eo_recon(const Geom& gh, int n, double* xo, const double* eta_o, const double* t, double kappa,
-                     double* partials, hipStream_t st);
+// x_o = eta_o + kappa t (t = H_oe x_e, one-parity FP64 fields) and the canonical solution
+// from x_e and x_o in one pass (g: the full lattice); |odd residual rows|^2 partials,
+// site_grid(half_geom(g)) rows per right-hand side
+void launch_eo_recon_unpack(const Geom& g, int n, double* canon, const double* xe, const double* eta_o,
+                            const double* t, double kappa, double* partials, hipStream_t st);
 // start of the device-driven refinement: |b| (from b2_dev, or the start norm),
 // the even-odd tolerance relative to it, and the step bookkeeping
 void launch_ir_dev_start(int n, Scalars* sc, const double* b2_dev, double tol, int max_outer, hipStream_t st);
+// with log (device-driven refinement): log[rhs][k] = (|r|, zeros of y~) of step k
 void launch_outer_residual_norm(int n, Scalars* sc, const double* partials, int nrows, double s_target,
                                 hipStream_t st, double* log = nullptr);
 void launch_convert(const Geom& g, int prec, int n, Scalars* sc, const double* r64, void* y, void* rstar,
