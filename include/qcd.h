@@ -327,7 +327,9 @@ qcd_status qcd_solve_mixed_ir_static(const qcd_gauge* g, double kappa, int nrhs,
  * inner.max_iter, nrhs[i]) bytes (a NULL entry selects that handle's own);
  * with every ws[i] given the call allocates no device memory and creates no
  * HIP objects (the streams and events it forks onto were made at upload).
- * p->precond must be NULL (QCD_ERR_UNSUPPORTED otherwise).  nlat in 1..64.
+ * p->precond must be NULL (QCD_ERR_UNSUPPORTED otherwise: a network is bound
+ * to one gauge handle; several right-hand sides of one lattice take it through
+ * qcd_solve_mixed_ir).  nlat in 1..64.
  * QCD_ERR_WORKSPACE if a ws[i] is too small. */
 qcd_status qcd_solve_mixed_ir_batched(int nlat, const qcd_gauge* const* g, const double* kappa, const int* nrhs,
                                       void* const* x_dev, const void* const* b_dev, const qcd_ir_params* p,
