@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="run the launch-shape tuner first (default: the library's measured defaults)")
     ap.add_argument("--only-dslash", action="store_true",
-                    help="time only the Wilson operator and the calibration copy (for counter runs)")
+                    help="time only the Wilson operator (one and 12 right-hand sides) and the calibration copy "
+                         "(for counter runs)")
     ap.add_argument("--profile-form", choices=("headline", "headline-graph", "twelve", "twelve-seq", "mixed",
                                                "mixed-seq"),
                     help="run one solve form twice, 0.3 s apart, and nothing else (for kernel traces: the "
@@ -626,6 +627,10 @@ def main():
                          link_reals=g.link_reals(prec))
         print(f"[bench] dslash {name}: {ms*1e3:.1f} us {gbs:.0f} GB/s", file=sys.stderr, flush=True)
     if args.only_dslash:
+        # and the 12-right-hand-side FP16 operator of the batched form (register tile)
+        ms12 = time_dslash(q, torch, g, q.FP16, max(5, args.dslash_reps // 5), V, nrhs=12)
+        print(f"[bench] dslash fp16 12 rhs: {ms12*1e3:.1f} us {(144 + 12 * 96) * V / ms12 / 1e6:.0f} GB/s",
+              file=sys.stderr, flush=True)
         print(f"[bench] calibration copy: {calib_bytes} bytes read and written", file=sys.stderr, flush=True)
         g.close()
         return

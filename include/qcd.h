@@ -173,6 +173,8 @@ int qcd_gauge_link_reals(const qcd_gauge* g, qcd_prec prec);
  * each of the GPU's eight XCDs its own slab of z, swept in t order as 2^(m-1)
  * thinner sub-slabs one after the other (applies when (Lx/2)*Ly is a multiple
  * of the block's half-sites and Lz of 8*2^(m-1), else falls back to 0);
+ * sched 4 gives each XCD a slab of t, swept in z order (applies when
+ * (Lx/2)*Ly is a multiple of the block's half-sites and Lt of 8);
  * variant 0..5 selects how many hops' loads are prefetched while one hop is
  * computed and the minimum waves per SIMD the kernel is compiled for:
  * 0 (1 hop, 2 waves), 1 (2, 2), 2 (0, 3), 3 (1, 3), 4 (0, 4), 5 (1, 4), and 6:
