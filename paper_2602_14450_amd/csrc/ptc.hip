@@ -15,7 +15,9 @@
 // Kp = 2K rounded up to 16).  The backward pass uses A^T for dX (MFMA), the
 // adjoint transports (T_{+mu}^dag = T_{-mu} for unitary links) as a gather,
 // and an MFMA reduction over columns for dW = dOut X^H.  Activations are
-// native FP32 spinor fields; links are the handle's native FP32 copy.
+// native FP32 spinor fields; links are the handle's native FP32 copy.  The
+// fused inference layer forms X in registers instead and multiplies on the
+// 16x16x32 BF16 instruction (K padded to 32).
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -29,6 +31,8 @@
 namespace qcd {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));    // BF16 bits, 8 k of one lane
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));  // the 16x16x32 BF16 operand type
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (finite inputs).
@@ -234,69 +238,65 @@ __global__ __launch_bounds__(256) void k_ptc_mix(Geom g, PtcLayerDev L, const E*
 // activations and links crosses HBM.
 //
 // Column ordering: a wave takes 16 sites (one per lane % 16) and all three
-// colours (three accumulators).  The K index is slot * 4 + e with slot =
-// (p * C_in + i) * 2 + sh (transport path, input channel, spin half) and
-// e = s_lo * 2 + re/im for spin s = 2 sh + s_lo; lane group G = lane / 16
-// supplies slot 4 kt + G of k-tile kt.  Output rows are r = (j * 2 + sh') * 4
-// + s'_lo * 2 + re/im, so lane group G ends up holding channel j = G / 2,
-// spins 2 (G % 2) and 2 (G % 2) + 1 of its site for all three colours.
+// colours (three accumulators).  The products run on the 16 x 16 x 32 BF16
+// instruction; K is ordered by position q of a (path, input channel) pair,
+// 8 k each: k = 8 q + 4 sh + 2 s_lo + re/im for spin s = 2 sh + s_lo.
+// Position q holds channel i = q % C_in of path p = (q / C_in + 1) mod 9, so
+// the hops come first, the forward and backward hop of one direction side
+// by side, and the identity path last.  K-tile kt holds positions 4 kt + G,
+// lane group G = lane / 16 supplying all 8 k of its pair: a lane transports
+// a whole spinor, loading and rebuilding the link once for both spin halves;
+// with C_in = 2 the direction of a k-tile is the same for the whole wave, and
+// the last k-tile is the identity path only.  Output rows are
+// r = (j * 2 + sh') * 4 + s'_lo * 2 + re/im, so lane group G ends up holding
+// channel j = G / 2, spins 2 (G % 2) and 2 (G % 2) + 1 of its site for all
+// three colours.
 
-// A for the fused ordering, from W[p][j][i][s'][s] of one layer.
+// K of the fused layer's weight operand: 2K rounded up to whole 32-wide k-tiles.
+__host__ __device__ inline int fused_kp(const PtcLayerDev& L) { return ((2 * L.K + 31) / 32) * 32; }
+// path of pair position q
+__host__ __device__ inline int fused_path(int q, int cin) { return (q / cin + 1) % 9; }
+
+// A for the fused ordering, from W[p][j][i][s'][s] of one layer (rows of fused_kp(L)).
 __global__ void k_ptc_prep_Af(PtcLayerDev L, const float2* __restrict__ W, short* __restrict__ A) {
+  const int kf = fused_kp(L);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 16 * L.Kp) return;
-  const int r = idx / L.Kp, k = idx % L.Kp;
+  if (idx >= 16 * kf) return;
+  const int r = idx / kf, k = idx % kf;
   const int j = r >> 3, spo = ((r >> 2) & 1) * 2 + ((r >> 1) & 1), ro = r & 1;
-  const int slot = k >> 2, e = k & 3;
+  const int q = k >> 3, e = k & 7;
   float v = 0.0f;
-  if (j < L.cout && slot < 18 * L.cin) {
-    const int p = slot / (2 * L.cin), i = (slot >> 1) % L.cin, s = (slot & 1) * 2 + (e >> 1), ri = e & 1;
+  if (j < L.cout && q < 9 * L.cin) {
+    const int p = fused_path(q, L.cin), i = q % L.cin, s = (e >> 2) * 2 + ((e >> 1) & 1), ri = e & 1;
     const float2 w = W[(((size_t)(p * L.cout + j) * L.cin + i) * 4 + spo) * 4 + s];
     v = ro == ri ? w.x : (ro == 0 ? -w.y : w.y);
   }
   A[idx] = to_bf16(v);
 }
 
-// The transported spin half of one k-slot in binary16 form (FP16 activations
-// and links): the two spins' colour vectors come from three 8-byte loads, the
-// link's row 2 is rebuilt in binary16, and U v / U^dag v use exact binary16
-// products summed in FP32 (the Wilson operator's FP16 arithmetic).
+// The transported spinor of one (path, input channel) pair in binary16 form
+// (FP16 activations and links): the neighbour's three 16-byte granules, the
+// link's row 2 rebuilt in binary16, and U v / U^dag v as exact binary16
+// products summed in FP32 (the Wilson operator's FP16 arithmetic).  The lanes
+// of a wave take different paths (forward and backward hops), so each lane
+// selects its entries and signs into the one forward product form.
 template <int CIN>
 __device__ __forceinline__ void fused_transport_h(const Geom& g, const __half2* __restrict__ in,
-                                                  const __half2* __restrict__ U, int recon, int b, int slot, int par,
-                                                  int h, const Coord& c, size_t fstride, cx<float> (&t)[2][3]) {
+                                                  const __half2* __restrict__ U, int recon, int b, int p, int i,
+                                                  int par, int h, const Coord& c, size_t fstride,
+                                                  cx<float> (&t)[4][3]) {
   using Gr = typename Lay<__half2>::Gran;  // 4 complex components
-  const int p = slot / (2 * CIN), i = (slot >> 1) % CIN, sh = slot & 1;
   const __half2* f = in + ((size_t)b * CIN + i) * fstride;
-  int sp = par, sh_idx = h, mu = 0;
-  bool fwd = true;
-  if (p > 0) {
-    mu = (p - 1) >> 1;
-    fwd = ((p - 1) & 1) == 0;
-    sp = par ^ 1;
-    sh_idx = nbr(g, h, c, mu, fwd ? 1 : -1);
-  }
-  // components 6 sh + 2 m, 6 sh + 2 m + 1 (m = 0..2; spins 2 sh, 2 sh + 1)
-  // share a granule: three 8-byte loads at computed offsets, so the spin
-  // half is never picked out of loaded registers by a run-time index
-  typedef _Float16 h4v __attribute__((ext_vector_type(4)));
-  const __half2* fb = f + sp_block(g, sp, sh_idx) + (sh_idx & 63) * 4;
-  h2v v[2][3];  // v[sl][cc]: component 6 sh + 3 sl + cc
+  const int mu = (p - 1) >> 1;  // p = 1..8
+  const bool fwd = ((p - 1) & 1) == 0;
+  const int sh_idx = nbr(g, h, c, mu, fwd ? 1 : -1);
+  const __half2* fb = f + sp_block(g, par ^ 1, sh_idx) + (sh_idx & 63) * 4;
+  h2v v[4][3];  // v[spin][colour]: component 3 spin + colour
 #pragma unroll
-  for (int m = 0; m < 3; m++) {
-    const int k = 6 * sh + 2 * m;
-    const h4v d = *reinterpret_cast<const h4v*>(fb + (k >> 2) * 64 * 4 + (k & 3));
-    // swizzles, not __builtin_bit_cast of the elements of a two-dword
-    // vector: the compiler (ROCm 7.2 clang) gives element 0 for d.y there
-    v[(2 * m) / 3][(2 * m) % 3] = d.xy;
-    v[(2 * m + 1) / 3][(2 * m + 1) % 3] = d.zw;
-  }
-  if (p == 0) {
+  for (int j = 0; j < 3; j++) {
+    const Gr q = *reinterpret_cast<const Gr*>(fb + j * 64 * 4);
 #pragma unroll
-    for (int sl = 0; sl < 2; sl++)
-#pragma unroll
-      for (int cc = 0; cc < 3; cc++) t[sl][cc] = cx<float>((float)v[sl][cc].x, (float)v[sl][cc].y);
-    return;
+    for (int e = 0; e < 4; e++) v[(4 * j + e) / 3][(4 * j + e) % 3] = h2_of(q.s[e]);
   }
   // U_mu(x) (forward) or U_mu(x - mu) (backward, applied as its adjoint)
   const int lp = fwd ? par : par ^ 1, lh = fwd ? h : sh_idx, lane = lh & 63;
@@ -321,39 +321,26 @@ __device__ __forceinline__ void fused_transport_h(const Geom& g, const __half2* 
     }
     u[8] = h2_of(lb[8 * 64 + lane]);
   }
-  if constexpr (CIN == 1) {
-    // The two lane halves of a wave take a forward and a backward hop here,
-    // so both take one product form: entry (r, b) of U, or of U^dag read as
-    // conj(u[3b + r]), with the sign flips of each form applied per lane.
-    // Same products in the same order as h_mult, without running both forms.
-    const uint32_t pm = fwd ? 0x80000000u : 0u;  // (re, -im) forward, (re, im) backward
-    const uint32_t qm = fwd ? 0u : 0x8000u;      // (im, re) forward, (-im, re) backward
-    HLink<false> L;
+  // Entry (r, b) of U, or of U^dag read as conj(u[3b + r]), with the sign
+  // flips of each form applied per lane: the same products in the same order
+  // as h_mult, without running both forms.
+  const uint32_t pm = fwd ? 0x80000000u : 0u;  // (re, -im) forward, (re, im) backward
+  const uint32_t qm = fwd ? 0u : 0x8000u;      // (im, re) forward, (-im, re) backward
+  HLink<false> L;
 #pragma unroll
-    for (int r = 0; r < 3; r++)
+  for (int r = 0; r < 3; r++)
 #pragma unroll
-      for (int bb = 0; bb < 3; bb++) {
-        // both entries as values first: a conditional of two array elements
-        // would select an address and index the array at run time
-        const uint32_t ef = __builtin_bit_cast(uint32_t, u[3 * r + bb]);
-        const uint32_t eb = __builtin_bit_cast(uint32_t, u[3 * bb + r]);
-        const uint32_t a = fwd ? ef : eb;
-        L.p[3 * r + bb] = __builtin_bit_cast(h2v, a ^ pm);
-        L.q[3 * r + bb] = __builtin_bit_cast(h2v, ((a >> 16) | (a << 16)) ^ qm);
-      }
+    for (int bb = 0; bb < 3; bb++) {
+      // both entries as values first: a conditional of two array elements
+      // would select an address and index the array at run time
+      const uint32_t ef = __builtin_bit_cast(uint32_t, u[3 * r + bb]);
+      const uint32_t eb = __builtin_bit_cast(uint32_t, u[3 * bb + r]);
+      const uint32_t a = fwd ? ef : eb;
+      L.p[3 * r + bb] = __builtin_bit_cast(h2v, a ^ pm);
+      L.q[3 * r + bb] = __builtin_bit_cast(h2v, ((a >> 16) | (a << 16)) ^ qm);
+    }
 #pragma unroll
-    for (int sl = 0; sl < 2; sl++) h_mult<false>(L, v[sl], t[sl]);
-  } else if (fwd) {  // uniform over the wave: one path per k-tile when C_in = 2
-    HLink<false> L;
-    h_link_prep<false>(u, L);
-#pragma unroll
-    for (int sl = 0; sl < 2; sl++) h_mult<false>(L, v[sl], t[sl]);
-  } else {
-    HLink<true> L;
-    h_link_prep<true>(u, L);
-#pragma unroll
-    for (int sl = 0; sl < 2; sl++) h_mult<true>(L, v[sl], t[sl]);
-  }
+  for (int s_ = 0; s_ < 4; s_++) h_mult<false>(L, v[s_], t[s_]);
 }
 
 // out[b][j] = oscale * sum_{p,i} W[p][j][i] T_p in[b][i] for batch b = blockIdx.y;
@@ -362,8 +349,8 @@ __device__ __forceinline__ void fused_transport_h(const Geom& g, const __half2* 
 template <typename SA, typename SL, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict__ in, SA* __restrict__ out,
                                                    const SL* __restrict__ U, int recon, const short* __restrict__ A,
-                                                   int Kp, float oscale, const Scalars* __restrict__ scal, int ftz) {
-  constexpr int NK = (18 * CIN + 3) / 4;
+                                                   int Kf, float oscale, const Scalars* __restrict__ scal, int ftz) {
+  constexpr int NK = (9 * CIN + 3) / 4;  // 32-wide k-tiles: four (path, channel) pairs each
   const int b = blockIdx.y;
   if (scal && !scal[b].active) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -374,66 +361,68 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
   const int h = valid ? h_raw : 0;  // padding lanes compute on site 0 and store nothing
   const Coord c = decode(g, par, h);
   const size_t fstride = spinor_elems(g);
-  bf16x4 af[NK];
+  bf16x8 af[NK];
 #pragma unroll
-  for (int kt = 0; kt < NK; kt++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) af[kt][q] = A[(lane & 15) * Kp + kt * 16 + 4 * G + q];
+  for (int kt = 0; kt < NK; kt++) {
+    const s16x8 a8 = *reinterpret_cast<const s16x8*>(A + (lane & 15) * Kf + kt * 32 + 8 * G);
+    af[kt] = __builtin_bit_cast(bf16x8, a8);
+  }
   f32x4 acc[3];
 #pragma unroll
   for (int cc = 0; cc < 3; cc++) acc[cc] = (f32x4){0, 0, 0, 0};
 #pragma unroll
   for (int kt = 0; kt < NK; kt++) {
-    const int slot = 4 * kt + G;
-    cx<float> t[2][3];  // transported spins 2 sh, 2 sh + 1, colours 0..2
+    const int q = 4 * kt + G;  // pair position: channel q % C_in of path fused_path(q, C_in)
+    cx<float> t[4][3];         // transported spins 0..3, colours 0..2
 #pragma unroll
-    for (int sl = 0; sl < 2; sl++)
+    for (int s_ = 0; s_ < 4; s_++)
 #pragma unroll
-      for (int cc = 0; cc < 3; cc++) t[sl][cc] = cx<float>(0, 0);
-    if constexpr (std::is_same<SA, __half2>::value && std::is_same<SL, __half2>::value) {
-      if (slot < 18 * CIN) fused_transport_h<CIN>(g, in, U, recon, b, slot, par, h, c, fstride, t);
-    } else if (slot < 18 * CIN) {
-      const int p = slot / (2 * CIN), i = (slot >> 1) % CIN, sh = slot & 1;
-      const SA* f = in + ((size_t)b * CIN + i) * fstride;
-      if (p == 0) {
-        const SA* fb = f + sp_block(g, par, h);
+      for (int cc = 0; cc < 3; cc++) t[s_][cc] = cx<float>(0, 0);
+    if (kt == NK - 1) {  // the identity path (positions past 9 C_in are padding)
+      if (q < 9 * CIN) {
+        const SA* fb = in + ((size_t)b * CIN + q % CIN) * fstride + sp_block(g, par, h);
 #pragma unroll
-        for (int sl = 0; sl < 2; sl++)
+        for (int s_ = 0; s_ < 4; s_++)
 #pragma unroll
-          for (int cc = 0; cc < 3; cc++) t[sl][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * (2 * sh + sl) + cc, h & 63));
-      } else {
-        const int mu = (p - 1) >> 1;
-        const bool fwd = ((p - 1) & 1) == 0;
-        const int hn = nbr(g, h, c, mu, fwd ? 1 : -1);
-        const SA* fb = f + sp_block(g, par ^ 1, hn);
-        cx<float> v[2][3], u[9];
-#pragma unroll
-        for (int sl = 0; sl < 2; sl++)
-#pragma unroll
-          for (int cc = 0; cc < 3; cc++) v[sl][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * (2 * sh + sl) + cc, hn & 63));
-        const int lp = fwd ? par : par ^ 1, lh = fwd ? h : hn;  // U_mu(x) or U_mu(x - mu)
-        load_link_any(g, U, recon, mu, lp, lh, u);
-#pragma unroll
-        for (int sl = 0; sl < 2; sl++)
-#pragma unroll
-          for (int a = 0; a < 3; a++) {
-            cx<float> s_(0, 0);
-#pragma unroll
-            for (int bb = 0; bb < 3; bb++)
-              s_ = s_ + (fwd ? u[3 * a + bb] * v[sl][bb] : cmulc(u[3 * bb + a], v[sl][bb]));
-            t[sl][a] = s_;
-          }
+          for (int cc = 0; cc < 3; cc++) t[s_][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * s_ + cc, h & 63));
       }
+    } else if constexpr (std::is_same<SA, __half2>::value && std::is_same<SL, __half2>::value) {
+      fused_transport_h<CIN>(g, in, U, recon, b, q / CIN + 1, q % CIN, par, h, c, fstride, t);
+    } else {
+      const int p = q / CIN + 1, i = q % CIN;  // a hop, p = 1..8
+      const SA* f = in + ((size_t)b * CIN + i) * fstride;
+      const int mu = (p - 1) >> 1;
+      const bool fwd = ((p - 1) & 1) == 0;
+      const int hn = nbr(g, h, c, mu, fwd ? 1 : -1);
+      const SA* fb = f + sp_block(g, par ^ 1, hn);
+      cx<float> v[4][3], u[9];
+#pragma unroll
+      for (int s_ = 0; s_ < 4; s_++)
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) v[s_][cc] = Traits<SA>::load(fb + sp_off<SA>(3 * s_ + cc, hn & 63));
+      const int lp = fwd ? par : par ^ 1, lh = fwd ? h : hn;  // U_mu(x) or U_mu(x - mu)
+      load_link_any(g, U, recon, mu, lp, lh, u);
+#pragma unroll
+      for (int s_ = 0; s_ < 4; s_++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+          cx<float> acc_(0, 0);
+#pragma unroll
+          for (int bb = 0; bb < 3; bb++)
+            acc_ = acc_ + (fwd ? u[3 * a + bb] * v[s_][bb] : cmulc(u[3 * bb + a], v[s_][bb]));
+          t[s_][a] = acc_;
+        }
     }
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      bf16x4 bv;
-      bv[0] = to_bf16(t[0][cc].re);
-      bv[1] = to_bf16(t[0][cc].im);
-      bv[2] = to_bf16(t[1][cc].re);
-      bv[3] = to_bf16(t[1][cc].im);
-      if (!valid) bv = (bf16x4){0, 0, 0, 0};
-      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[kt], bv, acc[cc], 0, 0, 0);
+      s16x8 bv;  // k = 8 q + 4 sh + 2 s_lo + re/im
+#pragma unroll
+      for (int s_ = 0; s_ < 4; s_++) {
+        bv[2 * s_] = to_bf16(t[s_][cc].re);
+        bv[2 * s_ + 1] = to_bf16(t[s_][cc].im);
+      }
+      if (!valid) bv = (s16x8){0, 0, 0, 0, 0, 0, 0, 0};
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kt], __builtin_bit_cast(bf16x8, bv), acc[cc], 0, 0, 0);
     }
   }
   const int j = G >> 1, sh = G & 1;
@@ -826,14 +815,14 @@ qcd_status alloc(qcd_ptc* n, void** p, size_t bytes) {
 
 void prep_weights(qcd_ptc* n, hipStream_t st) {
   for (int l = 0; l < n->nlayers; l++) {
-    const int cnt = 16 * n->L[l].Kp;
+    const int cnt = 16 * n->L[l].Kp, cntf = 16 * fused_kp(n->L[l]);
     if (n->mix_fp32)
       hipLaunchKernelGGL(k_ptc_prep_A<float>, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
                          (const float2*)(n->w + n->woff[l]), (float*)n->A[l]);
     else
       hipLaunchKernelGGL(k_ptc_prep_A<short>, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
                          (const float2*)(n->w + n->woff[l]), (short*)n->A[l]);
-    hipLaunchKernelGGL(k_ptc_prep_Af, dim3((cnt + 255) / 256), dim3(256), 0, st, n->L[l],
+    hipLaunchKernelGGL(k_ptc_prep_Af, dim3((cntf + 255) / 256), dim3(256), 0, st, n->L[l],
                        (const float2*)(n->w + n->woff[l]), n->Af[l]);
   }
 }
@@ -877,7 +866,7 @@ void fused_layer(const qcd_ptc* n, int l, int nb, const SA* in, SA* out, const S
   const int recon = recon_of(n, sizeof(SL) == sizeof(float2) ? kFP32 : kFP16);
 #define PTC_FUSED(CI, CO)                                                                                          \
   hipLaunchKernelGGL((k_ptc_fused<SA, SL, CI, CO>), grid, block, 0, st, g, in, out, U, recon, (const short*)n->Af[l], \
-                     L.Kp, oscale, scal, ftz)
+                     fused_kp(L), oscale, scal, ftz)
   if (L.cin == 1 && L.cout == 1) PTC_FUSED(1, 1);
   else if (L.cin == 1) PTC_FUSED(1, 2);
   else if (L.cout == 1) PTC_FUSED(2, 1);
@@ -1141,7 +1130,7 @@ qcd_status qcd_ptc_create(qcd_ptc** out, const qcd_gauge* gauge, int nlayers, co
   PTC_ALLOC(n->adam_v, n->nweights * sizeof(float2));
   for (int l = 0; l < nlayers; l++) {
     PTC_ALLOC(n->A[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
-    PTC_ALLOC(n->Af[l], 16 * (size_t)n->L[l].Kp * sizeof(short));
+    PTC_ALLOC(n->Af[l], 16 * (size_t)fused_kp(n->L[l]) * sizeof(short));
   }
   for (int l = 0; l <= nlayers; l++) PTC_ALLOC(n->act[l], fields_bytes(g, (size_t)max_batch * channels[l]));
   // act16[0] and act16[nlayers] hold the input and output of qcd_ptc_apply_prec in FP16
