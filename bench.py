@@ -58,9 +58,9 @@ def parse():
                     help="time only the Wilson operator (one and 12 right-hand sides) and the calibration copy "
                          "(for counter runs)")
     ap.add_argument("--profile-form", choices=("headline", "headline-graph", "twelve", "twelve-seq", "mixed",
-                                               "mixed-seq"),
-                    help="run one solve form twice, 0.3 s apart, and nothing else (for kernel traces: the "
-                         "second run follows the largest gap in the trace)")
+                                               "mixed-seq", "network"),
+                    help="run one solve form (or one FP16 network application) twice, 0.3 s apart, and nothing "
+                         "else (for kernel traces: the second run follows the largest gap in the trace)")
     return ap.parse_args()
 
 
@@ -560,10 +560,15 @@ def profile_form(args, q, torch, np, qi):
         else:
             b = torch.from_numpy(qi.gaussian_source(dims, 202)).cuda()
         x = torch.zeros_like(b)
+        if form == "network":
+            net = q.PTC(g, (1, 2, 2, 1), max_batch=1)
+            net.init_neumann(k)
 
         def run():
             x.zero_()
-            if form == "twelve-seq":
+            if form == "network":   # one FP16 application of the network, as the inner solve applies it
+                net.apply_prec(x, b, q.FP16)
+            elif form == "twelve-seq":
                 for r in range(12):
                     q.solve_mixed_ir(g, k, x[r], b[r].contiguous(), use_graph=True, **kw)
             else:
