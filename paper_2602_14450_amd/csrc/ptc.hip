@@ -33,6 +33,9 @@ namespace qcd {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));    // BF16 bits, 8 k of one lane
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));  // the 16x16x32 BF16 operand type
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest even (finite inputs).
@@ -415,14 +418,15 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
     }
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      s16x8 bv;  // k = 8 q + 4 sh + 2 s_lo + re/im
+      // k = 8 q + 4 sh + 2 s_lo + re/im; the conversion is the hardware's
+      // round-to-nearest-even (two values per instruction), as to_bf16
+      u32x4 bw;
 #pragma unroll
       for (int s_ = 0; s_ < 4; s_++) {
-        bv[2 * s_] = to_bf16(t[s_][cc].re);
-        bv[2 * s_ + 1] = to_bf16(t[s_][cc].im);
+        const f32x2 f = {valid ? t[s_][cc].re : 0.0f, valid ? t[s_][cc].im : 0.0f};
+        bw[s_] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f, bf16x2));
       }
-      if (!valid) bv = (s16x8){0, 0, 0, 0, 0, 0, 0, 0};
-      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kt], __builtin_bit_cast(bf16x8, bv), acc[cc], 0, 0, 0);
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[kt], __builtin_bit_cast(bf16x8, bw), acc[cc], 0, 0, 0);
     }
   }
   const int j = G >> 1, sh = G & 1;
