@@ -38,12 +38,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (finite inputs).
-__device__ __forceinline__ short to_bf16(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
+// FP32 -> BF16 bits, round to nearest even (the hardware's conversion).
+__device__ __forceinline__ short to_bf16(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 __device__ __forceinline__ float from_bf16(short h) { return __uint_as_float(((unsigned)(unsigned short)h) << 16); }
 
 // Element type E of the two-pass GEMM operands (X, A, DO): BF16 (as short
@@ -418,8 +414,8 @@ __global__ __launch_bounds__(256) void k_ptc_fused(Geom g, const SA* __restrict_
     }
 #pragma unroll
     for (int cc = 0; cc < 3; cc++) {
-      // k = 8 q + 4 sh + 2 s_lo + re/im; the conversion is the hardware's
-      // round-to-nearest-even (two values per instruction), as to_bf16
+      // k = 8 q + 4 sh + 2 s_lo + re/im; the hardware's round-to-nearest-even
+      // conversion, two values per instruction
       u32x4 bw;
 #pragma unroll
       for (int s_ = 0; s_ < 4; s_++) {
