@@ -784,6 +784,11 @@ def main():
                        inner_iters=[i.inner_iters for i in ib], sequential_inner_iters=seq_iters,
                        dslash_12rhs_us=ms12 * 1e3, dslash_12rhs_GBps=bytes12 / (ms12 * 1e-3) / 1e9,
                        dslash_12rhs_bytes_per_site=144 + nb * 96)
+        if dims == (32, 32, 32, 64):
+            # fabric traffic of the 12-right-hand-side launch from the committed counters
+            t12 = measured_counter("traffic bytes per launch fp16 12 rhs")
+            batched["dslash_12rhs_traffic"] = t12
+            batched["dslash_12rhs_traffic_vs_two_row_bytes"] = (t12 / ((192 + nb * 96) * V)) if t12 else None
         print(f"[bench] batched 12 rhs: {t_batched*1e3:.1f} ms vs {t_seq*1e3:.1f} ms sequential; "
               f"12-rhs dslash {ms12*1e3:.1f} us {bytes12 / ms12 / 1e6:.0f} GB/s", file=sys.stderr, flush=True)
         del xb, bpd, wsb
